@@ -1,0 +1,55 @@
+"""Planted mistakes in a copy of the CPU oracle must each fail at least one pin.
+
+Every mutant is a one-line edit of dg_oracle.c that models a plausible
+mistake (a dropped term, a wrong sign, index or operand, the other reading of
+an ambiguous passage).  It is compiled to a temporary library on the CPU and
+the pin suite is run against it in a subprocess; the mutant must be caught.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "dg_oracle.c")
+
+MUTANTS = {
+    "drop_interior_kappa_term": ("val += P->kappa * (avvx * jux + avvy * juy);", "val += 0.0;"),
+    "drop_average_half": ("const double avux = 0.5 * eps * gxs[S][c]", "const double avux = eps * gxs[S][c]"),
+    "upwind_on_outflow": ("if (!(bnK < 0.0)) continue;", "if (!(bnK > 0.0)) continue;"),
+    "upwind_uses_inner_trace": ("val += bnK * (uout - uin) * vK;", "val += bnK * (uout + uin) * vK;"),
+    "transposed_convection": ("if (useC) s += (b1 * gx[c] + b2 * gy[c]) * v[a];",
+                              "if (useC) s += (b1 * gx[a] + b2 * gy[a]) * v[c];"),
+    "interior_penalty_on_dirichlet": ("const double pen = P->sigma_D * eps / he;",
+                                      "const double pen = P->sigma * eps / he;"),
+    "literal_dirichlet_rhs_sign": ("double r = gd * (pen * v[a] + P->kappa * eps * dnv);",
+                                   "double r = gd * (pen * v[a] - eps * dnv);"),
+    "inflow_on_neumann_too": ("if (M->bnd_type[bi] == 1) { /* Neumann",
+                              "if (0) { /* Neumann"),
+    "inward_normal": ("const double nx = ey / len, ny = -ex / len; /* outward normal of K_i */",
+                      "const double nx = -ey / len, ny = ex / len;"),
+    "stroud_weight_quarter": ("w[m] = 0.125 * wa[i] * wb[j];", "w[m] = 0.25 * wa[i] * wb[j];"),
+    "legendre_recurrence_sign": ("poly_axpy(-(double)p / (p + 1.0), &t2, &Q[p + 1]);",
+                                 "poly_axpy((double)p / (p + 1.0), &t2, &Q[p + 1]);"),
+    "jacobi_alpha_off_by_one": ("double al = 2.0 * p + 1.0;", "double al = 2.0 * p;"),
+    "drop_neumann_data": ("for (int a = 0; a < n; ++a) rhs[K * n + a] += ds * gn * v[a];", "(void)gn;"),
+    "volume_det_missing": ("const double dx = wv[g] * A.det;", "const double dx = wv[g];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor not found exactly once: %r" % old
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-w",
+                           str(mpath), "-o", str(so), "-lm"])
+    env = dict(os.environ, DG_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        "-x", "-q", "-p", "no:cacheprovider", "-k", "not brute_force"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "mutant %s survived every pin:\n%s" % (name, r.stdout[-2000:])

@@ -1,0 +1,572 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: closed forms,
+library routines, invariants of the bilinear form of section 1 eq. (ds),
+consistency (exact reproduction of global polynomials), convergence rates,
+the paper's printed fixtures, and brute-force evaluation on tiny meshes.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spl
+import scipy.special as ss
+
+import oracle as O
+from paper_1502_02941_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def omesh(m):
+    return O.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann)
+
+
+# ---------------------------------------------------------------- quadrature
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 6, 8])
+def test_edge_rule_matches_scipy_gauss_legendre(q):
+    t, w = O.edge_rule(q)
+    x, wx = ss.roots_legendre(q)
+    np.testing.assert_allclose(t, 0.5 * (x + 1), atol=1e-15)
+    np.testing.assert_allclose(w, 0.5 * wx, atol=1e-15)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 6, 8])
+def test_volume_rule_exact_on_monomials(q):
+    """int_T xi^i eta^j = i! j! / (i+j+2)! for every i+j <= 2q-1 (Stroud exactness)."""
+    xi, eta, w = O.volume_rule(q)
+    for i in range(2 * q):
+        for j in range(2 * q - i):
+            exact = math.factorial(i) * math.factorial(j) / math.factorial(i + j + 2)
+            assert abs(np.sum(w * xi ** i * eta ** j) - exact) <= 1e-15 + 1e-13 * exact, (i, j)
+
+
+def test_volume_rule_nodes_match_scipy_jacobi():
+    q = 5
+    xi, eta, w = O.volume_rule(q)
+    b, wb = ss.roots_jacobi(q, 1.0, 0.0)
+    np.testing.assert_allclose(np.unique(np.round(eta, 14)), np.sort(0.5 * (b + 1)), atol=1e-13)
+    assert abs(w.sum() - 0.5) < 1e-15
+
+
+# --------------------------------------------------------------------- basis
+def dubiner_scipy(k, xi, eta):
+    """Independent evaluation of the orthonormal Dubiner basis in collapsed
+    coordinates with scipy's Jacobi polynomials."""
+    a = 2.0 * xi / (1.0 - eta) - 1.0
+    b = 2.0 * eta - 1.0
+    out = []
+    for d in range(k + 1):
+        for q in range(d + 1):
+            p = d - q
+            c = math.sqrt(2.0 * (2 * p + 1) * (p + q + 1))
+            out.append(c * ss.eval_legendre(p, a) * (1 - eta) ** p * ss.eval_jacobi(q, 2 * p + 1, 0, b))
+    return np.stack(out, axis=-1)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+def test_basis_matches_independent_jacobi_evaluation(k):
+    rng = np.random.default_rng(k)
+    xi = rng.uniform(0, 1, 200)
+    eta = rng.uniform(0, 1, 200) * (1 - xi)
+    v, dx, de = O.basis_eval(k, xi, eta)
+    np.testing.assert_allclose(v, dubiner_scipy(k, xi, eta), rtol=1e-12, atol=1e-12)
+    h = 1e-6
+    fdx = (dubiner_scipy(k, xi + h, eta) - dubiner_scipy(k, xi - h, eta)) / (2 * h)
+    fde = (dubiner_scipy(k, xi, eta + h) - dubiner_scipy(k, xi, eta - h)) / (2 * h)
+    np.testing.assert_allclose(dx, fdx, atol=1e-6 * max(1, np.abs(fdx).max()))
+    np.testing.assert_allclose(de, fde, atol=1e-6 * max(1, np.abs(fde).max()))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_basis_orthonormal_under_independent_rule(k):
+    q = 12
+    a, wa = ss.roots_legendre(q)
+    b, wb = ss.roots_jacobi(q, 1.0, 0.0)
+    A, Bm = np.meshgrid(a, b, indexing="ij")
+    WA, WB = np.meshgrid(wa, wb, indexing="ij")
+    xi = (0.25 * (1 + A) * (1 - Bm)).ravel()
+    eta = (0.5 * (1 + Bm)).ravel()
+    w = (WA * WB / 8).ravel()
+    v, _, _ = O.basis_eval(k, xi, eta)
+    np.testing.assert_allclose(v.T @ (w[:, None] * v), np.eye(v.shape[1]), atol=1e-13)
+    # the constant mode is sqrt(2)
+    np.testing.assert_allclose(v[:, 0], math.sqrt(2.0), atol=1e-14)
+
+
+# ------------------------------------------------------------ mesh handling
+def test_paper_fixture_refines_to_the_8x8_grid():
+    g = json.load(open(os.path.join(GOLDEN, "paper_initial_mesh.json")))
+    pm = W.paper_mesh()
+    np.testing.assert_array_equal(pm.nodes, np.array(g["Nodes"], dtype=float))
+    np.testing.assert_array_equal(pm.elems + 1, np.array(g["Elements"]))
+    np.testing.assert_array_equal(pm.dirichlet + 1, np.array(g["Dirichlet"]))
+    m = pm
+    for _ in range(g["refinements_in_driver"]):
+        m = W.uniform_refine(m)
+    M = omesh(m)
+    assert M.T == 128 and M.n_dir == 32 and M.n_neu == 0
+    assert M.T * (1 + 1) * (1 + 2) // 2 == 384  # DoFs for degree 1, section 4's formula
+    s = W.structured_mesh(8)
+    tri = lambda mm: sorted(tuple(sorted(map(tuple, np.round(mm.nodes[e], 12)))) for e in mm.elems)
+    assert tri(m) == tri(s)
+
+
+def test_set_parameter_table():
+    g = json.load(open(os.path.join(GOLDEN, "set_parameter_table.json")))
+    for c in g["cases"]:
+        sigma, kappa = O.default_penalty(c["method"], c["degree"])
+        assert sigma == c["penalty"] and kappa == c["kappa"]
+
+
+def test_mesh_errors():
+    m = W.structured_mesh(2)
+    bad = m.elems.copy()
+    bad[0] = bad[0][::-1]
+    with pytest.raises(O.OracleError, match="-2"):
+        O.Mesh(m.nodes, bad, m.dirichlet, m.neumann)
+    with pytest.raises(O.OracleError, match="-3"):
+        O.Mesh(m.nodes, m.elems, m.dirichlet[1:], m.neumann)        # missing boundary edge
+    with pytest.raises(O.OracleError, match="-3"):
+        O.Mesh(m.nodes, m.elems, m.dirichlet, m.dirichlet[:1])      # listed twice
+    with pytest.raises(O.OracleError, match="-3"):
+        O.Mesh(m.nodes, m.elems, np.concatenate([m.dirichlet, [[0, 4]]]), m.neumann)  # interior edge listed
+    three = np.concatenate([m.elems, [[0, 1, 4]]])
+    with pytest.raises(O.OracleError):
+        O.Mesh(m.nodes, three, m.dirichlet, m.neumann)
+
+
+# -------------------------------------------------------------- closed forms
+def test_reaction_only_closed_form():
+    """eps = 0, b = 0: A = alpha M with M_K = det J_K I (orthonormal basis), and
+    for f in P_k the solution is u_h = f / alpha exactly."""
+    m = W.structured_mesh(4, jitter=0.2, seed=3)
+    M = omesh(m)
+    k, alpha = 2, 1.7
+    pts = M.volume_points(k + 2)
+    f = lambda x, y: 1 + x - 2 * y + 3 * x * y - x * x
+    B = O.assemble(M, k, sigma=0, kappa=-1, eps=0.0, bx=0.0, by=0.0, alpha=alpha,
+                   f=O.Field.points(f(pts[..., 0], pts[..., 1])))
+    p = m.nodes[m.elems]
+    det = (p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1])
+    np.testing.assert_allclose(B.diag, alpha * det[:, None, None] * np.eye(6)[None], atol=1e-14)
+    assert np.abs(B.off_ij).max() == 0 and np.abs(B.off_ji).max() == 0
+    x = B.rhs.reshape(M.T, 6) / (alpha * det[:, None])
+    X = pts[..., 0].ravel()
+    Y = pts[..., 1].ravel()
+    uh = O.eval_solution(M, k, x.ravel(), np.repeat(np.arange(M.T), (k + 2) ** 2), np.stack([X, Y], 1))
+    np.testing.assert_allclose(uh, f(X, Y) / alpha, atol=1e-12)
+
+
+def _edges_py(m):
+    """Edge classification recomputed in Python from the raw arrays."""
+    owner = {}
+    for K, tri in enumerate(m.elems):
+        for l in range(3):
+            a, b = int(tri[l]), int(tri[(l + 1) % 3])
+            owner.setdefault((min(a, b), max(a, b)), []).append((K, a, b))
+    dset = {(min(a, b), max(a, b)) for a, b in m.dirichlet}
+    interior, bnd = [], []
+    for key, lst in owner.items():
+        if len(lst) == 2:
+            lst.sort()
+            interior.append((lst[0][0], lst[1][0], lst[0][1], lst[0][2]))
+        else:
+            K, a, b = lst[0]
+            bnd.append((K, a, b, key in dset))
+    return interior, bnd
+
+
+def test_k0_closed_form():
+    """P0: phi = sqrt(2) on every element.  Interior edge: +2 sigma eps on both
+    diagonals, -2 sigma eps on both couplings (h_e = |e| cancels the edge
+    length); downwind diagonal +2|b.n||e|, coupling -2|b.n||e|.  Dirichlet edge:
+    +2 sigma_D eps, and +2|b.n||e| on inflow.  Mass: 2|K| alpha."""
+    m = W.structured_mesh(3, dirichlet=("bottom", "left", "top"), neumann=("right",), jitter=0.15, seed=1)
+    M = omesh(m)
+    sigma, sigma_D, eps, b, alpha = 5.0, 7.0, 0.3, (0.8, -0.35), 0.6
+    B = O.assemble(M, 0, sigma=sigma, sigma_D=sigma_D, kappa=-1, eps=eps, bx=b[0], by=b[1], alpha=alpha, f=0.0)
+    A = np.zeros((M.T, M.T))
+    p = m.nodes[m.elems]
+    det = (p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1])
+    A[np.arange(M.T), np.arange(M.T)] += alpha * det
+    interior, bnd = _edges_py(m)
+    for Ki, Kj, a, c in interior:
+        d = m.nodes[c] - m.nodes[a]
+        L = np.hypot(*d)
+        nrm = np.array([d[1], -d[0]]) / L
+        A[Ki, Ki] += 2 * sigma * eps
+        A[Kj, Kj] += 2 * sigma * eps
+        A[Ki, Kj] -= 2 * sigma * eps
+        A[Kj, Ki] -= 2 * sigma * eps
+        beta = b[0] * nrm[0] + b[1] * nrm[1]
+        up, dn = (Ki, Kj) if beta > 0 else (Kj, Ki)
+        A[dn, dn] += 2 * abs(beta) * L
+        A[dn, up] -= 2 * abs(beta) * L
+    for K, a, c, isD in bnd:
+        d = m.nodes[c] - m.nodes[a]
+        L = np.hypot(*d)
+        nrm = np.array([d[1], -d[0]]) / L
+        beta = b[0] * nrm[0] + b[1] * nrm[1]
+        if isD:
+            A[K, K] += 2 * sigma_D * eps
+            if beta < 0:
+                A[K, K] += 2 * abs(beta) * L
+    np.testing.assert_allclose(B.to_scipy().toarray(), A, atol=1e-13)
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_sipg_diffusion_symmetric_and_spd(k):
+    m = W.structured_mesh(4, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=2)
+    M = omesh(m)
+    sig, kap = O.default_penalty(O.SIPG, k)
+    B = O.assemble(M, k, sigma=sig, kappa=kap, eps=0.7, bx=0.0, by=0.0, alpha=0.0, f=0.0, parts=O.PART_D)
+    A = B.to_scipy().toarray()
+    assert np.linalg.norm(A - A.T) <= 1e-14 * np.linalg.norm(A)
+    sla.cholesky(A)  # SPD with Dirichlet on part of the boundary
+    Bn = O.assemble(M, k, sigma=1.0, kappa=1.0, eps=0.7, bx=0.0, by=0.0, alpha=0.0, f=0.0, parts=O.PART_D)
+    An = Bn.to_scipy().toarray()
+    assert np.linalg.norm(An - An.T) > 1e-3 * np.linalg.norm(An)
+    # NIPG: the skew part of D is exactly the two flux terms; the symmetric part is coercive
+    w = np.linalg.eigvalsh(0.5 * (An + An.T))
+    assert w.min() > 0
+
+
+def _trace_points(m, a, c, nq=10):
+    t, w = ss.roots_legendre(nq)
+    t, w = 0.5 * (t + 1), 0.5 * w
+    pa, pb = m.nodes[a], m.nodes[c]
+    return pa[None] + t[:, None] * (pb - pa)[None], w
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_upwind_energy_identity(k):
+    """For div b = 0: u^T C u = sum_int 1/2 int |b.n| [u]^2 + sum_bnd 1/2 int s |b.n| u^2
+    with s = -1 on Neumann inflow and +1 elsewhere (upwind form of section 1 eq. (ds),
+    inflow term on the Dirichlet part of Gamma^- only)."""
+    m = W.structured_mesh(3, dirichlet=("bottom", "right"), neumann=("top", "left"), jitter=0.2, seed=5)
+    M = omesh(m)
+    b = (0.7, 0.45)
+    B = O.assemble(M, k, sigma=0, kappa=0, eps=0.0, bx=b[0], by=b[1], alpha=0.0, f=0.0, parts=O.PART_C)
+    rng = np.random.default_rng(0)
+    n = (k + 1) * (k + 2) // 2
+    u = rng.standard_normal(M.T * n)
+    lhs = u @ (B.to_scipy() @ u)
+    interior, bnd = _edges_py(m)
+    rhs = 0.0
+    for Ki, Kj, a, c in interior:
+        X, w = _trace_points(m, a, c)
+        d = m.nodes[c] - m.nodes[a]
+        L = np.hypot(*d)
+        beta = abs(b[0] * d[1] - b[1] * d[0]) / L
+        ui = O.eval_solution(M, k, u, np.full(len(X), Ki), X)
+        uj = O.eval_solution(M, k, u, np.full(len(X), Kj), X)
+        rhs += 0.5 * beta * L * np.sum(w * (ui - uj) ** 2)
+    for K, a, c, isD in bnd:
+        X, w = _trace_points(m, a, c)
+        d = m.nodes[c] - m.nodes[a]
+        L = np.hypot(*d)
+        bn = (b[0] * d[1] - b[1] * d[0]) / L
+        s = -1.0 if (bn < 0 and not isD) else 1.0
+        uk = O.eval_solution(M, k, u, np.full(len(X), K), X)
+        rhs += 0.5 * s * abs(bn) * L * np.sum(w * uk ** 2)
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+# ------------------------------------------------------------- consistency
+def _poly_case(m, k, prob, kappa, sigma):
+    M = omesh(m)
+    q = k + 2
+    pts = M.volume_points(q)
+    bp, nrm = M.boundary_points(q)
+    f = O.Field.points(prob.f(pts[..., 0], pts[..., 1]))
+    gD = O.Field.points(prob.u(bp[..., 0], bp[..., 1]))
+    gN = O.Field.points(prob.gN(bp[..., 0], bp[..., 1], nrm[:, None, 0], nrm[:, None, 1]))
+    if prob.b[0] == "affine":
+        bx, by = O.Field.affine(*prob.b[1]), O.Field.affine(*prob.b[2])
+    else:
+        bx, by = prob.b
+    B = O.assemble(M, k, sigma=sigma, kappa=kappa, eps=prob.eps, bx=bx, by=by, alpha=prob.alpha, f=f, gD=gD, gN=gN)
+    x = spl.spsolve(B.to_scipy().tocsc(), B.rhs)
+    X = pts[..., 0].ravel()
+    Y = pts[..., 1].ravel()
+    uh = O.eval_solution(M, k, x, np.repeat(np.arange(M.T), q * q), np.stack([X, Y], 1))
+    ue = prob.u(X, Y)
+    return np.abs(uh - ue).max() / np.abs(ue).max()
+
+
+BCS = {
+    "allD": (W.SIDES, ()),
+    "mixed": (("bottom", "left"), ("top", "right")),
+    "oneD": (("left",), ("bottom", "right", "top")),
+}
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("kappa", [-1.0, 0.0, 1.0])
+@pytest.mark.parametrize("bc", sorted(BCS))
+def test_polynomial_reproduction(k, kappa, bc):
+    """Consistency of eq. (ds): a global u in P_k, with f, g^D, g^N derived
+    from it exactly, is reproduced exactly for every kappa and boundary split."""
+    d, nm = BCS[bc]
+    m = W.structured_mesh(3, dirichlet=d, neumann=nm, jitter=0.2, seed=k)
+    sigma = 3.0 * k * (k + 1) if kappa != 1.0 else 1.0
+    for prob in (W.polynomial_problem(k, 0.3, (0.9, -0.4), 0.5, seed=k),
+                 W.polynomial_problem(k, 0.05, W.rotating_b(), 0.0, seed=k + 10)):
+        err = _poly_case(m, k, prob, kappa, sigma)
+        assert err < 1e-9, (prob.name, err)
+
+
+def test_polynomial_reproduction_catches_literal_rhs_sign():
+    """The paper prints -eps grad v . n g^D in l_h for every kappa; only the kappa
+    reading (+kappa eps grad v.n g^D) is consistent for NIPG: with the literal
+    sign the NIPG solution differs from u.  Emulated by flipping kappa in l_h via
+    linearity: F_literal = F(kappa) - (kappa + 1) * [the g^D symmetry term]."""
+    m = W.structured_mesh(3, jitter=0.2, seed=0)
+    M = omesh(m)
+    k = 1
+    prob = W.polynomial_problem(k, 0.3, (0.0, 0.0), 0.5, seed=1)
+    q = k + 2
+    pts = M.volume_points(q)
+    bp, nrm = M.boundary_points(q)
+    f = O.Field.points(prob.f(pts[..., 0], pts[..., 1]))
+    gD = O.Field.points(prob.u(bp[..., 0], bp[..., 1]))
+    kw = dict(sigma=1.0, eps=prob.eps, bx=0.0, by=0.0, alpha=prob.alpha, f=f, gD=gD)
+    Bp = O.assemble(M, k, kappa=1.0, **kw)
+    Bm = O.assemble(M, k, kappa=-1.0, **kw)
+    F_literal = Bm.rhs  # rhs with -eps grad v.n g^D, i.e. the kappa=-1 rhs
+    x_lit = spl.spsolve(Bp.to_scipy().tocsc(), F_literal)
+    x_ok = spl.spsolve(Bp.to_scipy().tocsc(), Bp.rhs)
+    X = pts[..., 0].ravel()
+    Y = pts[..., 1].ravel()
+    el = np.repeat(np.arange(M.T), q * q)
+    ue = prob.u(X, Y)
+    e_ok = np.abs(O.eval_solution(M, k, x_ok, el, np.stack([X, Y], 1)) - ue).max()
+    e_lit = np.abs(O.eval_solution(M, k, x_lit, el, np.stack([X, Y], 1)) - ue).max()
+    assert e_ok < 1e-10 and e_lit > 1e-4
+
+
+# --------------------------------------------------------------- convergence
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_sipg_l2_convergence_order(k):
+    prob = W.sinsin_problem()
+    errs, hs = [], []
+    for N in (4, 8, 16, 32):
+        m = W.structured_mesh(N)
+        M = omesh(m)
+        pts = M.volume_points(k + 2)
+        sig, kap = O.default_penalty(O.SIPG, k)
+        B = O.assemble(M, k, sigma=sig, kappa=kap, eps=prob.eps, bx=1.0, by=1.0, alpha=1.0,
+                       f=O.Field.points(prob.f(pts[..., 0], pts[..., 1])), gD=0.0)
+        x = spl.spsolve(B.to_scipy().tocsc(), B.rhs)
+        errs.append(O.l2_error(M, k, x, prob.u))
+        hs.append(M.hmax)
+    rates = [math.log(errs[i] / errs[i + 1]) / math.log(hs[i] / hs[i + 1]) for i in range(len(errs) - 1)]
+    assert abs(rates[-1] - (k + 1)) <= 0.3 and abs(rates[-2] - (k + 1)) <= 0.3, rates
+
+
+# -------------------------------------------------------------------- solver
+@pytest.mark.parametrize("case", ["c1", "c2_sipg", "c2_nipg"])
+def test_gmres_matches_direct_solve(case):
+    if case == "c1":
+        m, k, prob, meth, tol = W.structured_mesh(8), 1, W.sinsin_problem(), O.SIPG, 1e-12
+    else:
+        m, k, prob = W.structured_mesh(24), 2, W.boundary_layer_problem()
+        meth, tol = (O.SIPG if case.endswith("sipg") else O.NIPG), 1e-10
+    M = omesh(m)
+    pts = M.volume_points(k + 2)
+    sig, kap = O.default_penalty(meth, k)
+    B = O.assemble(M, k, sigma=sig, kappa=kap, eps=prob.eps, bx=prob.b[0], by=prob.b[1], alpha=prob.alpha,
+                   f=O.Field.points(prob.f(pts[..., 0], pts[..., 1])), gD=0.0)
+    A = B.to_scipy().tocsc()
+    xd = spl.spsolve(A, B.rhs)
+    x, its, rel, conv = O.gmres(B, restart=50, tol=tol)
+    assert conv and rel <= tol
+    true_rel = np.linalg.norm(B.rhs - A @ x) / np.linalg.norm(B.rhs)
+    assert true_rel <= tol * 1.0001
+    cond = np.linalg.cond(A.toarray()) if A.shape[0] < 4000 else 1e6
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 10 * cond * tol
+    np.testing.assert_allclose(B.matvec(x), A @ x, rtol=1e-13, atol=1e-13 * np.abs(A @ x).max())
+
+
+def test_gmres_reports_non_convergence():
+    m = W.structured_mesh(8)
+    M = omesh(m)
+    prob = W.sinsin_problem()
+    pts = M.volume_points(3)
+    B = O.assemble(M, 1, sigma=6, kappa=-1, eps=prob.eps, bx=1.0, by=1.0, alpha=1.0,
+                   f=O.Field.points(prob.f(pts[..., 0], pts[..., 1])))
+    x, its, rel, conv = O.gmres(B, tol=1e-12, max_iters=1)
+    assert not conv and its == 1 and rel > 1e-12
+
+
+# ------------------------------------------------------------- relabelling
+def test_solution_invariant_under_relabelling():
+    """Renumbering elements, rotating each element's vertex list and listing the
+    boundary edges in another order and direction leaves u_h unchanged."""
+    m = W.structured_mesh(5, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=7)
+    k = 2
+    prob = W.polynomial_problem(4, 0.05, W.rotating_b(), 0.3, seed=3)  # not in P_k: a genuine solution
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(m.T)
+    rot = rng.integers(0, 3, m.T)
+    el2 = np.array([np.roll(m.elems[p], -r) for p, r in zip(perm, rot)], dtype=np.int32)
+    m2 = W.MeshArrays(m.nodes, el2, m.dirichlet[::-1, ::-1].copy(), m.neumann[::-1].copy())
+
+    def solve(mm):
+        M = omesh(mm)
+        pts = M.volume_points(k + 2)
+        bp, nrm = M.boundary_points(k + 2)
+        B = O.assemble(M, k, sigma=18, kappa=-1, eps=prob.eps, bx=O.Field.affine(*prob.b[1]),
+                       by=O.Field.affine(*prob.b[2]), alpha=prob.alpha,
+                       f=O.Field.points(prob.f(pts[..., 0], pts[..., 1])),
+                       gD=O.Field.points(prob.u(bp[..., 0], bp[..., 1])),
+                       gN=O.Field.points(prob.gN(bp[..., 0], bp[..., 1], nrm[:, None, 0], nrm[:, None, 1])))
+        return M, spl.spsolve(B.to_scipy().tocsc(), B.rhs)
+
+    M1, x1 = solve(m)
+    M2, x2 = solve(m2)
+    cent = m.nodes[m.elems].mean(axis=1) * 0.6 + m.nodes[m.elems][:, 0] * 0.4
+    u1 = O.eval_solution(M1, k, x1, np.arange(m.T), cent)
+    inv = np.argsort(perm)
+    u2 = O.eval_solution(M2, k, x2, inv[np.arange(m.T)], cent)
+    np.testing.assert_allclose(u1, u2, atol=1e-11 * np.abs(u1).max())
+
+
+# --------------------------------------------------------------- brute force
+@pytest.mark.parametrize("kappa_int", [-1, 1])
+def test_brute_force_two_triangles_sympy(kappa_int):
+    """Every entry of A and F on a 2-triangle mesh, recomputed symbolically
+    (exact integration over the triangles and edges with sympy) straight from
+    the forms of section 1 eq. (ds) with the monomial-free collapsed-coordinate
+    Dubiner definition.  Agreement to 1e-13 relative."""
+    sp = pytest.importorskip("sympy")
+    X, Y, t = sp.symbols("x y t", real=True)
+    nodes = np.array([[0.0, 0.0], [1.0, 0.1], [0.9, 1.0], [-0.1, 0.8]])
+    elems = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    dirichlet = np.array([[0, 1], [1, 2]], dtype=np.int32)
+    neumann = np.array([[2, 3], [3, 0]], dtype=np.int32)
+    k = 1
+    eps, bxv, byv, alpha, sigma, sigD, kappa = sp.Rational(3, 10), sp.Rational(7, 10), sp.Rational(-2, 5), \
+        sp.Rational(1, 2), 6, 11, kappa_int
+    f_expr = 1 + X * Y
+    gD_expr = X - Y
+    gN_expr = sp.Rational(1, 3) + X
+    M = O.Mesh(nodes, elems, dirichlet, neumann)
+    q = k + 2
+    pts = M.volume_points(q)
+    bp, _ = M.boundary_points(q)
+    fnum = sp.lambdify((X, Y), f_expr, "numpy")
+    B = O.assemble(M, k, sigma=sigma, sigma_D=sigD, kappa=kappa, eps=float(eps), bx=float(bxv), by=float(byv),
+                   alpha=float(alpha), f=O.Field.points(fnum(pts[..., 0], pts[..., 1])),
+                   gD=O.Field.affine(0.0, 1.0, -1.0), gN=O.Field.affine(1.0 / 3.0, 1.0, 0.0))
+    nd = [sp.Matrix([sp.nsimplify(v, rational=True) for v in p]) for p in nodes]
+
+    def basis(K):
+        P1, P2, P3 = (nd[i] for i in elems[K])
+        J = sp.Matrix.hstack(P2 - P1, P3 - P1)
+        ref = J.inv() * (sp.Matrix([X, Y]) - P1)
+        xi, eta = ref[0], ref[1]
+        phis = []
+        for d in range(k + 1):
+            for qq in range(d + 1):
+                p = d - qq
+                c = sp.sqrt(2 * (2 * p + 1) * (p + qq + 1))
+                Q = sp.expand((1 - eta) ** p * sp.legendre(p, sp.Symbol("a")).subs(
+                    sp.Symbol("a"), 2 * xi / (1 - eta) - 1))
+                Q = sp.cancel(Q)
+                R = sp.jacobi(qq, 2 * p + 1, 0, 2 * eta - 1)
+                phis.append(sp.expand(c * Q * R))
+        return phis, J.det()
+
+    def tri_integral(expr, K):
+        P1, P2, P3 = (nd[i] for i in elems[K])
+        u, v = sp.symbols("u v")
+        sub = {X: P1[0] + (P2[0] - P1[0]) * u + (P3[0] - P1[0]) * v,
+               Y: P1[1] + (P2[1] - P1[1]) * u + (P3[1] - P1[1]) * v}
+        J = abs((P2[0] - P1[0]) * (P3[1] - P1[1]) - (P3[0] - P1[0]) * (P2[1] - P1[1]))
+        e = sp.expand(expr.subs(sub, simultaneous=True))
+        return J * sp.integrate(sp.integrate(e, (u, 0, 1 - v)), (v, 0, 1))
+
+    def edge_integral(expr, a, c):
+        pa, pc = nd[a], nd[c]
+        L = sp.sqrt((pc - pa).dot(pc - pa))
+        e = sp.expand(expr.subs({X: pa[0] + t * (pc[0] - pa[0]), Y: pa[1] + t * (pc[1] - pa[1])}, simultaneous=True))
+        return L * sp.integrate(e, (t, 0, 1)), L
+
+    phis = [basis(K)[0] for K in range(2)]
+    n = 3
+    A = sp.zeros(2 * n, 2 * n)
+    F = sp.zeros(2 * n, 1)
+    grad = lambda e: (sp.diff(e, X), sp.diff(e, Y))
+    for K in range(2):
+        for a in range(n):
+            va = phis[K][a]
+            F[K * n + a] += tri_integral(f_expr * va, K)
+            for c in range(n):
+                uc = phis[K][c]
+                gu, gv = grad(uc), grad(va)
+                A[K * n + a, K * n + c] += tri_integral(eps * (gu[0] * gv[0] + gu[1] * gv[1]) +
+                                                        (bxv * gu[0] + byv * gu[1]) * va + alpha * uc * va, K)
+    # interior edge (0,2): K_0 is K_i, normal outward of K_0
+    a_, c_ = 0, 2  # K_0 traverses 2 -> 0, K_1 traverses 0 -> 2
+    pa, pc = nd[2], nd[0]
+    d = pc - pa
+    L = sp.sqrt(d.dot(d))
+    nx, ny = d[1] / L, -d[0] / L
+    beta = bxv * nx + byv * ny
+    for T in range(2):
+        for a in range(n):
+            for S in range(2):
+                for c in range(n):
+                    sT, sS = (1 if T == 0 else -1), (1 if S == 0 else -1)
+                    v, u = phis[T][a], phis[S][c]
+                    gu, gv = grad(u), grad(v)
+                    e = -(sp.Rational(1, 2) * eps * (gu[0] * nx + gu[1] * ny)) * sT * v \
+                        + kappa * sp.Rational(1, 2) * eps * (gv[0] * nx + gv[1] * ny) * sS * u \
+                        + sigma * eps / L * sS * sT * u * v
+                    # upwind: downwind element gets b.n_K (u_out - u_in) v
+                    dn = 1 if beta > 0 else 0
+                    bnK = -abs(beta)
+                    if T == dn:
+                        uin = u if S == dn else 0
+                        uout = u if S != dn else 0
+                        e += bnK * (uout - uin) * v
+                    val, _ = edge_integral(e, 2, 0)
+                    A[T * n + a, S * n + c] += val
+    # boundary edges
+    for K, (a_, c_), isD in ((0, (0, 1), True), (0, (1, 2), True), (1, (2, 3), False), (1, (3, 0), False)):
+        pa, pc = nd[a_], nd[c_]
+        d = pc - pa
+        L = sp.sqrt(d.dot(d))
+        nx, ny = d[1] / L, -d[0] / L
+        bn = bxv * nx + byv * ny
+        for a in range(n):
+            v = phis[K][a]
+            gv = grad(v)
+            if not isD:
+                F[K * n + a] += edge_integral(gN_expr * v, a_, c_)[0]
+                continue
+            r = gD_expr * (sigD * eps / L * v + kappa * eps * (gv[0] * nx + gv[1] * ny))
+            if bn < 0:
+                r += -bn * gD_expr * v
+            F[K * n + a] += edge_integral(r, a_, c_)[0]
+            for c in range(n):
+                u = phis[K][c]
+                gu = grad(u)
+                e = -eps * (gu[0] * nx + gu[1] * ny) * v + kappa * eps * (gv[0] * nx + gv[1] * ny) * u \
+                    + sigD * eps / L * u * v
+                if bn < 0:
+                    e += -bn * u * v
+                A[K * n + a, K * n + c] += edge_integral(e, a_, c_)[0]
+    An = np.array(A.evalf(30), dtype=float)
+    Fn = np.array(F.evalf(30), dtype=float).ravel()
+    Ao = B.to_scipy().toarray()
+    assert np.abs(Ao - An).max() <= 1e-13 * np.abs(An).max()
+    assert np.abs(B.rhs - Fn).max() <= 1e-13 * np.abs(Fn).max()
