@@ -1,0 +1,204 @@
+/*
+ * dgdcr.h -- C ABI of the MI355X (gfx950) discontinuous Galerkin library for
+ * steady diffusion-convection-reaction problems
+ *
+ *     alpha u - eps Lap u + b . grad u = f   in Omega,
+ *     u = g^D on Gamma^D,   eps grad u . n = g^N on Gamma^N,
+ *
+ * discretised as in Uzunca & Karasozen, "A Matlab Tutorial for
+ * Diffusion-Convection-Reaction Equations using DGFEM" (arXiv:1502.02941),
+ * section 1 eq. (1) and the interior penalty scheme eq. (ds): SIPG / NIPG /
+ * IIPG diffusion, upwind convection, reaction, and the load functional l_h.
+ * The matrix is D + C + R of section 2.3 eq. (dgscheme) and (system) in
+ * block-sparse row (BSR) form; it is solved by restarted GMRES with a right
+ * block-Jacobi preconditioner, in FP64 or with FP32 Arnoldi cycles and FP64
+ * residual / update steps (iterative refinement).
+ *
+ * Conventions shared by every call:
+ *  - indices are 0-based (the paper's arrays are 1-based);
+ *  - "dev_" pointers are device (HIP) memory owned by the caller; "host"
+ *    pointers are host memory owned by the caller and only read during the
+ *    call; objects (dg_mesh, dg_solver) are owned by the library until their
+ *    _destroy call;
+ *  - `stream` is a hipStream_t (NULL = the default stream); device work is
+ *    stream-ordered and the call returns before it finishes unless stated;
+ *  - errors are returned as negative dg_status codes, never by aborting;
+ *    a positive code is a warning (the outputs are valid but see the code).
+ *
+ * Layouts:
+ *  - element-local basis: orthonormal Dubiner basis of degree k on the
+ *    reference triangle, n_loc = (k+1)(k+2)/2 functions ordered by total
+ *    degree d = 0..k, then q = 0..d (p = d-q); vertex 1 of an element row maps
+ *    to (0,0), vertex 2 to (1,0), vertex 3 to (0,1);
+ *  - dof index = element * n_loc + local index (element-major);
+ *  - BSR: row_ptr[T+1], col_idx[nnzb] (int32); block row K holds the
+ *    diagonal block first, then one block per interior neighbour in local
+ *    edge order (edge l joins vertex l and vertex l+1 mod 3); values are
+ *    [nnzb][n_loc][n_loc] row-major, row = test function phi_i, column =
+ *    trial function phi_j (entry = a_h(phi_j, phi_i)), FP64 or FP32.
+ */
+#ifndef DGDCR_H
+#define DGDCR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DG_OK = 0,
+    DG_NOT_CONVERGED = 1,       /* warning: iteration cap reached; x holds the last iterate */
+    DG_ERR_ARG = -1,            /* null pointer, size or enum out of range, degree mismatch */
+    DG_ERR_ORIENTATION = -2,    /* an element is not counter-clockwise (det J <= 0), section 2.1 */
+    DG_ERR_BOUNDARY = -3,       /* a boundary edge is not listed in exactly one of Dirichlet /
+                                   Neumann, or a listed edge is not a boundary edge (eq. 1) */
+    DG_ERR_NONMANIFOLD = -4,    /* an edge shared by more than two elements, or a repeated element */
+    DG_ERR_DEGREE = -5,         /* degree outside [0, DG_MAX_DEGREE], or sigma undefined for k = 0 */
+    DG_ERR_METHOD = -6,         /* method not NIPG / SIPG / IIPG */
+    DG_ERR_NONFINITE = -7,      /* NaN / Inf in coordinates, parameters or a residual norm */
+    DG_ERR_HIP = -8,            /* a HIP runtime call failed */
+    DG_ERR_OOM = -9             /* device or host allocation failed */
+} dg_status;
+
+#define DG_MAX_DEGREE 4
+
+/* Method numbering of the paper's set_parameter routine (section 2.2, section 4). */
+typedef enum { DG_NIPG = 1, DG_SIPG = 2, DG_IIPG = 3 } dg_method;
+typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_prec;
+
+/* Parts of a_h = D_h + C_h + R_h (section 2.3 eq. (dgscheme)) selected by dg_assemble. */
+enum { DG_PART_D = 1, DG_PART_C = 2, DG_PART_R = 4, DG_PART_ALL = 7 };
+
+/* A coefficient or data field of eq. (1):
+ *   DG_CONST     c[0]
+ *   DG_AFFINE    c[0] + c[1] x + c[2] y
+ *   DG_GAUSS_SUM sum_{i<m} c[4i+3] exp(-((x-c[4i])^2 + (y-c[4i+1])^2) / (2 c[4i+2]^2)),  m <= 4
+ *   DG_QPOINTS   dev_vals: FP64 device values at the library's quadrature points
+ *                (dg_mesh_qpoints): f uses the volume points, g^D / g^N the
+ *                boundary-edge points.  Not allowed for eps, b, alpha.          */
+typedef enum { DG_CONST = 0, DG_AFFINE = 1, DG_GAUSS_SUM = 2, DG_QPOINTS = 3 } dg_field_kind;
+
+typedef struct {
+    int32_t kind;
+    int32_t m;
+    double c[16];
+    const double* dev_vals;
+} dg_field;
+
+/* Problem data of eq. (1) and the scheme parameters of eq. (ds).
+ * kappa follows the method (SIPG -1, NIPG +1, IIPG 0, section 1).
+ * sigma is the interior-edge penalty; sigma_D <= 0 selects 2*sigma on
+ * Dirichlet edges (section 1: boundary penalty twice the interior one).
+ * b0 is the superpenalty exponent of the penalty sigma eps / |e|^b0
+ * (1 in the standard setting of the paper's set_parameter).               */
+typedef struct {
+    int32_t method;
+    int32_t degree;
+    double sigma;
+    double sigma_D;
+    double b0;
+    dg_field eps, bx, by, alpha, f, gD, gN;
+} dg_problem;
+
+typedef struct {
+    int64_t n_elems, n_int_edges, n_dir_edges, n_neu_edges;
+    int64_t nnzb, n_dofs;
+    int32_t degree, n_loc, n_q, n_qe; /* n_q = (k+2)^2 volume points, n_qe = k+2 points per edge */
+    double h_max;                     /* largest edge length */
+} dg_mesh_info;
+
+typedef struct dg_mesh dg_mesh;
+typedef struct dg_solver dg_solver;
+
+/* Penalty and kappa of the paper's set_parameter (section 4): NIPG sigma = 1,
+ * kappa = 1; SIPG sigma = 3k(k+1), kappa = -1; IIPG sigma = 3k(k+1), kappa = 0.
+ * DG_ERR_METHOD for an unknown method, DG_ERR_DEGREE for k < 0 or
+ * k > DG_MAX_DEGREE, or for SIPG / IIPG at k = 0 (sigma would be 0). */
+int32_t dg_default_penalty(int32_t method, int32_t degree, double* sigma, double* kappa);
+
+/* Builds the mesh from the arrays of section 2.1 (host, 0-based): nodes_xy
+ * [n_nodes][2] FP64, elems [n_elems][3] counter-clockwise node ids,
+ * dir_edges [n_dir][2] and neu_edges [n_neu][2] (start, end node; either
+ * direction accepted).  Checks orientation, boundary classification and
+ * manifoldness, builds edge connectivity, the BSR pattern and the reference
+ * tables for `degree`, and uploads them with synchronous copies on the
+ * current device.  *out is NULL on error. */
+int32_t dg_mesh_create(const double* nodes_xy, int64_t n_nodes, const int32_t* elems, int64_t n_elems,
+                       const int32_t* dir_edges, int64_t n_dir, const int32_t* neu_edges, int64_t n_neu,
+                       int32_t degree, dg_mesh** out);
+int32_t dg_mesh_info_get(const dg_mesh* mesh, dg_mesh_info* out);
+void dg_mesh_destroy(dg_mesh* mesh);
+
+/* Copies the BSR pattern into dev_row_ptr [n_elems+1] and dev_col_idx [nnzb]. */
+int32_t dg_mesh_structure(const dg_mesh* mesh, int32_t* dev_row_ptr, int32_t* dev_col_idx, void* stream);
+
+/* Coordinates of the quadrature points where DG_QPOINTS values are expected:
+ * dev_vol_xy [n_elems][n_q][2]; dev_bnd_xy [n_bnd][n_qe][2] with n_bnd =
+ * n_dir_edges + n_neu_edges; dev_bnd_normal [n_bnd][2] outward unit normals;
+ * dev_bnd_type [n_bnd] (0 Dirichlet, 1 Neumann).  Any output may be NULL. */
+int32_t dg_mesh_qpoints(const dg_mesh* mesh, double* dev_vol_xy, double* dev_bnd_xy, double* dev_bnd_normal,
+                        int32_t* dev_bnd_type, void* stream);
+
+/* Assembles the parts of D + C + R selected by `parts` into dev_vals
+ * ([nnzb][n_loc][n_loc], FP64 if prec == DG_F64 else FP32) and the load
+ * vector F_i = l_h(phi_i) (section 1 eq. (ds)) into dev_rhs ([n_dofs], same
+ * precision), all in the given precision.  Every block has exactly one
+ * writer, so the result is bitwise deterministic.  dev_rhs may be NULL.
+ * problem->degree must equal the mesh degree. */
+int32_t dg_assemble(const dg_mesh* mesh, const dg_problem* problem, int32_t prec, uint32_t parts,
+                    void* dev_vals, void* dev_rhs, void* stream);
+
+/* Restarted GMRES(restart) with right block-Jacobi preconditioning M =
+ * blockdiag(A).  Stops when the true FP64 relative residual
+ * ||F - A x||_2 / ||F||_2 <= rel_tol (checked after every Arnoldi cycle) or
+ * after max_iters Arnoldi steps in total.  mixed = 1: the Arnoldi cycles run
+ * in FP32 on an FP32 copy of A M^{-1} (iterative refinement: each cycle is an
+ * inner solve of A d = r for the FP64 residual r, ended once its FP32 estimate
+ * falls below inner_tol relative to ||r||, and x += d in FP64). */
+typedef struct {
+    int32_t restart;      /* Krylov dimension m per cycle, 1..4096 */
+    int32_t max_iters;    /* cap on Arnoldi steps over all cycles */
+    double rel_tol;       /* target relative residual (FP64, true residual) */
+    int32_t mixed;        /* 0: FP64 cycles; 1: FP32 cycles + FP64 refinement */
+    double inner_tol;     /* mixed only: per-cycle relative reduction target (e.g. 1e-5) */
+    int32_t reorth;       /* 1: second classical Gram-Schmidt pass when the first loses > 1/sqrt(2) of the norm */
+} dg_solver_opts;
+
+typedef struct {
+    int32_t status;       /* DG_OK, DG_NOT_CONVERGED or an error */
+    int32_t iters;        /* Arnoldi steps */
+    int32_t cycles;       /* restart cycles (= refinement steps when mixed) */
+    int32_t pad;
+    double rel_res;       /* true FP64 relative residual of the returned x */
+    double rel_res0;      /* true FP64 relative residual of the initial guess */
+} dg_solve_report;
+
+/* Allocates the Krylov workspace for `mesh` (device memory, owned by the
+ * solver): restart+1 basis vectors, A M^{-1} without its identity diagonal
+ * blocks and the inverse diagonal blocks, in the cycle precision. */
+int32_t dg_solver_create(const dg_mesh* mesh, const dg_solver_opts* opts, dg_solver** out);
+/* Block-Jacobi setup: inverts every diagonal block of A (FP64, Gauss-Jordan
+ * with partial pivoting) and forms A M^{-1} in the cycle precision.  The
+ * solver keeps dev_vals64 (FP64 BSR values, caller-owned, must stay valid and
+ * unchanged until the last dg_solver_solve) for the true residual. */
+int32_t dg_solver_setup(dg_solver* solver, const double* dev_vals64, void* stream);
+/* Solves A x = F.  dev_x holds the initial guess on entry (zero for the plain
+ * method) and the solution on exit.  Synchronises `stream` before returning
+ * so that `report` is filled.  DG_NOT_CONVERGED if max_iters was reached;
+ * DG_ERR_NONFINITE if a residual norm became NaN / Inf. */
+int32_t dg_solver_solve(dg_solver* solver, const double* dev_rhs, double* dev_x, dg_solve_report* report,
+                        void* stream);
+void dg_solver_destroy(dg_solver* solver);
+
+/* y = b - A x in FP64 with the BSR values of the mesh (dev_b may be NULL: y = -A x). */
+int32_t dg_residual(const dg_mesh* mesh, const double* dev_vals64, const double* dev_b, const double* dev_x,
+                    double* dev_y, void* stream);
+
+const char* dg_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGDCR_H */

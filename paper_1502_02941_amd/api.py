@@ -1,0 +1,330 @@
+"""Python binding of libdgdcr.so (include/dgdcr.h): argument marshalling only.
+
+Every computation runs in the HIP library; PyTorch only provides device
+memory (tensors) and the current stream.  Importing this module loads the
+library and raises if it has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgdcr.so")
+
+DG_OK, DG_NOT_CONVERGED = 0, 1
+NIPG, SIPG, IIPG = 1, 2, 3
+F64, F32 = 0, 1
+PART_D, PART_C, PART_R, PART_ALL = 1, 2, 4, 7
+CONST, AFFINE, GAUSS_SUM, QPOINTS = 0, 1, 2, 3
+MAX_DEGREE = 4
+
+
+class DGError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__("%s failed: %s (%d)" % (what, status_str(status), status))
+        self.status = status
+
+
+class _Field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("m", C.c_int32), ("c", C.c_double * 16), ("dev_vals", C.c_void_p)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("method", C.c_int32), ("degree", C.c_int32), ("sigma", C.c_double), ("sigma_D", C.c_double),
+                ("b0", C.c_double), ("eps", _Field), ("bx", _Field), ("by", _Field), ("alpha", _Field),
+                ("f", _Field), ("gD", _Field), ("gN", _Field)]
+
+
+class _MeshInfo(C.Structure):
+    _fields_ = [("n_elems", C.c_int64), ("n_int_edges", C.c_int64), ("n_dir_edges", C.c_int64),
+                ("n_neu_edges", C.c_int64), ("nnzb", C.c_int64), ("n_dofs", C.c_int64), ("degree", C.c_int32),
+                ("n_loc", C.c_int32), ("n_q", C.c_int32), ("n_qe", C.c_int32), ("h_max", C.c_double)]
+
+
+class _SolverOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double), ("mixed", C.c_int32),
+                ("inner_tol", C.c_double), ("reorth", C.c_int32)]
+
+
+class _Report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32), ("pad", C.c_int32),
+                ("rel_res", C.c_double), ("rel_res0", C.c_double)]
+
+
+EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_destroy", "dg_mesh_structure",
+           "dg_mesh_qpoints", "dg_assemble", "dg_solver_create", "dg_solver_setup", "dg_solver_solve",
+           "dg_solver_destroy", "dg_residual", "dg_status_str"]
+
+_lib = None
+
+
+def lib():
+    """Loads libdgdcr.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libdgdcr.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_1502_02941_amd.build_lib)")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.dg_default_penalty.argtypes = [I32, I32, C.POINTER(D), C.POINTER(D)]
+        L.dg_mesh_create.argtypes = [P, I64, P, I64, P, I64, P, I64, I32, C.POINTER(P)]
+        L.dg_mesh_info_get.argtypes = [P, C.POINTER(_MeshInfo)]
+        L.dg_mesh_destroy.argtypes = [P]
+        L.dg_mesh_destroy.restype = None
+        L.dg_mesh_structure.argtypes = [P, P, P, P]
+        L.dg_mesh_qpoints.argtypes = [P, P, P, P, P, P]
+        L.dg_assemble.argtypes = [P, C.POINTER(_Problem), I32, C.c_uint32, P, P, P]
+        L.dg_solver_create.argtypes = [P, C.POINTER(_SolverOpts), C.POINTER(P)]
+        L.dg_solver_setup.argtypes = [P, P, P]
+        L.dg_solver_solve.argtypes = [P, P, P, C.POINTER(_Report), P]
+        L.dg_solver_destroy.argtypes = [P]
+        L.dg_solver_destroy.restype = None
+        L.dg_residual.argtypes = [P, P, P, P, P, P]
+        L.dg_status_str.argtypes = [I32]
+        L.dg_status_str.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("dg_mesh_destroy", "dg_solver_destroy", "dg_status_str"):
+                getattr(L, name).restype = I32
+        _lib = L
+    return _lib
+
+
+def status_str(s):
+    return lib().dg_status_str(int(s)).decode()
+
+
+def _check(st, what):
+    if st < 0:
+        raise DGError(st, what)
+    return st
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+def default_penalty(method, degree):
+    s, k = C.c_double(), C.c_double()
+    _check(lib().dg_default_penalty(int(method), int(degree), C.byref(s), C.byref(k)), "dg_default_penalty")
+    return s.value, k.value
+
+
+@dataclass
+class Field:
+    kind: int = CONST
+    c: tuple = (0.0,)
+    m: int = 0
+    vals: torch.Tensor | None = None
+
+    @staticmethod
+    def const(c0):
+        return Field(CONST, (float(c0),))
+
+    @staticmethod
+    def affine(c0, c1, c2):
+        return Field(AFFINE, (float(c0), float(c1), float(c2)))
+
+    @staticmethod
+    def gauss_sum(terms):
+        flat = tuple(float(v) for t in terms for v in t)
+        return Field(GAUSS_SUM, flat, m=len(flat) // 4)
+
+    @staticmethod
+    def qpoints(vals: torch.Tensor):
+        return Field(QPOINTS, (), vals=vals.contiguous().to(torch.float64))
+
+    def _fill(self, s: _Field):
+        s.kind, s.m = int(self.kind), int(self.m)
+        for i, v in enumerate(self.c):
+            s.c[i] = v
+        s.dev_vals = _dptr(self.vals) if self.vals is not None else None
+
+
+def _as_field(v):
+    if v is None:
+        return Field.const(0.0)
+    return v if isinstance(v, Field) else Field.const(float(v))
+
+
+@dataclass
+class Problem:
+    """Data of eq. (1) and the scheme parameters of eq. (ds).  sigma_D <= 0
+    selects twice sigma on Dirichlet edges."""
+    method: int
+    degree: int
+    sigma: float
+    eps: object
+    bx: object
+    by: object
+    alpha: object
+    f: object = None
+    gD: object = None
+    gN: object = None
+    sigma_D: float = 0.0
+    b0: float = 1.0
+    _keep: list = field(default_factory=list, repr=False)
+
+    def _c(self) -> _Problem:
+        p = _Problem()
+        p.method, p.degree = int(self.method), int(self.degree)
+        p.sigma, p.sigma_D, p.b0 = float(self.sigma), float(self.sigma_D), float(self.b0)
+        self._keep = []
+        for name in ("eps", "bx", "by", "alpha", "f", "gD", "gN"):
+            F = _as_field(getattr(self, name))
+            self._keep.append(F)
+            F._fill(getattr(p, name))
+        return p
+
+
+class Mesh:
+    """dg_mesh_create on host arrays (0-based; section 2.1 layout)."""
+
+    def __init__(self, nodes, elems, dirichlet, neumann, degree: int, device=None):
+        if device is not None:
+            torch.cuda.set_device(device)
+        L = lib()
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1, 2)
+        elems = np.ascontiguousarray(elems, dtype=np.int32).reshape(-1, 3)
+        d = np.ascontiguousarray(dirichlet if dirichlet is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
+        nm = np.ascontiguousarray(neumann if neumann is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
+        h = C.c_void_p()
+        st = L.dg_mesh_create(nodes.ctypes.data, len(nodes), elems.ctypes.data, len(elems),
+                              d.ctypes.data if len(d) else None, len(d), nm.ctypes.data if len(nm) else None, len(nm),
+                              int(degree), C.byref(h))
+        _check(st, "dg_mesh_create")
+        self._h = h
+        info = _MeshInfo()
+        _check(L.dg_mesh_info_get(h, C.byref(info)), "dg_mesh_info_get")
+        self.info = {k: getattr(info, k) for k, _ in _MeshInfo._fields_}
+        self.T, self.n_loc, self.nnzb, self.n_dofs = info.n_elems, info.n_loc, info.nnzb, info.n_dofs
+        self.degree, self.n_q, self.n_qe = info.degree, info.n_q, info.n_qe
+        self.n_bnd = info.n_dir_edges + info.n_neu_edges
+
+    @classmethod
+    def from_arrays(cls, m, degree):
+        return cls(m.nodes, m.elems, m.dirichlet, m.neumann, degree)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dg_mesh_destroy(h)
+            self._h = None
+
+    def structure(self, stream=None):
+        rp = torch.empty(self.T + 1, dtype=torch.int32, device="cuda")
+        ci = torch.empty(self.nnzb, dtype=torch.int32, device="cuda")
+        _check(lib().dg_mesh_structure(self._h, _dptr(rp), _dptr(ci), _stream(stream)), "dg_mesh_structure")
+        return rp, ci
+
+    def qpoints(self, stream=None):
+        vol = torch.empty(self.T, self.n_q, 2, dtype=torch.float64, device="cuda")
+        nb = max(self.n_bnd, 1)
+        bnd = torch.empty(nb, self.n_qe, 2, dtype=torch.float64, device="cuda")
+        nrm = torch.empty(nb, 2, dtype=torch.float64, device="cuda")
+        typ = torch.empty(nb, dtype=torch.int32, device="cuda")
+        _check(lib().dg_mesh_qpoints(self._h, _dptr(vol), _dptr(bnd), _dptr(nrm), _dptr(typ), _stream(stream)),
+               "dg_mesh_qpoints")
+        nb = self.n_bnd
+        return vol, bnd[:nb], nrm[:nb], typ[:nb]
+
+    def alloc_system(self, prec=F64):
+        dt = torch.float64 if prec == F64 else torch.float32
+        vals = torch.empty(self.nnzb, self.n_loc, self.n_loc, dtype=dt, device="cuda")
+        rhs = torch.empty(self.n_dofs, dtype=dt, device="cuda")
+        return vals, rhs
+
+
+def assemble(mesh: Mesh, prob: Problem, prec=F64, parts=PART_ALL, vals=None, rhs=None, stream=None):
+    """dg_assemble into (new or given) tensors; returns (vals, rhs)."""
+    if vals is None:
+        vals, rhs2 = mesh.alloc_system(prec)
+        rhs = rhs2 if rhs is None else rhs
+    dt = torch.float64 if prec == F64 else torch.float32
+    if vals.dtype != dt or vals.numel() != mesh.nnzb * mesh.n_loc ** 2:
+        raise ValueError("vals must hold nnzb*n_loc^2 values of the assembly precision")
+    if rhs is not None and (rhs.dtype != dt or rhs.numel() != mesh.n_dofs):
+        raise ValueError("rhs must hold n_dofs values of the assembly precision")
+    for name, need in (("f", mesh.T * mesh.n_q), ("gD", mesh.n_bnd * mesh.n_qe), ("gN", mesh.n_bnd * mesh.n_qe)):
+        F = getattr(prob, name)
+        if isinstance(F, Field) and F.kind == QPOINTS and (F.vals is None or F.vals.numel() != need):
+            raise ValueError("%s: DG_QPOINTS needs %d device values" % (name, need))
+    p = prob._c()
+    _check(lib().dg_assemble(mesh._h, C.byref(p), int(prec), int(parts), _dptr(vals), _dptr(rhs), _stream(stream)),
+           "dg_assemble")
+    return vals, rhs
+
+
+def residual(mesh: Mesh, vals64, b, x, y=None, stream=None):
+    y = torch.empty_like(x) if y is None else y
+    _check(lib().dg_residual(mesh._h, _dptr(vals64), _dptr(b), _dptr(x), _dptr(y), _stream(stream)), "dg_residual")
+    return y
+
+
+@dataclass
+class Report:
+    status: int
+    iters: int
+    cycles: int
+    rel_res: float
+    rel_res0: float
+
+    @property
+    def converged(self):
+        return self.status == DG_OK
+
+
+class Solver:
+    """dg_solver_*: restarted GMRES with right block-Jacobi preconditioning,
+    FP64 or FP32 cycles with FP64 refinement (mixed=True)."""
+
+    def __init__(self, mesh: Mesh, restart=50, max_iters=20000, rel_tol=1e-10, mixed=False, inner_tol=1e-5,
+                 reorth=True):
+        self.mesh = mesh
+        o = _SolverOpts(int(restart), int(max_iters), float(rel_tol), int(bool(mixed)), float(inner_tol),
+                        int(bool(reorth)))
+        h = C.c_void_p()
+        _check(lib().dg_solver_create(mesh._h, C.byref(o), C.byref(h)), "dg_solver_create")
+        self._h = h
+        self._vals = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dg_solver_destroy(h)
+            self._h = None
+
+    def setup(self, vals64: torch.Tensor, stream=None):
+        assert vals64.dtype == torch.float64
+        self._vals = vals64  # the library keeps the pointer: keep the tensor alive
+        _check(lib().dg_solver_setup(self._h, _dptr(vals64), _stream(stream)), "dg_solver_setup")
+
+    def solve(self, rhs: torch.Tensor, x: torch.Tensor, stream=None) -> Report:
+        r = _Report()
+        st = lib().dg_solver_solve(self._h, _dptr(rhs), _dptr(x), C.byref(r), _stream(stream))
+        _check(st, "dg_solver_solve")
+        return Report(r.status, r.iters, r.cycles, r.rel_res, r.rel_res0)
+
+
+def bsr_to_scipy(mesh: Mesh, vals: torch.Tensor, row_ptr=None, col_idx=None):
+    """Host copy of the BSR matrix as scipy.sparse.bsr_matrix (for tests and tools)."""
+    import scipy.sparse as sp
+    if row_ptr is None:
+        row_ptr, col_idx = mesh.structure()
+    n = mesh.n_loc
+    return sp.bsr_matrix((vals.double().cpu().numpy(), col_idx.cpu().numpy(), row_ptr.cpu().numpy()),
+                         shape=(mesh.n_dofs, mesh.n_dofs), blocksize=(n, n))

@@ -1,0 +1,91 @@
+// Internal definitions of the gfx950 DG library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/dgdcr.h"
+
+#define DG_HIP_CHECK(expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return DG_ERR_HIP;             \
+    } while (0)
+
+namespace dg {
+
+// Reference-table layout for degree k (shared by host code that fills the
+// tables and the kernels that read them).  All entries are on the reference
+// triangle {xi, eta >= 0, xi + eta <= 1}:
+//   volume rule (Stroud conical product, q = k+2 points per direction):
+//     w[g], xi[g], eta[g], then phi / dphi/dxi / dphi/deta [g][n]
+//   edge rule (Gauss-Legendre, k+2 points on [0,1]): t[g], w[g], then for the
+//     three local edges l (vertex l -> vertex l+1): phi / dxi / deta [l][g][n]
+struct TabLayout {
+    int n, nq, nqe;
+    int vw, vxi, veta, vphi, vdx, vde, et, ew, ephi, edx, ede, size;
+    __host__ __device__ constexpr explicit TabLayout(int k)
+        : n((k + 1) * (k + 2) / 2), nq((k + 2) * (k + 2)), nqe(k + 2),
+          vw(0), vxi(nq), veta(2 * nq), vphi(3 * nq), vdx(3 * nq + nq * n), vde(3 * nq + 2 * nq * n),
+          et(3 * nq + 3 * nq * n), ew(3 * nq + 3 * nq * n + nqe), ephi(3 * nq + 3 * nq * n + 2 * nqe),
+          edx(3 * nq + 3 * nq * n + 2 * nqe + 3 * nqe * n), ede(3 * nq + 3 * nq * n + 2 * nqe + 6 * nqe * n),
+          size(3 * nq + 3 * nq * n + 2 * nqe + 9 * nqe * n) {}
+};
+
+// Field as seen by the kernels (same meaning as dg_field).
+struct FieldDev {
+    int32_t kind;
+    int32_t m;
+    double c[16];
+    const double* vals;
+};
+
+struct AsmArgs {
+    const double* xy;        // [T][6]: element vertex coordinates (x1,y1,x2,y2,x3,y3)
+    const int32_t* nbr;      // [T][3]: neighbour across local edge l, or -(b+1) for boundary edge b
+    const int32_t* nbr_edge; // [T]: bits 2l..2l+1 = neighbour's local edge index
+    const int32_t* row_ptr;  // [T+1]
+    const int32_t* bnd_type; // [n_bnd]: 0 Dirichlet, 1 Neumann
+    const void* tab;         // reference tables in the assembly precision
+    int64_t T;
+    double sigma, sigma_D, kappa, b0;
+    uint32_t parts;
+    FieldDev eps, bx, by, alpha, f, gD, gN;
+    void* vals;
+    void* rhs;
+};
+
+}  // namespace dg
+
+struct dg_mesh {
+    int k, n, nq, nqe;
+    int64_t T, n_nodes, n_int, n_dir, n_neu, n_bnd, nnzb;
+    double hmax;
+    int device;
+    // host copies
+    std::vector<double> xy6;
+    std::vector<int32_t> nbr, nbr_edge, row_ptr, col_idx, bnd_el, bnd_loc, bnd_type;
+    std::vector<double> tab64;
+    // device copies (owned)
+    double* d_xy = nullptr;
+    int32_t* d_nbr = nullptr;
+    int32_t* d_nbr_edge = nullptr;
+    int32_t* d_row_ptr = nullptr;
+    int32_t* d_col_idx = nullptr;
+    int32_t* d_bnd_type = nullptr;
+    int32_t* d_bnd_el = nullptr;
+    int32_t* d_bnd_loc = nullptr;
+    double* d_tab64 = nullptr;
+    float* d_tab32 = nullptr;
+};
+
+namespace dg {
+// Host-side reference tables for degree k (Golub-Welsch quadrature, Dubiner
+// basis in collapsed coordinates); returns TabLayout(k).size values.
+std::vector<double> build_tables(int k);
+// Gauss-Jacobi rule for the weight (1-x)^a (1+x)^b on [-1,1].
+void gauss_jacobi_gw(int n, double a, double b, double* x, double* w);
+int launch_assemble(const dg_mesh* m, const AsmArgs& a, int prec, hipStream_t s);
+}  // namespace dg

@@ -1,0 +1,218 @@
+"""GPU (HIP, gfx950) vs CPU oracle parity, called through the C ABI.
+
+FP64 assembly must match the oracle within 1e-12 (relative Frobenius norm,
+and blockwise max |dA| <= 1e-12 max |A|); solutions must reach the requested
+relative residual when judged with the oracle's own FP64 matrix and vector.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import dgcases as DC
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_02941_amd import api as A
+    A.lib()
+    return A
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+SMALL = DC.small_cases()
+
+
+def _gpu_system(api, c, prec=0, parts=7):
+    mesh = api.Mesh.from_arrays(c.mesh, c.k)
+    prob = DC.gpu_problem(c, mesh, api)
+    vals, rhs = api.assemble(mesh, prob, prec=prec, parts=parts)
+    torch.cuda.synchronize()
+    return mesh, prob, vals, rhs
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c.name for c in SMALL])
+def test_fp64_assembly_matches_oracle(api, case):
+    _say("assembly parity %s T=%d k=%d" % (case.name, case.mesh.T, case.k))
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    Ag = api.bsr_to_scipy(mesh, vals).tocsr()
+    M, B = DC.oracle_system(case)
+    Ao = B.to_scipy()
+    assert DC.rel_fro(Ag, Ao) <= 1e-12
+    d, mx = DC.max_abs_diff(Ag, Ao)
+    assert d <= 1e-12 * mx
+    bg = rhs.cpu().numpy()
+    assert DC.rel_fro(bg, B.rhs) <= 1e-12
+    assert np.abs(bg - B.rhs).max() <= 1e-12 * max(np.abs(B.rhs).max(), 1e-300)
+
+
+@pytest.mark.parametrize("parts", [1, 2, 4, 3, 6])
+def test_parts_match_oracle(api, parts):
+    case = SMALL[3]
+    _say("parts %d on %s" % (parts, case.name))
+    mesh, _, vals, rhs = _gpu_system(api, case, parts=parts)
+    M, B = DC.oracle_system(case)
+    sigma, kappa = case.penalty()
+    Bp = O.assemble(M, case.k, sigma=sigma, kappa=kappa, eps=case.eps, bx=O.Field.affine(*case.b[1]),
+                    by=O.Field.affine(*case.b[2]), alpha=case.alpha, f=0.0, parts=parts)
+    Ag = api.bsr_to_scipy(mesh, vals).tocsr()
+    assert DC.rel_fro(Ag, Bp.to_scipy()) <= 1e-12
+
+
+def test_fp32_assembly_error_vs_oracle(api):
+    for case in (SMALL[0], SMALL[8], SMALL[-3]):
+        _say("fp32 assembly %s" % case.name)
+        mesh, _, vals, rhs = _gpu_system(api, case, prec=1)
+        assert vals.dtype == torch.float32
+        M, B = DC.oracle_system(case)
+        e = DC.rel_fro(api.bsr_to_scipy(mesh, vals).tocsr(), B.to_scipy())
+        eb = DC.rel_fro(rhs.double().cpu().numpy(), B.rhs)
+        _say("  fp32 rel err A %.2e  F %.2e" % (e, eb))
+        assert e <= 2e-6 and eb <= 2e-6
+
+
+def test_assembly_bitwise_deterministic(api):
+    case = SMALL[8]
+    mesh, prob, v1, r1 = _gpu_system(api, case)
+    v2, r2 = api.assemble(mesh, prob)
+    torch.cuda.synchronize()
+    assert torch.equal(v1, v2) and torch.equal(r1, r2)
+
+
+def _oracle_relres(B, x):
+    A = B.to_scipy()
+    return float(np.linalg.norm(B.rhs - A @ x) / np.linalg.norm(B.rhs))
+
+
+SOLVE_CASES = [c for c in SMALL if c.k >= 1 and c.name.split("_")[0] in ("c1", "c2like", "c3like", "c4like",
+                                                                            "paper")] + [SMALL[3], SMALL[8]]
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", SOLVE_CASES, ids=[c.name for c in SOLVE_CASES])
+def test_gmres_solution_oracle_judged(api, case, mixed):
+    tol = case.tol
+    _say("solve %s mixed=%s tol=%g" % (case.name, mixed, tol))
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    solver = api.Solver(mesh, restart=50, max_iters=20000, rel_tol=tol, mixed=mixed, inner_tol=1e-5)
+    solver.setup(vals)
+    x = torch.zeros_like(rhs)
+    rep = solver.solve(rhs, x)
+    _say("  iters %d cycles %d relres %.3e" % (rep.iters, rep.cycles, rep.rel_res))
+    assert rep.converged and rep.rel_res <= tol
+    M, B = DC.oracle_system(case)
+    assert _oracle_relres(B, x.cpu().numpy()) <= tol * 1.01
+
+
+def test_solver_reports_non_convergence_and_warm_start(api):
+    case = SMALL[0]
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    s = api.Solver(mesh, restart=10, max_iters=3, rel_tol=1e-12)
+    s.setup(vals)
+    x = torch.zeros_like(rhs)
+    rep = s.solve(rhs, x)
+    assert rep.status == api.DG_NOT_CONVERGED and rep.iters == 3 and rep.rel_res > 1e-12
+    # restart from the returned iterate: the initial residual is the previous final one
+    s2 = api.Solver(mesh, restart=50, max_iters=5000, rel_tol=1e-12)
+    s2.setup(vals)
+    rep2 = s2.solve(rhs, x)
+    assert rep2.converged and abs(rep2.rel_res0 - rep.rel_res) <= 1e-9 * rep.rel_res
+
+
+def test_residual_entry_point(api):
+    case = SMALL[8]
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    x = torch.randn(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    y = api.residual(mesh, vals, rhs, x)
+    torch.cuda.synchronize()
+    A = api.bsr_to_scipy(mesh, vals)
+    ref = rhs.cpu().numpy() - A @ x.cpu().numpy()
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_qpoints_match_oracle_points(api):
+    case = SMALL[3]
+    mesh = api.Mesh.from_arrays(case.mesh, case.k)
+    vol, bnd, nrm, typ = mesh.qpoints()
+    M = O.Mesh(case.mesh.nodes, case.mesh.elems, case.mesh.dirichlet, case.mesh.neumann)
+    ov = M.volume_points(case.k + 2)
+    # same rule, same element order: identical up to rounding
+    assert np.abs(vol.cpu().numpy() - ov).max() <= 1e-14
+    assert int((typ == 0).sum()) == M.n_dir and int((typ == 1).sum()) == M.n_neu
+
+
+# ---------------------------------------------------------------- full sizes
+@pytest.mark.parametrize("method", [2, 1])
+def test_c2_full_size_assembly_and_solve(api, method):
+    """256x256 P2 (131072 triangles): full FP64 assembly parity, and the GPU
+    solution judged with the oracle's matrix at 1e-10, FP64 and mixed."""
+    case = DC.c2_full(method)
+    _say("C2 full size method %d" % method)
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    M, B = DC.oracle_system(case)
+    Ao = B.to_scipy()
+    Ag = api.bsr_to_scipy(mesh, vals).tocsr()
+    assert DC.rel_fro(Ag, Ao) <= 1e-12
+    d, mx = DC.max_abs_diff(Ag, Ao)
+    assert d <= 1e-12 * mx
+    assert DC.rel_fro(rhs.cpu().numpy(), B.rhs) <= 1e-12
+    # b = (1, 0): block Jacobi couples one element per operator application along
+    # a 2N-element transport chain, so the Krylov dimension has to exceed it.
+    for mixed in (False, True):
+        s = api.Solver(mesh, restart=2 * 256 + 64, max_iters=6000, rel_tol=1e-10, mixed=mixed, inner_tol=1e-5)
+        s.setup(vals)
+        x = torch.zeros_like(rhs)
+        rep = s.solve(rhs, x)
+        _say("  mixed=%s iters %d cycles %d relres %.3e" % (mixed, rep.iters, rep.cycles, rep.rel_res))
+        assert rep.converged
+        xr = x.cpu().numpy()
+        assert np.linalg.norm(B.rhs - Ao @ xr) / np.linalg.norm(B.rhs) <= 1.01e-10
+
+
+def test_c3_full_size_assembly_sampled(api):
+    """512x512 jittered P3 IIPG (524288 triangles): FP64 assembly checked on
+    every block row of a sample of elements against the oracle assembled on the
+    whole mesh; FP32 error reported."""
+    case = DC.c3_full()
+    _say("C3 full size")
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    M, B = DC.oracle_system(case)
+    rp, ci = mesh.structure()
+    rp, ci = rp.cpu().numpy(), ci.cpu().numpy()
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([rng.integers(0, mesh.T, 4000), [0, mesh.T - 1]]))
+    # oracle blocks of the sampled block rows: (row, col) -> block
+    ref = {(int(el), int(el)): B.diag[el] for el in sample}
+    sel_i = np.isin(M.int_el[:, 0], sample)
+    sel_j = np.isin(M.int_el[:, 1], sample)
+    for e in np.nonzero(sel_i)[0]:
+        ref[(int(M.int_el[e, 0]), int(M.int_el[e, 1]))] = B.off_ij[e]
+    for e in np.nonzero(sel_j)[0]:
+        ref[(int(M.int_el[e, 1]), int(M.int_el[e, 0]))] = B.off_ji[e]
+    V = vals.cpu().numpy()
+    seen = 0
+    for el in sample:
+        scale = max(np.abs(ref[(int(el), int(el))]).max(), 1e-300)
+        for s in range(rp[el], rp[el + 1]):
+            r = ref[(int(el), int(ci[s]))]
+            assert np.abs(V[s] - r).max() <= 1e-12 * max(scale, np.abs(r).max()), (el, ci[s])
+            seen += 1
+    assert seen == sum(1 for key in ref)
+    assert DC.rel_fro(rhs.cpu().numpy(), B.rhs) <= 1e-12
+    v32, r32 = api.assemble(mesh, DC.gpu_problem(case, mesh, api), prec=1)
+    torch.cuda.synchronize()
+    e32 = float(torch.linalg.norm(v32.double() - vals) / torch.linalg.norm(vals))
+    _say("  C3 FP32 vs FP64 assembly rel err %.3e" % e32)
+    assert e32 <= 2e-6
