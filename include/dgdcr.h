@@ -76,7 +76,8 @@ enum { DG_PART_D = 1, DG_PART_C = 2, DG_PART_R = 4, DG_PART_ALL = 7 };
  *   DG_GAUSS_SUM sum_{i<m} c[4i+3] exp(-((x-c[4i])^2 + (y-c[4i+1])^2) / (2 c[4i+2]^2)),  m <= 4
  *   DG_QPOINTS   dev_vals: FP64 device values at the library's quadrature points
  *                (dg_mesh_qpoints): f uses the volume points, g^D / g^N the
- *                boundary-edge points.  Not allowed for eps, b, alpha.          */
+ *                boundary-edge points.
+ * eps, b and alpha must be DG_CONST or DG_AFFINE (DG_ERR_ARG otherwise).        */
 typedef enum { DG_CONST = 0, DG_AFFINE = 1, DG_GAUSS_SUM = 2, DG_QPOINTS = 3 } dg_field_kind;
 
 typedef struct {
@@ -163,13 +164,14 @@ typedef struct {
     int32_t mixed;        /* 0: FP64 cycles; 1: FP32 cycles + FP64 refinement */
     double inner_tol;     /* mixed only: per-cycle relative reduction target (e.g. 1e-5) */
     int32_t reorth;       /* 1: second classical Gram-Schmidt pass when the first loses > 1/sqrt(2) of the norm */
+    int32_t profile;      /* 1: time the heavy kernels with HIP events on the solve stream (dg_solver_profile) */
 } dg_solver_opts;
 
 typedef struct {
     int32_t status;       /* DG_OK, DG_NOT_CONVERGED or an error */
     int32_t iters;        /* Arnoldi steps */
     int32_t cycles;       /* restart cycles (= refinement steps when mixed) */
-    int32_t pad;
+    int32_t reorth_passes; /* second Gram-Schmidt passes taken */
     double rel_res;       /* true FP64 relative residual of the returned x */
     double rel_res0;      /* true FP64 relative residual of the initial guess */
 } dg_solve_report;
@@ -190,6 +192,20 @@ int32_t dg_solver_setup(dg_solver* solver, const double* dev_vals64, void* strea
 int32_t dg_solver_solve(dg_solver* solver, const double* dev_rhs, double* dev_x, dg_solve_report* report,
                         void* stream);
 void dg_solver_destroy(dg_solver* solver);
+
+/* Per-kernel statistics gathered when opts.profile = 1: for each heavy kernel
+ * of the solve (spmv_hat, multidot, update, residual64, combine), the number
+ * of launches that did work, their summed duration between HIP events
+ * recorded on the solve stream, and their algorithmic HBM bytes (each
+ * operand read or written once).  Writes up to `max` entries into `out`
+ * (host) and their number into *count; reset = 1 clears the totals. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double ms;
+    double bytes;
+} dg_kernel_stats;
+int32_t dg_solver_profile(dg_solver* solver, dg_kernel_stats* out, int32_t max, int32_t* count, int32_t reset);
 
 /* y = b - A x in FP64 with the BSR values of the mesh (dev_b may be NULL: y = -A x). */
 int32_t dg_residual(const dg_mesh* mesh, const double* dev_vals64, const double* dev_b, const double* dev_x,

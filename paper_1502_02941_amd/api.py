@@ -48,17 +48,21 @@ class _MeshInfo(C.Structure):
 
 class _SolverOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double), ("mixed", C.c_int32),
-                ("inner_tol", C.c_double), ("reorth", C.c_int32)]
+                ("inner_tol", C.c_double), ("reorth", C.c_int32), ("profile", C.c_int32)]
+
+
+class _KStats(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double)]
 
 
 class _Report(C.Structure):
-    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32), ("reorth_passes", C.c_int32),
                 ("rel_res", C.c_double), ("rel_res0", C.c_double)]
 
 
 EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_destroy", "dg_mesh_structure",
            "dg_mesh_qpoints", "dg_assemble", "dg_solver_create", "dg_solver_setup", "dg_solver_solve",
-           "dg_solver_destroy", "dg_residual", "dg_status_str"]
+           "dg_solver_destroy", "dg_residual", "dg_status_str", "dg_solver_profile"]
 
 _lib = None
 
@@ -86,6 +90,7 @@ def lib():
         L.dg_solver_destroy.argtypes = [P]
         L.dg_solver_destroy.restype = None
         L.dg_residual.argtypes = [P, P, P, P, P, P]
+        L.dg_solver_profile.argtypes = [P, C.POINTER(_KStats), I32, C.POINTER(I32), I32]
         L.dg_status_str.argtypes = [I32]
         L.dg_status_str.restype = C.c_char_p
         for name in EXPORTS:
@@ -282,6 +287,7 @@ class Report:
     cycles: int
     rel_res: float
     rel_res0: float
+    reorth_passes: int = 0
 
     @property
     def converged(self):
@@ -293,10 +299,10 @@ class Solver:
     FP64 or FP32 cycles with FP64 refinement (mixed=True)."""
 
     def __init__(self, mesh: Mesh, restart=50, max_iters=20000, rel_tol=1e-10, mixed=False, inner_tol=1e-5,
-                 reorth=True):
+                 reorth=False, profile=False):
         self.mesh = mesh
         o = _SolverOpts(int(restart), int(max_iters), float(rel_tol), int(bool(mixed)), float(inner_tol),
-                        int(bool(reorth)))
+                        int(bool(reorth)), int(bool(profile)))
         h = C.c_void_p()
         _check(lib().dg_solver_create(mesh._h, C.byref(o), C.byref(h)), "dg_solver_create")
         self._h = h
@@ -313,11 +319,18 @@ class Solver:
         self._vals = vals64  # the library keeps the pointer: keep the tensor alive
         _check(lib().dg_solver_setup(self._h, _dptr(vals64), _stream(stream)), "dg_solver_setup")
 
+    def profile(self, reset=False):
+        """{kernel: (launches, ms, bytes)} from the built-in profiler (profile=True)."""
+        arr = (_KStats * 16)()
+        cnt = C.c_int32()
+        _check(lib().dg_solver_profile(self._h, arr, 16, C.byref(cnt), int(bool(reset))), "dg_solver_profile")
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(cnt.value)}
+
     def solve(self, rhs: torch.Tensor, x: torch.Tensor, stream=None) -> Report:
         r = _Report()
         st = lib().dg_solver_solve(self._h, _dptr(rhs), _dptr(x), C.byref(r), _stream(stream))
         _check(st, "dg_solver_solve")
-        return Report(r.status, r.iters, r.cycles, r.rel_res, r.rel_res0)
+        return Report(r.status, r.iters, r.cycles, r.rel_res, r.rel_res0, r.reorth_passes)
 
 
 def bsr_to_scipy(mesh: Mesh, vals: torch.Tensor, row_ptr=None, col_idx=None):

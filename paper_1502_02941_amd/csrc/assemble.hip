@@ -54,6 +54,13 @@ __device__ __forceinline__ R field_at(const FieldDev& F, R x, R y, int64_t pidx)
     return R(0);
 }
 
+// eps, b and alpha are affine in (x, y): c0 + c1 x + c2 y (constants have c1 = c2 = 0)
+template <typename R>
+__device__ __forceinline__ R affine_at(const FieldDev& F, R x, R y)
+{
+    return (R)F.c[0] + (R)F.c[1] * x + (R)F.c[2] * y;
+}
+
 template <int K, typename R>
 __global__ __launch_bounds__(256) void assemble_kernel(const AsmArgs a)
 {
@@ -89,26 +96,23 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmArgs a)
         accd[i] = R(0);
         acco[0][i] = acco[1][i] = acco[2][i] = R(0);
     }
-    R rhs = R(0);
-
     // ---- volume terms ----
-#pragma unroll
+#pragma unroll 1
     for (int g = 0; g < NQ; ++g) {
         const R w = tab[L.vw + g] * det;
         const R xi = tab[L.vxi + g], eta = tab[L.veta + g];
         const R x = x1 + j11 * xi + j12 * eta, y = y1 + j21 * xi + j22 * eta;
         const R pj = tab[L.vphi + g * N + j], dxj = tab[L.vdx + g * N + j], dej = tab[L.vde + g * N + j];
         const R gx = G11 * dxj + G12 * dej, gy = G21 * dxj + G22 * dej;
-        const R eps = field_at<R>(a.eps, x, y, -1);
-        const R bx = field_at<R>(a.bx, x, y, -1), by = field_at<R>(a.by, x, y, -1);
-        const R al = field_at<R>(a.alpha, x, y, -1);
-        const R we = w * cD * eps;
+        const R we = w * cD * affine_at<R>(a.eps, x, y);
         const R U = we * (G11 * gx + G21 * gy), V = we * (G12 * gx + G22 * gy);
-        const R W = w * (cC * (bx * gx + by * gy) + cR * al * pj);
+        const R W = w * (cC * (affine_at<R>(a.bx, x, y) * gx + affine_at<R>(a.by, x, y) * gy) +
+                         cR * affine_at<R>(a.alpha, x, y) * pj);
+        const R* tp = tab + L.vphi + g * N;
+        const R* tx = tab + L.vdx + g * N;
+        const R* te = tab + L.vde + g * N;
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            accd[i] += tab[L.vdx + g * N + i] * U + tab[L.vde + g * N + i] * V + tab[L.vphi + g * N + i] * W;
-        rhs += w * field_at<R>(a.f, x, y, el * NQ + g) * pj;
+        for (int i = 0; i < N; ++i) accd[i] += tx[i] * U + te[i] * V + tp[i] * W;
     }
 
     // ---- edge terms ----
@@ -141,13 +145,13 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmArgs a)
             lp = (nbe >> (2 * l)) & 3;
         }
         const R cI = interior ? R(1) : R(0);
-#pragma unroll
+#pragma unroll 1
         for (int g = 0; g < NQE; ++g) {
             const R t = tab[L.et + g];
             const R wl = tab[L.ew + g] * len;
             const R x = xA + t * ex, y = yA + t * ey;
-            const R eps = field_at<R>(a.eps, x, y, -1);
-            const R beta = field_at<R>(a.bx, x, y, -1) * nx + field_at<R>(a.by, x, y, -1) * ny;
+            const R eps = affine_at<R>(a.eps, x, y);
+            const R beta = affine_at<R>(a.bx, x, y) * nx + affine_at<R>(a.by, x, y) * ny;
             const R up = (!isN && beta < R(0)) ? -beta : R(0);
             const int ge = (l * NQE + g) * N;
             const R pK = tab[L.ephi + ge + j];
@@ -160,18 +164,15 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmArgs a)
             const R dnL = cI * (tab[L.edx + gl] * mLx + tab[L.ede + gl] * mLy);
             const R Ao = -wl * (cD * eps * (R(0.5) * dnL + pen * pL) + cC * up * pL);
             const R Bo = -wl * cD * kappa * R(0.5) * eps * pL;
+            const R* tp = tab + L.ephi + ge;
+            const R* tx = tab + L.edx + ge;
+            const R* te = tab + L.ede + ge;
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                const R ti = tab[L.ephi + ge + i];
-                const R tn = tab[L.edx + ge + i] * mKx + tab[L.ede + ge + i] * mKy;
+                const R ti = tp[i];
+                const R tn = tx[i] * mKx + te[i] * mKy;
                 accd[i] += ti * Ad + tn * Bd;
                 acco[l][i] += ti * Ao + tn * Bo;
-            }
-            if (isD) {
-                const R gd = field_at<R>(a.gD, x, y, (int64_t)bidx * NQE + g);
-                rhs += wl * gd * ((eps * pen + up) * pK + kappa * eps * dnK);
-            } else if (isN) {
-                rhs += wl * field_at<R>(a.gN, x, y, (int64_t)bidx * NQE + g) * pK;
             }
         }
     }
@@ -191,7 +192,72 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmArgs a)
             ++slot;
         }
     }
-    if (a.rhs) ((R*)a.rhs)[el * N + j] = rhs;
+}
+
+// Load vector F_j = l_h(phi_j) of element K (section 1 eq. (ds)): the volume
+// term f phi_j, and on boundary edges g^D ((sigma_D eps/|e|^b0 + max(-beta,0))
+// phi_j + kappa eps grad phi_j . n) (Dirichlet) or g^N phi_j (Neumann).
+// Lane per (element, j); kept apart from the matrix kernel so that the general
+// data fields (Gaussian sums, point values) do not raise its register count.
+template <int K, typename R>
+__global__ __launch_bounds__(256) void load_vector_kernel(const AsmArgs a)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NQ = L.nq, NQE = L.nqe;
+    constexpr int EPW = 64 / N;
+    const R* __restrict__ tab = (const R*)a.tab;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e_in_wave = lane / N;
+    const int j = lane - e_in_wave * N;
+    const int64_t el = ((int64_t)blockIdx.x * 4 + wave) * EPW + e_in_wave;
+    if (e_in_wave >= EPW || el >= a.T) return;
+
+    const double* p = a.xy + 6 * el;
+    const double dj11 = p[2] - p[0], dj12 = p[4] - p[0], dj21 = p[3] - p[1], dj22 = p[5] - p[1];
+    const double ddet = dj11 * dj22 - dj12 * dj21;
+    const R det = (R)ddet, x1 = (R)p[0], y1 = (R)p[1], j11 = (R)dj11, j12 = (R)dj12, j21 = (R)dj21, j22 = (R)dj22;
+    R rhs = R(0);
+#pragma unroll 1
+    for (int g = 0; g < NQ; ++g) {
+        const R xi = tab[L.vxi + g], eta = tab[L.veta + g];
+        const R x = x1 + j11 * xi + j12 * eta, y = y1 + j21 * xi + j22 * eta;
+        rhs += tab[L.vw + g] * det * field_at<R>(a.f, x, y, el * NQ + g) * tab[L.vphi + g * N + j];
+    }
+    const R G11 = (R)(dj22 / ddet), G12 = (R)(-dj21 / ddet), G21 = (R)(-dj12 / ddet), G22 = (R)(dj11 / ddet);
+    const R kappa = (R)a.kappa;
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) {
+        const int32_t nb = a.nbr[3 * el + l];
+        if (nb >= 0) continue;
+        const int bidx = -nb - 1;
+        const bool isD = a.bnd_type[bidx] == 0;
+        const double xa = p[2 * l], ya = p[2 * l + 1];
+        const double xb = p[(2 * l + 2) % 6], yb = p[(2 * l + 3) % 6];
+        const double dex = xb - xa, dey = yb - ya;
+        const double dlen = sqrt(dex * dex + dey * dey);
+        const R len = (R)dlen, nx = (R)(dey / dlen), ny = (R)(-dex / dlen);
+        const R mKx = G11 * nx + G21 * ny, mKy = G12 * nx + G22 * ny;
+        const R pen = (R)(a.sigma_D / (a.b0 == 1.0 ? dlen : pow(dlen, a.b0)));
+#pragma unroll 1
+        for (int g = 0; g < NQE; ++g) {
+            const R t = tab[L.et + g];
+            const R wl = tab[L.ew + g] * len;
+            const R x = (R)xa + t * (R)dex, y = (R)ya + t * (R)dey;
+            const int ge = (l * NQE + g) * N + j;
+            const R pK = tab[L.ephi + ge];
+            if (isD) {
+                const R eps = affine_at<R>(a.eps, x, y);
+                const R beta = affine_at<R>(a.bx, x, y) * nx + affine_at<R>(a.by, x, y) * ny;
+                const R up = beta < R(0) ? -beta : R(0);
+                const R dnK = tab[L.edx + ge] * mKx + tab[L.ede + ge] * mKy;
+                const R gd = field_at<R>(a.gD, x, y, (int64_t)bidx * NQE + g);
+                rhs += wl * gd * ((eps * pen + up) * pK + kappa * eps * dnK);
+            } else {
+                rhs += wl * field_at<R>(a.gN, x, y, (int64_t)bidx * NQE + g) * pK;
+            }
+        }
+    }
+    ((R*)a.rhs)[el * N + j] = rhs;
 }
 
 template <int K, typename R>
@@ -201,7 +267,8 @@ static int launch_k(const dg_mesh* m, const AsmArgs& a, hipStream_t s)
     const int64_t per_block = 4 * EPW;
     const int64_t blocks = (m->T + per_block - 1) / per_block;
     if (blocks <= 0) return DG_OK;
-    hipLaunchKernelGGL((assemble_kernel<K, R>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.vals) hipLaunchKernelGGL((assemble_kernel<K, R>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.rhs) hipLaunchKernelGGL((load_vector_kernel<K, R>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
 }
 
@@ -267,6 +334,22 @@ static int field_check(const dg_field& f, bool allow_points)
     return DG_OK;
 }
 
+static FieldDev to_affine(const dg_field& f)
+{
+    FieldDev d{};
+    d.kind = DG_AFFINE;
+    d.c[0] = f.c[0];
+    d.c[1] = f.kind == DG_AFFINE ? f.c[1] : 0.0;
+    d.c[2] = f.kind == DG_AFFINE ? f.c[2] : 0.0;
+    return d;
+}
+
+static int affine_check(const dg_field& f)
+{
+    if (f.kind != DG_CONST && f.kind != DG_AFFINE) return DG_ERR_ARG;
+    return field_check(f, false);
+}
+
 static FieldDev to_dev(const dg_field& f)
 {
     FieldDev d;
@@ -319,8 +402,8 @@ extern "C" int32_t dg_assemble(const dg_mesh* m, const dg_problem* P, int32_t pr
     if (!std::isfinite(P->sigma) || !std::isfinite(P->sigma_D) || !std::isfinite(P->b0) || P->sigma < 0)
         return DG_ERR_NONFINITE;
     int st;
-    if ((st = field_check(P->eps, false)) || (st = field_check(P->bx, false)) || (st = field_check(P->by, false)) ||
-        (st = field_check(P->alpha, false)) || (st = field_check(P->f, true)) || (st = field_check(P->gD, true)) ||
+    if ((st = affine_check(P->eps)) || (st = affine_check(P->bx)) || (st = affine_check(P->by)) ||
+        (st = affine_check(P->alpha)) || (st = field_check(P->f, true)) || (st = field_check(P->gD, true)) ||
         (st = field_check(P->gN, true)))
         return st;
     AsmArgs a;
@@ -336,10 +419,10 @@ extern "C" int32_t dg_assemble(const dg_mesh* m, const dg_problem* P, int32_t pr
     a.kappa = kappa;
     a.b0 = P->b0;
     a.parts = parts;
-    a.eps = to_dev(P->eps);
-    a.bx = to_dev(P->bx);
-    a.by = to_dev(P->by);
-    a.alpha = to_dev(P->alpha);
+    a.eps = to_affine(P->eps);
+    a.bx = to_affine(P->bx);
+    a.by = to_affine(P->by);
+    a.alpha = to_affine(P->alpha);
     a.f = to_dev(P->f);
     a.gD = to_dev(P->gD);
     a.gN = to_dev(P->gN);

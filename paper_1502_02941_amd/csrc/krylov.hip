@@ -22,18 +22,20 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <new>
+#include <vector>
 
 #include "dg_internal.h"
 
 namespace dg {
 
-enum { C_J = 0, C_STOP = 1, C_REORTH = 2, C_TICKET0 = 4, C_NCTRL = 16 };
+enum { C_J = 0, C_STOP = 1, C_REORTH = 2, C_NREORTH = 3, C_NCTRL = 16 };
 enum { S_BNORM2 = 0, S_RNORM2 = 1, S_INVH = 2, S_WNORM2 = 3, S_HN = 4, S_CYCTOL = 5, S_BETA = 6, S_NSCAL = 8 };
 
 constexpr int BLK = 256;
-constexpr int CHUNK_E = 4;                // vector entries per thread in the chunked kernels
-constexpr int CHUNK = BLK * CHUNK_E;      // entries per block
+constexpr int MD_TARGET_BLOCKS = 2048;   // multidot: column tiles x row splits aimed at this many blocks
+constexpr int MD_MIN_ROWS = 2048;        // multidot: fewest rows per split
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -54,21 +56,23 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
     return r;
 }
 
-// Block partials are published with a device-scope release; the block that
-// draws the last ticket acquires them and reduces in fixed block order
-// (deterministic), then resets the ticket for the next launch.
-__device__ __forceinline__ bool last_block(int* ticket)
+// out[slot] = sum of partials[0..count) in fixed order (one block)
+__global__ __launch_bounds__(1024) void reduce_sum_kernel(const double* __restrict__ partials, int count,
+                                                          double* out, int slot, const int* ctrl, int j,
+                                                          int only_if_reorth)
 {
-    __shared__ bool last;
+    if (ctrl && (ctrl[C_STOP] || ctrl[C_J] != j || (only_if_reorth && !ctrl[C_REORTH]))) return;
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += 1024) acc += partials[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        int t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == (int)gridDim.x - 1);
-        if (last) __threadfence();
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += sh[w];
+        out[slot] = t;
     }
-    __syncthreads();
-    return last;
 }
 
 // ---------------------------------------------------------------------------
@@ -79,8 +83,7 @@ template <int N>
 __global__ __launch_bounds__(BLK) void residual64_kernel(const double* __restrict__ A, const int32_t* __restrict__ rp,
                                                          const int32_t* __restrict__ ci, const double* __restrict__ b,
                                                          const double* __restrict__ x, double* __restrict__ y,
-                                                         int64_t T, double* partials, int* ticket, double* scal,
-                                                         int slot)
+                                                         int64_t T, double* partials)
 {
     constexpr int EPW = 64 / N;
     __shared__ double sh[4];
@@ -103,29 +106,16 @@ __global__ __launch_bounds__(BLK) void residual64_kernel(const double* __restric
     if (!partials) return;
     const double bs = block_sum(v, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block(ticket)) {
-        double acc = 0.0;
-        for (int bl = threadIdx.x; bl < (int)gridDim.x; bl += BLK) acc += partials[bl];
-        acc = block_sum(acc, sh);
-        if (threadIdx.x == 0) { scal[slot] = acc; *ticket = 0; }
-    }
 }
 
 // ||v||^2 of an FP64 vector into scal[slot]
-__global__ __launch_bounds__(BLK) void norm2_kernel(const double* __restrict__ v, int64_t n, double* partials,
-                                                    int* ticket, double* scal, int slot)
+__global__ __launch_bounds__(BLK) void norm2_kernel(const double* __restrict__ v, int64_t n, double* partials)
 {
     __shared__ double sh[4];
     double acc = 0.0;
     for (int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) acc += v[t] * v[t];
     const double bs = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block(ticket)) {
-        double a2 = 0.0;
-        for (int bl = threadIdx.x; bl < (int)gridDim.x; bl += BLK) a2 += partials[bl];
-        a2 = block_sum(a2, sh);
-        if (threadIdx.x == 0) { scal[slot] = a2; *ticket = 0; }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -242,121 +232,171 @@ __global__ __launch_bounds__(BLK) void spmv_hat_kernel(const P* __restrict__ Aha
     w[el * N + i] = s;
 }
 
-// h[i] = V_i . w for i = 0..j, and ||w||^2 (into hcol[j+1]); chunked over n.
+// h[c] = V_c . w for c = 0..j and ||w||^2 (column j+1): a tall-skinny GEMV.
+// Block (tile, split) reduces CT columns over one row range, reading w once
+// per tile, and writes one partial per (column, split); reduce_cols_kernel
+// then sums the splits.  j is the host's iteration index; the kernels do
+// nothing if the cycle has stopped or the device count differs.
+constexpr int CT = 16;
 template <typename P>
 __global__ __launch_bounds__(BLK) void multidot_kernel(const P* __restrict__ V, const P* __restrict__ w, int64_t n,
-                                                       int* ctrl, double* partials, int ldp, double* hcol,
-                                                       int ticket_slot, int only_if_reorth)
+                                                       int j, int64_t rows_per_split, const int* ctrl,
+                                                       double* __restrict__ partials, int only_if_reorth)
 {
-    if (ctrl[C_STOP] || (only_if_reorth && !ctrl[C_REORTH])) return;
-    __shared__ double sh[4];
-    const int j = ctrl[C_J];
-    const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
-    double wr[CHUNK_E];
+    if (ctrl[C_STOP] || ctrl[C_J] != j || (only_if_reorth && !ctrl[C_REORTH])) return;
+    __shared__ double sh[4][CT];
+    const int ncols = j + 2;
+    const int c0 = blockIdx.x * CT;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+    const int64_t r1 = r0 + rows_per_split < n ? r0 + rows_per_split : n;
+    const P* col[CT];
 #pragma unroll
-    for (int e = 0; e < CHUNK_E; ++e) {
-        const int64_t t = base + (int64_t)e * BLK;
-        wr[e] = t < n ? (double)w[t] : 0.0;
+    for (int c = 0; c < CT; ++c) col[c] = (c0 + c <= j) ? V + (int64_t)(c0 + c) * n : w;  // c = j+1 -> w . w
+    double acc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[c] = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += BLK) {
+        const double wv = (double)w[r];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] += (double)col[c][r] * wv;
     }
-    for (int i = 0; i <= j + 1; ++i) {
-        double acc = 0.0;
-        if (i <= j) {
-            const P* vi = V + (int64_t)i * n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-            for (int e = 0; e < CHUNK_E; ++e) {
-                const int64_t t = base + (int64_t)e * BLK;
-                if (t < n) acc += (double)vi[t] * wr[e];
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < CHUNK_E; ++e) acc += wr[e] * wr[e];
-        }
-        const double bs = block_sum(acc, sh);
-        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * ldp + i] = bs;
+    for (int c = 0; c < CT; ++c) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) sh[wave][c] = v;
     }
-    if (last_block(ctrl + ticket_slot)) {
-        for (int i = threadIdx.x; i <= j + 1; i += BLK) {
-            double s = 0.0;
-            for (int bl = 0; bl < (int)gridDim.x; ++bl) s += partials[(int64_t)bl * ldp + i];
-            hcol[i] = s;
-        }
-        if (threadIdx.x == 0) ctrl[ticket_slot] = 0;
+    __syncthreads();
+    if (threadIdx.x < CT && c0 + (int)threadIdx.x < ncols) {
+        const int c = threadIdx.x;
+        partials[(int64_t)(c0 + c) * gridDim.y + blockIdx.y] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
     }
 }
 
-// w -= sum_i h[i] V_i; ||w||^2 into scal[S_WNORM2]; in the reorthogonalisation
-// pass (reorth != 0) it runs only when flagged and adds h2 into h.
-template <typename P>
-__global__ __launch_bounds__(BLK) void update_kernel(const P* __restrict__ V, P* __restrict__ w, int64_t n, int* ctrl,
-                                                     double* partials, const double* hcol, double* scal,
-                                                     int ticket_slot, int reorth_pass)
+// hcol[c] = sum over the row splits of column c's partials; one wavefront per
+// column, fixed summation order (deterministic).
+__global__ __launch_bounds__(BLK) void reduce_cols_kernel(const double* __restrict__ partials, int ncols,
+                                                          int splits, int j, const int* ctrl, double* hcol,
+                                                          int only_if_reorth)
 {
-    if (ctrl[C_STOP] || (reorth_pass && !ctrl[C_REORTH])) return;
+    if (ctrl[C_STOP] || ctrl[C_J] != j || (only_if_reorth && !ctrl[C_REORTH])) return;
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * (BLK / 64) + (threadIdx.x >> 6);
+    if (c >= ncols) return;
+    const double* pc = partials + (int64_t)c * splits;
+    double acc = 0.0;
+    for (int sp = lane; sp < splits; sp += 64) acc += pc[sp];
+    acc = wave_sum(acc);
+    if (lane == 0) hcol[c] = acc;
+}
+
+// w -= sum_{c<=j} h[c] V_c and ||w||^2 (into scal[S_WNORM2]); rows split over
+// threads, columns unrolled by 4 to keep many loads in flight.  In the
+// reorthogonalisation pass (reorth_pass != 0) it runs only when flagged.
+constexpr int UPD_E = 4;
+template <typename P>
+__global__ __launch_bounds__(BLK) void update_kernel(const P* __restrict__ V, P* __restrict__ w, int64_t n, int j,
+                                                     const int* ctrl, double* partials,
+                                                     const double* __restrict__ hcol, int reorth_pass)
+{
+    if (ctrl[C_STOP] || ctrl[C_J] != j || (reorth_pass && !ctrl[C_REORTH])) return;
     __shared__ double sh[4];
-    const int j = ctrl[C_J];
-    const int64_t base = (int64_t)blockIdx.x * CHUNK + threadIdx.x;
-    double wr[CHUNK_E];
+    const int64_t base = (int64_t)blockIdx.x * (BLK * UPD_E) + threadIdx.x;
+    double wr[UPD_E];
+    bool in[UPD_E];
 #pragma unroll
-    for (int e = 0; e < CHUNK_E; ++e) {
+    for (int e = 0; e < UPD_E; ++e) {
         const int64_t t = base + (int64_t)e * BLK;
-        wr[e] = t < n ? (double)w[t] : 0.0;
+        in[e] = t < n;
+        wr[e] = in[e] ? (double)w[t] : 0.0;
     }
-    for (int i = 0; i <= j; ++i) {
-        const double h = hcol[i];
-        const P* vi = V + (int64_t)i * n;
+    int c = 0;
+    for (; c + 3 <= j; c += 4) {
+        const double h0 = hcol[c], h1 = hcol[c + 1], h2 = hcol[c + 2], h3 = hcol[c + 3];
+        const P* v0 = V + (int64_t)c * n;
 #pragma unroll
-        for (int e = 0; e < CHUNK_E; ++e) {
+        for (int e = 0; e < UPD_E; ++e) {
             const int64_t t = base + (int64_t)e * BLK;
-            if (t < n) wr[e] -= h * (double)vi[t];
+            if (in[e])
+                wr[e] -= h0 * (double)v0[t] + h1 * (double)v0[t + n] + h2 * (double)v0[t + 2 * n] +
+                         h3 * (double)v0[t + 3 * n];
+        }
+    }
+    for (; c <= j; ++c) {
+        const double h = hcol[c];
+        const P* vc = V + (int64_t)c * n;
+#pragma unroll
+        for (int e = 0; e < UPD_E; ++e) {
+            const int64_t t = base + (int64_t)e * BLK;
+            if (in[e]) wr[e] -= h * (double)vc[t];
         }
     }
     double acc = 0.0;
 #pragma unroll
-    for (int e = 0; e < CHUNK_E; ++e) {
-        const int64_t t = base + (int64_t)e * BLK;
-        if (t < n) {
+    for (int e = 0; e < UPD_E; ++e) {
+        if (in[e]) {
             const P pv = (P)wr[e];
-            w[t] = pv;
+            w[base + (int64_t)e * BLK] = pv;
             acc += (double)pv * (double)pv;
         }
     }
     const double bs = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block(ctrl + ticket_slot)) {
-        double a2 = 0.0;
-        for (int bl = threadIdx.x; bl < (int)gridDim.x; bl += BLK) a2 += partials[bl];
-        a2 = block_sum(a2, sh);
-        if (threadIdx.x == 0) {
-            scal[S_WNORM2] = a2;
-            ctrl[ticket_slot] = 0;
-        }
-    }
 }
 
 // One thread: reorthogonalisation decision (after the first pass) or the
 // Hessenberg column, Givens rotations, residual estimate and stop flag.
-__global__ void arnoldi_decide_kernel(int* ctrl, const double* hcol, double* scal, int want_reorth)
-{
-    if (ctrl[C_STOP]) return;
-    const double before = hcol[ctrl[C_J] + 1];  // ||w||^2 before the first pass
-    ctrl[C_REORTH] = (want_reorth && scal[S_WNORM2] < 0.5 * before) ? 1 : 0;
-}
-
-__global__ void givens_kernel(int* ctrl, double* hcol, const double* hcol2, double* H, double* cs, double* sn,
-                              double* g, double* scal, int ldh, int mcyc)
+__global__ void arnoldi_decide_kernel(int* ctrl, const double* hcol, double* scal, int want_reorth, int* rflags)
 {
     if (ctrl[C_STOP]) return;
     const int j = ctrl[C_J];
+    const double before = hcol[j + 1];  // ||w||^2 before the first pass
+    ctrl[C_REORTH] = (want_reorth && scal[S_WNORM2] < 0.5 * before) ? 1 : 0;
+    ctrl[C_NREORTH] += ctrl[C_REORTH];
+    rflags[j] = ctrl[C_REORTH];
+}
+
+// Hessenberg column j, previous Givens rotations, new rotation, residual
+// estimate and stop test.  One block of 64 threads stages the column and the
+// rotations in LDS in chunks; thread 0 runs the sequential chain.
+constexpr int GV_CHUNK = 1024;
+__global__ __launch_bounds__(64) void givens_kernel(int* ctrl, const double* __restrict__ hcol,
+                                                    const double* __restrict__ hcol2, double* __restrict__ H,
+                                                    double* __restrict__ cs, double* __restrict__ sn,
+                                                    double* __restrict__ g, double* scal, int ldh, int mcyc)
+{
+    if (ctrl[C_STOP]) return;
+    __shared__ double sc[GV_CHUNK], ss[GV_CHUNK], sh[GV_CHUNK + 1], so[GV_CHUNK];
+    __shared__ double carry;
+    const int j = ctrl[C_J];
     const bool re = ctrl[C_REORTH] != 0;
     double* col = H + (int64_t)j * ldh;  // column-major: H[i + j*ldh]
-    for (int i = 0; i <= j; ++i) col[i] = hcol[i] + (re ? hcol2[i] : 0.0);
-    const double hn = sqrt(scal[S_WNORM2]);
-    for (int i = 0; i < j; ++i) {
-        const double a = col[i], b = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * b;
-        col[i + 1] = -sn[i] * a + cs[i] * b;
+    if (threadIdx.x == 0) carry = hcol[0] + (re ? hcol2[0] : 0.0);
+    __syncthreads();
+    for (int i0 = 0; i0 < j; i0 += GV_CHUNK) {
+        const int cnt = j - i0 < GV_CHUNK ? j - i0 : GV_CHUNK;
+        for (int t = threadIdx.x; t < cnt; t += 64) {
+            sc[t] = cs[i0 + t];
+            ss[t] = sn[i0 + t];
+            sh[t + 1] = hcol[i0 + t + 1] + (re ? hcol2[i0 + t + 1] : 0.0);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = carry;
+            for (int t = 0; t < cnt; ++t) {
+                const double b = sh[t + 1];
+                so[t] = sc[t] * a + ss[t] * b;
+                a = -ss[t] * a + sc[t] * b;
+            }
+            carry = a;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 64) col[i0 + t] = so[t];
+        __syncthreads();
     }
-    const double a = col[j], b = hn;
+    if (threadIdx.x != 0) return;
+    const double hn = sqrt(scal[S_WNORM2]);
+    const double a = carry, b = hn;
     const double d = sqrt(a * a + b * b);
     cs[j] = d == 0.0 ? 1.0 : a / d;
     sn[j] = d == 0.0 ? 0.0 : b / d;
@@ -402,27 +442,85 @@ __global__ __launch_bounds__(BLK) void cycle_init_kernel(P* __restrict__ V, cons
     }
 }
 
-// y = H(0:J,0:J)^{-1} g(0:J), one thread (H column-major, leading dimension ldh)
-__global__ void trisolve_kernel(const int* ctrl, const double* H, const double* g, double* y, int ldh)
+// y = R^{-1} g(0:J) with R = H(0:J,0:J) upper triangular (column-major,
+// leading dimension ldh), by 64-column panels from the bottom: one wave solves
+// the panel's triangle from LDS, then the whole block updates the remaining
+// right-hand side with the panel's columns.
+constexpr int TS_PB = 48;
+constexpr int TS_MAXJ = 4096;
+__global__ __launch_bounds__(1024) void trisolve_kernel(const int* ctrl, const double* __restrict__ H,
+                                                        const double* __restrict__ g, double* __restrict__ y,
+                                                        int ldh)
 {
+    __shared__ double rhs[TS_MAXJ];
+    __shared__ double tri[TS_PB][TS_PB + 1];
+    __shared__ double ys[TS_PB];
     const int J = ctrl[C_J];
-    for (int i = J - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int c = i + 1; c < J; ++c) s -= H[i + (int64_t)c * ldh] * y[c];
-        y[i] = s / H[i + (int64_t)i * ldh];
+    for (int k = threadIdx.x; k < J; k += blockDim.x) rhs[k] = g[k];
+    __syncthreads();
+    for (int c1 = J; c1 > 0; c1 -= TS_PB) {
+        const int c0 = c1 - TS_PB > 0 ? c1 - TS_PB : 0;
+        const int pb = c1 - c0;
+        for (int q = threadIdx.x; q < pb * pb; q += blockDim.x) {
+            const int r = q % pb, c = q / pb;  // R(c0 + r, c0 + c)
+            tri[r][c] = H[(c0 + r) + (int64_t)(c0 + c) * ldh];
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            double v = lane < pb ? rhs[c0 + lane] : 0.0;
+            for (int i = pb - 1; i >= 0; --i) {
+                const double yi = __shfl(v, i, 64) / tri[i][i];
+                if (lane == i) ys[i] = yi;
+                if (lane < i) v -= tri[lane][i] * yi;
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < c0; k += blockDim.x) {
+            double s = rhs[k];
+            for (int c = 0; c < pb; ++c) s -= H[k + (int64_t)(c0 + c) * ldh] * ys[c];
+            rhs[k] = s;
+        }
+        for (int c = threadIdx.x; c < pb; c += blockDim.x) y[c0 + c] = ys[c];
+        __syncthreads();
     }
 }
 
-// u = V(:,0:J) y
+// u = V(:,0:J) y; rows split over threads, columns unrolled by 4
 template <typename P>
 __global__ __launch_bounds__(BLK) void combine_kernel(const P* __restrict__ V, int64_t n, const int* ctrl,
                                                       const double* __restrict__ y, P* __restrict__ u)
 {
     const int J = ctrl[C_J];
-    for (int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
-        double s = 0.0;
-        for (int i = 0; i < J; ++i) s += y[i] * (double)V[(int64_t)i * n + t];
-        u[t] = (P)s;
+    const int64_t base = (int64_t)blockIdx.x * (BLK * UPD_E) + threadIdx.x;
+    double acc[UPD_E];
+#pragma unroll
+    for (int e = 0; e < UPD_E; ++e) acc[e] = 0.0;
+    int c = 0;
+    for (; c + 4 <= J; c += 4) {
+        const double y0 = y[c], y1 = y[c + 1], y2 = y[c + 2], y3 = y[c + 3];
+        const P* v0 = V + (int64_t)c * n;
+#pragma unroll
+        for (int e = 0; e < UPD_E; ++e) {
+            const int64_t t = base + (int64_t)e * BLK;
+            if (t < n)
+                acc[e] += y0 * (double)v0[t] + y1 * (double)v0[t + n] + y2 * (double)v0[t + 2 * n] +
+                          y3 * (double)v0[t + 3 * n];
+        }
+    }
+    for (; c < J; ++c) {
+        const double yc = y[c];
+        const P* vc = V + (int64_t)c * n;
+#pragma unroll
+        for (int e = 0; e < UPD_E; ++e) {
+            const int64_t t = base + (int64_t)e * BLK;
+            if (t < n) acc[e] += yc * (double)vc[t];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < UPD_E; ++e) {
+        const int64_t t = base + (int64_t)e * BLK;
+        if (t < n) u[t] = (P)acc[e];
     }
 }
 
@@ -474,11 +572,86 @@ struct dg_solver {
     double* scal = nullptr;
     int* ctrl = nullptr;
     int* bad = nullptr;
+    int* rflags = nullptr;  // [restart]: 1 if iteration j took the second Gram-Schmidt pass
     int ready = 0;
+    // built-in profiler (opts.profile): HIP events around the heavy kernels
+    struct Rec { int cls; double bytes; int j; int pass; hipEvent_t e0, e1; };
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    std::vector<Rec> pending;
+    int64_t pl[8] = {0};
+    double pms[8] = {0}, pbytes[8] = {0};
+    // multidot split for iteration j: (column tiles, row splits, rows per split)
+    void md_shape(int j, int* tiles, int* splits, int64_t* rows) const;
 };
+
+void dg_solver::md_shape(int j, int* tiles, int* splits, int64_t* rows) const
+{
+    const int ncols = j + 2;
+    const int nt = (ncols + dg::CT - 1) / dg::CT;
+    const int64_t max_splits = std::max<int64_t>(1, n / dg::MD_MIN_ROWS);
+    int64_t sp = (dg::MD_TARGET_BLOCKS + nt - 1) / nt;
+    sp = std::max<int64_t>(1, std::min<int64_t>(sp, max_splits));
+    int64_t r = (n + sp - 1) / sp;
+    r = (r + dg::BLK - 1) / dg::BLK * dg::BLK;
+    *tiles = nt;
+    *splits = (int)((n + r - 1) / r);
+    *rows = r;
+}
+
+enum { PK_SPMV = 0, PK_MULTIDOT = 1, PK_UPDATE = 2, PK_RESIDUAL = 3, PK_COMBINE = 4, PK_N = 5 };
+static const char* PK_NAMES[PK_N] = {"spmv_hat", "multidot", "update", "residual64", "combine"};
+
+static hipEvent_t prof_event(dg_solver* s)
+{
+    if (s->evused == s->evpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        s->evpool.push_back(e);
+    }
+    return s->evpool[s->evused++];
+}
+
+// brackets one launch: returns true if recording (call prof_end after the launch)
+static bool prof_begin(dg_solver* s, hipStream_t st, int cls, double bytes, int j, int pass)
+{
+    if (!s->o.profile) return false;
+    dg_solver::Rec r{cls, bytes, j, pass, prof_event(s), prof_event(s)};
+    if (!r.e0 || !r.e1) return false;
+    hipEventRecord(r.e0, st);
+    s->pending.push_back(r);
+    return true;
+}
+
+static void prof_end(dg_solver* s, hipStream_t st, bool on)
+{
+    if (on) hipEventRecord(s->pending.back().e1, st);
+}
+
+// after a synchronisation: accumulate the launches that did work (iteration
+// j < J of the cycle, and for second passes only when the flag was raised)
+static void prof_flush(dg_solver* s, int J, const int* rflags)
+{
+    for (const auto& r : s->pending) {
+        const bool eff = r.j < 0 || (r.j < J && (r.pass == 0 || (rflags && rflags[r.j])));
+        if (!eff) continue;
+        double bytes = r.bytes;
+        if (r.j == -2) bytes = ((double)J + 1.0) * (double)s->n * (s->mixed ? 4.0 : 8.0);  // combine: J columns + u
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) continue;
+        s->pl[r.cls]++;
+        s->pms[r.cls] += ms;
+        s->pbytes[r.cls] += bytes;
+    }
+    s->pending.clear();
+    s->evused = 0;
+}
 
 static void solver_free(dg_solver* s)
 {
+    for (auto e : s->evpool) hipEventDestroy(e);
+    s->evpool.clear();
+    hipFree(s->rflags);
     hipFree(s->Ahat); hipFree(s->Dinv); hipFree(s->Dinv64); hipFree(s->V); hipFree(s->w); hipFree(s->u);
     hipFree(s->r); hipFree(s->partials); hipFree(s->hcol); hipFree(s->hcol2); hipFree(s->H); hipFree(s->cs);
     hipFree(s->sn); hipFree(s->g); hipFree(s->y); hipFree(s->scal); hipFree(s->ctrl); hipFree(s->bad);
@@ -503,12 +676,18 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     s->mixed = o->mixed;
     const int EPW = 64 / s->N;
     s->grid_elem = (int)((s->T + 4 * EPW - 1) / (4 * EPW));
-    s->grid_chunk = (int)((s->n + CHUNK - 1) / CHUNK);
+    s->grid_chunk = (int)((s->n + BLK * UPD_E - 1) / (BLK * UPD_E));
     s->grid_vec = (int)std::min<int64_t>((s->n + BLK - 1) / BLK, 2048);
     const size_t ps = s->mixed ? sizeof(float) : sizeof(double);
     const int mm = o->restart;
     const size_t NN = (size_t)s->N * s->N;
-    const int maxgrid = std::max(std::max(s->grid_elem, s->grid_chunk), s->grid_vec);
+    int64_t maxgrid = std::max(std::max(s->grid_elem, s->grid_chunk), s->grid_vec);
+    for (int j = 0; j < mm; ++j) {  // multidot partials: splits x (j+2) columns
+        int nt, sp;
+        int64_t rows;
+        s->md_shape(j, &nt, &sp, &rows);
+        maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 2));
+    }
     bool ok = true;
     auto al = [&](void** p, size_t bytes) { if (ok && hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) { *p = nullptr; ok = false; } };
     al(&s->Ahat, ps * NN * std::max<int64_t>(s->n_off, 1));
@@ -518,7 +697,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     al(&s->w, ps * s->n);
     al(&s->u, ps * s->n);
     al((void**)&s->r, sizeof(double) * s->n);
-    al((void**)&s->partials, sizeof(double) * (size_t)maxgrid * (mm + 2));
+    al((void**)&s->partials, sizeof(double) * (size_t)maxgrid);
     al((void**)&s->hcol, sizeof(double) * (mm + 2));
     al((void**)&s->hcol2, sizeof(double) * (mm + 2));
     al((void**)&s->H, sizeof(double) * (size_t)(mm + 1) * mm);
@@ -529,6 +708,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     al((void**)&s->scal, sizeof(double) * S_NSCAL);
     al((void**)&s->ctrl, sizeof(int) * C_NCTRL);
     al((void**)&s->bad, sizeof(int));
+    al((void**)&s->rflags, sizeof(int) * mm);
     if (!ok) { solver_free(s); delete s; return DG_ERR_OOM; }
     if (hipMemset(s->ctrl, 0, sizeof(int) * C_NCTRL) != hipSuccess) { solver_free(s); delete s; return DG_ERR_HIP; }
     *out = s;
@@ -588,12 +768,14 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
 {
     const dg_mesh* m = s->m;
     const int mm = s->o.restart;
-    const int ldp = mm + 2;
+    s->pending.clear();
+    s->evused = 0;
     P* V = (P*)s->V;
     P* w = (P*)s->w;
     // ||b||
-    hipLaunchKernelGGL(norm2_kernel, dim3(s->grid_vec), dim3(BLK), 0, st, b, s->n, s->partials, s->ctrl + C_TICKET0,
-                       s->scal, (int)S_BNORM2);
+    hipLaunchKernelGGL(norm2_kernel, dim3(s->grid_vec), dim3(BLK), 0, st, b, s->n, s->partials);
+    hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(1024), 0, st, (const double*)s->partials, s->grid_vec, s->scal,
+                       (int)S_BNORM2, (const int*)nullptr, 0, 0);
     DG_HIP_CHECK(hipGetLastError());
     double hs[S_NSCAL];
     int hc[C_NCTRL];
@@ -601,6 +783,7 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
     DG_HIP_CHECK(hipStreamSynchronize(st));
     const double bnorm = std::sqrt(hs[S_BNORM2]);
     if (!std::isfinite(bnorm)) return DG_ERR_NONFINITE;
+    DG_HIP_CHECK(hipMemsetAsync(s->ctrl + C_NREORTH, 0, sizeof(int), st));
     rep->iters = 0;
     rep->cycles = 0;
     rep->rel_res0 = 0.0;
@@ -615,53 +798,91 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
     const double cyc_rel = s->mixed ? s->o.inner_tol : 0.0;
     int its = 0;
     int status = DG_NOT_CONVERGED;
+    const double ps = (double)sizeof(P);
+    const double nb = (double)s->n;
+    const double idx_bytes = 4.0 * (double)(s->T + 1 + m->nnzb);
+    std::vector<int> hflags(s->o.profile ? mm : 0);
     for (;;) {
+        bool pr = prof_begin(s, st, PK_RESIDUAL, (double)m->nnzb * N * N * 8.0 + 3.0 * nb * 8.0 + idx_bytes, -1, 0);
         hipLaunchKernelGGL((residual64_kernel<N>), dim3(s->grid_elem), dim3(BLK), 0, st, s->A64, m->d_row_ptr,
-                           m->d_col_idx, b, x, s->r, s->T, s->partials, s->ctrl + C_TICKET0 + 1, s->scal,
-                           (int)S_RNORM2);
+                           m->d_col_idx, b, x, s->r, s->T, s->partials);
+        prof_end(s, st, pr);
+        hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(1024), 0, st, (const double*)s->partials, s->grid_elem,
+                           s->scal, (int)S_RNORM2, (const int*)nullptr, 0, 0);
         DG_HIP_CHECK(hipGetLastError());
         DG_HIP_CHECK(hipMemcpyAsync(hs, s->scal, sizeof(hs), hipMemcpyDeviceToHost, st));
         DG_HIP_CHECK(hipMemcpyAsync(hc, s->ctrl, sizeof(hc), hipMemcpyDeviceToHost, st));
+        if (s->o.profile && s->o.reorth)
+            DG_HIP_CHECK(hipMemcpyAsync(hflags.data(), s->rflags, sizeof(int) * mm, hipMemcpyDeviceToHost, st));
         DG_HIP_CHECK(hipStreamSynchronize(st));
+        if (s->o.profile) prof_flush(s, rep->cycles > 0 ? hc[C_J] : 0, s->o.reorth ? hflags.data() : nullptr);
         if (rep->cycles > 0) its += hc[C_J];
         const double rel = std::sqrt(hs[S_RNORM2]) / bnorm;
         if (rep->cycles == 0) rep->rel_res0 = rel;
         rep->rel_res = rel;
         rep->iters = its;
+        rep->reorth_passes = hc[C_NREORTH];
         if (!std::isfinite(rel)) { status = DG_ERR_NONFINITE; break; }
         if (rel <= s->o.rel_tol) { status = DG_OK; break; }
         if (its >= s->o.max_iters) { status = DG_NOT_CONVERGED; break; }
         const int mcyc = std::min(mm, s->o.max_iters - its);
         hipLaunchKernelGGL((cycle_init_kernel<P>), dim3(s->grid_vec), dim3(BLK), 0, st, V, s->r, s->n, s->ctrl,
                            s->scal, s->g, cyc_rel, abs_tol);
+        const double spmv_bytes = (double)s->n_off * N * N * ps + 2.0 * nb * ps + idx_bytes;
         for (int j = 0; j < mcyc; ++j) {
+            int nt, sp;
+            int64_t rows;
+            s->md_shape(j, &nt, &sp, &rows);
+            const double md_bytes = (j + 2.0) * nb * ps, up_bytes = (j + 3.0) * nb * ps;
+            pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
             hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
                                m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, w, s->T, s->ctrl);
-            hipLaunchKernelGGL((multidot_kernel<P>), dim3(s->grid_chunk), dim3(BLK), 0, st, (const P*)V,
-                               (const P*)w, s->n, s->ctrl, s->partials, ldp, s->hcol, (int)C_TICKET0 + 2, 0);
-            hipLaunchKernelGGL((update_kernel<P>), dim3(s->grid_chunk), dim3(BLK), 0, st, (const P*)V, w, s->n,
-                               s->ctrl, s->partials, s->hcol, s->scal, (int)C_TICKET0 + 3, 0);
+            prof_end(s, st, pr);
+            pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
+            hipLaunchKernelGGL((multidot_kernel<P>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, (const P*)w, s->n, j,
+                               rows, (const int*)s->ctrl, s->partials, 0);
+            prof_end(s, st, pr);
+            hipLaunchKernelGGL(reduce_cols_kernel, dim3((j + 2 + 3) / 4), dim3(BLK), 0, st, (const double*)s->partials,
+                               j + 2, sp, j, (const int*)s->ctrl, s->hcol, 0);
+            pr = prof_begin(s, st, PK_UPDATE, up_bytes, j, 0);
+            hipLaunchKernelGGL((update_kernel<P>), dim3(s->grid_chunk), dim3(BLK), 0, st, (const P*)V, w, s->n, j,
+                               (const int*)s->ctrl, s->partials, s->hcol, 0);
+            prof_end(s, st, pr);
+            hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(1024), 0, st, (const double*)s->partials, s->grid_chunk,
+                               s->scal, (int)S_WNORM2, (const int*)s->ctrl, j, 0);
             if (s->o.reorth) {
-                hipLaunchKernelGGL(arnoldi_decide_kernel, dim3(1), dim3(1), 0, st, s->ctrl, s->hcol, s->scal, 1);
-                hipLaunchKernelGGL((multidot_kernel<P>), dim3(s->grid_chunk), dim3(BLK), 0, st, (const P*)V,
-                                   (const P*)w, s->n, s->ctrl, s->partials, ldp, s->hcol2, (int)C_TICKET0 + 2, 1);
-                hipLaunchKernelGGL((update_kernel<P>), dim3(s->grid_chunk), dim3(BLK), 0, st, (const P*)V, w, s->n,
-                                   s->ctrl, s->partials, s->hcol2, s->scal, (int)C_TICKET0 + 3, 1);
+                hipLaunchKernelGGL(arnoldi_decide_kernel, dim3(1), dim3(1), 0, st, s->ctrl, s->hcol, s->scal, 1,
+                                   s->rflags);
+                pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 1);
+                hipLaunchKernelGGL((multidot_kernel<P>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, (const P*)w,
+                                   s->n, j, rows, (const int*)s->ctrl, s->partials, 1);
+                prof_end(s, st, pr);
+                hipLaunchKernelGGL(reduce_cols_kernel, dim3((j + 2 + 3) / 4), dim3(BLK), 0, st,
+                                   (const double*)s->partials, j + 2, sp, j, (const int*)s->ctrl, s->hcol2, 1);
+                pr = prof_begin(s, st, PK_UPDATE, up_bytes, j, 1);
+                hipLaunchKernelGGL((update_kernel<P>), dim3(s->grid_chunk), dim3(BLK), 0, st, (const P*)V, w, s->n, j,
+                                   (const int*)s->ctrl, s->partials, s->hcol2, 1);
+                prof_end(s, st, pr);
+                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(1024), 0, st, (const double*)s->partials,
+                                   s->grid_chunk, s->scal, (int)S_WNORM2, (const int*)s->ctrl, j, 1);
             }
-            hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(1), 0, st, s->ctrl, s->hcol, s->hcol2, s->H, s->cs, s->sn,
-                               s->g, s->scal, mm + 1, mcyc);
+            hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, s->ctrl, s->hcol, s->hcol2, s->H, s->cs,
+                               s->sn, s->g, s->scal, mm + 1, mcyc);
             hipLaunchKernelGGL((normalize_kernel<P>), dim3(s->grid_vec), dim3(BLK), 0, st, V, (const P*)w, s->n,
                                s->ctrl, s->scal);
         }
         DG_HIP_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(trisolve_kernel, dim3(1), dim3(1), 0, st, s->ctrl, s->H, s->g, s->y, mm + 1);
-        hipLaunchKernelGGL((combine_kernel<P>), dim3(s->grid_vec), dim3(BLK), 0, st, (const P*)V, s->n, s->ctrl, s->y,
-                           (P*)s->u);
+        hipLaunchKernelGGL(trisolve_kernel, dim3(1), dim3(1024), 0, st, s->ctrl, s->H, s->g, s->y, mm + 1);
+        pr = prof_begin(s, st, PK_COMBINE, 0.0, -2, 0);
+        hipLaunchKernelGGL((combine_kernel<P>), dim3(s->grid_chunk), dim3(BLK), 0, st, (const P*)V, s->n, s->ctrl,
+                           s->y, (P*)s->u);
+        prof_end(s, st, pr);
         hipLaunchKernelGGL((dinv_update_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Dinv,
                            (const P*)s->u, x, s->T);
         DG_HIP_CHECK(hipGetLastError());
         rep->cycles++;
     }
+    if (s->o.profile) prof_flush(s, 0, nullptr);
     rep->status = status;
     return status;
 }
@@ -691,7 +912,7 @@ static int residual_n(const dg_mesh* m, const double* A, const double* b, const 
     const int EPW = 64 / N;
     const int grid = (int)((m->T + 4 * EPW - 1) / (4 * EPW));
     hipLaunchKernelGGL((residual64_kernel<N>), dim3(grid), dim3(BLK), 0, st, A, m->d_row_ptr, m->d_col_idx, b, x, y,
-                       m->T, (double*)nullptr, (int*)nullptr, (double*)nullptr, 0);
+                       m->T, (double*)nullptr);
     return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
 }
 
@@ -708,4 +929,20 @@ extern "C" int32_t dg_residual(const dg_mesh* m, const double* A, const double* 
     case 15: return residual_n<15>(m, A, b, x, y, st);
     }
     return DG_ERR_DEGREE;
+}
+
+extern "C" int32_t dg_solver_profile(dg_solver* s, dg_kernel_stats* out, int32_t max, int32_t* count, int32_t reset)
+{
+    if (!s || !count || (max > 0 && !out)) return DG_ERR_ARG;
+    int c = 0;
+    for (int k = 0; k < PK_N && c < max; ++k, ++c) {
+        std::snprintf(out[c].name, sizeof(out[c].name), "%s", PK_NAMES[k]);
+        out[c].launches = s->pl[k];
+        out[c].ms = s->pms[k];
+        out[c].bytes = s->pbytes[k];
+    }
+    *count = c;
+    if (reset)
+        for (int k = 0; k < PK_N; ++k) { s->pl[k] = 0; s->pms[k] = 0.0; s->pbytes[k] = 0.0; }
+    return DG_OK;
 }
