@@ -211,6 +211,77 @@ int32_t dg_solver_profile(dg_solver* solver, dg_kernel_stats* out, int32_t max, 
 int32_t dg_residual(const dg_mesh* mesh, const double* dev_vals64, const double* dev_b, const double* dev_x,
                     double* dev_y, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent instances (own mesh, degree 1 or 2,
+ * coefficients and data) assembled and solved by one persistent kernel
+ * launch.  Per instance, the mesh arrays are those of dg_mesh_create and the
+ * problem as in dg_assemble with these restrictions: degree 1 or 2; eps, b,
+ * alpha DG_CONST or DG_AFFINE; f DG_CONST, DG_AFFINE or DG_GAUSS_SUM; g^D and
+ * g^N DG_CONST or DG_AFFINE (no DG_QPOINTS).  The solve is the restarted
+ * block-Jacobi GMRES of dg_solver_solve (FP64 true residual before each
+ * cycle, FP64 or FP32 cycles) with a per-instance restart length
+ * clamp(restart_min + restart_per_side * sqrt(n_elems / 2), 1, restart_max)
+ * (sqrt(n_elems / 2) is the side N of an N x N structured grid).
+ * Every instance is assembled by one element-parallel launch.  Instances with
+ * fewer than lockstep_min_dofs unknowns are then solved by one persistent
+ * launch (one workgroup per instance at a time, a queue ordered by decreasing
+ * cost); larger ones by the lockstep solver, in which every Arnoldi step is
+ * one launch per kernel over all of them (chunks of instances under a memory
+ * budget), so that instances whose cost differs by orders of magnitude share
+ * the whole GPU.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const double* nodes_xy;
+    int64_t n_nodes;
+    const int32_t* elems;
+    int64_t n_elems;
+    const int32_t* dir_edges;
+    int64_t n_dir;
+    const int32_t* neu_edges;
+    int64_t n_neu;
+    dg_problem problem;
+} dg_instance;
+
+typedef struct {
+    int32_t mixed;            /* 0: FP64 cycles; 1: FP32 cycles + FP64 refinement */
+    int32_t max_iters;        /* per instance */
+    double rel_tol;           /* per instance, true FP64 relative residual */
+    double inner_tol;         /* mixed only: per-cycle relative reduction target */
+    int32_t restart_min;      /* restart length policy, see above; restart_max <= 512 */
+    int32_t restart_max;
+    double restart_per_side;
+    int32_t block_threads;    /* persistent solve: threads per workgroup, 256 or 512 (0 = 512) */
+    int32_t slots;            /* persistent solve: workgroups = workspace slots (0 = number of compute units) */
+    int64_t lockstep_min_dofs; /* instances with at least this many unknowns use the lockstep solver */
+    double lockstep_mem_gb;   /* lockstep workspace budget per chunk of instances (<= 0: 64 GB) */
+} dg_batch_opts;
+
+typedef struct dg_batch dg_batch;
+
+/* Validates and preprocesses every instance on the host (several threads),
+ * uploads the concatenated arrays, and allocates one workspace per slot sized
+ * for the largest instance.  Instance errors return that instance's code. */
+int32_t dg_batch_create(const dg_instance* instances, int32_t count, const dg_batch_opts* opts, dg_batch** out);
+/* Offsets of every instance's dofs in the concatenated solution vector
+ * (host int64 [count + 1]; the last entry is the total). */
+int32_t dg_batch_offsets(const dg_batch* batch, int64_t* x_offsets);
+/* Assembles and solves every instance: dev_x (FP64, concatenated) holds the
+ * initial guesses on entry and the solutions on exit; dev_reports
+ * ([count], device) receives one report per instance.  Without lockstep
+ * instances it is stream-ordered with no host synchronisation (so it can be
+ * captured in a HIP graph); the lockstep solver synchronises the stream once
+ * per restart cycle and every 8 Arnoldi steps to read two counters. */
+int32_t dg_batch_run(dg_batch* batch, double* dev_x, dg_solve_report* dev_reports, void* stream);
+/* Progress callback for the lockstep part, called on the host thread of
+ * dg_batch_run after every restart cycle with the number of lockstep
+ * instances finished and their total. */
+typedef void (*dg_progress_fn)(void* user, int32_t finished, int32_t total);
+int32_t dg_batch_set_progress(dg_batch* batch, dg_progress_fn fn, void* user);
+/* Number of instances the running (or last) dg_batch_run has started, read
+ * with a copy on a separate non-blocking stream while the launch runs. */
+int32_t dg_batch_progress(dg_batch* batch, int32_t* started);
+void dg_batch_destroy(dg_batch* batch);
+
 const char* dg_status_str(int32_t status);
 
 #ifdef __cplusplus

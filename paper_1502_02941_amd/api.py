@@ -60,9 +60,30 @@ class _Report(C.Structure):
                 ("rel_res", C.c_double), ("rel_res0", C.c_double)]
 
 
+class _Instance(C.Structure):
+    _fields_ = [("nodes_xy", C.c_void_p), ("n_nodes", C.c_int64), ("elems", C.c_void_p), ("n_elems", C.c_int64),
+                ("dir_edges", C.c_void_p), ("n_dir", C.c_int64), ("neu_edges", C.c_void_p), ("n_neu", C.c_int64),
+                ("problem", _Problem)]
+
+
+class _BatchOpts(C.Structure):
+    _fields_ = [("mixed", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double), ("inner_tol", C.c_double),
+                ("restart_min", C.c_int32), ("restart_max", C.c_int32), ("restart_per_side", C.c_double),
+                ("block_threads", C.c_int32), ("slots", C.c_int32), ("lockstep_min_dofs", C.c_int64),
+                ("lockstep_mem_gb", C.c_double)]
+
+
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32)
+
+
+REPORT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32), ("reorth", np.int32),
+                         ("rel_res", np.float64), ("rel_res0", np.float64)])
+
 EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_destroy", "dg_mesh_structure",
            "dg_mesh_qpoints", "dg_assemble", "dg_solver_create", "dg_solver_setup", "dg_solver_solve",
-           "dg_solver_destroy", "dg_residual", "dg_status_str", "dg_solver_profile"]
+           "dg_solver_destroy", "dg_residual", "dg_status_str", "dg_solver_profile",
+           "dg_batch_create", "dg_batch_offsets", "dg_batch_run", "dg_batch_destroy", "dg_batch_progress",
+           "dg_batch_set_progress"]
 
 _lib = None
 
@@ -91,10 +112,17 @@ def lib():
         L.dg_solver_destroy.restype = None
         L.dg_residual.argtypes = [P, P, P, P, P, P]
         L.dg_solver_profile.argtypes = [P, C.POINTER(_KStats), I32, C.POINTER(I32), I32]
+        L.dg_batch_create.argtypes = [C.POINTER(_Instance), I32, C.POINTER(_BatchOpts), C.POINTER(P)]
+        L.dg_batch_offsets.argtypes = [P, P]
+        L.dg_batch_run.argtypes = [P, P, P, P]
+        L.dg_batch_progress.argtypes = [P, C.POINTER(I32)]
+        L.dg_batch_set_progress.argtypes = [P, PROGRESS_FN, P]
+        L.dg_batch_destroy.argtypes = [P]
+        L.dg_batch_destroy.restype = None
         L.dg_status_str.argtypes = [I32]
         L.dg_status_str.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("dg_mesh_destroy", "dg_solver_destroy", "dg_status_str"):
+            if name not in ("dg_mesh_destroy", "dg_solver_destroy", "dg_status_str", "dg_batch_destroy"):
                 getattr(L, name).restype = I32
         _lib = L
     return _lib
@@ -341,3 +369,111 @@ def bsr_to_scipy(mesh: Mesh, vals: torch.Tensor, row_ptr=None, col_idx=None):
     n = mesh.n_loc
     return sp.bsr_matrix((vals.double().cpu().numpy(), col_idx.cpu().numpy(), row_ptr.cpu().numpy()),
                          shape=(mesh.n_dofs, mesh.n_dofs), blocksize=(n, n))
+
+
+class Batch:
+    """dg_batch_*: many independent instances assembled and solved by one
+    element-parallel assembly launch and one persistent solve launch.
+
+    instances: list of (MeshArrays, Problem); degree 1 or 2; eps/b/alpha
+    CONST or AFFINE, f CONST/AFFINE/GAUSS_SUM, gD/gN CONST/AFFINE."""
+
+    def __init__(self, instances, mixed=True, rel_tol=1e-10, inner_tol=1e-5, max_iters=20000, restart_min=64,
+                 restart_per_side=2.0, restart_max=512, block_threads=256, slots=0, lockstep_min_dofs=16384,
+                 lockstep_mem_gb=64.0, log=None):
+        L = lib()
+        self.count = len(instances)
+        arr = (_Instance * self.count)()
+        self._keep = []
+        for i, (m, prob) in enumerate(instances):
+            nodes = np.ascontiguousarray(m.nodes, dtype=np.float64)
+            el = np.ascontiguousarray(m.elems, dtype=np.int32)
+            d = np.ascontiguousarray(m.dirichlet, dtype=np.int32).reshape(-1, 2)
+            nm = np.ascontiguousarray(m.neumann, dtype=np.int32).reshape(-1, 2)
+            self._keep += [nodes, el, d, nm, prob]
+            I = arr[i]
+            I.nodes_xy, I.n_nodes = nodes.ctypes.data, len(nodes)
+            I.elems, I.n_elems = el.ctypes.data, len(el)
+            I.dir_edges, I.n_dir = (d.ctypes.data if len(d) else None), len(d)
+            I.neu_edges, I.n_neu = (nm.ctypes.data if len(nm) else None), len(nm)
+            I.problem = prob._c()
+        o = _BatchOpts(int(bool(mixed)), int(max_iters), float(rel_tol), float(inner_tol), int(restart_min),
+                       int(restart_max), float(restart_per_side), int(block_threads), int(slots),
+                       int(lockstep_min_dofs), float(lockstep_mem_gb))
+        h = C.c_void_p()
+        _check(L.dg_batch_create(arr, self.count, C.byref(o), C.byref(h)), "dg_batch_create")
+        self._h = h
+        self._log = log
+        self._last_progress = [0.0]
+
+        def _progress(user, done, total):
+            import time as _t
+            now = _t.perf_counter()
+            if self._log is not None and (now - self._last_progress[0] >= 20.0 or done == total):
+                self._log("batch (lockstep): %d/%d instances finished" % (done, total))
+                self._last_progress[0] = now
+
+        self._progress_cb = PROGRESS_FN(_progress)
+        _check(L.dg_batch_set_progress(h, self._progress_cb, None), "dg_batch_set_progress")
+        self._keep = None
+        off = np.zeros(self.count + 1, dtype=np.int64)
+        _check(L.dg_batch_offsets(h, off.ctypes.data), "dg_batch_offsets")
+        self.offsets = off
+        self.n_dofs = int(off[-1])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dg_batch_destroy(h)
+            self._h = None
+
+    def alloc(self):
+        x = torch.zeros(self.n_dofs, dtype=torch.float64, device="cuda")
+        rep = torch.zeros(self.count * REPORT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        return x, rep
+
+    def run(self, x: torch.Tensor, reports: torch.Tensor, stream=None):
+        """Asynchronous: assembles and solves every instance (x: initial guesses in, solutions out)."""
+        assert x.dtype == torch.float64 and x.numel() == self.n_dofs
+        assert reports.numel() == self.count * REPORT_DTYPE.itemsize
+        _check(lib().dg_batch_run(self._h, _dptr(x), _dptr(reports), _stream(stream)), "dg_batch_run")
+
+    def progress(self):
+        """Instances started by the running (or last) launch."""
+        v = C.c_int32()
+        _check(lib().dg_batch_progress(self._h, C.byref(v)), "dg_batch_progress")
+        return v.value
+
+    def wait(self, log=None, every=20.0, stream=None):
+        """Waits for the launch, printing the number of started instances when it
+        changes (at most every `every` seconds)."""
+        import time as _t
+        ev = torch.cuda.Event()
+        ev.record(stream if stream is not None else torch.cuda.current_stream())
+        last_t, last_v = _t.perf_counter(), -1
+        while not ev.query():
+            _t.sleep(0.05)
+            now = _t.perf_counter()
+            if log and now - last_t >= every:
+                v = self.progress()
+                if v != last_v:
+                    log("batch: %d/%d instances started" % (v, self.count))
+                    last_v = v
+                last_t = now
+        ev.synchronize()
+
+    @staticmethod
+    def reports(rep: torch.Tensor):
+        return np.frombuffer(rep.cpu().numpy().tobytes(), dtype=REPORT_DTYPE)
+
+    def segment(self, x, i):
+        return x[int(self.offsets[i]):int(self.offsets[i + 1])]
+
+
+def instance_problem(inst, method=SIPG):
+    """Problem of a sampled batch instance (workloads.Instance): SIPG with the
+    default penalty, constant eps, b, alpha, Gaussian-sum f, g^D = 0."""
+    sigma, _ = default_penalty(method, inst.k)
+    bx, by = inst.b
+    return Problem(method, inst.k, sigma, eps=inst.eps, bx=bx, by=by, alpha=inst.alpha,
+                   f=Field.gauss_sum([tuple(t) for t in inst.gauss]), gD=0.0)

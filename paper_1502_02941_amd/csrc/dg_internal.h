@@ -88,4 +88,6 @@ std::vector<double> build_tables(int k);
 // Gauss-Jacobi rule for the weight (1-x)^a (1+x)^b on [-1,1].
 void gauss_jacobi_gw(int n, double a, double b, double* x, double* w);
 int launch_assemble(const dg_mesh* m, const AsmArgs& a, int prec, hipStream_t s);
+int build_host_mesh(const double* xy, int64_t n_nodes, const int32_t* elems, int64_t T, const int32_t* dir,
+                    int64_t n_dir, const int32_t* neu, int64_t n_neu, int32_t degree, dg_mesh* m, bool with_tables);
 }  // namespace dg

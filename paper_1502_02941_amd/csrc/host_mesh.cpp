@@ -220,21 +220,18 @@ extern "C" int32_t dg_default_penalty(int32_t method, int32_t degree, double* si
     return DG_OK;
 }
 
-extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32_t* elems, int64_t T,
-                                  const int32_t* dir, int64_t n_dir, const int32_t* neu, int64_t n_neu,
-                                  int32_t degree, dg_mesh** out)
+namespace dg {
+// Validates the section 2.1 arrays and fills the host-side mesh: connectivity,
+// boundary classification, BSR pattern, per-element geometry and tables.
+int build_host_mesh(const double* xy, int64_t n_nodes, const int32_t* elems, int64_t T, const int32_t* dir,
+                    int64_t n_dir, const int32_t* neu, int64_t n_neu, int32_t degree, dg_mesh* m, bool with_tables)
 {
-    if (!out) return DG_ERR_ARG;
-    *out = nullptr;
     if (!xy || !elems || n_nodes <= 0 || T <= 0 || n_dir < 0 || n_neu < 0) return DG_ERR_ARG;
     if ((n_dir > 0 && !dir) || (n_neu > 0 && !neu)) return DG_ERR_ARG;
     if (degree < 0 || degree > DG_MAX_DEGREE) return DG_ERR_DEGREE;
     if (T > (int64_t)1 << 29) return DG_ERR_ARG;  // int32 block indices
     for (int64_t i = 0; i < 2 * n_nodes; ++i)
         if (!std::isfinite(xy[i])) return DG_ERR_NONFINITE;
-
-    dg_mesh* m = new (std::nothrow) dg_mesh();
-    if (!m) return DG_ERR_OOM;
     m->k = degree;
     const TabLayout L(degree);
     m->n = L.n; m->nq = L.nq; m->nqe = L.nqe;
@@ -243,13 +240,13 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
     for (int64_t K = 0; K < T; ++K) {
         for (int l = 0; l < 3; ++l) {
             int32_t v = elems[3 * K + l];
-            if (v < 0 || v >= n_nodes) { delete m; return DG_ERR_ARG; }
+            if (v < 0 || v >= n_nodes) return DG_ERR_ARG;
             m->xy6[6 * K + 2 * l] = xy[2 * v];
             m->xy6[6 * K + 2 * l + 1] = xy[2 * v + 1];
         }
         const double* p = &m->xy6[6 * K];
         double det = (p[2] - p[0]) * (p[5] - p[1]) - (p[4] - p[0]) * (p[3] - p[1]);
-        if (!(det > 0.0)) { delete m; return DG_ERR_ORIENTATION; }
+        if (!(det > 0.0)) return DG_ERR_ORIENTATION;
     }
 
     // Edge connectivity through a hash map keyed by the sorted node pair.
@@ -270,13 +267,11 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
             auto it = first.find(kk);
             if (it == first.end()) { first.emplace(kk, 3 * K + l); continue; }
             const int64_t h = it->second;
-            if (h < 0) { delete m; return DG_ERR_NONMANIFOLD; }  // third element on this edge
+            if (h < 0) return DG_ERR_NONMANIFOLD;  // third element on this edge
             const int64_t K2 = h / 3;
             const int l2 = (int)(h % 3);
             // the two elements must traverse the shared edge in opposite directions
-            if (K2 == K || elems[3 * K2 + l2] != b || elems[3 * K2 + (l2 + 1) % 3] != a) {
-                delete m; return DG_ERR_NONMANIFOLD;
-            }
+            if (K2 == K || elems[3 * K2 + l2] != b || elems[3 * K2 + (l2 + 1) % 3] != a) return DG_ERR_NONMANIFOLD;
             m->nbr[3 * K + l] = (int32_t)K2;
             m->nbr[3 * K2 + l2] = (int32_t)K;
             m->nbr_edge[K] |= l2 << (2 * l);
@@ -289,9 +284,11 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
     bc.reserve((size_t)(n_dir + n_neu));
     for (int64_t i = 0; i < n_dir + n_neu; ++i) {
         const int32_t* e = i < n_dir ? dir + 2 * i : neu + 2 * (i - n_dir);
-        if (e[0] < 0 || e[0] >= n_nodes || e[1] < 0 || e[1] >= n_nodes) { delete m; return DG_ERR_ARG; }
-        if (!bc.emplace(key(e[0], e[1]), i < n_dir ? 0 : 1).second) { delete m; return DG_ERR_BOUNDARY; }
+        if (e[0] < 0 || e[0] >= n_nodes || e[1] < 0 || e[1] >= n_nodes) return DG_ERR_ARG;
+        if (!bc.emplace(key(e[0], e[1]), i < n_dir ? 0 : 1).second) return DG_ERR_BOUNDARY;
     }
+    m->n_dir = m->n_neu = 0;
+    m->bnd_el.clear(); m->bnd_loc.clear(); m->bnd_type.clear();
     for (int64_t K = 0; K < T; ++K)
         for (int l = 0; l < 3; ++l) {
             const int32_t a = elems[3 * K + l], b = elems[3 * K + (l + 1) % 3];
@@ -299,7 +296,7 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
             hmax = std::max(hmax, std::sqrt(dx * dx + dy * dy));
             if (m->nbr[3 * K + l] != INT32_MIN) continue;
             auto it = bc.find(key(a, b));
-            if (it == bc.end() || it->second >= 2) { delete m; return DG_ERR_BOUNDARY; }
+            if (it == bc.end() || it->second >= 2) return DG_ERR_BOUNDARY;
             const int type = it->second;
             it->second += 2;
             const int32_t bidx = (int32_t)m->bnd_el.size();
@@ -310,7 +307,7 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
             (type == 0 ? m->n_dir : m->n_neu)++;
         }
     for (auto& kv : bc)
-        if (kv.second < 2) { delete m; return DG_ERR_BOUNDARY; }  // listed edge not on the boundary
+        if (kv.second < 2) return DG_ERR_BOUNDARY;  // listed edge not on the boundary
     m->n_int = n_int;
     m->n_bnd = (int64_t)m->bnd_el.size();
     m->hmax = hmax;
@@ -331,11 +328,22 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
         for (int l = 0; l < 3; ++l)
             if (m->nbr[3 * K + l] >= 0) m->col_idx[s++] = m->nbr[3 * K + l];
     }
+    if (with_tables) m->tab64 = build_tables(degree);
+    return DG_OK;
+}
+}  // namespace dg
 
-    m->tab64 = build_tables(degree);
+extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32_t* elems, int64_t T,
+                                  const int32_t* dir, int64_t n_dir, const int32_t* neu, int64_t n_neu,
+                                  int32_t degree, dg_mesh** out)
+{
+    if (!out) return DG_ERR_ARG;
+    *out = nullptr;
+    dg_mesh* m = new (std::nothrow) dg_mesh();
+    if (!m) return DG_ERR_OOM;
+    int st = build_host_mesh(xy, n_nodes, elems, T, dir, n_dir, neu, n_neu, degree, m, true);
+    if (st != DG_OK) { delete m; return st; }
     std::vector<float> tab32(m->tab64.begin(), m->tab64.end());
-
-    int st = DG_OK;
     if (hipGetDevice(&m->device) != hipSuccess) st = DG_ERR_HIP;
     if (st == DG_OK) st = upload(&m->d_xy, m->xy6);
     if (st == DG_OK) st = upload(&m->d_nbr, m->nbr);

@@ -1,0 +1,65 @@
+// Internal: lockstep batched GMRES (lockstep.hip), used by the batch object.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+struct LsInst {
+    int64_t T, n;
+    int32_t k, m;              // degree, restart length
+    int32_t id, id_local;      // batch instance index, index within the lockstep chunk
+    int32_t nchunks, neblk;    // row chunks, element blocks
+    int64_t rp_off, ci_off, val_off, x_off;               // batch arrays
+    int64_t dinv_off, ahat_off, v_off, part_off;          // chunk buffers
+    int64_t red_off, red2_off, hc_off, h_off, H_off;
+};
+
+struct LsState {
+    int32_t active, stop, J, mcyc, its, cycles, status, pad;
+    double bnorm, beta, cyctol, invh;
+};
+
+struct LsArgs {
+    int32_t count;
+    const LsInst* inst;
+    LsState* state;
+    const int64_t* eblk;  // [count+1] element-block prefix
+    const int64_t* rblk;  // [count+1] row-chunk prefix
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const double* A64;
+    const double* rhs;
+    double* x;
+    double* r;
+    void* w;
+    void* V;
+    void* Ahat;
+    void* DinvP;
+    double* Dinv64;
+    double* part;
+    double* red;
+    double* red2;
+    double* hcol;
+    double* H;
+    double* cs;
+    double* sn;
+    double* g;
+    double* y;
+    dg_solve_report* reports;
+    int* counters;
+    double rel_tol, inner_tol;
+    int32_t max_iters, mixed;
+};
+
+int ls_solve(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m, int mixed, hipStream_t st,
+             dg_progress_fn fn, void* user, int done_before, int total);
+int64_t ls_elem_blocks(int k, int64_t T);
+int64_t ls_row_chunks(int64_t n);
+int ls_init(const LsArgs& A, hipStream_t st);
+
+}  // namespace dg

@@ -66,3 +66,21 @@ def test_mesh_validation_errors(what, code):
 
 def test_status_strings():
     assert api.status_str(0) == "DG_OK" and api.status_str(-9) == "DG_ERR_OOM"
+
+
+def test_batch_rejects_bad_instances_on_host():
+    m = W.structured_mesh(4)
+    ok = api.Problem(api.SIPG, 1, 6.0, eps=0.01, bx=1.0, by=0.0, alpha=0.0, f=1.0)
+    bad_deg = api.Problem(api.SIPG, 3, 36.0, eps=0.01, bx=1.0, by=0.0, alpha=0.0, f=1.0)
+    with pytest.raises(api.DGError) as e:
+        api.Batch([(m, ok), (m, bad_deg)])
+    assert e.value.status == -5
+    bad_field = api.Problem(api.SIPG, 1, 6.0, eps=api.Field.gauss_sum([(0.5, 0.5, 0.1, 1.0)]), bx=1.0, by=0.0,
+                            alpha=0.0, f=1.0)
+    with pytest.raises(api.DGError) as e:
+        api.Batch([(m, bad_field)])
+    assert e.value.status == -1
+    bad_mesh = W.MeshArrays(m.nodes, m.elems[:, ::-1].copy(), m.dirichlet, m.neumann)
+    with pytest.raises(api.DGError) as e:
+        api.Batch([(bad_mesh, ok)])
+    assert e.value.status == -2

@@ -1,0 +1,111 @@
+"""Batched assembly + solve (one element-parallel assembly launch, one
+persistent solve launch) vs the CPU oracle, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1502_02941_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_02941_amd import api as A
+    A.lib()
+    return A
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _instances(count, seed, n_range=(6, 24)):
+    return W.sample_instances(count, seed=seed, n_range=n_range)
+
+
+def _oracle_relres(inst, x):
+    m = W.structured_mesh(inst.N)
+    M = O.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann)
+    sigma, kappa = O.default_penalty(O.SIPG, inst.k)
+    B = O.assemble(M, inst.k, sigma=sigma, kappa=kappa, eps=inst.eps, bx=inst.b[0], by=inst.b[1],
+                   alpha=inst.alpha, f=O.Field.gauss_sum([tuple(t) for t in inst.gauss]), gD=0.0)
+    A = B.to_scipy()
+    return float(np.linalg.norm(B.rhs - A @ x) / np.linalg.norm(B.rhs))
+
+
+ALL_PERSISTENT = 1 << 62
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("block_threads,split", [(512, ALL_PERSISTENT), (256, ALL_PERSISTENT), (256, 0),
+                                                  (256, 1500)])
+def test_batch_solutions_oracle_judged(api, mixed, block_threads, split):
+    """split: instances with at least this many dofs use the lockstep solver."""
+    insts = _instances(24, seed=11)
+    _say("batch of %d instances, mixed=%s, block %d, lockstep from %d dofs" % (len(insts), mixed, block_threads,
+                                                                                 min(split, 10 ** 9)))
+    b = api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], mixed=mixed, rel_tol=1e-10,
+                  inner_tol=1e-5, block_threads=block_threads, slots=7, lockstep_min_dofs=split, log=_say)
+    x, rep = b.alloc()
+    b.run(x, rep)
+    torch.cuda.synchronize()
+    R = b.reports(rep)
+    xs = x.cpu().numpy()
+    for i, inst in enumerate(insts):
+        assert R[i]["status"] == 0, (i, R[i])
+        assert R[i]["rel_res"] <= 1e-10
+        seg = xs[b.offsets[i]:b.offsets[i + 1]]
+        rr = _oracle_relres(inst, seg)
+        assert rr <= 1.01e-10, (i, inst.k, inst.N, inst.eps, rr)
+    _say("  iters: %s" % list(R["iters"]))
+
+
+def test_batch_matches_single_mesh_solver(api):
+    """The batch solution of an instance equals the single-mesh solver's to solver tolerance."""
+    insts = _instances(3, seed=5)
+    b = api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], mixed=False, rel_tol=1e-12,
+                  lockstep_min_dofs=0)
+    x, rep = b.alloc()
+    b.run(x, rep)
+    torch.cuda.synchronize()
+    for i, inst in enumerate(insts):
+        mesh = api.Mesh.from_arrays(W.structured_mesh(inst.N), inst.k)
+        vals, rhs = api.assemble(mesh, api.instance_problem(inst))
+        s = api.Solver(mesh, restart=2 * inst.N + 64, rel_tol=1e-12)
+        s.setup(vals)
+        xs = torch.zeros_like(rhs)
+        assert s.solve(rhs, xs).converged
+        seg = b.segment(x, i)
+        assert float(torch.linalg.norm(seg - xs) / torch.linalg.norm(xs)) <= 1e-8
+
+
+def test_batch_in_hip_graph_replays(api):
+    """dg_batch_run captured in a HIP graph: every replay (with eager work and
+    synchronisation between replays) reproduces the eager solution bitwise."""
+    insts = _instances(10, seed=3)
+    b = api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], mixed=True, slots=5,
+                  lockstep_min_dofs=ALL_PERSISTENT)
+    x, rep = b.alloc()
+    b.run(x, rep)
+    torch.cuda.synchronize()
+    ref = x.clone()
+    xg, repg = b.alloc()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run(xg, repg, stream=s)
+    for r in range(3):
+        xg.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(xg, ref), r
+        _ = (ref * 2).sum()  # eager work between replays
+        torch.cuda.synchronize()
+    assert (b.reports(repg)["status"] == 0).all()
