@@ -282,6 +282,42 @@ int32_t dg_batch_set_progress(dg_batch* batch, dg_progress_fn fn, void* user);
 int32_t dg_batch_progress(dg_batch* batch, int32_t* started);
 void dg_batch_destroy(dg_batch* batch);
 
+/* ------------------------------------------------------------------------
+ * Learned initial guess: a multilayer perceptron Z_l = H_{l-1} W_l^T + b_l,
+ * H_l = silu(Z_l) (identity on the last layer), trained and evaluated by the
+ * library's own kernels: BF16 weights and activations as product operands,
+ * FP32 accumulation (MFMA), FP32 master weights and Adam moments.
+ * Parameters are one flat FP32 vector: W_1 ([w1][w0] row-major), b_1, W_2,
+ * b_2, ...  All dev_ arrays are FP32 row-major [batch][width].
+ * ------------------------------------------------------------------------ */
+typedef struct dg_mlp dg_mlp;
+/* widths[0..n_widths-1]: input, hidden..., output; init_params: host FP32
+ * flat vector (dg_mlp_num_params values) copied into the model. */
+int32_t dg_mlp_create(const int32_t* widths, int32_t n_widths, int32_t max_batch, const float* init_params,
+                      dg_mlp** out);
+int64_t dg_mlp_num_params(const dg_mlp* mlp);
+/* Y = MLP(X) for B <= max_batch rows; keeps the activations for backward. dev_y may be NULL. */
+int32_t dg_mlp_forward(dg_mlp* mlp, const float* dev_x, int32_t B, float* dev_y, void* stream);
+/* For the last forward batch: loss = mean (Y - T)^2 (device scalar) and dY = dloss/dY. */
+int32_t dg_mlp_loss_mse(dg_mlp* mlp, const float* dev_target, int32_t B, float* dev_dy, float* dev_loss, void* stream);
+/* Gradients of sum(dY * Y) w.r.t. all parameters for the last forward batch (overwritten, not accumulated). */
+int32_t dg_mlp_backward(dg_mlp* mlp, const float* dev_dy, int32_t B, void* stream);
+/* One Adam step (step number t >= 1) with the last gradients. */
+int32_t dg_mlp_adam_step(dg_mlp* mlp, float lr, float beta1, float beta2, float eps, int32_t t, void* stream);
+/* Copies the FP32 parameters and / or gradients (either may be NULL). */
+int32_t dg_mlp_params(dg_mlp* mlp, float* dev_params, float* dev_grads, void* stream);
+void dg_mlp_destroy(dg_mlp* mlp);
+
+/* Initial guesses on `mesh` from values on an nc x nc grid of cells of the
+ * unit square (dev_coarse [B][nc*nc] FP32, cell (i, j) at index j*nc + i):
+ * mode 0 = injection (each element takes its cell's value as a constant),
+ * mode 1 = continuous piecewise-bilinear interpolation of the cell-centre
+ * values with zero on the boundary, taken at the element vertices as a P1
+ * function.  dev_x [B][ldx] FP64 coefficients (modes above P1 set to zero).
+ * Synchronises `stream`. */
+int32_t dg_warmstart_prolong(const dg_mesh* mesh, const float* dev_coarse, int32_t B, int32_t nc, int32_t mode,
+                             double* dev_x, int64_t ldx, void* stream);
+
 const char* dg_status_str(int32_t status);
 
 #ifdef __cplusplus

@@ -83,7 +83,8 @@ EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_
            "dg_mesh_qpoints", "dg_assemble", "dg_solver_create", "dg_solver_setup", "dg_solver_solve",
            "dg_solver_destroy", "dg_residual", "dg_status_str", "dg_solver_profile",
            "dg_batch_create", "dg_batch_offsets", "dg_batch_run", "dg_batch_destroy", "dg_batch_progress",
-           "dg_batch_set_progress"]
+           "dg_batch_set_progress", "dg_mlp_create", "dg_mlp_num_params", "dg_mlp_forward", "dg_mlp_loss_mse",
+           "dg_mlp_backward", "dg_mlp_adam_step", "dg_mlp_params", "dg_mlp_destroy", "dg_warmstart_prolong"]
 
 _lib = None
 
@@ -117,12 +118,24 @@ def lib():
         L.dg_batch_run.argtypes = [P, P, P, P]
         L.dg_batch_progress.argtypes = [P, C.POINTER(I32)]
         L.dg_batch_set_progress.argtypes = [P, PROGRESS_FN, P]
+        L.dg_mlp_create.argtypes = [P, I32, I32, P, C.POINTER(P)]
+        L.dg_mlp_num_params.argtypes = [P]
+        L.dg_mlp_num_params.restype = I64
+        L.dg_mlp_forward.argtypes = [P, P, I32, P, P]
+        L.dg_mlp_loss_mse.argtypes = [P, P, I32, P, P, P]
+        L.dg_mlp_backward.argtypes = [P, P, I32, P]
+        L.dg_mlp_adam_step.argtypes = [P, C.c_float, C.c_float, C.c_float, C.c_float, I32, P]
+        L.dg_mlp_params.argtypes = [P, P, P, P]
+        L.dg_mlp_destroy.argtypes = [P]
+        L.dg_mlp_destroy.restype = None
+        L.dg_warmstart_prolong.argtypes = [P, P, I32, I32, I32, P, I64, P]
         L.dg_batch_destroy.argtypes = [P]
         L.dg_batch_destroy.restype = None
         L.dg_status_str.argtypes = [I32]
         L.dg_status_str.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("dg_mesh_destroy", "dg_solver_destroy", "dg_status_str", "dg_batch_destroy"):
+            if name not in ("dg_mesh_destroy", "dg_solver_destroy", "dg_status_str", "dg_batch_destroy",
+                            "dg_mlp_destroy", "dg_mlp_num_params"):
                 getattr(L, name).restype = I32
         _lib = L
     return _lib
@@ -477,3 +490,67 @@ def instance_problem(inst, method=SIPG):
     bx, by = inst.b
     return Problem(method, inst.k, sigma, eps=inst.eps, bx=bx, by=by, alpha=inst.alpha,
                    f=Field.gauss_sum([tuple(t) for t in inst.gauss]), gD=0.0)
+
+
+class MLP:
+    """dg_mlp_*: the perceptron of the learned initial guess (BF16 products,
+    FP32 accumulation and master weights, Adam)."""
+
+    def __init__(self, widths, max_batch, init_params):
+        L = lib()
+        self.widths = [int(w) for w in widths]
+        self.max_batch = int(max_batch)
+        p0 = np.ascontiguousarray(init_params, dtype=np.float32)
+        w = np.asarray(self.widths, dtype=np.int32)
+        h = C.c_void_p()
+        _check(L.dg_mlp_create(w.ctypes.data, len(w), self.max_batch, p0.ctypes.data, C.byref(h)), "dg_mlp_create")
+        self._h = h
+        self.n_params = int(L.dg_mlp_num_params(h))
+        assert self.n_params == p0.size, "init_params has the wrong length"
+        self._loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        self.t = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dg_mlp_destroy(h)
+            self._h = None
+
+    def forward(self, x: torch.Tensor, y: torch.Tensor = None, stream=None):
+        x = x.contiguous().float()
+        B = x.shape[0]
+        if y is None:
+            y = torch.empty(B, self.widths[-1], dtype=torch.float32, device="cuda")
+        _check(lib().dg_mlp_forward(self._h, _dptr(x), B, _dptr(y), _stream(stream)), "dg_mlp_forward")
+        return y
+
+    def loss_mse(self, target: torch.Tensor, stream=None):
+        target = target.contiguous().float()
+        dy = torch.empty_like(target)
+        _check(lib().dg_mlp_loss_mse(self._h, _dptr(target), target.shape[0], _dptr(dy), _dptr(self._loss),
+                                     _stream(stream)), "dg_mlp_loss_mse")
+        return self._loss, dy
+
+    def backward(self, dy: torch.Tensor, stream=None):
+        dy = dy.contiguous().float()
+        _check(lib().dg_mlp_backward(self._h, _dptr(dy), dy.shape[0], _stream(stream)), "dg_mlp_backward")
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.t += 1
+        _check(lib().dg_mlp_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), self.t,
+                                      _stream(stream)), "dg_mlp_adam_step")
+
+    def params(self, stream=None):
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().dg_mlp_params(self._h, _dptr(p), _dptr(g), _stream(stream)), "dg_mlp_params")
+        return p, g
+
+
+def warmstart_prolong(mesh: Mesh, coarse: torch.Tensor, nc: int, mode: int, x: torch.Tensor, stream=None):
+    """dg_warmstart_prolong: coarse [B, nc*nc] FP32 -> x [B, ldx] FP64 (mode 0 injection, 1 bilinear P1)."""
+    coarse = coarse.contiguous().float()
+    assert x.dtype == torch.float64 and x.dim() == 2 and x.is_contiguous()
+    _check(lib().dg_warmstart_prolong(mesh._h, _dptr(coarse), coarse.shape[0], int(nc), int(mode), _dptr(x),
+                                      x.shape[1], _stream(stream)), "dg_warmstart_prolong")
+    return x

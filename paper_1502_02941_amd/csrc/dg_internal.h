@@ -79,6 +79,7 @@ struct dg_mesh {
     int32_t* d_bnd_loc = nullptr;
     double* d_tab64 = nullptr;
     float* d_tab32 = nullptr;
+    double* d_p1map = nullptr;  // [3][3]: P1 coefficients from vertex values (k >= 1)
 };
 
 namespace dg {

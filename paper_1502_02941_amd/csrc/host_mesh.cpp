@@ -173,7 +173,7 @@ static void free_device(dg_mesh* m)
 {
     hipFree(m->d_xy); hipFree(m->d_nbr); hipFree(m->d_nbr_edge); hipFree(m->d_row_ptr);
     hipFree(m->d_col_idx); hipFree(m->d_bnd_type); hipFree(m->d_bnd_el); hipFree(m->d_bnd_loc);
-    hipFree(m->d_tab64); hipFree(m->d_tab32);
+    hipFree(m->d_tab64); hipFree(m->d_tab32); hipFree(m->d_p1map);
 }
 
 template <typename T>
@@ -355,6 +355,18 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
     if (st == DG_OK) st = upload(&m->d_bnd_loc, m->bnd_loc);
     if (st == DG_OK) st = upload(&m->d_tab64, m->tab64);
     if (st == DG_OK) st = upload(&m->d_tab32, tab32);
+    if (st == DG_OK) {
+        // P[m][v] = int_ref lambda_v phi_m: coefficients of the linear function with vertex values u_v
+        const TabLayout L(degree);
+        std::vector<double> P(9, 0.0);
+        for (int g = 0; g < L.nq && degree >= 1; ++g) {
+            const double xi = m->tab64[L.vxi + g], eta = m->tab64[L.veta + g], w = m->tab64[L.vw + g];
+            const double lam[3] = {1.0 - xi - eta, xi, eta};
+            for (int mm = 0; mm < 3; ++mm)
+                for (int v = 0; v < 3; ++v) P[mm * 3 + v] += w * lam[v] * m->tab64[L.vphi + g * L.n + mm];
+        }
+        st = upload(&m->d_p1map, P);
+    }
     if (st != DG_OK) { free_device(m); delete m; return st; }
     *out = m;
     return DG_OK;

@@ -283,3 +283,24 @@ def sample_instances(count: int, seed: int = 0, k_choices=(1, 2), n_range=(16, 1
         a = rng.standard_normal(size=(4, 1))
         out.append(Instance(k, N, eps, theta, bnorm, alpha, np.concatenate([c, w, a], axis=1)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Learned initial guess: seeded initial weights of the multilayer perceptron.
+# ----------------------------------------------------------------------------
+def mlp_widths():
+    """23 instance parameters -> 3 hidden layers of 256 -> 32 x 32 coarse values."""
+    return [23, 256, 256, 256, 1024]
+
+
+def mlp_init(widths, seed=0):
+    """Flat FP32 parameter vector W_1, b_1, W_2, b_2, ...: weights ~ N(0, 1/fan_in)
+    (the last layer scaled by 0.1), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(len(widths) - 1):
+        fan_in, fan_out = widths[l], widths[l + 1]
+        scale = (1.0 if l < len(widths) - 2 else 0.1) / math.sqrt(fan_in)
+        parts.append((rng.standard_normal((fan_out, fan_in)) * scale).ravel())
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
