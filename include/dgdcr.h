@@ -174,6 +174,9 @@ typedef struct {
     int32_t reorth_passes; /* second Gram-Schmidt passes taken */
     double rel_res;       /* true FP64 relative residual of the returned x */
     double rel_res0;      /* true FP64 relative residual of the initial guess */
+    int32_t guess_rejected; /* 1: the initial guess had ||F - A x0|| > (1 + 1e-8) ||F|| (or a
+                               non-finite residual) and was replaced by the zero guess */
+    int32_t reserved;
 } dg_solve_report;
 
 /* Allocates the Krylov workspace for `mesh` (device memory, owned by the
@@ -186,7 +189,9 @@ int32_t dg_solver_create(const dg_mesh* mesh, const dg_solver_opts* opts, dg_sol
  * unchanged until the last dg_solver_solve) for the true residual. */
 int32_t dg_solver_setup(dg_solver* solver, const double* dev_vals64, void* stream);
 /* Solves A x = F.  dev_x holds the initial guess on entry (zero for the plain
- * method) and the solution on exit.  Synchronises `stream` before returning
+ * method) and the solution on exit.  The true FP64 residual judges the guess:
+ * one whose residual norm exceeds (1 + 1e-8) ||F|| (or is not finite) is
+ * replaced by the zero guess before the first cycle (report->guess_rejected = 1).  Synchronises `stream` before returning
  * so that `report` is filled.  DG_NOT_CONVERGED if max_iters was reached;
  * DG_ERR_NONFINITE if a residual norm became NaN / Inf. */
 int32_t dg_solver_solve(dg_solver* solver, const double* dev_rhs, double* dev_x, dg_solve_report* report,

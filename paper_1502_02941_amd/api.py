@@ -57,7 +57,8 @@ class _KStats(C.Structure):
 
 class _Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32), ("reorth_passes", C.c_int32),
-                ("rel_res", C.c_double), ("rel_res0", C.c_double)]
+                ("rel_res", C.c_double), ("rel_res0", C.c_double), ("guess_rejected", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class _Instance(C.Structure):
@@ -77,7 +78,8 @@ PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32)
 
 
 REPORT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32), ("reorth", np.int32),
-                         ("rel_res", np.float64), ("rel_res0", np.float64)])
+                         ("rel_res", np.float64), ("rel_res0", np.float64), ("guess_rejected", np.int32),
+                         ("reserved", np.int32)])
 
 EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_destroy", "dg_mesh_structure",
            "dg_mesh_qpoints", "dg_assemble", "dg_solver_create", "dg_solver_setup", "dg_solver_solve",
@@ -329,6 +331,7 @@ class Report:
     rel_res: float
     rel_res0: float
     reorth_passes: int = 0
+    guess_rejected: int = 0
 
     @property
     def converged(self):
@@ -371,7 +374,7 @@ class Solver:
         r = _Report()
         st = lib().dg_solver_solve(self._h, _dptr(rhs), _dptr(x), C.byref(r), _stream(stream))
         _check(st, "dg_solver_solve")
-        return Report(r.status, r.iters, r.cycles, r.rel_res, r.rel_res0, r.reorth_passes)
+        return Report(r.status, r.iters, r.cycles, r.rel_res, r.rel_res0, r.reorth_passes, r.guess_rejected)
 
 
 def bsr_to_scipy(mesh: Mesh, vals: torch.Tensor, row_ptr=None, col_idx=None):

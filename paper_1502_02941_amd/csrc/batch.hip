@@ -279,7 +279,15 @@ __device__ void run_instance(const BatchArgs& A, const BatchInst& I, const int i
         }
         const double beta = sqrt(wg_sum<BT>(acc, sm));
         const double rel = beta / bnorm;
-        if (rep.cycles == 0) rep.rel_res0 = rel;
+        if (rep.cycles == 0 && !rep.guess_rejected && !(rel <= GUESS_LIMIT)) {
+            // the guess is worse than zero: restart from x = 0
+            for (int64_t t = tid; t < n; t += BT) x[t] = 0.0;
+            rep.guess_rejected = 1;
+            rep.rel_res0 = rel;
+            __syncthreads();
+            continue;
+        }
+        if (rep.cycles == 0 && !rep.guess_rejected) rep.rel_res0 = rel;
         rep.rel_res = rel;
         rep.iters = its;
         if (!isfinite(rel)) { rep.status = DG_ERR_NONFINITE; break; }

@@ -787,6 +787,8 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
     rep->iters = 0;
     rep->cycles = 0;
     rep->rel_res0 = 0.0;
+    rep->guess_rejected = 0;
+    rep->reserved = 0;
     if (bnorm == 0.0) {
         DG_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * s->n, st));
         DG_HIP_CHECK(hipStreamSynchronize(st));
@@ -818,7 +820,14 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
         if (s->o.profile) prof_flush(s, rep->cycles > 0 ? hc[C_J] : 0, s->o.reorth ? hflags.data() : nullptr);
         if (rep->cycles > 0) its += hc[C_J];
         const double rel = std::sqrt(hs[S_RNORM2]) / bnorm;
-        if (rep->cycles == 0) rep->rel_res0 = rel;
+        if (rep->cycles == 0 && !rep->guess_rejected && !(rel <= GUESS_LIMIT)) {
+            // the guess is worse than zero: restart from x = 0
+            DG_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * s->n, st));
+            rep->guess_rejected = 1;
+            rep->rel_res0 = rel;
+            continue;
+        }
+        if (rep->cycles == 0 && !rep->guess_rejected) rep->rel_res0 = rel;
         rep->rel_res = rel;
         rep->iters = its;
         rep->reorth_passes = hc[C_NREORTH];

@@ -272,12 +272,32 @@ __global__ __launch_bounds__(LS_BT) void ls_check_kernel(const LsArgs A, int fir
     double a = 0.0;
     for (int c = threadIdx.x; c < I.neblk; c += LS_BT) a += A.red2[I.red2_off + c];
     a = ls_block_sum(a, sh);
+    // the true residual judges the initial guess: one worse than zero is
+    // replaced by x = 0, for which r = F
+    __shared__ int reject;
+    if (threadIdx.x == 0)
+        reject = first && S.bnorm > 0.0 && isfinite(S.bnorm) && !(sqrt(a) <= GUESS_LIMIT * S.bnorm);
+    __syncthreads();
+    if (reject) {
+        double* x = A.x + I.x_off;
+        double* r = A.r + I.x_off;
+        const double* f = A.rhs + I.x_off;
+        for (int64_t t = threadIdx.x; t < I.n; t += LS_BT) {
+            x[t] = 0.0;
+            r[t] = f[t];
+        }
+    }
     if (threadIdx.x != 0) return;
     dg_solve_report& R = A.reports[I.id];
     if (!first) { S.its += S.J; S.cycles += 1; }
-    const double beta = sqrt(a);
+    double beta = sqrt(a);
+    if (first) {
+        R.guess_rejected = reject;
+        R.reserved = 0;
+        R.rel_res0 = S.bnorm > 0.0 ? beta / S.bnorm : 0.0;
+        if (reject) beta = S.bnorm;
+    }
     const double rel = S.bnorm > 0.0 ? beta / S.bnorm : 0.0;
-    if (first) R.rel_res0 = rel;
     R.rel_res = rel;
     R.iters = S.its;
     R.cycles = S.cycles;

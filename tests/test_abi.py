@@ -84,3 +84,37 @@ def test_batch_rejects_bad_instances_on_host():
     with pytest.raises(api.DGError) as e:
         api.Batch([(bad_mesh, ok)])
     assert e.value.status == -2
+
+
+STRUCTS = {"dg_field": "_Field", "dg_problem": "_Problem", "dg_mesh_info": "_MeshInfo",
+           "dg_solver_opts": "_SolverOpts", "dg_kernel_stats": "_KStats", "dg_solve_report": "_Report",
+           "dg_instance": "_Instance", "dg_batch_opts": "_BatchOpts"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets a C compiler gives the header."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dgdcr.h"', "int main(void) {"]
+    for cname, pname in STRUCTS.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in getattr(api, pname)._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, pname in STRUCTS.items():
+        cls = getattr(api, pname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+    assert api.REPORT_DTYPE.itemsize == ctypes.sizeof(api._Report)
+    for fname, (_, off) in api.REPORT_DTYPE.fields.items():
+        assert off == getattr(api._Report, {"reorth": "reorth_passes"}.get(fname, fname)).offset

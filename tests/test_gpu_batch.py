@@ -109,3 +109,43 @@ def test_batch_in_hip_graph_replays(api):
         _ = (ref * 2).sum()  # eager work between replays
         torch.cuda.synchronize()
     assert (b.reports(repg)["status"] == 0).all()
+
+
+@pytest.mark.parametrize("split", [ALL_PERSISTENT, 0])
+def test_batch_rejects_guesses_worse_than_zero(api, split):
+    """Per instance, a guess whose true residual exceeds ||F|| is replaced by
+    zero (same iterations and solution as the zero-guess run); a good guess is
+    kept and saves iterations."""
+    insts = _instances(6, seed=21)
+    _say("guess fallback, lockstep from %d dofs" % min(split, 10 ** 9))
+    b = api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], mixed=True, rel_tol=1e-10,
+                  slots=3, lockstep_min_dofs=split)
+    x0, rep0 = b.alloc()
+    b.run(x0, rep0)
+    torch.cuda.synchronize()
+    R0 = b.reports(rep0)
+    assert (R0["status"] == 0).all() and (R0["guess_rejected"] == 0).all()
+    g = torch.Generator(device="cpu").manual_seed(4)
+    x = 1e4 * torch.randn(b.n_dofs, generator=g, dtype=torch.float64).cuda()
+    for i in (1, 4):  # good guesses for two instances: the converged solution, slightly perturbed
+        b.segment(x, i).copy_(b.segment(x0, i) * (1 + 1e-7))
+    x_in = x.clone()
+    rep = torch.zeros_like(rep0)
+    b.run(x, rep)
+    torch.cuda.synchronize()
+    R = b.reports(rep)
+    for i in range(len(insts)):
+        assert R[i]["status"] == 0, (i, R[i])
+        if i in (1, 4):
+            assert R[i]["guess_rejected"] == 0 and R[i]["iters"] < R0[i]["iters"]
+            assert R[i]["rel_res0"] < 1e-6
+        else:
+            assert R[i]["guess_rejected"] == 1 and R[i]["rel_res0"] > 1.0
+            if split == ALL_PERSISTENT:  # the restart from zero is the zero-guess run exactly
+                assert R[i]["iters"] == R0[i]["iters"]
+                assert torch.equal(b.segment(x, i), b.segment(x0, i))
+            else:  # the lockstep restart takes beta = ||F||, equal to ||F - A 0|| up to rounding
+                assert abs(int(R[i]["iters"]) - int(R0[i]["iters"])) <= 1
+                d = (b.segment(x, i) - b.segment(x0, i)).norm() / b.segment(x0, i).norm()
+                assert float(d) <= 1e-6
+    assert not torch.equal(x, x_in)

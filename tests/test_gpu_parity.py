@@ -216,3 +216,28 @@ def test_c3_full_size_assembly_sampled(api):
     e32 = float(torch.linalg.norm(v32.double() - vals) / torch.linalg.norm(vals))
     _say("  C3 FP32 vs FP64 assembly rel err %.3e" % e32)
     assert e32 <= 2e-6
+
+
+def test_solver_rejects_a_guess_worse_than_zero(api):
+    """The true FP64 residual judges the initial guess: a guess with
+    ||F - A x0|| > ||F|| (or non-finite) is replaced by x0 = 0, giving the
+    zero-guess run exactly; a good guess is kept."""
+    case = SMALL[0]
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    s = api.Solver(mesh, restart=50, max_iters=5000, rel_tol=1e-12)
+    s.setup(vals)
+    x0 = torch.zeros_like(rhs)
+    rep0 = s.solve(rhs, x0)
+    assert rep0.converged and rep0.guess_rejected == 0 and abs(rep0.rel_res0 - 1.0) <= 1e-14
+    g = torch.Generator(device="cpu").manual_seed(3)
+    for bad in (1e3 * torch.randn(rhs.numel(), generator=g, dtype=torch.float64).cuda(),
+                torch.full_like(rhs, float("nan"))):
+        x = bad.clone()
+        rep = s.solve(rhs, x)
+        assert rep.guess_rejected == 1 and rep.converged
+        assert not (rep.rel_res0 <= 1.0)
+        assert rep.iters == rep0.iters
+        assert torch.equal(x, x0)
+    good = x0 * (1 + 1e-6)
+    rep = s.solve(rhs, good)
+    assert rep.guess_rejected == 0 and rep.rel_res0 < 1e-5 and rep.iters < rep0.iters
