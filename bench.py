@@ -17,8 +17,11 @@ Other workloads (not the default line):
      log10 eps ~ U[-6,-1], b angle ~ U[0, 2 pi], |b| ~ U[0.5, 2], alpha ~ U[0, 1], f = sum of 4
      Gaussians, g^D = 0, SIPG; one element-parallel assembly launch + one persistent solve
      launch per batch, launch shape picked by the autotuner; step = the whole batch.
+  --workload c5: 512 held-out instances (seed 2) of the 64 x 64 P1 SIPG family (parameters as c4),
+     zero guess vs the learned initial guess (perceptron + prolongation, model trained on 20000
+     method solves of seed 1), FP64 and mixed cycles; step = the whole batch incl. the network.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c2|c4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c2|c4|c5]
        python bench.py --profile-run     (one FP64 step + a copy probe, for rocprofv3)
 """
 from __future__ import annotations
@@ -72,8 +75,8 @@ def main():
     ap.add_argument("--restart", type=int, default=2 * N_GRID + 64)
     ap.add_argument("--reorth", type=int, default=0, help="1: conditional second Gram-Schmidt pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c4"))
-    ap.add_argument("--count", type=int, default=4096, help="c4: number of instances")
+    ap.add_argument("--workload", default="c2", choices=("c2", "c4", "c5"))
+    ap.add_argument("--count", type=int, default=None, help="c4 / c5: number of instances (4096 / 512)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one FP64 step and a 512 MiB device copy (counter scaling), no JSON baseline")
     args = ap.parse_args()
@@ -93,6 +96,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c4":
         return bench_c4(args, api, W, torch)
+    if args.workload == "c5":
+        return bench_c5(args, api, W, torch)
     log("building workload %dx%d P%d" % (N_GRID, N_GRID, DEGREE))
     m, mesh, P, prob = build_workload(api, W, torch)
     vals64, rhs64 = mesh.alloc_system(api.F64)
@@ -224,7 +229,7 @@ def main():
 def bench_c4(args, api, W, torch):
     import numpy as np
     from paper_1502_02941_amd import autotune
-    insts = W.sample_instances(args.count, seed=0)
+    insts = W.sample_instances(args.count or 4096, seed=0)
     meshes = {}
     pairs = []
     for i in insts:
@@ -309,6 +314,59 @@ def bench_c4(args, api, W, torch):
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c4(insts),
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_c5(args, api, W, torch):
+    import numpy as np
+    from paper_1502_02941_amd import learned as L
+    model = L.load(os.path.join(ROOT, "paper_1502_02941_amd", "data", "c5_mlp.npz"))
+    count = args.count or 512
+    out = L.evaluate(model, count=count, seed=2, reps=max(args.steps, 1), log=log)
+    forms = {k: {kk: vv for kk, vv in v.items() if kk != "iters"} for k, v in out.items()
+             if isinstance(v, dict) and "seconds" in v}
+    F = forms["mixed+learned"]
+    line = {
+        "metric": "DG assembly Melem/s; solves/s at rel-res 1e-10, learned+mixed vs plain FP64",
+        "value": F["solves_per_s"], "unit": "solves/s (batched: network + prolongation + assemble + solve "
+                                            "to rel-res 1e-10)",
+        "n_gpus": 1, "steps": max(args.steps, 1), "warmup": 1, "ms_per_step": F["seconds"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 network; f32 cycles + f64 refinement",
+        "data": "synthetic (seeded instance sampler: training seed 1, held-out seed 2)",
+        "config": {"workload": "learned warm start: %d held-out instances, 64x64 P1 SIPG (8192 triangles, 24576 "
+                               "dofs each), Gaussian-sum f" % count,
+                   "form": "mixed+learned", "plain_fp64_solves_per_s": forms["fp64"]["solves_per_s"],
+                   "speedup_vs_plain_fp64": F["solves_per_s"] / forms["fp64"]["solves_per_s"]},
+        "forms": forms, "by_log10_eps": out["by_log10_eps"],
+        "coarse_rel_err_median": out["coarse_rel_err_median"], "coarse_rel_err_p90": out["coarse_rel_err_p90"],
+        "guess_ms": out["guess_ms"],
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c5(count),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_c5(count, sample=8):
+    """The CPU oracle (single thread, FP64, zero guess, restart 2N + 64) on the
+    first `sample` held-out instances; solves/s of the oracle itself."""
+    import oracle as O
+    from paper_1502_02941_amd import learned as L
+    insts = L.instances(count, seed=2)[:sample]
+    from paper_1502_02941_amd import workloads as W
+    ma = W.structured_mesh(L.FINE)
+    t0 = time.perf_counter()
+    m = O.Mesh(ma.nodes, ma.elems, ma.dirichlet, ma.neumann)
+    ok = 0
+    for inst in insts:
+        sigma, kappa = O.default_penalty(O.SIPG, 1)
+        B = O.assemble(m, 1, sigma=sigma, kappa=kappa, eps=inst.eps, bx=inst.b[0], by=inst.b[1], alpha=inst.alpha,
+                       f=O.Field.gauss_sum([tuple(t) for t in inst.gauss]), gD=0.0)
+        _, its, rel, conv = O.gmres(B, restart=2 * L.FINE + 64, tol=1e-10, max_iters=20000)
+        ok += conv
+    dt = time.perf_counter() - t0
+    return {"value": len(insts) / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d held-out instances (assemble + GMRES from zero), %.1f s, %d converged"
+                      % (len(insts), dt, ok)}
 
 
 def cpu_baseline_c4(insts, sample=12):

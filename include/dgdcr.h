@@ -165,6 +165,9 @@ typedef struct {
     double inner_tol;     /* mixed only: per-cycle relative reduction target (e.g. 1e-5) */
     int32_t reorth;       /* 1: second classical Gram-Schmidt pass when the first loses > 1/sqrt(2) of the norm */
     int32_t profile;      /* 1: time the heavy kernels with HIP events on the solve stream (dg_solver_profile) */
+    double guess_limit;   /* the initial guess is replaced by zero when ||F - A x0|| > guess_limit ||F||
+                             or is not finite; <= 0 selects 1 + 1e-8 (no worse than the zero guess;
+                             the margin absorbs the rounding of the two norms); +inf keeps any finite guess */
 } dg_solver_opts;
 
 typedef struct {
@@ -174,8 +177,8 @@ typedef struct {
     int32_t reorth_passes; /* second Gram-Schmidt passes taken */
     double rel_res;       /* true FP64 relative residual of the returned x */
     double rel_res0;      /* true FP64 relative residual of the initial guess */
-    int32_t guess_rejected; /* 1: the initial guess had ||F - A x0|| > (1 + 1e-8) ||F|| (or a
-                               non-finite residual) and was replaced by the zero guess */
+    int32_t guess_rejected; /* 1: the initial guess failed the guess_limit test of the options
+                               and was replaced by the zero guess */
     int32_t reserved;
 } dg_solve_report;
 
@@ -190,8 +193,8 @@ int32_t dg_solver_create(const dg_mesh* mesh, const dg_solver_opts* opts, dg_sol
 int32_t dg_solver_setup(dg_solver* solver, const double* dev_vals64, void* stream);
 /* Solves A x = F.  dev_x holds the initial guess on entry (zero for the plain
  * method) and the solution on exit.  The true FP64 residual judges the guess:
- * one whose residual norm exceeds (1 + 1e-8) ||F|| (or is not finite) is
- * replaced by the zero guess before the first cycle (report->guess_rejected = 1).  Synchronises `stream` before returning
+ * one whose residual norm exceeds opts.guess_limit ||F|| (or is not finite)
+ * is replaced by the zero guess before the first cycle (report->guess_rejected = 1).  Synchronises `stream` before returning
  * so that `report` is filled.  DG_NOT_CONVERGED if max_iters was reached;
  * DG_ERR_NONFINITE if a residual norm became NaN / Inf. */
 int32_t dg_solver_solve(dg_solver* solver, const double* dev_rhs, double* dev_x, dg_solve_report* report,
@@ -259,6 +262,7 @@ typedef struct {
     int32_t slots;            /* persistent solve: workgroups = workspace slots (0 = number of compute units) */
     int64_t lockstep_min_dofs; /* instances with at least this many unknowns use the lockstep solver */
     double lockstep_mem_gb;   /* lockstep workspace budget per chunk of instances (<= 0: 64 GB) */
+    double guess_limit;       /* per instance, as dg_solver_opts.guess_limit */
 } dg_batch_opts;
 
 typedef struct dg_batch dg_batch;

@@ -65,7 +65,7 @@ struct BatchArgs {
     const double* rhs;  // concatenated load vectors
     int* queue;
     dg_solve_report* reports;
-    double rel_tol, inner_tol;
+    double rel_tol, inner_tol, guess_limit;
     int32_t max_iters, mixed;
 };
 
@@ -279,7 +279,7 @@ __device__ void run_instance(const BatchArgs& A, const BatchInst& I, const int i
         }
         const double beta = sqrt(wg_sum<BT>(acc, sm));
         const double rel = beta / bnorm;
-        if (rep.cycles == 0 && !rep.guess_rejected && !(rel <= GUESS_LIMIT)) {
+        if (rep.cycles == 0 && !rep.guess_rejected && !(rel <= A.guess_limit)) {
             // the guess is worse than zero: restart from x = 0
             for (int64_t t = tid; t < n; t += BT) x[t] = 0.0;
             rep.guess_rejected = 1;
@@ -848,6 +848,7 @@ extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev
     A.queue = b->d_queue;
     A.reports = dev_reports;
     A.rel_tol = b->o.rel_tol;
+    A.guess_limit = guess_limit_of(b->o.guess_limit);
     A.inner_tol = b->o.inner_tol;
     A.max_iters = b->o.max_iters;
     A.mixed = b->o.mixed;
@@ -896,6 +897,7 @@ extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev
         L.reports = dev_reports;
         L.counters = b->ls_counters;
         L.rel_tol = b->o.rel_tol;
+        L.guess_limit = guess_limit_of(b->o.guess_limit);
         L.inner_tol = b->o.inner_tol;
         L.max_iters = b->o.max_iters;
         L.mixed = b->o.mixed;

@@ -1,11 +1,12 @@
 // Internal definitions of the gfx950 DG library (not part of the public ABI).
 #pragma once
 
-// An initial guess is replaced by zero when ||F - A x0|| > GUESS_LIMIT ||F||
-// (or is not finite).  The margin above 1 absorbs the rounding of the two
-// norms, which are summed in different orders, so the zero guess is never
-// flagged.
-constexpr double GUESS_LIMIT = 1.0 + 1e-8;
+// An initial guess is replaced by zero when ||F - A x0|| > limit ||F|| (or is
+// not finite).  Default limit: no worse than zero, with a margin above 1 that
+// absorbs the rounding of the two norms (summed in different orders), so the
+// zero guess itself is never flagged.
+constexpr double GUESS_LIMIT_DEFAULT = 1.0 + 1e-8;
+inline double guess_limit_of(double requested) { return requested > 0.0 ? requested : GUESS_LIMIT_DEFAULT; }
 
 #include <hip/hip_runtime.h>
 

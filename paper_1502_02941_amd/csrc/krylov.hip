@@ -669,6 +669,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     if (!s) return DG_ERR_OOM;
     s->m = m;
     s->o = *o;
+    s->o.guess_limit = guess_limit_of(o->guess_limit);
     s->N = m->n;
     s->T = m->T;
     s->n = m->T * m->n;
@@ -820,7 +821,7 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
         if (s->o.profile) prof_flush(s, rep->cycles > 0 ? hc[C_J] : 0, s->o.reorth ? hflags.data() : nullptr);
         if (rep->cycles > 0) its += hc[C_J];
         const double rel = std::sqrt(hs[S_RNORM2]) / bnorm;
-        if (rep->cycles == 0 && !rep->guess_rejected && !(rel <= GUESS_LIMIT)) {
+        if (rep->cycles == 0 && !rep->guess_rejected && !(rel <= s->o.guess_limit)) {
             // the guess is worse than zero: restart from x = 0
             DG_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * s->n, st));
             rep->guess_rejected = 1;

@@ -52,7 +52,7 @@ struct LsArgs {
     double* y;
     dg_solve_report* reports;
     int* counters;
-    double rel_tol, inner_tol;
+    double rel_tol, inner_tol, guess_limit;
     int32_t max_iters, mixed;
 };
 

@@ -276,7 +276,7 @@ __global__ __launch_bounds__(LS_BT) void ls_check_kernel(const LsArgs A, int fir
     // replaced by x = 0, for which r = F
     __shared__ int reject;
     if (threadIdx.x == 0)
-        reject = first && S.bnorm > 0.0 && isfinite(S.bnorm) && !(sqrt(a) <= GUESS_LIMIT * S.bnorm);
+        reject = first && S.bnorm > 0.0 && isfinite(S.bnorm) && !(sqrt(a) <= A.guess_limit * S.bnorm);
     __syncthreads();
     if (reject) {
         double* x = A.x + I.x_off;
