@@ -189,31 +189,19 @@ __device__ __forceinline__ void assemble_element(const AsmArgs& a, const int64_t
     }
 }
 
-// Load vector F_j = l_h(phi_j) of element K (section 1 eq. (ds)): the volume
-// term f phi_j, and on boundary edges g^D ((sigma_D eps/|e|^b0 + max(-beta,0))
-// phi_j + kappa eps grad phi_j . n) (Dirichlet) or g^N phi_j (Neumann).
-// Lane per (element, j); kept apart from the matrix kernel so that the general
-// data fields (Gaussian sums, point values) do not raise its register count.
+// Boundary-edge part of the load vector entry F_j of element K (section 1
+// eq. (ds)): on Dirichlet edges g^D ((sigma_D eps/|e|^b0 + max(-beta,0))
+// phi_j + kappa eps grad phi_j . n), on Neumann edges g^N phi_j.  p: the
+// element's vertex coordinates, G = J^{-T}.
 template <int K, typename R>
-__device__ __forceinline__ void load_vector_element(const AsmArgs& a, const int64_t el, const int j, R* __restrict__ rhs_out)
+__device__ __forceinline__ R load_vector_boundary(const AsmArgs& a, const int64_t el, const int j, const double* p,
+                                                  R G11, R G12, R G21, R G22)
 {
     constexpr TabLayout L(K);
-    constexpr int N = L.n, NQ = L.nq, NQE = L.nqe;
+    constexpr int N = L.n, NQE = L.nqe;
     const R* __restrict__ tab = (const R*)a.tab;
-
-    const double* p = a.xy + 6 * el;
-    const double dj11 = p[2] - p[0], dj12 = p[4] - p[0], dj21 = p[3] - p[1], dj22 = p[5] - p[1];
-    const double ddet = dj11 * dj22 - dj12 * dj21;
-    const R det = (R)ddet, x1 = (R)p[0], y1 = (R)p[1], j11 = (R)dj11, j12 = (R)dj12, j21 = (R)dj21, j22 = (R)dj22;
-    R rhs = R(0);
-#pragma unroll 1
-    for (int g = 0; g < NQ; ++g) {
-        const R xi = tab[L.vxi + g], eta = tab[L.veta + g];
-        const R x = x1 + j11 * xi + j12 * eta, y = y1 + j21 * xi + j22 * eta;
-        rhs += tab[L.vw + g] * det * field_at<R>(a.f, x, y, el * NQ + g) * tab[L.vphi + g * N + j];
-    }
-    const R G11 = (R)(dj22 / ddet), G12 = (R)(-dj21 / ddet), G21 = (R)(-dj12 / ddet), G22 = (R)(dj11 / ddet);
     const R kappa = (R)a.kappa;
+    R rhs = R(0);
 #pragma unroll 1
     for (int l = 0; l < 3; ++l) {
         const int32_t nb = a.nbr[3 * el + l];
@@ -246,6 +234,54 @@ __device__ __forceinline__ void load_vector_element(const AsmArgs& a, const int6
             }
         }
     }
+    return rhs;
+}
+
+// Volume part sum_g w_g f(x_g) phi_j(x_g) on the reference triangle (times
+// det J by the caller) for f given as a function (not point values).  w, xi,
+// eta: [NQ] weights and reference coordinates; phi: [NQ][N] basis values.
+template <int K, typename R>
+__device__ __forceinline__ R load_vector_volume_field(const AsmArgs& a, const int j, R x1, R y1, R j11, R j12, R j21,
+                                                      R j22, const R* w, const R* xi, const R* eta, const R* phi)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NQ = L.nq;
+    R s = R(0);
+#pragma unroll 4
+    for (int g = 0; g < NQ; ++g) {
+        const R x = x1 + j11 * xi[g] + j12 * eta[g], y = y1 + j21 * xi[g] + j22 * eta[g];
+        s += w[g] * field_at<R>(a.f, x, y, 0) * phi[g * N + j];
+    }
+    return s;
+}
+
+// Load vector F_j = l_h(phi_j) of element K (section 1 eq. (ds)): the volume
+// term f phi_j plus the boundary-edge terms.  Lane per (element, j); kept apart
+// from the point-quadrature matrix kernel so that the general data fields
+// (Gaussian sums, point values) do not raise its register count.
+template <int K, typename R>
+__device__ __forceinline__ void load_vector_element(const AsmArgs& a, const int64_t el, const int j, R* __restrict__ rhs_out)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NQ = L.nq;
+    const R* __restrict__ tab = (const R*)a.tab;
+
+    const double* p = a.xy + 6 * el;
+    const double dj11 = p[2] - p[0], dj12 = p[4] - p[0], dj21 = p[3] - p[1], dj22 = p[5] - p[1];
+    const double ddet = dj11 * dj22 - dj12 * dj21;
+    R rhs;
+    if (a.f.kind == DG_QPOINTS) {  // all point values in flight at once
+        const double* fv = a.f.vals + el * NQ;
+        rhs = R(0);
+#pragma unroll
+        for (int g = 0; g < NQ; ++g) rhs += tab[L.vw + g] * (R)fv[g] * tab[L.vphi + g * N + j];
+    } else {
+        rhs = load_vector_volume_field<K, R>(a, j, (R)p[0], (R)p[1], (R)dj11, (R)dj12, (R)dj21, (R)dj22, tab + L.vw,
+                                             tab + L.vxi, tab + L.veta, tab + L.vphi);
+    }
+    rhs *= (R)ddet;
+    const R G11 = (R)(dj22 / ddet), G12 = (R)(-dj21 / ddet), G21 = (R)(-dj12 / ddet), G22 = (R)(dj11 / ddet);
+    rhs += load_vector_boundary<K, R>(a, el, j, p, G11, G12, G21, G22);
     rhs_out[el * N + j] = rhs;
 }
 

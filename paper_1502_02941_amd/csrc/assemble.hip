@@ -1,7 +1,9 @@
 // Single-mesh assembly kernels (see asm_device.h for the terms computed).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "asm_device.h"
 
@@ -21,16 +23,277 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmArgs a)
     assemble_element<K, R>(a, el, j, (R*)a.vals);
 }
 
-template <int K, typename R>
-__global__ __launch_bounds__(256) void load_vector_kernel(const AsmArgs a)
+
+// Load vector, volume term: F_j = det J sum_g w_g f(x_g) phi_j(x_g).  Lane per
+// (element, j); the block's f point values (contiguous in memory) are staged
+// in LDS by coalesced loads and the reference weights / basis values too, so
+// the per-lane loop reads only LDS.
+// Volume term of the load vector, det J sum_g w_g f(x_g) phi_j(x_g), from the
+// tables sw = w[NQ], phi[NQ][N], xi[NQ], eta[NQ] (in LDS); fe: the element's
+// point values of f when f is given by point values (FE = R in LDS or double
+// in global memory).
+template <int K, typename R, typename FE>
+__device__ __forceinline__ R volume_rhs(const AsmArgs& a, const R* sw, const FE* fe, bool fpts, const double* p,
+                                        int j)
 {
-    constexpr int N = (K + 1) * (K + 2) / 2, EPW = 64 / N;
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NQ = L.nq;
+    const double dj11 = p[2] - p[0], dj12 = p[4] - p[0], dj21 = p[3] - p[1], dj22 = p[5] - p[1];
+    const double det = dj11 * dj22 - dj12 * dj21;
+    R r = R(0);
+    if (fpts) {
+#pragma unroll
+        for (int g = 0; g < NQ; ++g) r += sw[g] * (R)fe[g] * sw[NQ + g * N + j];
+    } else if (a.f.kind == DG_CONST) {
+#pragma unroll
+        for (int g = 0; g < NQ; ++g) r += sw[g] * sw[NQ + g * N + j];
+        r *= (R)a.f.c[0];
+    } else {
+        r = load_vector_volume_field<K, R>(a, j, (R)p[0], (R)p[1], (R)dj11, (R)dj12, (R)dj21, (R)dj22, sw, sw + NQ * (N + 1),
+                                           sw + NQ * (N + 2), sw + NQ);
+    }
+    return r * (R)det;
+}
+
+// The point tables of volume_rhs, staged by a workgroup.
+template <int K, typename R>
+__device__ __forceinline__ void stage_point_tables(const AsmArgs& a, R* sw, int nthreads)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NQ = L.nq;
+    const R* __restrict__ tab = (const R*)a.tab;
+    for (int t = threadIdx.x; t < NQ; t += nthreads) {
+        sw[t] = tab[L.vw + t];
+        sw[NQ * (N + 1) + t] = tab[L.vxi + t];
+        sw[NQ * (N + 2) + t] = tab[L.veta + t];
+    }
+    for (int t = threadIdx.x; t < NQ * N; t += nthreads) sw[NQ + t] = tab[L.vphi + t];
+}
+
+template <int K, typename R>
+__global__ __launch_bounds__(256) void load_vector_volume_kernel(const AsmArgs a)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NQ = L.nq, EPW = 64 / N, EPB = 4 * EPW;
+    __shared__ R sw[NQ * (N + 3)];  // w[NQ], phi[NQ][N], xi[NQ], eta[NQ]
+    __shared__ R sf[EPB * NQ];
+    const bool fpts = a.f.kind == DG_QPOINTS;
+    stage_point_tables<K, R>(a, sw, 256);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int e_in_wave = lane / N;
-    const int j = lane - e_in_wave * N;
-    const int64_t el = ((int64_t)blockIdx.x * 4 + wave) * EPW + e_in_wave;
-    if (e_in_wave >= EPW || el >= a.T) return;
-    load_vector_element<K, R>(a, el, j, (R*)a.rhs);
+    const int e_in = lane / N;
+    const int j = lane - e_in * N;
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    if (fpts) {
+        const int64_t nf = (a.T - e0 < EPB ? a.T - e0 : (int64_t)EPB) * NQ;
+        const double* fv = a.f.vals + e0 * NQ;
+        for (int64_t t = threadIdx.x; t < nf; t += 256) sf[t] = (R)fv[t];
+    }
+    __syncthreads();
+    const int64_t el = e0 + wave * EPW + e_in;
+    if (e_in < EPW && el < a.T)
+        ((R*)a.rhs)[el * N + j] = volume_rhs<K, R, R>(a, sw, sf + (el - e0) * NQ, fpts, a.xy + 6 * el, j);
+}
+
+
+// Load vector, boundary-edge terms, added after the volume term: thread per
+// (boundary element, j), so every entry has one writer.
+template <int K, typename R>
+__global__ __launch_bounds__(256) void load_vector_boundary_kernel(const AsmArgs a, const int32_t* __restrict__ belems,
+                                                                   int64_t nbe)
+{
+    constexpr int N = (K + 1) * (K + 2) / 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nbe * N) return;
+    const int64_t el = belems[t / N];
+    const int j = (int)(t - (t / N) * N);
+    const double* p = a.xy + 6 * el;
+    const double dj11 = p[2] - p[0], dj12 = p[4] - p[0], dj21 = p[3] - p[1], dj22 = p[5] - p[1];
+    const double det = dj11 * dj22 - dj12 * dj21;
+    const R G11 = (R)(dj22 / det), G12 = (R)(-dj21 / det), G21 = (R)(-dj12 / det), G22 = (R)(dj11 / det);
+    ((R*)a.rhs)[el * N + j] += load_vector_boundary<K, R>(a, el, j, p, G11, G12, G21, G22);
+}
+
+// Boundary-edge terms of the load vector (after its volume term).
+template <int K, typename R>
+static void launch_load_boundary(const dg_mesh* m, const AsmArgs& a, hipStream_t s)
+{
+    constexpr int N = (K + 1) * (K + 2) / 2;
+    // the boundary terms of l_h are g^D (...) and g^N phi: nothing to add when both vanish
+    const bool zero_data = a.gD.kind == DG_CONST && a.gD.c[0] == 0.0 && a.gN.kind == DG_CONST && a.gN.c[0] == 0.0;
+    const int64_t nb = (int64_t)m->bnd_elems.size();
+    if (nb > 0 && !zero_data)
+        hipLaunchKernelGGL((load_vector_boundary_kernel<K, R>), dim3((unsigned)((nb * N + 255) / 256)), dim3(256), 0,
+                           s, a, (const int32_t*)m->d_bnd_elems, nb);
+}
+
+template <int K, typename R>
+static void launch_load_vector(const dg_mesh* m, const AsmArgs& a, hipStream_t s)
+{
+    constexpr int N = (K + 1) * (K + 2) / 2, EPB = 4 * (64 / N);
+    const int64_t grid = (m->T + EPB - 1) / EPB;
+    if (grid > 0) hipLaunchKernelGGL((load_vector_volume_kernel<K, R>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    launch_load_boundary<K, R>(m, a, s);
+}
+
+// Constant eps, b and alpha on affine elements: every entry of the block row
+// is a linear combination of the reference tensors of TenLayout with
+// coefficients from the element's geometry and the problem constants (the
+// same terms as assemble_element, integrated exactly by the same rules):
+//   volume  det (eps (M11 SXX + M12 SXY + M22 SYY) + (G^T b) . (CX, CY) + alpha MASS),  M = G^T G,
+//   edge l  |e| ((eps pen + up) E - c1 eps m_K . (DX, DY) + kappa c1 eps m_K . (TX, TY)),
+//   K -> L  -|e| ((eps pen + up) F + 1/2 eps m_L . (GX, GY) + kappa 1/2 eps m_K . (HX, HY)),
+// with G = J^{-T}, m = G^T n, up = max(-b . n, 0) (b . n is constant on an
+// edge, so the per-point upwind decision is one decision per edge).  The
+// tensors are staged in LDS; a lane (element, trial j) reads column j.  Each
+// neighbour block is stored as soon as its edge is done, so that only the
+// diagonal block and one neighbour block are live in registers.
+constexpr int TEN_BLOCK = 512;
+
+
+template <int K, typename R>
+__device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, const int64_t el, const int j)
+{
+    constexpr int N = (K + 1) * (K + 2) / 2, NN = N * N;
+    // all global loads of the element first, so that they are in flight together
+    // (up to P2; at P3 the neighbour data is loaded per edge to save registers)
+    constexpr bool HOIST = K <= 2;
+    const double* p = a.xy + 6 * el;
+    const double X1 = p[0], Y1 = p[1], X2 = p[2], Y2 = p[3], X3 = p[4], Y3 = p[5];
+    int32_t nb[3];
+    int32_t btype[3];
+    double gL[3][4];  // J^{-T} of the neighbours
+#pragma unroll
+    for (int l = 0; l < 3; ++l) nb[l] = a.nbr[3 * el + l];
+    const int32_t nbe = a.nbr_edge[el];
+    const int64_t s0 = a.row_ptr[el];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if constexpr (HOIST) {
+            const double* gl = a.gt + 4 * (nb[l] >= 0 ? (int64_t)nb[l] : el);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gL[l][v] = gl[v];
+        }
+        btype[l] = nb[l] >= 0 ? -1 : a.bnd_type[-nb[l] - 1];
+    }
+
+    const double cD = (a.parts & DG_PART_D) ? 1.0 : 0.0;
+    const double cC = (a.parts & DG_PART_C) ? 1.0 : 0.0;
+    const double cR = (a.parts & DG_PART_R) ? 1.0 : 0.0;
+    const double deps = cD * a.eps.c[0], bx = a.bx.c[0], by = a.by.c[0];
+    const double dj11 = X2 - X1, dj12 = X3 - X1, dj21 = Y2 - Y1, dj22 = Y3 - Y1;
+    const double det = dj11 * dj22 - dj12 * dj21;
+    const double inv = 1.0 / det;
+    // G = J^{-T} = [[G11, G12], [G21, G22]]
+    const double G11 = dj22 * inv, G12 = -dj21 * inv, G21 = -dj12 * inv, G22 = dj11 * inv;
+    const R* col = st + j * N;
+
+    R* __restrict__ vals = (R*)a.vals;
+    int64_t slot = s0 + 1;
+    R accd[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) accd[i] = R(0);
+    {
+        // det (G^T G) = adj(J)^T adj(J) / det
+        const double ed = deps * inv;
+        R c[6];
+        c[0] = (R)(ed * (dj22 * dj22 + dj12 * dj12));
+        c[1] = (R)(-ed * (dj22 * dj21 + dj12 * dj11));
+        c[2] = (R)(ed * (dj21 * dj21 + dj11 * dj11));
+        c[3] = (R)(cC * (dj22 * bx - dj12 * by));  // det G^T b
+        c[4] = (R)(cC * (dj11 * by - dj21 * bx));
+        c[5] = (R)(cR * a.alpha.c[0] * det);
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            const R* T = col + (TenStage::VOL + t) * NN;
+#pragma unroll
+            for (int i = 0; i < N; ++i) accd[i] += c[t] * T[i];
+        }
+    }
+    // edge vectors from vertex l to vertex l+1
+    const double evx[3] = {dj11, dj12 - dj11, -dj12}, evy[3] = {dj21, dj22 - dj21, -dj22};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const bool interior = nb[l] >= 0;
+        if (btype[l] == 1) continue;  // Neumann edge: load vector only
+        // |e| n = (dy, -dx): every edge coefficient carries the factor |e| of ds
+        const double nx = evy[l], ny = -evx[l];
+        const double mKx = G11 * nx + G21 * ny, mKy = G12 * nx + G22 * ny;  // |e| G^T n
+        const double c1 = interior ? 0.5 : 1.0;
+        const double sig = interior ? a.sigma : a.sigma_D;
+        // |e| * sigma / |e|^b0
+        const double pl = a.b0 == 1.0 ? sig : sig * pow(sqrt(nx * nx + ny * ny), 1.0 - a.b0);
+        const double bl = bx * nx + by * ny;  // |e| b . n
+        const double s = deps * pl + cC * (bl < 0.0 ? -bl : 0.0);
+        {
+            const double dc = deps * c1;
+            const R c0 = (R)s, cx = (R)(dc * mKx), cy = (R)(dc * mKy);
+            const R* T = col + (TenStage::ED + 3 * l) * NN;
+#pragma unroll
+            for (int i = 0; i < N; ++i) accd[i] += c0 * T[i] + cx * T[NN + i] + cy * T[2 * NN + i];
+        }
+        if (interior) {
+            const double hk = 0.5 * deps;
+            const int lp = (nbe >> (2 * l)) & 3;
+            if constexpr (!HOIST) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) gL[l][v] = a.gt[4 * (int64_t)nb[l] + v];
+            }
+            R c[5];
+            c[0] = (R)(-s);
+            c[1] = (R)(-hk * (gL[l][0] * nx + gL[l][1] * ny));  // -1/2 eps |e| m_L
+            c[2] = (R)(-hk * (gL[l][2] * nx + gL[l][3] * ny));
+            c[3] = (R)(-0.5 * deps * a.kappa * mKx);
+            c[4] = (R)(-0.5 * deps * a.kappa * mKy);
+            const R* Tl = col + (TenStage::EO + 5 * (3 * l + lp)) * NN;
+            R acco[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) acco[i] = c[0] * Tl[i];
+#pragma unroll
+            for (int t = 1; t < 5; ++t) {
+                const R* T = Tl + t * NN;
+#pragma unroll
+                for (int i = 0; i < N; ++i) acco[i] += c[t] * T[i];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) vals[(slot * N + i) * N + j] = acco[i];
+            ++slot;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) vals[(s0 * N + i) * N + j] = accd[i];
+}
+
+template <int K, typename R>
+__global__ __launch_bounds__(TEN_BLOCK) void assemble_tensor_kernel(const AsmArgs a, const R* __restrict__ ten)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NN = N * N, NQ = L.nq, EPW = 64 / N, WPB = TEN_BLOCK / 64;
+    constexpr int NT = TenStage::COUNT * NN;
+    __shared__ R st[NT + NQ * (N + 3)];  // staged tensors, then the load vector's point tables
+    R* sw = st + NT;
+    for (int t = threadIdx.x; t < NT; t += TEN_BLOCK) st[t] = ten[t];
+    if (a.rhs) stage_point_tables<K, R>(a, sw, TEN_BLOCK);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e_in = lane / N;
+    const int j = lane - e_in * N;
+    const int64_t el = ((int64_t)blockIdx.x * WPB + wave) * EPW + e_in;
+    if (e_in >= EPW || el >= a.T) return;
+    tensor_element<K, R>(a, st, el, j);
+    if (a.rhs) {
+        const bool fpts = a.f.kind == DG_QPOINTS;
+        ((R*)a.rhs)[el * N + j] = volume_rhs<K, R, double>(a, sw, fpts ? a.f.vals + el * NQ : nullptr, fpts,
+                                                             a.xy + 6 * el, j);
+    }
+}
+
+// eps, b and alpha constant (the affine form with zero slopes)
+static bool constant_coefficients(const AsmArgs& a)
+{
+    const FieldDev* f[4] = {&a.eps, &a.bx, &a.by, &a.alpha};
+    for (const FieldDev* F : f)
+        if (F->c[1] != 0.0 || F->c[2] != 0.0) return false;
+    return true;
 }
 
 template <int K, typename R>
@@ -40,8 +303,23 @@ static int launch_k(const dg_mesh* m, const AsmArgs& a, hipStream_t s)
     const int64_t per_block = 4 * EPW;
     const int64_t blocks = (m->T + per_block - 1) / per_block;
     if (blocks <= 0) return DG_OK;
-    if (a.vals) hipLaunchKernelGGL((assemble_kernel<K, R>), dim3((unsigned)blocks), dim3(256), 0, s, a);
-    if (a.rhs) hipLaunchKernelGGL((load_vector_kernel<K, R>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    bool done = false;
+    if constexpr (K <= 3) {
+        const R* ten = std::is_same<R, double>::value ? (const R*)(const void*)m->d_ten64
+                                                      : (const R*)(const void*)m->d_ten32;
+        if (a.vals && ten && constant_coefficients(a)) {
+            const int64_t per = (TEN_BLOCK / 64) * EPW;
+            const int64_t grid = (m->T + per - 1) / per;
+            // the staged set of this method (kappa = -1, 0, 1)
+            const int ki = a.kappa < 0 ? 0 : (a.kappa > 0 ? 2 : 1);
+            hipLaunchKernelGGL((assemble_tensor_kernel<K, R>), dim3((unsigned)grid), dim3(TEN_BLOCK), 0, s, a,
+                               ten + (size_t)ki * TenStage::COUNT * N * N);
+            if (a.rhs) launch_load_boundary<K, R>(m, a, s);
+            done = true;
+        }
+    }
+    if (a.vals && !done) hipLaunchKernelGGL((assemble_kernel<K, R>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.rhs && !done) launch_load_vector<K, R>(m, a, s);
     return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
 }
 
@@ -181,6 +459,7 @@ extern "C" int32_t dg_assemble(const dg_mesh* m, const dg_problem* P, int32_t pr
         return st;
     AsmArgs a;
     a.xy = m->d_xy;
+    a.gt = m->d_gt;
     a.nbr = m->d_nbr;
     a.nbr_edge = m->d_nbr_edge;
     a.row_ptr = m->d_row_ptr;

@@ -41,6 +41,35 @@ struct TabLayout {
           size(3 * nq + 3 * nq * n + 2 * nqe + 9 * nqe * n) {}
 };
 
+// Reference tensors of the constant-coefficient assembly.  Each is an n x n
+// matrix of integrals over the reference triangle or one of its edges,
+// stored trial-major: entry (test i, trial j) at [j * n + i], so that the
+// lane of trial function j reads a contiguous column.  Derivatives are with
+// respect to the reference coordinates (xi, eta); edge integrals use the
+// edge parameter t in [0, 1] (weights sum to 1); psi denotes the basis traced
+// on the neighbour's edge lp at the same physical point (parameter 1 - t).
+struct TenLayout {
+    // volume: SXX = d_xi phi_i d_xi phi_j, SXY = d_xi phi_i d_eta phi_j + d_eta phi_i d_xi phi_j,
+    // SYY = d_eta phi_i d_eta phi_j, CX = phi_i d_xi phi_j, CY = phi_i d_eta phi_j, MASS = phi_i phi_j
+    static constexpr int VOL = 0;
+    // edge l of K, index ED + 5 l + t: E = phi_i phi_j, DX = phi_i d_xi phi_j, DY = phi_i d_eta phi_j,
+    // TX = d_xi phi_i phi_j, TY = d_eta phi_i phi_j
+    static constexpr int ED = 6;
+    // edge l of K against edge lp of the neighbour, index EO + 5 (3 l + lp) + t: F = phi_i psi_j,
+    // GX = phi_i d_xi psi_j, GY = phi_i d_eta psi_j, HX = d_xi phi_i psi_j, HY = d_eta phi_i psi_j
+    static constexpr int EO = 21;
+    static constexpr int COUNT = 66;
+};
+
+// The set the constant-coefficient kernel stages, one per method (kappa = -1,
+// 0, 1 at index kappa + 1): the volume tensors, per local edge E and
+// Z = kappa T - D (X and Y; the two normal-derivative terms of the diagonal
+// block share their coefficient up to kappa), then the neighbour tensors.
+struct TenStage {
+    static constexpr int VOL = 0, ED = 6, EO = 15, COUNT = 60;
+};
+std::vector<double> stage_tensors(int k, const std::vector<double>& ten, double kappa);
+
 // Field as seen by the kernels (same meaning as dg_field).
 struct FieldDev {
     int32_t kind;
@@ -51,6 +80,7 @@ struct FieldDev {
 
 struct AsmArgs {
     const double* xy;        // [T][6]: element vertex coordinates (x1,y1,x2,y2,x3,y3)
+    const double* gt;        // [T][4]: G = J^{-T} as (G11, G21, G12, G22), so G^T n = (g0 nx + g1 ny, g2 nx + g3 ny)
     const int32_t* nbr;      // [T][3]: neighbour across local edge l, or -(b+1) for boundary edge b
     const int32_t* nbr_edge; // [T]: bits 2l..2l+1 = neighbour's local edge index
     const int32_t* row_ptr;  // [T+1]
@@ -74,6 +104,7 @@ struct dg_mesh {
     // host copies
     std::vector<double> xy6;
     std::vector<int32_t> nbr, nbr_edge, row_ptr, col_idx, bnd_el, bnd_loc, bnd_type;
+    std::vector<int32_t> bnd_elems;  // elements with at least one boundary edge, ascending
     std::vector<double> tab64;
     // device copies (owned)
     double* d_xy = nullptr;
@@ -84,8 +115,12 @@ struct dg_mesh {
     int32_t* d_bnd_type = nullptr;
     int32_t* d_bnd_el = nullptr;
     int32_t* d_bnd_loc = nullptr;
+    int32_t* d_bnd_elems = nullptr;
     double* d_tab64 = nullptr;
     float* d_tab32 = nullptr;
+    double* d_gt = nullptr;     // [T][4] J^{-T} per element (see AsmArgs::gt)
+    double* d_ten64 = nullptr;  // [3][TenStage::COUNT] n x n staged tensors per kappa (k <= 3)
+    float* d_ten32 = nullptr;
     double* d_p1map = nullptr;  // [3][3]: P1 coefficients from vertex values (k >= 1)
 };
 
@@ -93,6 +128,8 @@ namespace dg {
 // Host-side reference tables for degree k (Golub-Welsch quadrature, Dubiner
 // basis in collapsed coordinates); returns TabLayout(k).size values.
 std::vector<double> build_tables(int k);
+// Reference tensors (TenLayout) of degree k from the tables of build_tables.
+std::vector<double> build_tensors(int k, const std::vector<double>& tab);
 // Gauss-Jacobi rule for the weight (1-x)^a (1+x)^b on [-1,1].
 void gauss_jacobi_gw(int n, double a, double b, double* x, double* w);
 int launch_assemble(const dg_mesh* m, const AsmArgs& a, int prec, hipStream_t s);

@@ -169,11 +169,88 @@ std::vector<double> build_tables(int k)
     return tab;
 }
 
+std::vector<double> build_tensors(int k, const std::vector<double>& tab)
+{
+    const TabLayout L(k);
+    const int n = L.n, nn = n * n, q = L.nqe;
+    std::vector<double> ten((size_t)TenLayout::COUNT * nn, 0.0);
+    auto at = [&](int t, int i, int j) -> double& { return ten[(size_t)t * nn + (size_t)j * n + i]; };
+    for (int g = 0; g < L.nq; ++g) {
+        const double w = tab[L.vw + g];
+        const double* v = &tab[L.vphi + g * n];
+        const double* dx = &tab[L.vdx + g * n];
+        const double* de = &tab[L.vde + g * n];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                at(TenLayout::VOL + 0, i, j) += w * dx[i] * dx[j];
+                at(TenLayout::VOL + 1, i, j) += w * (dx[i] * de[j] + de[i] * dx[j]);
+                at(TenLayout::VOL + 2, i, j) += w * de[i] * de[j];
+                at(TenLayout::VOL + 3, i, j) += w * v[i] * dx[j];
+                at(TenLayout::VOL + 4, i, j) += w * v[i] * de[j];
+                at(TenLayout::VOL + 5, i, j) += w * v[i] * v[j];
+            }
+    }
+    for (int l = 0; l < 3; ++l)
+        for (int g = 0; g < q; ++g) {
+            const double w = tab[L.ew + g];
+            const int ge = (l * q + g) * n;
+            const double* v = &tab[L.ephi + ge];
+            const double* dx = &tab[L.edx + ge];
+            const double* de = &tab[L.ede + ge];
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    const int b = TenLayout::ED + 5 * l;
+                    at(b + 0, i, j) += w * v[i] * v[j];
+                    at(b + 1, i, j) += w * v[i] * dx[j];
+                    at(b + 2, i, j) += w * v[i] * de[j];
+                    at(b + 3, i, j) += w * dx[i] * v[j];
+                    at(b + 4, i, j) += w * de[i] * v[j];
+                }
+            // the neighbour's point: its edge lp at the reversed parameter (Gauss points are symmetric)
+            for (int lp = 0; lp < 3; ++lp) {
+                const int gl = (lp * q + (q - 1 - g)) * n;
+                const double* u = &tab[L.ephi + gl];
+                const double* ux = &tab[L.edx + gl];
+                const double* ue = &tab[L.ede + gl];
+                const int b = TenLayout::EO + 5 * (3 * l + lp);
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        at(b + 0, i, j) += w * v[i] * u[j];
+                        at(b + 1, i, j) += w * v[i] * ux[j];
+                        at(b + 2, i, j) += w * v[i] * ue[j];
+                        at(b + 3, i, j) += w * dx[i] * u[j];
+                        at(b + 4, i, j) += w * de[i] * u[j];
+                    }
+            }
+        }
+    return ten;
+}
+
+std::vector<double> stage_tensors(int k, const std::vector<double>& ten, double kappa)
+{
+    const int n = (k + 1) * (k + 2) / 2, nn = n * n;
+    std::vector<double> st((size_t)TenStage::COUNT * nn);
+    for (int t = 0; t < 6; ++t)
+        for (int e = 0; e < nn; ++e) st[(size_t)(TenStage::VOL + t) * nn + e] = ten[(size_t)(TenLayout::VOL + t) * nn + e];
+    for (int l = 0; l < 3; ++l)
+        for (int e = 0; e < nn; ++e) {
+            const double* T = &ten[(size_t)(TenLayout::ED + 5 * l) * nn + e];  // E, DX, DY, TX, TY
+            st[(size_t)(TenStage::ED + 3 * l) * nn + e] = T[0];
+            st[(size_t)(TenStage::ED + 3 * l + 1) * nn + e] = kappa * T[3 * nn] - T[nn];
+            st[(size_t)(TenStage::ED + 3 * l + 2) * nn + e] = kappa * T[4 * nn] - T[2 * nn];
+        }
+    for (int t = 0; t < 45; ++t)
+        for (int e = 0; e < nn; ++e) st[(size_t)(TenStage::EO + t) * nn + e] = ten[(size_t)(TenLayout::EO + t) * nn + e];
+    return st;
+}
+
 static void free_device(dg_mesh* m)
 {
     hipFree(m->d_xy); hipFree(m->d_nbr); hipFree(m->d_nbr_edge); hipFree(m->d_row_ptr);
     hipFree(m->d_col_idx); hipFree(m->d_bnd_type); hipFree(m->d_bnd_el); hipFree(m->d_bnd_loc);
-    hipFree(m->d_tab64); hipFree(m->d_tab32); hipFree(m->d_p1map);
+    hipFree(m->d_bnd_elems);
+    hipFree(m->d_tab64); hipFree(m->d_tab32); hipFree(m->d_p1map); hipFree(m->d_ten64); hipFree(m->d_ten32);
+    hipFree(m->d_gt);
 }
 
 template <typename T>
@@ -310,6 +387,9 @@ int build_host_mesh(const double* xy, int64_t n_nodes, const int32_t* elems, int
         if (kv.second < 2) return DG_ERR_BOUNDARY;  // listed edge not on the boundary
     m->n_int = n_int;
     m->n_bnd = (int64_t)m->bnd_el.size();
+    m->bnd_elems.clear();
+    for (int32_t K : m->bnd_el)  // bnd_el is ascending
+        if (m->bnd_elems.empty() || m->bnd_elems.back() != K) m->bnd_elems.push_back(K);
     m->hmax = hmax;
 
     // BSR pattern: block row K = [K, neighbours in local edge order].
@@ -353,8 +433,33 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
     if (st == DG_OK) st = upload(&m->d_bnd_type, m->bnd_type);
     if (st == DG_OK) st = upload(&m->d_bnd_el, m->bnd_el);
     if (st == DG_OK) st = upload(&m->d_bnd_loc, m->bnd_loc);
+    if (st == DG_OK) st = upload(&m->d_bnd_elems, m->bnd_elems);
     if (st == DG_OK) st = upload(&m->d_tab64, m->tab64);
     if (st == DG_OK) st = upload(&m->d_tab32, tab32);
+    if (st == DG_OK) {
+        std::vector<double> gt((size_t)4 * m->T);
+        for (int64_t K = 0; K < m->T; ++K) {
+            const double* p = &m->xy6[6 * K];
+            const double j11 = p[2] - p[0], j12 = p[4] - p[0], j21 = p[3] - p[1], j22 = p[5] - p[1];
+            const double det = j11 * j22 - j12 * j21;
+            gt[4 * K + 0] = j22 / det;   // G11
+            gt[4 * K + 1] = -j12 / det;  // G21
+            gt[4 * K + 2] = -j21 / det;  // G12
+            gt[4 * K + 3] = j11 / det;   // G22
+        }
+        st = upload(&m->d_gt, gt);
+    }
+    if (st == DG_OK && degree <= 3) {
+        const std::vector<double> ref = build_tensors(degree, m->tab64);
+        std::vector<double> ten;
+        for (int kap = -1; kap <= 1; ++kap) {
+            const std::vector<double> s = stage_tensors(degree, ref, (double)kap);
+            ten.insert(ten.end(), s.begin(), s.end());
+        }
+        const std::vector<float> ten32(ten.begin(), ten.end());
+        st = upload(&m->d_ten64, ten);
+        if (st == DG_OK) st = upload(&m->d_ten32, ten32);
+    }
     if (st == DG_OK) {
         // P[m][v] = int_ref lambda_v phi_m: coefficients of the linear function with vertex values u_v
         const TabLayout L(degree);

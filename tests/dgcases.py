@@ -110,6 +110,17 @@ def small_cases():
                                   seed=k + meth)
             cases.append(Case("jit13_p%d_m%d_mixedbc_rot" % (k, meth), m, k, meth, pr.eps, pr.b, pr.alpha, pr.f,
                               gD=pr.u, gN=pr.gN))
+    # constant eps, b, alpha: the reference-tensor assembly path (k <= 3) on jittered meshes with
+    # mixed boundaries (b enters through Dirichlet and Neumann sides)
+    for k in (0, 1, 2, 3, 4):
+        for meth in (1, 2, 3):
+            if k == 0 and meth != 1:
+                continue
+            pr = W.polynomial_problem(max(k, 1) + 1, 0.03, (0.8, -0.5), 0.3, seed=100 + 10 * k + meth)
+            m = W.structured_mesh(11, dirichlet=("top", "right"), neumann=("bottom", "left"), jitter=0.2,
+                                  seed=50 + k + meth)
+            cases.append(Case("jit11_p%d_m%d_mixedbc_const" % (k, meth), m, k, meth, pr.eps, pr.b, pr.alpha, pr.f,
+                              gD=pr.u, gN=pr.gN))
     bl = W.boundary_layer_problem()
     for meth in (1, 2):
         cases.append(Case("c2like_32_p2_m%d" % meth, W.structured_mesh(32), 2, meth, bl.eps, bl.b, bl.alpha, bl.f))

@@ -83,8 +83,10 @@ def test_fp32_assembly_error_vs_oracle(api):
         assert e <= 2e-6 and eb <= 2e-6
 
 
-def test_assembly_bitwise_deterministic(api):
-    case = SMALL[8]
+@pytest.mark.parametrize("name", ["jit13_p3_m1_mixedbc_rot", "jit11_p3_m2_mixedbc_const"])
+def test_assembly_bitwise_deterministic(api, name):
+    """Point path (affine b) and reference-tensor path (constant coefficients)."""
+    case = [c for c in SMALL if c.name == name][0]
     mesh, prob, v1, r1 = _gpu_system(api, case)
     v2, r2 = api.assemble(mesh, prob)
     torch.cuda.synchronize()
