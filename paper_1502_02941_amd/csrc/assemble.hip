@@ -150,10 +150,36 @@ static void launch_load_vector(const dg_mesh* m, const AsmArgs& a, hipStream_t s
 constexpr int TEN_BLOCK = 512;
 
 
+// Upwind term of edge l summed point by point (an edge on which b . n changes
+// sign between quadrature points): acc[i] += scale sum_g w_g max(-bl(t_g), 0)
+// phi_i(l, t_g) u_j, with bl(t) = blA + t dbl (|e| b . n) and u_j the trial
+// function on the same edge (diagonal block) or the neighbour's trace on its
+// edge lp at the same point (parameter 1 - t).
+template <int K, typename R>
+__device__ void upwind_points(const AsmArgs& a, int l, int lp, int j, double blA, double dbl, double scale, R* acc,
+                              bool same = false)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, Q = L.nqe;
+    const R* __restrict__ tab = (const R*)a.tab;
+#pragma unroll 1
+    for (int g = 0; g < Q; ++g) {
+        const double bl = blA + (double)tab[L.et + g] * dbl;
+        if (!(bl < 0.0)) continue;
+        const R* ti = tab + L.ephi + (l * Q + g) * N;
+        const R u = same ? ti[j] : tab[L.ephi + (lp * Q + (Q - 1 - g)) * N + j];
+        const R w = (R)(scale * (double)tab[L.ew + g] * -bl) * u;
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] += w * ti[i];
+    }
+}
+
 template <int K, typename R>
 __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, const int64_t el, const int j)
 {
     constexpr int N = (K + 1) * (K + 2) / 2, NN = N * N;
+    constexpr TabLayout L(K);
+    const R t_first = ((const R*)a.tab)[L.et], t_last = ((const R*)a.tab)[L.et + L.nqe - 1];
     // all global loads of the element first, so that they are in flight together
     // (up to P2; at P3 the neighbour data is loaded per edge to save registers)
     constexpr bool HOIST = K <= 2;
@@ -179,7 +205,10 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     const double cD = (a.parts & DG_PART_D) ? 1.0 : 0.0;
     const double cC = (a.parts & DG_PART_C) ? 1.0 : 0.0;
     const double cR = (a.parts & DG_PART_R) ? 1.0 : 0.0;
-    const double deps = cD * a.eps.c[0], bx = a.bx.c[0], by = a.by.c[0];
+    const double deps = cD * a.eps.c[0];
+    // b = (bx, by), each affine: c0 + c1 x + c2 y
+    const double bx1 = a.bx.c[1], bx2 = a.bx.c[2], by1 = a.by.c[1], by2 = a.by.c[2];
+    const bool baff = bx1 != 0.0 || bx2 != 0.0 || by1 != 0.0 || by2 != 0.0;
     const double dj11 = X2 - X1, dj12 = X3 - X1, dj21 = Y2 - Y1, dj22 = Y3 - Y1;
     const double det = dj11 * dj22 - dj12 * dj21;
     const double inv = 1.0 / det;
@@ -199,14 +228,31 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         c[0] = (R)(ed * (dj22 * dj22 + dj12 * dj12));
         c[1] = (R)(-ed * (dj22 * dj21 + dj12 * dj11));
         c[2] = (R)(ed * (dj21 * dj21 + dj11 * dj11));
-        c[3] = (R)(cC * (dj22 * bx - dj12 * by));  // det G^T b
-        c[4] = (R)(cC * (dj11 * by - dj21 * bx));
+        // det G^T b(xi, eta), b at vertex 1 plus its slopes along xi and eta
+        const double bx0 = a.bx.c[0] + bx1 * X1 + bx2 * Y1, by0 = a.by.c[0] + by1 * X1 + by2 * Y1;
+        c[3] = (R)(cC * (dj22 * bx0 - dj12 * by0));
+        c[4] = (R)(cC * (dj11 * by0 - dj21 * bx0));
         c[5] = (R)(cR * a.alpha.c[0] * det);
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
             const R* T = col + (TenStage::VOL + t) * NN;
 #pragma unroll
             for (int i = 0; i < N; ++i) accd[i] += c[t] * T[i];
+        }
+        if (baff) {
+            const double bxa = bx1 * dj11 + bx2 * dj21, bxb = bx1 * dj12 + bx2 * dj22;  // d bx / d xi, d eta
+            const double bya = by1 * dj11 + by2 * dj21, byb = by1 * dj12 + by2 * dj22;
+            R cb[4];
+            cb[0] = (R)(cC * (dj22 * bxa - dj12 * bya));
+            cb[1] = (R)(cC * (dj22 * bxb - dj12 * byb));
+            cb[2] = (R)(cC * (dj11 * bya - dj21 * bxa));
+            cb[3] = (R)(cC * (dj11 * byb - dj21 * bxb));
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const R* T = col + (TenStage::VB + t) * NN;
+#pragma unroll
+                for (int i = 0; i < N; ++i) accd[i] += cb[t] * T[i];
+            }
         }
     }
     // edge vectors from vertex l to vertex l+1
@@ -222,14 +268,31 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         const double sig = interior ? a.sigma : a.sigma_D;
         // |e| * sigma / |e|^b0
         const double pl = a.b0 == 1.0 ? sig : sig * pow(sqrt(nx * nx + ny * ny), 1.0 - a.b0);
-        const double bl = bx * nx + by * ny;  // |e| b . n
-        const double s = deps * pl + cC * (bl < 0.0 ? -bl : 0.0);
+        // |e| b . n is linear along the edge: blA at vertex l, blA + dbl at vertex l+1.
+        // Upwinding is decided at the quadrature points; when all of them have
+        // the same sign of b . n, the upwind weight max(-b . n, 0) is linear in
+        // t and integrates exactly through E (and t E); otherwise the upwind
+        // term of this edge is summed point by point below.
+        const double xa = l == 0 ? X1 : (l == 1 ? X2 : X3), ya = l == 0 ? Y1 : (l == 1 ? Y2 : Y3);
+        const double blA = (a.bx.c[0] + bx1 * xa + bx2 * ya) * nx + (a.by.c[0] + by1 * xa + by2 * ya) * ny;
+        const double dbl = (bx1 * evx[l] + bx2 * evy[l]) * nx + (by1 * evx[l] + by2 * evy[l]) * ny;
+        const double bl0 = blA + (double)t_first * dbl, bl1 = blA + (double)t_last * dbl;
+        const bool inflow = bl0 < 0.0 && bl1 < 0.0;
+        const bool mixed = (bl0 < 0.0) != (bl1 < 0.0);
+        const double s = deps * pl + cC * (inflow ? -blA : 0.0);
+        const double s1 = cC * (inflow ? -dbl : 0.0);
         {
             const double dc = deps * c1;
             const R c0 = (R)s, cx = (R)(dc * mKx), cy = (R)(dc * mKy);
             const R* T = col + (TenStage::ED + 3 * l) * NN;
 #pragma unroll
             for (int i = 0; i < N; ++i) accd[i] += c0 * T[i] + cx * T[NN + i] + cy * T[2 * NN + i];
+            if (baff) {
+                const R c1t = (R)s1;
+                const R* T1 = col + (TenStage::E1 + l) * NN;
+#pragma unroll
+                for (int i = 0; i < N; ++i) accd[i] += c1t * T1[i];
+            }
         }
         if (interior) {
             const double hk = 0.5 * deps;
@@ -254,10 +317,18 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
 #pragma unroll
                 for (int i = 0; i < N; ++i) acco[i] += c[t] * T[i];
             }
+            if (baff) {
+                const R c1t = (R)(-s1);
+                const R* T1 = col + (TenStage::F1 + 3 * l + lp) * NN;
+#pragma unroll
+                for (int i = 0; i < N; ++i) acco[i] += c1t * T1[i];
+                if (mixed) upwind_points<K, R>(a, l, lp, j, blA, dbl, -cC, acco);
+            }
 #pragma unroll
             for (int i = 0; i < N; ++i) vals[(slot * N + i) * N + j] = acco[i];
             ++slot;
         }
+        if (baff && mixed) upwind_points<K, R>(a, l, l, j, blA, dbl, cC, accd, true);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) vals[(s0 * N + i) * N + j] = accd[i];
@@ -271,7 +342,9 @@ __global__ __launch_bounds__(TEN_BLOCK) void assemble_tensor_kernel(const AsmArg
     constexpr int NT = TenStage::COUNT * NN;
     __shared__ R st[NT + NQ * (N + 3)];  // staged tensors, then the load vector's point tables
     R* sw = st + NT;
-    for (int t = threadIdx.x; t < NT; t += TEN_BLOCK) st[t] = ten[t];
+    const bool baff = a.bx.c[1] != 0.0 || a.bx.c[2] != 0.0 || a.by.c[1] != 0.0 || a.by.c[2] != 0.0;
+    const int nst = (baff ? TenStage::COUNT : TenStage::CONST_B) * NN;
+    for (int t = threadIdx.x; t < nst; t += TEN_BLOCK) st[t] = ten[t];
     if (a.rhs) stage_point_tables<K, R>(a, sw, TEN_BLOCK);
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -287,10 +360,10 @@ __global__ __launch_bounds__(TEN_BLOCK) void assemble_tensor_kernel(const AsmArg
     }
 }
 
-// eps, b and alpha constant (the affine form with zero slopes)
+// eps and alpha constant (the affine form with zero slopes), b affine
 static bool constant_coefficients(const AsmArgs& a)
 {
-    const FieldDev* f[4] = {&a.eps, &a.bx, &a.by, &a.alpha};
+    const FieldDev* f[2] = {&a.eps, &a.alpha};
     for (const FieldDev* F : f)
         if (F->c[1] != 0.0 || F->c[2] != 0.0) return false;
     return true;

@@ -58,7 +58,10 @@ struct TenLayout {
     // edge l of K against edge lp of the neighbour, index EO + 5 (3 l + lp) + t: F = phi_i psi_j,
     // GX = phi_i d_xi psi_j, GY = phi_i d_eta psi_j, HX = d_xi phi_i psi_j, HY = d_eta phi_i psi_j
     static constexpr int EO = 21;
-    static constexpr int COUNT = 66;
+    // for affine b: VB + t: xi phi_i d_xi phi_j, eta phi_i d_xi phi_j, xi phi_i d_eta phi_j, eta phi_i d_eta phi_j;
+    // E1 + l: t phi_i phi_j on edge l; F1 + 3 l + lp: t phi_i psi_j
+    static constexpr int VB = 66, E1 = 70, F1 = 73;
+    static constexpr int COUNT = 82;
 };
 
 // The set the constant-coefficient kernel stages, one per method (kappa = -1,
@@ -66,7 +69,8 @@ struct TenLayout {
 // Z = kappa T - D (X and Y; the two normal-derivative terms of the diagonal
 // block share their coefficient up to kappa), then the neighbour tensors.
 struct TenStage {
-    static constexpr int VOL = 0, ED = 6, EO = 15, COUNT = 60;
+    static constexpr int VOL = 0, ED = 6, EO = 15, VB = 60, E1 = 64, F1 = 67, COUNT = 76;
+    static constexpr int CONST_B = 60;  // staged prefix used when b is constant
 };
 std::vector<double> stage_tensors(int k, const std::vector<double>& ten, double kappa);
 

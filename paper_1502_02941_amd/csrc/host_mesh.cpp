@@ -180,8 +180,13 @@ std::vector<double> build_tensors(int k, const std::vector<double>& tab)
         const double* v = &tab[L.vphi + g * n];
         const double* dx = &tab[L.vdx + g * n];
         const double* de = &tab[L.vde + g * n];
+        const double xi = tab[L.vxi + g], eta = tab[L.veta + g];
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
+                at(TenLayout::VB + 0, i, j) += w * xi * v[i] * dx[j];
+                at(TenLayout::VB + 1, i, j) += w * eta * v[i] * dx[j];
+                at(TenLayout::VB + 2, i, j) += w * xi * v[i] * de[j];
+                at(TenLayout::VB + 3, i, j) += w * eta * v[i] * de[j];
                 at(TenLayout::VOL + 0, i, j) += w * dx[i] * dx[j];
                 at(TenLayout::VOL + 1, i, j) += w * (dx[i] * de[j] + de[i] * dx[j]);
                 at(TenLayout::VOL + 2, i, j) += w * de[i] * de[j];
@@ -192,7 +197,7 @@ std::vector<double> build_tensors(int k, const std::vector<double>& tab)
     }
     for (int l = 0; l < 3; ++l)
         for (int g = 0; g < q; ++g) {
-            const double w = tab[L.ew + g];
+            const double w = tab[L.ew + g], t = tab[L.et + g];
             const int ge = (l * q + g) * n;
             const double* v = &tab[L.ephi + ge];
             const double* dx = &tab[L.edx + ge];
@@ -205,6 +210,7 @@ std::vector<double> build_tensors(int k, const std::vector<double>& tab)
                     at(b + 2, i, j) += w * v[i] * de[j];
                     at(b + 3, i, j) += w * dx[i] * v[j];
                     at(b + 4, i, j) += w * de[i] * v[j];
+                    at(TenLayout::E1 + l, i, j) += w * t * v[i] * v[j];
                 }
             // the neighbour's point: its edge lp at the reversed parameter (Gauss points are symmetric)
             for (int lp = 0; lp < 3; ++lp) {
@@ -220,6 +226,7 @@ std::vector<double> build_tensors(int k, const std::vector<double>& tab)
                         at(b + 2, i, j) += w * v[i] * ue[j];
                         at(b + 3, i, j) += w * dx[i] * u[j];
                         at(b + 4, i, j) += w * de[i] * u[j];
+                        at(TenLayout::F1 + 3 * l + lp, i, j) += w * t * v[i] * u[j];
                     }
             }
         }
@@ -239,8 +246,14 @@ std::vector<double> stage_tensors(int k, const std::vector<double>& ten, double 
             st[(size_t)(TenStage::ED + 3 * l + 1) * nn + e] = kappa * T[3 * nn] - T[nn];
             st[(size_t)(TenStage::ED + 3 * l + 2) * nn + e] = kappa * T[4 * nn] - T[2 * nn];
         }
-    for (int t = 0; t < 45; ++t)
-        for (int e = 0; e < nn; ++e) st[(size_t)(TenStage::EO + t) * nn + e] = ten[(size_t)(TenLayout::EO + t) * nn + e];
+    auto copy = [&](int dst, int src, int cnt) {
+        for (int t = 0; t < cnt; ++t)
+            for (int e = 0; e < nn; ++e) st[(size_t)(dst + t) * nn + e] = ten[(size_t)(src + t) * nn + e];
+    };
+    copy(TenStage::EO, TenLayout::EO, 45);
+    copy(TenStage::VB, TenLayout::VB, 4);
+    copy(TenStage::E1, TenLayout::E1, 3);
+    copy(TenStage::F1, TenLayout::F1, 9);
     return st;
 }
 
