@@ -17,11 +17,14 @@ Other workloads (not the default line):
      log10 eps ~ U[-6,-1], b angle ~ U[0, 2 pi], |b| ~ U[0.5, 2], alpha ~ U[0, 1], f = sum of 4
      Gaussians, g^D = 0, SIPG; one element-parallel assembly launch + one persistent solve
      launch per batch, launch shape picked by the autotuner; step = the whole batch.
+  --workload c3: assembly only, 512 x 512 squares jittered by +-0.2 h (seed 0, 524288 triangles), P3 IIPG
+     sigma = 36 (72 on Dirichlet), rotating b = (-(y - 1/2), x - 1/2), eps = 1e-4, alpha = 1/2, f = 1,
+     Dirichlet on x = 0 and y = 0, g^N = 0 elsewhere; FP64 and FP32 assembly, FP32 error vs FP64.
   --workload c5: 512 held-out instances (seed 2) of the 64 x 64 P1 SIPG family (parameters as c4),
      zero guess vs the learned initial guess (perceptron + prolongation, model trained on 20000
      method solves of seed 1), FP64 and mixed cycles; step = the whole batch incl. the network.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c2|c4|c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c2|c3|c4|c5]
        python bench.py --profile-run     (one FP64 step + a copy probe, for rocprofv3)
 """
 from __future__ import annotations
@@ -56,6 +59,17 @@ def build_workload(api, W, torch):
     return m, mesh, P, prob
 
 
+def copy_probe(torch):
+    """A plain copy kernel of known size for scaling HBM counters: 3 launches,
+    each reading and writing 512 MiB."""
+    src = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log("profile run done")
+
+
 def measured_traffic(kernel, form):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic.json), or None when there is none for this kernel and
@@ -71,14 +85,15 @@ def measured_traffic(kernel, form):
     return entry["bytes_per_launch"]
 
 
-def assembly_bytes(mesh, prec_bytes):
-    """Algorithmic HBM bytes of one assembly: BSR values + load vector written,
-    element geometry (6 FP64), neighbour table (3 int32), packed neighbour edge
-    ids (int32), row pointer (int32), and the f values at the volume points (FP64)
-    read once each."""
+def assembly_bytes(mesh, prec_bytes, f_points=True):
+    """Algorithmic HBM bytes of one assembly: BSR values + load vector written;
+    per element its vertex coordinates (6 FP64), J^{-T} of its three neighbours
+    (3 x 4 FP64), neighbour table (3 int32), packed neighbour edge ids (int32),
+    row pointer (int32), and the f values at the volume points (FP64) when f is
+    given by point values, each read once."""
     n = mesh.n_loc
     out = mesh.nnzb * n * n * prec_bytes + mesh.n_dofs * prec_bytes
-    inp = mesh.T * (6 * 8 + 3 * 4 + 4 + 4) + mesh.T * mesh.n_q * 8
+    inp = mesh.T * (6 * 8 + 3 * 4 * 8 + 3 * 4 + 4 + 4) + (mesh.T * mesh.n_q * 8 if f_points else 0)
     return out + inp
 
 
@@ -90,7 +105,7 @@ def main():
     ap.add_argument("--restart", type=int, default=2 * N_GRID + 64)
     ap.add_argument("--reorth", type=int, default=0, help="1: conditional second Gram-Schmidt pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c4", "c5"))
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"))
     ap.add_argument("--count", type=int, default=None, help="c4 / c5: number of instances (4096 / 512)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one FP64 step and a 512 MiB device copy (counter scaling), no JSON baseline")
@@ -113,6 +128,8 @@ def main():
         return bench_c4(args, api, W, torch)
     if args.workload == "c5":
         return bench_c5(args, api, W, torch)
+    if args.workload == "c3":
+        return bench_c3(args, api, W, torch)
     log("building workload %dx%d P%d" % (N_GRID, N_GRID, DEGREE))
     m, mesh, P, prob = build_workload(api, W, torch)
     vals64, rhs64 = mesh.alloc_system(api.F64)
@@ -171,12 +188,7 @@ def main():
         return ev[0].elapsed_time(ev[1]) / reps * 1e-3
 
     if args.profile_run:
-        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 1.0, out=dst)  # copy probe: one kernel, 512 MiB read + 512 MiB written per launch
-        torch.cuda.synchronize()
-        log("profile run done")
+        copy_probe(torch)
         return
 
     t_asm64 = time_assembly(api.F64, vals64, rhs64)
@@ -229,15 +241,16 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, best),
                      "launches": launches, "avg_us": ms / launches * 1e3,
                      "bytes_per_launch_avg": nbytes / launches},
-        "assembly_roofline": {"bound": "hbm", "kernel": "assemble_kernel<2,double> + load_vector_kernel<2,double>",
+        "assembly_roofline": {"bound": "hbm", "kernel": "assemble_tensor_kernel<2,double> (matrix and load vector)",
                               "achieved": asm["fp64_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": asm["fp64_gbs"] / HBM_PEAK_GBS},
+                              "frac": asm["fp64_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic("assemble_c2", "fp64"),
+                              "bytes_per_launch": b64},
         "cpu_baseline": None,
     }
     log("best form %s; dominant kernel %s: %d launches, avg %.1f us, %.0f GB/s" % (
         best, dom, launches, ms / launches * 1e3, achieved))
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(m, prob)
+        line["cpu_baseline"] = cpu_baseline(m, prob, int(results["fp64"]["iters"][0]) if "fp64" in results else 538)
     print(json.dumps(line), flush=True)
 
 
@@ -331,6 +344,84 @@ def bench_c4(args, api, W, torch):
     print(json.dumps(line), flush=True)
 
 
+def build_c3(api, W, n=512):
+    m = W.structured_mesh(n, dirichlet=("left", "bottom"), neumann=("right", "top"), jitter=0.2, seed=0)
+    sigma, _ = api.default_penalty(api.IIPG, 3)
+    prob = api.Problem(api.IIPG, 3, sigma, eps=1e-4, bx=api.Field.affine(0.5, 0.0, -1.0),
+                       by=api.Field.affine(-0.5, 1.0, 0.0), alpha=0.5, f=1.0)
+    return m, prob
+
+
+def bench_c3(args, api, W, torch):
+    m, prob = build_c3(api, W)
+    mesh = api.Mesh.from_arrays(m, 3)
+    log("c3: %d triangles, %d dofs, nnzb %d" % (mesh.T, mesh.n_dofs, mesh.nnzb))
+    if args.profile_run:
+        vals, rhs = mesh.alloc_system(api.F64)
+        for _ in range(3):
+            api.assemble(mesh, prob, prec=api.F64, vals=vals, rhs=rhs)
+        torch.cuda.synchronize()
+        copy_probe(torch)
+        return
+    stream = torch.cuda.current_stream()
+    res = {}
+    systems = {}
+    reps = max(args.steps, 1) * 10
+    for name, prec in (("fp64", api.F64), ("fp32", api.F32)):
+        vals, rhs = mesh.alloc_system(prec)
+        for _ in range(max(args.warmup, 1)):
+            api.assemble(mesh, prob, prec=prec, vals=vals, rhs=rhs)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            api.assemble(mesh, prob, prec=prec, vals=vals, rhs=rhs)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        t = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+        nbytes = assembly_bytes(mesh, 8 if prec == api.F64 else 4, f_points=False)
+        res[name] = {"us": t * 1e6, "melem_s": mesh.T / t / 1e6, "GB_s": nbytes / t / 1e9,
+                     "algorithmic_bytes": nbytes}
+        systems[name] = (vals, rhs)
+        log("%s: %.1f us, %.0f Melem/s, %.0f GB/s" % (name, t * 1e6, mesh.T / t / 1e6, nbytes / t / 1e9))
+    v64, r64 = systems["fp64"]
+    v32, r32 = systems["fp32"]
+    err_a = float((v32.double() - v64).norm() / v64.norm())
+    err_f = float((r32.double() - r64).norm() / r64.norm())
+    log("FP32 vs FP64: matrix %.3e, load vector %.3e (relative Frobenius / 2-norm)" % (err_a, err_f))
+    F = res["fp64"]
+    line = {
+        "metric": "DG assembly Melem/s; solves/s at rel-res 1e-10, learned+mixed vs plain FP64",
+        "value": F["melem_s"], "unit": "Melem/s (FP64 assembly of matrix and load vector)",
+        "n_gpus": 1, "steps": reps, "warmup": max(args.warmup, 1), "ms_per_step": F["us"] * 1e-3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (jittered structured mesh, seed 0)",
+        "config": {"workload": "512x512 jittered (+-0.2h, seed 0), P3 IIPG (524288 triangles, 5242880 dofs), "
+                               "rotating b, eps=1e-4, alpha=0.5, f=1, D on x=0,y=0, N elsewhere; assembly only"},
+        "forms": res, "fp32_vs_fp64": {"matrix_rel_fro": err_a, "load_vector_rel": err_f},
+        "roofline": {"bound": "hbm", "kernel": "assemble_tensor_kernel<3,double>", "achieved": F["GB_s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": F["GB_s"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("assemble_c3", "fp64"),
+                     "bytes_per_launch": F["algorithmic_bytes"]},
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c3(api, W),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_c3(api, W, n=128):
+    """The CPU oracle (single thread, FP64) assembling the same problem on a
+    128 x 128 jittered mesh (32768 triangles, same recipe); Melem/s."""
+    import oracle as O
+    m, _ = build_c3(api, W, n)
+    M = O.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann)
+    sigma, kappa = O.default_penalty(O.IIPG, 3)
+    t0 = time.perf_counter()
+    O.assemble(M, 3, sigma=sigma, kappa=kappa, eps=1e-4, bx=O.Field.affine(0.5, 0.0, -1.0),
+               by=O.Field.affine(-0.5, 1.0, 0.0), alpha=0.5, f=1.0, gD=0.0, gN=0.0)
+    t = time.perf_counter() - t0
+    return {"value": M.T / t / 1e6, "unit": "Melem/s (FP64 assembly)", "cores": 1, "kind": "oracle",
+            "sample": "same problem on a %dx%d jittered mesh (%d triangles), %.2f s" % (n, n, M.T, t)}
+
+
 def bench_c5(args, api, W, torch):
     import numpy as np
     from paper_1502_02941_amd import learned as L
@@ -414,7 +505,7 @@ def cpu_baseline_c4(insts, sample=12):
                       % (len(pick), 100 * share, dt, ok)}
 
 
-def cpu_baseline(m, prob):
+def cpu_baseline(m, prob, iters):
     """The CPU oracle (single thread, FP64) on a bounded sample of the same
     workload: full assembly of the 256x256 P2 system, then 20 GMRES iterations;
     the solve rate is extrapolated from the measured per-iteration time and
@@ -429,14 +520,25 @@ def cpu_baseline(m, prob):
     B = O.assemble(M, DEGREE, sigma=sigma, kappa=kappa, eps=prob.eps, bx=prob.b[0], by=prob.b[1],
                    alpha=prob.alpha, f=O.Field.points(prob.f(pts[..., 0], pts[..., 1])))
     t_asm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    its = 20
-    O.gmres(B, restart=its, tol=1e-30, max_iters=its)
-    t_it = (time.perf_counter() - t0) / its
-    return {"value": M.T / t_asm / 1e6, "unit": "Melem/s (FP64 assembly)", "cores": 1, "kind": "oracle",
-            "sample": "full 256x256 P2 assembly (%.2f s) + %d GMRES iterations (%.3f s/iter, restart 20)"
-                      % (t_asm, its, t_it),
-            "gmres_s_per_iter": t_it}
+    # modified Gram-Schmidt: iteration j costs about alpha + beta j; two short
+    # single-cycle runs fix alpha and beta
+    runs = {}
+    for its in (10, 40):
+        t0 = time.perf_counter()
+        O.gmres(B, restart=its, tol=1e-30, max_iters=its)
+        runs[its] = time.perf_counter() - t0
+    s10, s40 = 10 * 11 / 2.0, 40 * 41 / 2.0
+    beta = (runs[40] - 4.0 * runs[10]) / (s40 - 4.0 * s10)
+    alpha = (runs[10] - beta * s10) / 10.0
+    J = iters
+    t_solve = J * alpha + beta * J * (J + 1) / 2.0
+    return {"value": 1.0 / (t_asm + t_solve), "unit": "solves/s (assemble + GMRES, extrapolated)", "cores": 1,
+            "kind": "oracle",
+            "sample": "full 256x256 P2 assembly (%.2f s, %.3f Melem/s) + single-cycle GMRES runs of 10 and 40 "
+                      "iterations (%.2f s, %.2f s) fitting t(j) = %.4f + %.2e j s per iteration, extrapolated to "
+                      "the %d iterations of one cycle that the FP64 GPU solve takes (%.1f s)"
+                      % (t_asm, M.T / t_asm / 1e6, runs[10], runs[40], alpha, beta, J, t_solve),
+            "assembly_melem_s": M.T / t_asm / 1e6}
 
 
 if __name__ == "__main__":
