@@ -336,7 +336,7 @@ def bench_c4(args, api, W, torch):
         "config": {"workload": "batched: %d instances, P1/P2, N~U{16..128}, Gaussian-sum f, SIPG" % len(insts),
                    "form": best_form, "triangles": n_el, "dofs": n_dofs},
         "forms": forms,
-        "roofline": {"bound": "hbm", "kernel": "batch_assemble_kernel + batch_kernel (whole batch)",
+        "roofline": {"bound": "hbm", "kernel": "batch_assemble_kernel + solve kernels of the tuned split (whole batch)",
                      "achieved": F["achieved_GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": F["achieved_GB_s"] / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c4(insts),

@@ -22,11 +22,19 @@ CACHE = os.environ.get("DGDCR_TUNE_CACHE", os.path.join(os.path.expanduser("~"),
 NONE = 1 << 62
 
 
-def candidates(n_cu):
+# Largest instance (unknowns) for which solving everything in the persistent
+# kernel is tried: one workgroup per instance leaves larger ones running alone
+# on a compute unit long after the rest (measured: 97 s instead of 3.5 s on a
+# 48-instance sample reaching 98k unknowns).
+PERSISTENT_ONLY_MAX_DOFS = 32768
+
+
+def candidates(n_cu, max_dofs=0):
     """Stage 1: split between the persistent solve (small instances) and the
     lockstep solve (large ones); later stages in tune_batch."""
     base = dict(block_threads=256, slots=2 * n_cu, restart_min=64, restart_per_side=2.0)
-    return [dict(base, lockstep_min_dofs=t) for t in (0, 16384, NONE)]
+    splits = (0, 16384, NONE) if max_dofs <= PERSISTENT_ONLY_MAX_DOFS else (0, 16384)
+    return [dict(base, lockstep_min_dofs=t) for t in splits]
 
 
 def stratified_sample(items, sizes, count, seed=0):
@@ -82,7 +90,7 @@ def tune_batch(api, instances, mixed, rel_tol=1e-10, inner_tol=1e-5, sample=48, 
         del b, x, rep
         torch.cuda.empty_cache()
 
-    for c in candidates(n_cu):
+    for c in candidates(n_cu, max(sizes)):
         measure(c)
     results.sort(key=lambda r: r[0])
     shape = dict(results[0][1])

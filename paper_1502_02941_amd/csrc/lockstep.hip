@@ -439,17 +439,49 @@ __global__ __launch_bounds__(LS_BT) void ls_update_kernel(const LsArgs A)
     P* w = (P*)A.w + I.x_off;
     const double* h = A.hcol + I.hc_off;
     const int64_t r0 = ch * LS_CH, r1 = min(r0 + LS_CH, I.n);
+    const int64_t n = I.n;
     double acc = 0.0;
-    for (int64_t t = r0 + threadIdx.x; t < r1; t += LS_BT) {
-        double wv = (double)w[t];
+    // E rows per thread advance through the columns together (4 columns x E
+    // rows of loads in flight)
+    constexpr int E = 4;
+    for (int64_t t0 = r0 + threadIdx.x; t0 < r1; t0 += (int64_t)LS_BT * E) {
+        double wr[E];
+        bool in[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t t = t0 + (int64_t)e * LS_BT;
+            in[e] = t < r1;
+            wr[e] = in[e] ? (double)w[t] : 0.0;
+        }
         int c = 0;
-        for (; c + 3 <= J; c += 4)
-            wv -= h[c] * (double)V[(int64_t)c * I.n + t] + h[c + 1] * (double)V[(int64_t)(c + 1) * I.n + t] +
-                  h[c + 2] * (double)V[(int64_t)(c + 2) * I.n + t] + h[c + 3] * (double)V[(int64_t)(c + 3) * I.n + t];
-        for (; c <= J; ++c) wv -= h[c] * (double)V[(int64_t)c * I.n + t];
-        const P pv = (P)wv;
-        w[t] = pv;
-        acc += (double)pv * (double)pv;
+        for (; c + 3 <= J; c += 4) {
+            const double h0 = h[c], h1 = h[c + 1], h2 = h[c + 2], h3 = h[c + 3];
+            const P* v0 = V + (int64_t)c * n;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t t = t0 + (int64_t)e * LS_BT;
+                if (in[e])
+                    wr[e] -= h0 * (double)v0[t] + h1 * (double)v0[t + n] + h2 * (double)v0[t + 2 * n] +
+                             h3 * (double)v0[t + 3 * n];
+            }
+        }
+        for (; c <= J; ++c) {
+            const double hc = h[c];
+            const P* vc = V + (int64_t)c * n;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t t = t0 + (int64_t)e * LS_BT;
+                if (in[e]) wr[e] -= hc * (double)vc[t];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (in[e]) {
+                const P pv = (P)wr[e];
+                w[t0 + (int64_t)e * LS_BT] = pv;
+                acc += (double)pv * (double)pv;
+            }
+        }
     }
     acc = ls_block_sum(acc, sh);
     if (threadIdx.x == 0) A.red[I.red_off + ch] = acc;

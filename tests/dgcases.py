@@ -27,6 +27,7 @@ class Case:
     sigma: float | None = None
     sigma_D: float | None = None
     tol: float = 1e-10
+    b0: float = 1.0      # superpenalty exponent: h_e = |e|^b0
 
     def penalty(self):
         if self.sigma is not None:
@@ -55,7 +56,7 @@ def oracle_system(c: Case):
         bx, by = O.Field.affine(*c.b[1]), O.Field.affine(*c.b[2])
     else:
         bx, by = O.Field.const(c.b[0]), O.Field.const(c.b[1])
-    B = O.assemble(M, c.k, sigma=sigma, kappa=kappa, sigma_D=c.sigma_D, eps=c.eps, bx=bx, by=by, alpha=c.alpha,
+    B = O.assemble(M, c.k, sigma=sigma, kappa=kappa, sigma_D=c.sigma_D, b0=c.b0, eps=c.eps, bx=bx, by=by, alpha=c.alpha,
                    **kw)
     return M, B
 
@@ -86,8 +87,8 @@ def gpu_problem(c: Case, mesh, api):
         bx, by = F.affine(*c.b[1]), F.affine(*c.b[2])
     else:
         bx, by = F.const(c.b[0]), F.const(c.b[1])
-    return api.Problem(method=c.method, degree=c.k, sigma=sigma, sigma_D=c.sigma_D or 0.0, eps=F.const(c.eps),
-                       bx=bx, by=by, alpha=F.const(c.alpha), f=f, gD=gD, gN=gN)
+    return api.Problem(method=c.method, degree=c.k, sigma=sigma, sigma_D=c.sigma_D or 0.0, b0=c.b0,
+                       eps=F.const(c.eps), bx=bx, by=by, alpha=F.const(c.alpha), f=f, gD=gD, gN=gN)
 
 
 def _gauss_terms(seed):
@@ -134,6 +135,18 @@ def small_cases():
     cases.append(Case("paper_e1_linear_p1", W.uniform_refine(W.uniform_refine(W.paper_mesh())), 1, 2, tl.eps, tl.b,
                       tl.alpha, tl.f, gD=tl.u))
     return cases
+
+
+def superpenalty_cases():
+    """b0 != 1 (h_e = |e|^b0): reference-tensor path with constant and with
+    rotating b, and the point path (P4)."""
+    out = []
+    for k, b, b0 in ((2, (0.8, -0.5), 2.0), (3, W.rotating_b(), 1.5), (4, (0.3, 0.9), 2.0)):
+        pr = W.polynomial_problem(k + 1, 0.02, b, 0.5, seed=200 + k)
+        m = W.structured_mesh(9, dirichlet=("top", "left"), neumann=("bottom", "right"), jitter=0.2, seed=70 + k)
+        out.append(Case("jit9_p%d_sipg_b0_%g" % (k, b0), m, k, 2, pr.eps, pr.b, pr.alpha, pr.f, gD=pr.u, gN=pr.gN,
+                        b0=b0))
+    return out
 
 
 def c2_full(method=2):

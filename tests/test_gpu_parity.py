@@ -58,6 +58,18 @@ def test_fp64_assembly_matches_oracle(api, case):
     assert np.abs(bg - B.rhs).max() <= 1e-12 * max(np.abs(B.rhs).max(), 1e-300)
 
 
+SUPER = DC.superpenalty_cases()
+
+
+@pytest.mark.parametrize("case", SUPER, ids=[c.name for c in SUPER])
+def test_superpenalty_assembly_matches_oracle(api, case):
+    """h_e = |e|^b0 with b0 != 1 on both assembly paths."""
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    M, B = DC.oracle_system(case)
+    assert DC.rel_fro(api.bsr_to_scipy(mesh, vals).tocsr(), B.to_scipy()) <= 1e-12
+    assert DC.rel_fro(rhs.cpu().numpy(), B.rhs) <= 1e-12
+
+
 @pytest.mark.parametrize("parts", [1, 2, 4, 3, 6])
 def test_parts_match_oracle(api, parts):
     case = SMALL[3]
