@@ -141,6 +141,20 @@ int32_t dg_mesh_structure(const dg_mesh* mesh, int32_t* dev_row_ptr, int32_t* de
 int32_t dg_mesh_qpoints(const dg_mesh* mesh, double* dev_vol_xy, double* dev_bnd_xy, double* dev_bnd_normal,
                         int32_t* dev_bnd_type, void* stream);
 
+/* L2 error of a DG solution (dg_error of section 2.4): ||u_h - u||_L2(Omega)
+ * with a Stroud conical rule of q = k + 4 points per direction on every
+ * element (exact for u_h^2), and h_max = the longest element edge.
+ * dg_mesh_error_points writes that rule's physical points, dev_xy
+ * [n_elems][(k+4)^2][2] (FP64, caller-owned), where the caller evaluates u.
+ * dg_l2_error reads dev_x [n_dofs] (the coefficients) and dev_exact
+ * [n_elems][(k+4)^2] (u at those points), writes *l2 and *h_max (host; either
+ * may be NULL) and synchronises `stream`.  The sum is reduced in a fixed order
+ * (deterministic) through a buffer owned by the mesh: calls on one mesh must
+ * not overlap. */
+int32_t dg_mesh_error_points(const dg_mesh* mesh, double* dev_xy, void* stream);
+int32_t dg_l2_error(const dg_mesh* mesh, const double* dev_x, const double* dev_exact, double* l2, double* h_max,
+                    void* stream);
+
 /* Assembles the parts of D + C + R selected by `parts` into dev_vals
  * ([nnzb][n_loc][n_loc], FP64 if prec == DG_F64 else FP32) and the load
  * vector F_i = l_h(phi_i) (section 1 eq. (ds)) into dev_rhs ([n_dofs], same

@@ -87,7 +87,8 @@ EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_
            "dg_solver_destroy", "dg_residual", "dg_status_str", "dg_solver_profile",
            "dg_batch_create", "dg_batch_offsets", "dg_batch_run", "dg_batch_destroy", "dg_batch_progress",
            "dg_batch_set_progress", "dg_mlp_create", "dg_mlp_num_params", "dg_mlp_forward", "dg_mlp_loss_mse",
-           "dg_mlp_backward", "dg_mlp_adam_step", "dg_mlp_params", "dg_mlp_destroy", "dg_warmstart_prolong"]
+           "dg_mlp_backward", "dg_mlp_adam_step", "dg_mlp_params", "dg_mlp_destroy", "dg_warmstart_prolong",
+           "dg_mesh_error_points", "dg_l2_error"]
 
 _lib = None
 
@@ -132,6 +133,8 @@ def lib():
         L.dg_mlp_destroy.argtypes = [P]
         L.dg_mlp_destroy.restype = None
         L.dg_warmstart_prolong.argtypes = [P, P, I32, I32, I32, P, I64, P]
+        L.dg_mesh_error_points.argtypes = [P, P, P]
+        L.dg_l2_error.argtypes = [P, P, P, C.POINTER(C.c_double), C.POINTER(C.c_double), P]
         L.dg_batch_destroy.argtypes = [P]
         L.dg_batch_destroy.restype = None
         L.dg_status_str.argtypes = [I32]
@@ -558,3 +561,24 @@ def warmstart_prolong(mesh: Mesh, coarse: torch.Tensor, nc: int, mode: int, x: t
     _check(lib().dg_warmstart_prolong(mesh._h, _dptr(coarse), coarse.shape[0], int(nc), int(mode), _dptr(x),
                                       x.shape[1], _stream(stream)), "dg_warmstart_prolong")
     return x
+
+
+def error_points(mesh: Mesh, stream=None):
+    """dg_mesh_error_points: [T, (k+4)^2, 2] physical points of the error rule."""
+    q = mesh.info["degree"] + 4
+    out = torch.empty(mesh.T, q * q, 2, dtype=torch.float64, device="cuda")
+    _check(lib().dg_mesh_error_points(mesh._h, _dptr(out), _stream(stream)), "dg_mesh_error_points")
+    return out
+
+
+def l2_error(mesh: Mesh, x: torch.Tensor, exact, stream=None):
+    """dg_l2_error: (||u_h - u||_L2, h_max).  exact: values at error_points()
+    ([T, (k+4)^2] FP64 tensor) or a function u(x, y) of numpy arrays."""
+    if callable(exact):
+        pts = error_points(mesh, stream).cpu().numpy()
+        exact = torch.from_numpy(np.ascontiguousarray(exact(pts[..., 0], pts[..., 1]), dtype=np.float64)).cuda()
+    exact = exact.contiguous().to(torch.float64)
+    l2, hmax = C.c_double(), C.c_double()
+    _check(lib().dg_l2_error(mesh._h, _dptr(x), _dptr(exact), C.byref(l2), C.byref(hmax), _stream(stream)),
+           "dg_l2_error")
+    return l2.value, hmax.value

@@ -555,3 +555,89 @@ extern "C" int32_t dg_assemble(const dg_mesh* m, const dg_problem* P, int32_t pr
     a.rhs = dev_rhs;
     return launch_assemble(m, a, prec, (hipStream_t)stream);
 }
+
+// ---------------------------------------------------------------------------
+// L2 error of a DG solution (dg_error, section 2.4).
+// ---------------------------------------------------------------------------
+namespace dg {
+
+__global__ void error_points_kernel(const double* __restrict__ xy, const double* __restrict__ et, int nq, int64_t T,
+                                    double* __restrict__ out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= T * nq) return;
+    const int64_t K = idx / nq;
+    const int g = (int)(idx - K * nq);
+    const double* p = xy + 6 * K;
+    const double xi = et[nq + g], eta = et[2 * nq + g];
+    out[2 * idx] = p[0] + (p[2] - p[0]) * xi + (p[4] - p[0]) * eta;
+    out[2 * idx + 1] = p[1] + (p[3] - p[1]) * xi + (p[5] - p[1]) * eta;
+}
+
+// Fixed grid of ERR_BLOCKS workgroups striding over (element, point) pairs:
+// the order of every sum is fixed by the launch, so the result is
+// deterministic.  part[b] = sum of w_g det_K (u_h - u)^2 over block b's pairs.
+__global__ __launch_bounds__(256) void l2_error_kernel(const double* __restrict__ xy, const double* __restrict__ et,
+                                                       int nq, int n, int64_t T, const double* __restrict__ x,
+                                                       const double* __restrict__ exact, double* __restrict__ part)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    const int64_t tot = T * nq;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < tot; idx += (int64_t)ERR_BLOCKS * 256) {
+        const int64_t K = idx / nq;
+        const int g = (int)(idx - K * nq);
+        const double* p = xy + 6 * K;
+        const double det = (p[2] - p[0]) * (p[5] - p[1]) - (p[4] - p[0]) * (p[3] - p[1]);
+        const double* phi = et + 3 * nq + (int64_t)g * n;
+        double uh = 0.0;
+        for (int m = 0; m < n; ++m) uh += x[K * n + m] * phi[m];
+        const double d = uh - exact[idx];
+        acc += et[g] * det * d * d;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(256) void sum_parts_kernel(double* part)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < ERR_BLOCKS; i += 256) acc += part[i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[ERR_BLOCKS] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+}  // namespace dg
+
+extern "C" int32_t dg_mesh_error_points(const dg_mesh* m, double* dev_xy, void* stream)
+{
+    if (!m || !dev_xy) return DG_ERR_ARG;
+    const int64_t tot = m->T * m->nqr;
+    if (tot > 0)
+        hipLaunchKernelGGL(dg::error_points_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                           (hipStream_t)stream, m->d_xy, m->d_etab, m->nqr, m->T, dev_xy);
+    return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
+}
+
+extern "C" int32_t dg_l2_error(const dg_mesh* m, const double* dev_x, const double* dev_exact, double* l2,
+                               double* h_max, void* stream)
+{
+    if (!m || !dev_x || !dev_exact) return DG_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(dg::l2_error_kernel, dim3(dg::ERR_BLOCKS), dim3(256), 0, s, m->d_xy, m->d_etab, m->nqr, m->n,
+                       m->T, dev_x, dev_exact, m->d_epart);
+    hipLaunchKernelGGL(dg::sum_parts_kernel, dim3(1), dim3(256), 0, s, m->d_epart);
+    double ssq = 0.0;
+    DG_HIP_CHECK(hipGetLastError());
+    DG_HIP_CHECK(hipMemcpyAsync(&ssq, m->d_epart + dg::ERR_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, s));
+    DG_HIP_CHECK(hipStreamSynchronize(s));
+    if (!std::isfinite(ssq)) return DG_ERR_NONFINITE;
+    if (l2) *l2 = std::sqrt(ssq);
+    if (h_max) *h_max = m->hmax;
+    return DG_OK;
+}

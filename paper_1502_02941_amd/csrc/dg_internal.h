@@ -126,12 +126,18 @@ struct dg_mesh {
     double* d_ten64 = nullptr;  // [3][TenStage::COUNT] n x n staged tensors per kappa (k <= 3)
     float* d_ten32 = nullptr;
     double* d_p1map = nullptr;  // [3][3]: P1 coefficients from vertex values (k >= 1)
+    double* d_etab = nullptr;   // error rule (q = k + 4): w[nqr], xi[nqr], eta[nqr], phi[nqr][n]
+    double* d_epart = nullptr;  // [ERR_BLOCKS + 1] partial sums of dg_l2_error
+    int nqr = 0;
 };
 
 namespace dg {
 // Host-side reference tables for degree k (Golub-Welsch quadrature, Dubiner
 // basis in collapsed coordinates); returns TabLayout(k).size values.
 std::vector<double> build_tables(int k);
+// Error rule of dg_l2_error: Stroud q = k + 4; [w, xi, eta, phi[nqr][n]].
+std::vector<double> build_error_table(int k, int* nqr);
+constexpr int ERR_BLOCKS = 1024;
 // Reference tensors (TenLayout) of degree k from the tables of build_tables.
 std::vector<double> build_tensors(int k, const std::vector<double>& tab);
 // Gauss-Jacobi rule for the weight (1-x)^a (1+x)^b on [-1,1].

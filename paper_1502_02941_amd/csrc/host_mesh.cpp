@@ -257,13 +257,34 @@ std::vector<double> stage_tensors(int k, const std::vector<double>& ten, double 
     return st;
 }
 
+std::vector<double> build_error_table(int k, int* nqr)
+{
+    const int q = k + 4, nq = q * q, n = (k + 1) * (k + 2) / 2;
+    std::vector<double> t((size_t)nq * (3 + n));
+    double ga[16], gwa[16], gb[16], gwb[16], v[32], dx[32], de[32];
+    gauss_jacobi_gw(q, 0.0, 0.0, ga, gwa);
+    gauss_jacobi_gw(q, 1.0, 0.0, gb, gwb);
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
+            const int g = i * q + j;
+            const double xi = 0.25 * (1.0 + ga[i]) * (1.0 - gb[j]), eta = 0.5 * (1.0 + gb[j]);
+            t[g] = 0.125 * gwa[i] * gwb[j];
+            t[nq + g] = xi;
+            t[2 * nq + g] = eta;
+            dubiner_at(k, xi, eta, v, dx, de);
+            for (int m = 0; m < n; ++m) t[3 * nq + (size_t)g * n + m] = v[m];
+        }
+    *nqr = nq;
+    return t;
+}
+
 static void free_device(dg_mesh* m)
 {
     hipFree(m->d_xy); hipFree(m->d_nbr); hipFree(m->d_nbr_edge); hipFree(m->d_row_ptr);
     hipFree(m->d_col_idx); hipFree(m->d_bnd_type); hipFree(m->d_bnd_el); hipFree(m->d_bnd_loc);
     hipFree(m->d_bnd_elems);
     hipFree(m->d_tab64); hipFree(m->d_tab32); hipFree(m->d_p1map); hipFree(m->d_ten64); hipFree(m->d_ten32);
-    hipFree(m->d_gt);
+    hipFree(m->d_gt); hipFree(m->d_etab); hipFree(m->d_epart);
 }
 
 template <typename T>
@@ -449,6 +470,8 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
     if (st == DG_OK) st = upload(&m->d_bnd_elems, m->bnd_elems);
     if (st == DG_OK) st = upload(&m->d_tab64, m->tab64);
     if (st == DG_OK) st = upload(&m->d_tab32, tab32);
+    if (st == DG_OK) st = upload(&m->d_etab, build_error_table(degree, &m->nqr));
+    if (st == DG_OK) st = upload(&m->d_epart, std::vector<double>(ERR_BLOCKS + 1, 0.0));
     if (st == DG_OK) {
         std::vector<double> gt((size_t)4 * m->T);
         for (int64_t K = 0; K < m->T; ++K) {
