@@ -17,6 +17,8 @@ Other workloads (not the default line):
      log10 eps ~ U[-6,-1], b angle ~ U[0, 2 pi], |b| ~ U[0.5, 2], alpha ~ U[0, 1], f = sum of 4
      Gaussians, g^D = 0, SIPG; one element-parallel assembly launch + one persistent solve
      launch per batch, launch shape picked by the autotuner; step = the whole batch.
+  --workload c1: latency of one solve of the 8 x 8 P1 SIPG problem (128 triangles, sigma = 6, eps = 1e-2,
+     b = (1, 1), alpha = 1, u = sin(pi x) sin(pi y)): assembly + block-Jacobi setup + GMRES to 1e-12.
   --workload c3: assembly only, 512 x 512 squares jittered by +-0.2 h (seed 0, 524288 triangles), P3 IIPG
      sigma = 36 (72 on Dirichlet), rotating b = (-(y - 1/2), x - 1/2), eps = 1e-4, alpha = 1/2, f = 1,
      Dirichlet on x = 0 and y = 0, g^N = 0 elsewhere; FP64 and FP32 assembly, FP32 error vs FP64.
@@ -24,7 +26,7 @@ Other workloads (not the default line):
      zero guess vs the learned initial guess (perceptron + prolongation, model trained on 20000
      method solves of seed 1), FP64 and mixed cycles; step = the whole batch incl. the network.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c2|c3|c4|c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c1|c2|c3|c4|c5]
        python bench.py --profile-run     (one FP64 step + a copy probe, for rocprofv3)
 """
 from __future__ import annotations
@@ -105,7 +107,7 @@ def main():
     ap.add_argument("--restart", type=int, default=2 * N_GRID + 64)
     ap.add_argument("--reorth", type=int, default=0, help="1: conditional second Gram-Schmidt pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"))
+    ap.add_argument("--workload", default="c2", choices=("c1", "c2", "c3", "c4", "c5"))
     ap.add_argument("--count", type=int, default=None, help="c4 / c5: number of instances (4096 / 512)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one FP64 step and a 512 MiB device copy (counter scaling), no JSON baseline")
@@ -130,6 +132,8 @@ def main():
         return bench_c5(args, api, W, torch)
     if args.workload == "c3":
         return bench_c3(args, api, W, torch)
+    if args.workload == "c1":
+        return bench_c1(args, api, W, torch)
     log("building workload %dx%d P%d" % (N_GRID, N_GRID, DEGREE))
     m, mesh, P, prob = build_workload(api, W, torch)
     vals64, rhs64 = mesh.alloc_system(api.F64)
@@ -342,6 +346,76 @@ def bench_c4(args, api, W, torch):
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c4(insts),
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_c1(args, api, W, torch):
+    import numpy as np
+    m = W.structured_mesh(8)
+    prob = W.sinsin_problem()
+    mesh = api.Mesh.from_arrays(m, 1)
+    vol = mesh.qpoints()[0].cpu().numpy()
+    f = api.Field.qpoints(torch.from_numpy(np.ascontiguousarray(prob.f(vol[..., 0], vol[..., 1]))).cuda())
+    gd_pts = mesh.qpoints()[1].cpu().numpy()
+    gD = api.Field.qpoints(torch.from_numpy(np.ascontiguousarray(prob.u(gd_pts[..., 0], gd_pts[..., 1]))).cuda())
+    sigma, _ = api.default_penalty(api.SIPG, 1)
+    P = api.Problem(api.SIPG, 1, sigma, eps=prob.eps, bx=prob.b[0], by=prob.b[1], alpha=prob.alpha, f=f, gD=gD)
+    vals, rhs = mesh.alloc_system(api.F64)
+    x = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    s = api.Solver(mesh, restart=64, max_iters=5000, rel_tol=1e-12)
+
+    def step():
+        api.assemble(mesh, P, prec=api.F64, vals=vals, rhs=rhs)
+        s.setup(vals)
+        x.zero_()
+        return s.solve(rhs, x)  # synchronises
+
+    for _ in range(max(args.warmup, 3)):
+        step()
+    reps = max(args.steps, 1) * 100
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = step()
+        ts.append(time.perf_counter() - t0)
+    ts = np.array(ts)
+    l2, _ = api.l2_error(mesh, x, prob.u)
+    log("c1: median %.3f ms, p90 %.3f ms, %d iterations, rel-res %.2e, L2 error %.3e"
+        % (np.median(ts) * 1e3, np.percentile(ts, 90) * 1e3, r.iters, r.rel_res, l2))
+    line = {
+        "metric": "DG assembly Melem/s; solves/s at rel-res 1e-10, learned+mixed vs plain FP64",
+        "value": float(np.median(ts) * 1e3), "unit": "ms per solve (assemble + setup + GMRES to rel-res 1e-12, "
+                                                      "host-synchronised, median)",
+        "n_gpus": 1, "steps": reps, "warmup": max(args.warmup, 3), "ms_per_step": float(np.median(ts) * 1e3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (manufactured solution)",
+        "config": {"workload": "8x8 structured, P1 SIPG (128 triangles, 384 dofs), sigma=6, eps=1e-2, b=(1,1), "
+                               "alpha=1, u=sin(pi x)sin(pi y)", "p90_ms": float(np.percentile(ts, 90) * 1e3),
+                   "iters": int(r.iters), "rel_res": float(r.rel_res), "l2_error": float(l2)},
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c1(m, prob),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_c1(m, prob, reps=20):
+    """The CPU oracle (single thread, FP64): assembly + GMRES(64) to 1e-12 of
+    the same problem, median of `reps` runs."""
+    import numpy as np
+    import oracle as O
+    M = O.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann)
+    pts = M.volume_points(3)
+    bp, _ = M.boundary_points(3)
+    sigma, kappa = O.default_penalty(O.SIPG, 1)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        B = O.assemble(M, 1, sigma=sigma, kappa=kappa, eps=prob.eps, bx=prob.b[0], by=prob.b[1], alpha=prob.alpha,
+                       f=O.Field.points(prob.f(pts[..., 0], pts[..., 1])),
+                       gD=O.Field.points(prob.u(bp[..., 0], bp[..., 1])))
+        O.gmres(B, restart=64, tol=1e-12, max_iters=5000)
+        ts.append(time.perf_counter() - t0)
+    return {"value": float(np.median(ts) * 1e3), "unit": "ms per solve", "cores": 1, "kind": "oracle",
+            "sample": "the full problem, median of %d runs" % reps}
 
 
 def build_c3(api, W, n=512):

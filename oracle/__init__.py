@@ -76,6 +76,8 @@ def lib():
         L.orc_eval_solution.argtypes = [P, C.c_int, P, I64, P, P, P]
         L.orc_l2_error.argtypes = [P, C.c_int, P, C.c_int, P]
         L.orc_l2_error.restype = D
+        L.orc_reaction_terms.argtypes = [P, C.c_int, C.c_int, P, P, P, P]
+        L.orc_reaction_terms.restype = C.c_int
         _lib = L
     return _lib
 
@@ -331,3 +333,47 @@ def l2_error(mesh: Mesh, k: int, coef, exact_fn, q=None):
     ex = np.ascontiguousarray(exact_fn(pts[..., 0], pts[..., 1]), dtype=np.float64)
     coef = np.ascontiguousarray(coef, dtype=np.float64)
     return float(lib().orc_l2_error(mesh._h, k, _ptr(coef), q, _ptr(ex)))
+
+
+# ----------------------------------------------------------------------------
+# Non-linear reaction and Newton's method (section 3).
+# ----------------------------------------------------------------------------
+def reaction_terms(mesh: Mesh, k: int, c, coef):
+    """H_i = int r(u_h) phi_i and the diagonal blocks HJ[K] (row = test) of its
+    Jacobian, r(u) = sum_p c[p-1] u^p, with the assembly's volume rule."""
+    n = (k + 1) * (k + 2) // 2
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    h = np.zeros(mesh.T * n)
+    hj = np.zeros((mesh.T, n, n))
+    st = lib().orc_reaction_terms(mesh._h, k, len(c), _ptr(c), _ptr(coef), _ptr(h), _ptr(hj))
+    if st != 0:
+        raise OracleError("orc_reaction_terms: %d" % st)
+    return h, hj
+
+
+def newton(mesh: Mesh, k: int, blocks, c, tol=1e-10, max_newton=50, x0=None):
+    """Newton's method for (D + C + R) v + H(v) = F: J w = -Res, v <- v + w with
+    Res = A v + H(v) - F and J = A + HJ(v); every linear system is solved
+    directly.  Stops when ||Res|| / ||F|| <= tol (checked before each step).
+    Returns (v, newton steps, final relative residual, converged)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    A = blocks.to_scipy().tocsr()
+    F = blocks.rhs
+    n = (k + 1) * (k + 2) // 2
+    T = mesh.T
+    x = np.zeros(T * n) if x0 is None else np.array(x0, dtype=np.float64)
+    fn = np.linalg.norm(F)
+    rel = np.inf
+    for it in range(max_newton + 1):
+        h, hj = reaction_terms(mesh, k, c, x)
+        res = A @ x + h - F
+        rel = np.linalg.norm(res) / fn
+        if rel <= tol:
+            return x, it, rel, True
+        if it == max_newton:
+            break
+        HJ = sp.bsr_matrix((hj, np.arange(T), np.arange(T + 1)), shape=(T * n, T * n))
+        x = x + spl.spsolve((A + HJ).tocsc(), -res)
+    return x, max_newton, rel, False

@@ -977,3 +977,48 @@ double orc_l2_error(const orc_mesh* M, int k, const double* coef, int q, const d
     }
     return sqrt(s);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Non-linear reaction (section 3): H_i(v) = int r(u_h) phi_i and its        */
+/* Jacobian HJ_ij = int r'(u_h) phi_j phi_i, with r(u) = sum_p c_p u^p        */
+/* (p = 1..np) and the volume rule of the assembly (q = k + 2).  HJ is       */
+/* element-local: hj[K][i][j] is the diagonal block of element K (row = test */
+/* i, column = trial j).  Either output may be NULL.                          */
+/* ------------------------------------------------------------------------ */
+int orc_reaction_terms(const orc_mesh* M, int k, int np, const double* c, const double* coef, double* h, double* hj)
+{
+    if (k < 0 || k > ORC_MAXK || np < 0 || np > 8) return ORC_ERR_ARG;
+    basis_t B;
+    build_basis(k, &B);
+    const int n = B.n, q = k + 2;
+    double xi[ORC_MAXQ * ORC_MAXQ], eta[ORC_MAXQ * ORC_MAXQ], w[ORC_MAXQ * ORC_MAXQ];
+    const int nq = orc_volume_rule(q, xi, eta, w);
+    double v[ORC_MAXN];
+    for (int64_t K = 0; K < M->T; ++K) {
+        affine_t A;
+        element_map(M, K, &A);
+        if (h)
+            for (int i = 0; i < n; ++i) h[K * n + i] = 0.0;
+        if (hj)
+            for (int i = 0; i < n * n; ++i) hj[K * n * n + i] = 0.0;
+        for (int g = 0; g < nq; ++g) {
+            eval_basis(&B, xi[g], eta[g], v, NULL, NULL);
+            double u = 0.0;
+            for (int m = 0; m < n; ++m) u += coef[K * n + m] * v[m];
+            /* r(u) and r'(u) term by term */
+            double r = 0.0, dr = 0.0, up = 1.0; /* up = u^(p-1) */
+            for (int p = 1; p <= np; ++p) {
+                dr += p * c[p - 1] * up;
+                up *= u;
+                r += c[p - 1] * up;
+            }
+            const double dx = w[g] * A.det;
+            if (h)
+                for (int i = 0; i < n; ++i) h[K * n + i] += dx * r * v[i];
+            if (hj)
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) hj[(K * n + i) * n + j] += dx * dr * v[j] * v[i];
+        }
+    }
+    return ORC_OK;
+}

@@ -35,6 +35,9 @@ MUTANTS = {
     "jacobi_alpha_off_by_one": ("double al = 2.0 * p + 1.0;", "double al = 2.0 * p;"),
     "drop_neumann_data": ("for (int a = 0; a < n; ++a) rhs[K * n + a] += ds * gn * v[a];", "(void)gn;"),
     "volume_det_missing": ("const double dx = wv[g] * A.det;", "const double dx = wv[g];"),
+    "reaction_derivative_drops_power": ("dr += p * c[p - 1] * up;", "dr += c[p - 1] * up;"),
+    "reaction_det_missing": ("const double dx = w[g] * A.det;", "const double dx = w[g];"),
+    "reaction_power_off_by_one": ("r += c[p - 1] * up;", "r += c[p - 1] * up * u;"),
 }
 
 

@@ -570,3 +570,95 @@ def test_brute_force_two_triangles_sympy(kappa_int):
     Ao = B.to_scipy().toarray()
     assert np.abs(Ao - An).max() <= 1e-13 * np.abs(An).max()
     assert np.abs(B.rhs - Fn).max() <= 1e-13 * np.abs(Fn).max()
+
+
+# ------------------------------------------------------- non-linear reaction
+def _random_mesh(n=5, seed=3):
+    return omesh(W.structured_mesh(n, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=seed))
+
+
+def _dets(M, k):
+    """det J of every element, from the oracle's own points (|K| = det / 2)."""
+    m = W.structured_mesh(5, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=3)
+    p = m.nodes[m.elems]
+    return (p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1]) - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1])
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_reaction_terms_linear_r_is_the_mass_matrix(k):
+    """r(u) = u: H = M v and HJ = M, with M_K = det_K I for the orthonormal basis."""
+    M = _random_mesh()
+    n = (k + 1) * (k + 2) // 2
+    x = np.random.default_rng(k).standard_normal(M.T * n)
+    h, hj = O.reaction_terms(M, k, [1.0], x)
+    det = _dets(M, k)
+    np.testing.assert_allclose(h, np.repeat(det, n) * x, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(hj, det[:, None, None] * np.eye(n)[None], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_reaction_terms_square_on_piecewise_constants(k):
+    """r(u) = u^2 with only the constant mode (u_h = sqrt(2) c0 on K):
+    H_i = sqrt(2) c0^2 det delta_i0, HJ = 2 sqrt(2) c0 det I."""
+    M = _random_mesh()
+    n = (k + 1) * (k + 2) // 2
+    c0 = np.random.default_rng(7).uniform(-2, 2, M.T)
+    x = np.zeros(M.T * n)
+    x[0::n] = c0
+    h, hj = O.reaction_terms(M, k, [0.0, 1.0], x)
+    det = _dets(M, k)
+    ref = np.zeros((M.T, n))
+    ref[:, 0] = math.sqrt(2.0) * c0 ** 2 * det
+    np.testing.assert_allclose(h.reshape(M.T, n), ref, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(hj, (2.0 * math.sqrt(2.0) * c0 * det)[:, None, None] * np.eye(n)[None], rtol=1e-12,
+                               atol=1e-13)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_reaction_jacobian_matches_finite_differences(k):
+    """HJ = dH/dv (element-local): central differences of H, r = u^2 + 0.5 u^3 - 0.2 u^4."""
+    M = _random_mesh()
+    n = (k + 1) * (k + 2) // 2
+    c = [0.0, 1.0, 0.5, -0.2]
+    x = np.random.default_rng(k + 10).standard_normal(M.T * n) * 0.7
+    _, hj = O.reaction_terms(M, k, c, x)
+    d = 1e-6
+    for K in (0, M.T // 2, M.T - 1):
+        for j in range(n):
+            e = np.zeros_like(x)
+            e[K * n + j] = d
+            col = (O.reaction_terms(M, k, c, x + e)[0] - O.reaction_terms(M, k, c, x - e)[0]) / (2 * d)
+            np.testing.assert_allclose(col[K * n:(K + 1) * n], hj[K][:, j], rtol=1e-6, atol=1e-8)
+            other = np.delete(col, np.arange(K * n, (K + 1) * n))
+            assert np.abs(other).max() == 0.0  # no coupling to other elements
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("kappa", [-1.0, 0.0, 1.0])
+def test_newton_reproduces_polynomials_with_square_reaction(k, kappa):
+    """With r(u) = u^2 and f = alpha u - eps Lap u + b . grad u + u^2 for a global
+    u in P_k, the discrete non-linear problem has u as its exact solution
+    (every integrand is integrated exactly for k <= 3); Newton from zero finds
+    it, with quadratic convergence.  u is shifted to stay positive, where r is
+    monotone as section 3 assumes (for u < 0 the discrete problem can have
+    other solutions)."""
+    prob = W.polynomial_problem(k, 0.05, (0.6, -0.4), 0.3, seed=40 + k)
+    g = np.linspace(0, 1, 41)
+    shift = 0.2 - min(0.0, prob.u(*np.meshgrid(g, g)).min())
+    u = lambda X, Y: prob.u(X, Y) + shift  # the constant adds alpha * shift to f, nothing to g^N
+    m = W.structured_mesh(6, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=k)
+    M = omesh(m)
+    q = k + 2
+    pts = M.volume_points(q)
+    bp, nrm = M.boundary_points(q)
+    fnl = lambda X, Y: prob.f(X, Y) + prob.alpha * shift + u(X, Y) ** 2
+    sigma = 3.0 * k * (k + 1) if kappa != 1.0 else 1.0
+    B = O.assemble(M, k, sigma=sigma, kappa=kappa, eps=prob.eps, bx=0.6, by=-0.4, alpha=prob.alpha,
+                   f=O.Field.points(fnl(pts[..., 0], pts[..., 1])), gD=O.Field.points(u(bp[..., 0], bp[..., 1])),
+                   gN=O.Field.points(prob.gN(bp[..., 0], bp[..., 1], nrm[:, None, 0], nrm[:, None, 1])))
+    x, its, rel, conv = O.newton(M, k, B, [0.0, 1.0], tol=1e-13, max_newton=30)
+    assert conv and its <= 12, (its, rel)
+    X, Y = pts[..., 0].ravel(), pts[..., 1].ravel()
+    uh = O.eval_solution(M, k, x, np.repeat(np.arange(M.T), q * q), np.stack([X, Y], 1))
+    ue = u(X, Y)
+    assert np.abs(uh - ue).max() <= 1e-9 * np.abs(ue).max()
