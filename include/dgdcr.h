@@ -229,6 +229,53 @@ typedef struct {
 } dg_kernel_stats;
 int32_t dg_solver_profile(dg_solver* solver, dg_kernel_stats* out, int32_t max, int32_t* count, int32_t reset);
 
+/* ------------------------------------------------------------------------
+ * Non-linear reaction (section 3): alpha u - eps Lap u + b . grad u + r(u) = f
+ * with the discrete system (D + C + R) v + H(v) = F, H_i(v) = int r(u_h) phi_i
+ * (eq. (nonlinsystem)), solved by Newton's method, eq. (newton):
+ * J w = -Res, v <- v + w, Res = (D + C + R) v + H(v) - F, J = D + C + R + HJ(v).
+ * r is a polynomial without constant term, r(u) = sum_{p=1..n} c[p-1] u^p
+ * (r(0) = 0 as section 3 requires; the paper's example is r(u) = u^2).  The
+ * integrals use the volume rule of the assembly.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n;            /* number of terms, 0..8 */
+    int32_t reserved;
+    double c[8];          /* c[p-1]: coefficient of u^p */
+} dg_reaction;
+
+/* H(v) (dev_h [n_dofs]) and the diagonal blocks of its Jacobian HJ_ij =
+ * int r'(u_h) phi_j phi_i (dev_hj [n_elems][n_loc][n_loc], row = test i; HJ
+ * is element-local, so it has no other blocks) at the coefficients dev_x,
+ * FP64.  Either output may be NULL. */
+int32_t dg_reaction_terms(const dg_mesh* mesh, const dg_reaction* r, const double* dev_x, double* dev_h,
+                          double* dev_hj, void* stream);
+
+typedef struct {
+    int32_t max_newton;   /* cap on Newton steps */
+    int32_t reserved;
+    double tol;           /* stop when ||Res||_2 / ||F||_2 <= tol (checked before every step) */
+} dg_newton_opts;
+
+typedef struct {
+    int32_t status;       /* DG_OK, DG_NOT_CONVERGED or an error */
+    int32_t newton_steps; /* linear systems solved */
+    int64_t linear_iters; /* GMRES iterations over all steps */
+    double rel_res;       /* ||Res|| / ||F|| of the returned v (FP64) */
+} dg_newton_report;
+
+/* Newton's method for the mesh's system: dev_vals64 = D + C + R (FP64 BSR from
+ * dg_assemble, caller-owned), dev_rhs = F, dev_x the initial guess on entry
+ * (zero in the paper) and the solution on exit.  Each step solves J w = -Res
+ * with `solver` (created for this mesh; its options set the linear tolerance,
+ * restart and precision) from the zero guess.  Allocates the Jacobian's values
+ * and three vectors for the duration of the call; synchronises `stream`.  On
+ * return the solver holds no matrix (dg_solver_solve returns DG_ERR_ARG until
+ * the next dg_solver_setup). */
+int32_t dg_newton_solve(const dg_mesh* mesh, const dg_reaction* r, const dg_newton_opts* opts, dg_solver* solver,
+                        const double* dev_vals64, const double* dev_rhs, double* dev_x, dg_newton_report* report,
+                        void* stream);
+
 /* y = b - A x in FP64 with the BSR values of the mesh (dev_b may be NULL: y = -A x). */
 int32_t dg_residual(const dg_mesh* mesh, const double* dev_vals64, const double* dev_b, const double* dev_x,
                     double* dev_y, void* stream);

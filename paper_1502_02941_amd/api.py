@@ -75,6 +75,19 @@ class _BatchOpts(C.Structure):
                 ("lockstep_mem_gb", C.c_double), ("guess_limit", C.c_double)]
 
 
+class _Reaction(C.Structure):
+    _fields_ = [("n", C.c_int32), ("reserved", C.c_int32), ("c", C.c_double * 8)]
+
+
+class _NewtonOpts(C.Structure):
+    _fields_ = [("max_newton", C.c_int32), ("reserved", C.c_int32), ("tol", C.c_double)]
+
+
+class _NewtonReport(C.Structure):
+    _fields_ = [("status", C.c_int32), ("newton_steps", C.c_int32), ("linear_iters", C.c_int64),
+                ("rel_res", C.c_double)]
+
+
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32)
 
 
@@ -88,7 +101,7 @@ EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_
            "dg_batch_create", "dg_batch_offsets", "dg_batch_run", "dg_batch_destroy", "dg_batch_progress",
            "dg_batch_set_progress", "dg_mlp_create", "dg_mlp_num_params", "dg_mlp_forward", "dg_mlp_loss_mse",
            "dg_mlp_backward", "dg_mlp_adam_step", "dg_mlp_params", "dg_mlp_destroy", "dg_warmstart_prolong",
-           "dg_mesh_error_points", "dg_l2_error"]
+           "dg_mesh_error_points", "dg_l2_error", "dg_reaction_terms", "dg_newton_solve"]
 
 _lib = None
 
@@ -135,6 +148,9 @@ def lib():
         L.dg_warmstart_prolong.argtypes = [P, P, I32, I32, I32, P, I64, P]
         L.dg_mesh_error_points.argtypes = [P, P, P]
         L.dg_l2_error.argtypes = [P, P, P, C.POINTER(C.c_double), C.POINTER(C.c_double), P]
+        L.dg_reaction_terms.argtypes = [P, C.POINTER(_Reaction), P, P, P, P]
+        L.dg_newton_solve.argtypes = [P, C.POINTER(_Reaction), C.POINTER(_NewtonOpts), P, P, P, P,
+                                      C.POINTER(_NewtonReport), P]
         L.dg_batch_destroy.argtypes = [P]
         L.dg_batch_destroy.restype = None
         L.dg_status_str.argtypes = [I32]
@@ -582,3 +598,40 @@ def l2_error(mesh: Mesh, x: torch.Tensor, exact, stream=None):
     _check(lib().dg_l2_error(mesh._h, _dptr(x), _dptr(exact), C.byref(l2), C.byref(hmax), _stream(stream)),
            "dg_l2_error")
     return l2.value, hmax.value
+
+
+def _reaction(c):
+    c = [float(v) for v in c]
+    if len(c) > 8:
+        raise ValueError("at most 8 reaction terms")
+    r = _Reaction()
+    r.n = len(c)
+    for i, v in enumerate(c):
+        r.c[i] = v
+    return r
+
+
+def reaction_terms(mesh: Mesh, c, x: torch.Tensor, stream=None):
+    """dg_reaction_terms: H(x) [n_dofs] and the Jacobian's diagonal blocks HJ
+    [T, n_loc, n_loc] for r(u) = sum_p c[p-1] u^p."""
+    r = _reaction(c)
+    h = torch.empty(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    hj = torch.empty(mesh.T, mesh.n_loc, mesh.n_loc, dtype=torch.float64, device="cuda")
+    _check(lib().dg_reaction_terms(mesh._h, C.byref(r), _dptr(x), _dptr(h), _dptr(hj), _stream(stream)),
+           "dg_reaction_terms")
+    return h, hj
+
+
+def newton_solve(mesh: Mesh, solver, vals64: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor, c, tol=1e-10,
+                 max_newton=50, stream=None):
+    """dg_newton_solve: Newton's method for (D + C + R) v + H(v) = F; x holds
+    the initial guess and receives the solution.  The solver must be set up
+    again before its next plain solve."""
+    r = _reaction(c)
+    o = _NewtonOpts(int(max_newton), 0, float(tol))
+    rep = _NewtonReport()
+    st = lib().dg_newton_solve(mesh._h, C.byref(r), C.byref(o), solver._h, _dptr(vals64), _dptr(rhs), _dptr(x),
+                               C.byref(rep), _stream(stream))
+    _check(st, "dg_newton_solve")
+    return {"status": rep.status, "newton_steps": rep.newton_steps, "linear_iters": rep.linear_iters,
+            "rel_res": rep.rel_res}

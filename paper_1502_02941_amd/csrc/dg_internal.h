@@ -135,6 +135,7 @@ namespace dg {
 // Host-side reference tables for degree k (Golub-Welsch quadrature, Dubiner
 // basis in collapsed coordinates); returns TabLayout(k).size values.
 std::vector<double> build_tables(int k);
+void solver_invalidate(dg_solver* s);
 // Error rule of dg_l2_error: Stroud q = k + 4; [w, xi, eta, phi[nqr][n]].
 std::vector<double> build_error_table(int k, int* nqr);
 constexpr int ERR_BLOCKS = 1024;

@@ -897,6 +897,17 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
     return status;
 }
 
+namespace dg {
+// The solver no longer holds a matrix (its values were temporary): the next
+// solve needs dg_solver_setup first.
+void solver_invalidate(dg_solver* s)
+{
+    if (!s) return;
+    s->ready = false;
+    s->A64 = nullptr;
+}
+}  // namespace dg
+
 extern "C" int32_t dg_solver_solve(dg_solver* s, const double* b, double* x, dg_solve_report* rep, void* stream)
 {
     if (!s || !b || !x || !rep) return DG_ERR_ARG;
