@@ -19,6 +19,9 @@ Other workloads (not the default line):
      launch per batch, launch shape picked by the autotuner; step = the whole batch.
   --workload c1: latency of one solve of the 8 x 8 P1 SIPG problem (128 triangles, sigma = 6, eps = 1e-2,
      b = (1, 1), alpha = 1, u = sin(pi x) sin(pi y)): assembly + block-Jacobi setup + GMRES to 1e-12.
+  --workload nl: the paper's non-linear example (r(u) = u^2, u = (1 - tanh((2x - y - 1/4)/sqrt(5 eps)))/2,
+     eps = 1e-6, b = (1, 2)/sqrt(5), alpha = 1) on 256 x 256 squares, P2 SIPG: assembly + Newton from zero to
+     ||Res||/||F|| <= 1e-10, each step J w = -Res by block-Jacobi GMRES(576) to 1e-10.
   --workload c3: assembly only, 512 x 512 squares jittered by +-0.2 h (seed 0, 524288 triangles), P3 IIPG
      sigma = 36 (72 on Dirichlet), rotating b = (-(y - 1/2), x - 1/2), eps = 1e-4, alpha = 1/2, f = 1,
      Dirichlet on x = 0 and y = 0, g^N = 0 elsewhere; FP64 and FP32 assembly, FP32 error vs FP64.
@@ -26,7 +29,7 @@ Other workloads (not the default line):
      zero guess vs the learned initial guess (perceptron + prolongation, model trained on 20000
      method solves of seed 1), FP64 and mixed cycles; step = the whole batch incl. the network.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c1|c2|c3|c4|c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c1|c2|c3|c4|c5|nl]
        python bench.py --profile-run     (one FP64 step + a copy probe, for rocprofv3)
 """
 from __future__ import annotations
@@ -107,7 +110,7 @@ def main():
     ap.add_argument("--restart", type=int, default=2 * N_GRID + 64)
     ap.add_argument("--reorth", type=int, default=0, help="1: conditional second Gram-Schmidt pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=("c1", "c2", "c3", "c4", "c5"))
+    ap.add_argument("--workload", default="c2", choices=("c1", "c2", "c3", "c4", "c5", "nl"))
     ap.add_argument("--count", type=int, default=None, help="c4 / c5: number of instances (4096 / 512)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one FP64 step and a 512 MiB device copy (counter scaling), no JSON baseline")
@@ -134,6 +137,8 @@ def main():
         return bench_c3(args, api, W, torch)
     if args.workload == "c1":
         return bench_c1(args, api, W, torch)
+    if args.workload == "nl":
+        return bench_nl(args, api, W, torch)
     log("building workload %dx%d P%d" % (N_GRID, N_GRID, DEGREE))
     m, mesh, P, prob = build_workload(api, W, torch)
     vals64, rhs64 = mesh.alloc_system(api.F64)
@@ -395,6 +400,85 @@ def bench_c1(args, api, W, torch):
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c1(m, prob),
     }
     print(json.dumps(line), flush=True)
+
+
+def nl_problem(W):
+    tl = W.tanh_layer_problem()
+    return tl, (lambda X, Y: tl.f(X, Y) + tl.u(X, Y) ** 2)
+
+
+def bench_nl(args, api, W, torch):
+    import numpy as np
+    tl, fnl = nl_problem(W)
+    m = W.structured_mesh(N_GRID)
+    mesh = api.Mesh.from_arrays(m, DEGREE)
+    vol, bnd = [t.cpu().numpy() for t in mesh.qpoints()[:2]]
+    f = api.Field.qpoints(torch.from_numpy(np.ascontiguousarray(fnl(vol[..., 0], vol[..., 1]))).cuda())
+    gD = api.Field.qpoints(torch.from_numpy(np.ascontiguousarray(tl.u(bnd[..., 0], bnd[..., 1]))).cuda())
+    sigma, _ = api.default_penalty(api.SIPG, DEGREE)
+    P = api.Problem(api.SIPG, DEGREE, sigma, eps=tl.eps, bx=tl.b[0], by=tl.b[1], alpha=tl.alpha, f=f, gD=gD)
+    vals, rhs = mesh.alloc_system(api.F64)
+    x = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    s = api.Solver(mesh, restart=args.restart, max_iters=20000, rel_tol=1e-10, profile=True)
+
+    def step():
+        api.assemble(mesh, P, prec=api.F64, vals=vals, rhs=rhs)
+        x.zero_()
+        return api.newton_solve(mesh, s, vals, rhs, x, [0.0, 1.0], tol=1e-10, max_newton=50)
+
+    for _ in range(max(args.warmup, 1)):
+        r = step()
+        log("warmup: %s" % r)
+    s.profile(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = [step() for _ in range(max(args.steps, 1))]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / len(reps)
+    r = reps[-1]
+    l2, _ = api.l2_error(mesh, x, tl.u)
+    kern = {k: v for k, v in s.profile(reset=True).items() if v[0] > 0}
+    dom = max(kern, key=lambda k: kern[k][1])
+    launches, ms, nbytes = kern[dom]
+    log("nl: %.3f s per solve, %d Newton steps, %d GMRES iterations, rel-res %.2e, L2 error %.3e; %s %.0f GB/s"
+        % (dt, r["newton_steps"], r["linear_iters"], r["rel_res"], l2, dom, nbytes / (ms * 1e-3) / 1e9))
+    line = {
+        "metric": "DG assembly Melem/s; solves/s at rel-res 1e-10, learned+mixed vs plain FP64",
+        "value": 1.0 / dt, "unit": "non-linear solves/s (assembly + Newton to ||Res||/||F|| <= 1e-10)",
+        "n_gpus": 1, "steps": len(reps), "warmup": max(args.warmup, 1), "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (the paper's manufactured tanh-layer solution)",
+        "config": {"workload": "256x256 structured, P2 SIPG (131072 triangles, 786432 dofs), r(u)=u^2, eps=1e-6, "
+                               "b=(1,2)/sqrt(5), alpha=1; Newton + block-Jacobi GMRES(%d)" % args.restart,
+                   "newton_steps": r["newton_steps"], "gmres_iters": int(r["linear_iters"]),
+                   "rel_res": r["rel_res"], "l2_error": l2},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": nbytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "launches": launches, "avg_us": ms / launches * 1e3},
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_nl(W),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_nl(W, n=32):
+    """The CPU oracle (single thread, FP64; Newton with direct linear solves) on
+    the same problem over a 32 x 32 mesh: non-linear solves/s of that size."""
+    import numpy as np
+    import oracle as O
+    tl, fnl = nl_problem(W)
+    m = W.structured_mesh(n)
+    M = O.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann)
+    pts = M.volume_points(DEGREE + 2)
+    bp, _ = M.boundary_points(DEGREE + 2)
+    sigma, kappa = O.default_penalty(O.SIPG, DEGREE)
+    t0 = time.perf_counter()
+    B = O.assemble(M, DEGREE, sigma=sigma, kappa=kappa, eps=tl.eps, bx=tl.b[0], by=tl.b[1], alpha=tl.alpha,
+                   f=O.Field.points(fnl(pts[..., 0], pts[..., 1])), gD=O.Field.points(tl.u(bp[..., 0], bp[..., 1])))
+    _, its, rel, conv = O.newton(M, DEGREE, B, [0.0, 1.0], tol=1e-10, max_newton=50)
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / t, "unit": "non-linear solves/s (32x32 instance of the same problem)", "cores": 1,
+            "kind": "oracle", "sample": "same problem on a %dx%d mesh (%d triangles): assembly + %d Newton steps with "
+                                        "direct solves, %.2f s" % (n, n, M.T, its, t)}
 
 
 def cpu_baseline_c1(m, prob, reps=20):

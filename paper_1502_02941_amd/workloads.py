@@ -178,16 +178,20 @@ def tanh_layer_problem(eps=1e-6, b=(1.0 / math.sqrt(5.0), 2.0 / math.sqrt(5.0)),
     def u(x, y):
         return 0.5 * (1.0 - np.tanh((2 * x - y - 0.25) / s5))
 
+    def sech2(z):  # 1 / cosh(z)^2 without overflow
+        e = np.exp(-2.0 * np.abs(z))
+        return 4.0 * e / (1.0 + e) ** 2
+
     def gu(x, y):
-        sech2 = 1.0 / np.cosh((2 * x - y - 0.25) / s5) ** 2
-        return -sech2 / s5, 0.5 * sech2 / s5
+        s2 = sech2((2 * x - y - 0.25) / s5)
+        return -s2 / s5, 0.5 * s2 / s5
 
     def f(x, y):
         z = (2 * x - y - 0.25) / s5
-        sech2 = 1.0 / np.cosh(z) ** 2
-        uxx = (0.8 / eps) * np.tanh(z) * sech2
-        uyy = (0.2 / eps) * np.tanh(z) * sech2
-        ux, uy = -sech2 / s5, 0.5 * sech2 / s5
+        s2 = sech2(z)
+        uxx = (0.8 / eps) * np.tanh(z) * s2
+        uyy = (0.2 / eps) * np.tanh(z) * s2
+        ux, uy = -s2 / s5, 0.5 * s2 / s5
         return alpha * u(x, y) - eps * (uxx + uyy) + b[0] * ux + b[1] * uy
 
     return Problem("tanh_layer", eps, tuple(b), alpha, u, gu, f)
