@@ -18,7 +18,8 @@ Other workloads (not the default line):
      Gaussians, g^D = 0, SIPG; one element-parallel assembly launch + one persistent solve
      launch per batch, launch shape picked by the autotuner; step = the whole batch.
   --workload c1: latency of one solve of the 8 x 8 P1 SIPG problem (128 triangles, sigma = 6, eps = 1e-2,
-     b = (1, 1), alpha = 1, u = sin(pi x) sin(pi y)): assembly + block-Jacobi setup + GMRES to 1e-12.
+     b = (1, 1), alpha = 1, u = sin(pi x) sin(pi y)): assembly + block-Jacobi setup + GMRES(32) to 1e-12,
+     the solve run by one workgroup with its Krylov state in LDS.
   --workload nl: the paper's non-linear example (r(u) = u^2, u = (1 - tanh((2x - y - 1/4)/sqrt(5 eps)))/2,
      eps = 1e-6, b = (1, 2)/sqrt(5), alpha = 1) on 256 x 256 squares, P2 SIPG: assembly + Newton from zero to
      ||Res||/||F|| <= 1e-10, each step J w = -Res by block-Jacobi GMRES(576) to 1e-10.
@@ -46,6 +47,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 N_GRID, DEGREE, EPS = 256, 2, 1e-6
+C1_RESTART = 32
 
 
 def log(msg):
@@ -366,7 +368,8 @@ def bench_c1(args, api, W, torch):
     P = api.Problem(api.SIPG, 1, sigma, eps=prob.eps, bx=prob.b[0], by=prob.b[1], alpha=prob.alpha, f=f, gD=gD)
     vals, rhs = mesh.alloc_system(api.F64)
     x = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
-    s = api.Solver(mesh, restart=64, max_iters=5000, rel_tol=1e-12)
+    # GMRES(32): its Krylov state fits one workgroup's LDS, so the solve is one launch
+    s = api.Solver(mesh, restart=C1_RESTART, max_iters=5000, rel_tol=1e-12)
 
     def step():
         api.assemble(mesh, P, prec=api.F64, vals=vals, rhs=rhs)
@@ -394,8 +397,9 @@ def bench_c1(args, api, W, torch):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (manufactured solution)",
         "config": {"workload": "8x8 structured, P1 SIPG (128 triangles, 384 dofs), sigma=6, eps=1e-2, b=(1,1), "
-                               "alpha=1, u=sin(pi x)sin(pi y)", "p90_ms": float(np.percentile(ts, 90) * 1e3),
-                   "iters": int(r.iters), "rel_res": float(r.rel_res), "l2_error": float(l2)},
+                               "alpha=1, u=sin(pi x)sin(pi y); GMRES(%d)" % C1_RESTART,
+                   "p90_ms": float(np.percentile(ts, 90) * 1e3), "iters": int(r.iters), "rel_res": float(r.rel_res),
+                   "l2_error": float(l2), "one_workgroup_lds_solve": bool(r.persistent)},
         "roofline": None,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c1(m, prob),
     }
@@ -482,7 +486,7 @@ def cpu_baseline_nl(W, n=32):
 
 
 def cpu_baseline_c1(m, prob, reps=20):
-    """The CPU oracle (single thread, FP64): assembly + GMRES(64) to 1e-12 of
+    """The CPU oracle (single thread, FP64): assembly + GMRES(32) to 1e-12 of
     the same problem, median of `reps` runs."""
     import numpy as np
     import oracle as O
@@ -496,7 +500,7 @@ def cpu_baseline_c1(m, prob, reps=20):
         B = O.assemble(M, 1, sigma=sigma, kappa=kappa, eps=prob.eps, bx=prob.b[0], by=prob.b[1], alpha=prob.alpha,
                        f=O.Field.points(prob.f(pts[..., 0], pts[..., 1])),
                        gD=O.Field.points(prob.u(bp[..., 0], bp[..., 1])))
-        O.gmres(B, restart=64, tol=1e-12, max_iters=5000)
+        O.gmres(B, restart=C1_RESTART, tol=1e-12, max_iters=5000)
         ts.append(time.perf_counter() - t0)
     return {"value": float(np.median(ts) * 1e3), "unit": "ms per solve", "cores": 1, "kind": "oracle",
             "sample": "the full problem, median of %d runs" % reps}

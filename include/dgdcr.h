@@ -182,6 +182,12 @@ typedef struct {
     double guess_limit;   /* the initial guess is replaced by zero when ||F - A x0|| > guess_limit ||F||
                              or is not finite; <= 0 selects 1 + 1e-8 (no worse than the zero guess;
                              the margin absorbs the rounding of the two norms); +inf keeps any finite guess */
+    int32_t persistent;   /* one persistent workgroup runs the whole solve (one launch per solve, the same
+                             algorithm) instead of one launch per GMRES kernel; it supports degree 1 or 2,
+                             restart <= 512 and reorth = profile = 0.  0: automatic, taken for supported
+                             systems of at most 4096 unknowns; 1: always (DG_ERR_ARG if unsupported);
+                             -1: never */
+    int32_t reserved;
 } dg_solver_opts;
 
 typedef struct {
@@ -193,7 +199,8 @@ typedef struct {
     double rel_res0;      /* true FP64 relative residual of the initial guess */
     int32_t guess_rejected; /* 1: the initial guess failed the guess_limit test of the options
                                and was replaced by the zero guess */
-    int32_t reserved;
+    int32_t persistent;   /* dg_solver_solve: 1 if one persistent workgroup ran the solve
+                             (opts.persistent); batch reports: 0 */
 } dg_solve_report;
 
 /* Allocates the Krylov workspace for `mesh` (device memory, owned by the

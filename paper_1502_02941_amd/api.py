@@ -49,7 +49,7 @@ class _MeshInfo(C.Structure):
 class _SolverOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double), ("mixed", C.c_int32),
                 ("inner_tol", C.c_double), ("reorth", C.c_int32), ("profile", C.c_int32),
-                ("guess_limit", C.c_double)]
+                ("guess_limit", C.c_double), ("persistent", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _KStats(C.Structure):
@@ -59,7 +59,7 @@ class _KStats(C.Structure):
 class _Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32), ("reorth_passes", C.c_int32),
                 ("rel_res", C.c_double), ("rel_res0", C.c_double), ("guess_rejected", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("persistent", C.c_int32)]
 
 
 class _Instance(C.Structure):
@@ -93,7 +93,7 @@ PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32)
 
 REPORT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32), ("reorth", np.int32),
                          ("rel_res", np.float64), ("rel_res0", np.float64), ("guess_rejected", np.int32),
-                         ("reserved", np.int32)])
+                         ("persistent", np.int32)])
 
 EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_destroy", "dg_mesh_structure",
            "dg_mesh_qpoints", "dg_assemble", "dg_solver_create", "dg_solver_setup", "dg_solver_solve",
@@ -352,6 +352,7 @@ class Report:
     rel_res0: float
     reorth_passes: int = 0
     guess_rejected: int = 0
+    persistent: int = 0
 
     @property
     def converged(self):
@@ -363,10 +364,14 @@ class Solver:
     FP64 or FP32 cycles with FP64 refinement (mixed=True)."""
 
     def __init__(self, mesh: Mesh, restart=50, max_iters=20000, rel_tol=1e-10, mixed=False, inner_tol=1e-5,
-                 reorth=False, profile=False, guess_limit=0.0):
+                 reorth=False, profile=False, guess_limit=0.0, persistent="auto"):
+        """persistent: "auto" (one workgroup for small degree-1/2 systems),
+        True (always; an error where unsupported) or False (one launch per
+        GMRES kernel)."""
         self.mesh = mesh
+        pers = {"auto": 0, True: 1, False: -1}[persistent]
         o = _SolverOpts(int(restart), int(max_iters), float(rel_tol), int(bool(mixed)), float(inner_tol),
-                        int(bool(reorth)), int(bool(profile)), float(guess_limit))
+                        int(bool(reorth)), int(bool(profile)), float(guess_limit), pers, 0)
         h = C.c_void_p()
         _check(lib().dg_solver_create(mesh._h, C.byref(o), C.byref(h)), "dg_solver_create")
         self._h = h
@@ -394,7 +399,8 @@ class Solver:
         r = _Report()
         st = lib().dg_solver_solve(self._h, _dptr(rhs), _dptr(x), C.byref(r), _stream(stream))
         _check(st, "dg_solver_solve")
-        return Report(r.status, r.iters, r.cycles, r.rel_res, r.rel_res0, r.reorth_passes, r.guess_rejected)
+        return Report(r.status, r.iters, r.cycles, r.rel_res, r.rel_res0, r.reorth_passes, r.guess_rejected,
+                      r.persistent)
 
 
 def bsr_to_scipy(mesh: Mesh, vals: torch.Tensor, row_ptr=None, col_idx=None):

@@ -136,6 +136,31 @@ namespace dg {
 // basis in collapsed coordinates); returns TabLayout(k).size values.
 std::vector<double> build_tables(int k);
 void solver_invalidate(dg_solver* s);
+
+// One-workgroup GMRES with its state in LDS (small.hip): byte offsets of each
+// array in the dynamic LDS block.
+struct SmallLayout {
+    int64_t V, w0, w1, r, x, rp, ci, H, hcol, cs, sn, gv, yv, red, flag, bytes;
+};
+constexpr int SMALL_MAX_RESTART = 128;
+struct SmallArgs {
+    const double* A64;     // FP64 BSR values (true residual)
+    const int32_t* rp;     // block row pointers [T + 1]
+    const int32_t* ci;     // block column indices [nnzb]
+    const void* Ahat;      // A D^{-1} without its diagonal blocks, cycle precision
+    const void* Dinv;      // D^{-1} blocks, cycle precision
+    const double* b;
+    double* x;             // initial guess in, solution out
+    dg_solve_report* rep;  // host-mapped pinned memory
+    int64_t T;
+    int32_t nnzb, m, max_iters, mixed;
+    double rel_tol, inner_tol, guess_limit;
+    SmallLayout L;
+};
+SmallLayout small_layout(int64_t T, int N, int64_t nnzb, int m, size_t ps);
+int small_lds_limit();
+int small_prepare(int N, int mixed, int64_t lds_bytes);
+int small_launch(int N, int mixed, const SmallArgs& a, hipStream_t st);
 // Error rule of dg_l2_error: Stroud q = k + 4; [w, xi, eta, phi[nqr][n]].
 std::vector<double> build_error_table(int k, int* nqr);
 constexpr int ERR_BLOCKS = 1024;

@@ -573,6 +573,9 @@ struct dg_solver {
     int* ctrl = nullptr;
     int* bad = nullptr;
     int* rflags = nullptr;  // [restart]: 1 if iteration j took the second Gram-Schmidt pass
+    int small = 0;                   // one workgroup with its state in LDS solves the whole system
+    SmallLayout sl{};
+    dg_solve_report* h_rep = nullptr;  // pinned host report written by that kernel
     int ready = 0;
     // built-in profiler (opts.profile): HIP events around the heavy kernels
     struct Rec { int cls; double bytes; int j; int pass; hipEvent_t e0, e1; };
@@ -655,6 +658,8 @@ static void solver_free(dg_solver* s)
     hipFree(s->Ahat); hipFree(s->Dinv); hipFree(s->Dinv64); hipFree(s->V); hipFree(s->w); hipFree(s->u);
     hipFree(s->r); hipFree(s->partials); hipFree(s->hcol); hipFree(s->hcol2); hipFree(s->H); hipFree(s->cs);
     hipFree(s->sn); hipFree(s->g); hipFree(s->y); hipFree(s->scal); hipFree(s->ctrl); hipFree(s->bad);
+    if (s->h_rep) hipHostFree(s->h_rep);
+    s->h_rep = nullptr;
 }
 
 extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, dg_solver** out)
@@ -665,6 +670,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     if (o->restart < 1 || o->restart > 4096 || o->max_iters < 0 || !(o->rel_tol > 0) || (o->mixed != 0 && o->mixed != 1))
         return DG_ERR_ARG;
     if (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)) return DG_ERR_ARG;
+    if (o->persistent < -1 || o->persistent > 1) return DG_ERR_ARG;
     dg_solver* s = new (std::nothrow) dg_solver();
     if (!s) return DG_ERR_OOM;
     s->m = m;
@@ -712,6 +718,24 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     al((void**)&s->rflags, sizeof(int) * mm);
     if (!ok) { solver_free(s); delete s; return DG_ERR_OOM; }
     if (hipMemset(s->ctrl, 0, sizeof(int) * C_NCTRL) != hipSuccess) { solver_free(s); delete s; return DG_ERR_HIP; }
+    // A system whose Krylov state fits one workgroup's LDS is solved by one
+    // launch: the ~8 launches of every Arnoldi step would leave the chip idle.
+    if (o->persistent != -1 && mm <= SMALL_MAX_RESTART && !o->reorth && !o->profile) {
+        const SmallLayout L = small_layout(s->T, s->N, m->nnzb, mm, ps);
+        if (L.bytes <= small_lds_limit()) {
+            const int r = small_prepare(s->N, s->mixed, L.bytes);
+            if (r != DG_OK) { solver_free(s); delete s; return r; }
+            if (hipHostMalloc((void**)&s->h_rep, sizeof(dg_solve_report), hipHostMallocDefault) != hipSuccess) {
+                s->h_rep = nullptr;
+                solver_free(s);
+                delete s;
+                return DG_ERR_OOM;
+            }
+            s->small = 1;
+            s->sl = L;
+        }
+    }
+    if (o->persistent == 1 && !s->small) { solver_free(s); delete s; return DG_ERR_ARG; }
     *out = s;
     return DG_OK;
 }
@@ -789,7 +813,7 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
     rep->cycles = 0;
     rep->rel_res0 = 0.0;
     rep->guess_rejected = 0;
-    rep->reserved = 0;
+    rep->persistent = 0;
     if (bnorm == 0.0) {
         DG_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * s->n, st));
         DG_HIP_CHECK(hipStreamSynchronize(st));
@@ -914,6 +938,34 @@ extern "C" int32_t dg_solver_solve(dg_solver* s, const double* b, double* x, dg_
     if (!s->ready) return DG_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     *rep = dg_solve_report{};
+    if (s->small) {
+        SmallArgs a{};
+        a.A64 = s->A64;
+        a.rp = s->m->d_row_ptr;
+        a.ci = s->m->d_col_idx;
+        a.Ahat = s->Ahat;
+        a.Dinv = s->Dinv;
+        a.b = b;
+        a.x = x;
+        a.rep = s->h_rep;
+        a.T = s->T;
+        a.nnzb = (int32_t)s->m->nnzb;
+        a.m = s->o.restart;
+        a.max_iters = s->o.max_iters;
+        a.mixed = s->mixed;
+        a.rel_tol = s->o.rel_tol;
+        a.inner_tol = s->o.inner_tol;
+        a.guess_limit = s->o.guess_limit;
+        a.L = s->sl;
+        *s->h_rep = dg_solve_report{};
+        s->h_rep->status = DG_ERR_HIP;  // stays if the kernel never ran
+        const int r = small_launch(s->N, s->mixed, a, st);
+        if (r != DG_OK) return r;
+        DG_HIP_CHECK(hipStreamSynchronize(st));
+        *rep = *s->h_rep;
+        rep->persistent = 1;
+        return rep->status;
+    }
     int r;
     switch (s->N) {
     case 1: r = s->mixed ? solve_np<1, float>(s, b, x, rep, st) : solve_np<1, double>(s, b, x, rep, st); break;

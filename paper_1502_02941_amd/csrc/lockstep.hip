@@ -293,7 +293,7 @@ __global__ __launch_bounds__(LS_BT) void ls_check_kernel(const LsArgs A, int fir
     double beta = sqrt(a);
     if (first) {
         R.guess_rejected = reject;
-        R.reserved = 0;
+        R.persistent = 0;
         R.rel_res0 = S.bnorm > 0.0 ? beta / S.bnorm : 0.0;
         if (reject) beta = S.bnorm;
     }

@@ -114,32 +114,100 @@ SOLVE_CASES = [c for c in SMALL if c.k >= 1 and c.name.split("_")[0] in ("c1", "
                                                                             "paper")] + [SMALL[3], SMALL[8]]
 
 
+@pytest.mark.parametrize("persistent", ["auto", False], ids=["auto", "per_kernel"])
 @pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("case", SOLVE_CASES, ids=[c.name for c in SOLVE_CASES])
-def test_gmres_solution_oracle_judged(api, case, mixed):
+def test_gmres_solution_oracle_judged(api, case, mixed, persistent):
     tol = case.tol
-    _say("solve %s mixed=%s tol=%g" % (case.name, mixed, tol))
+    _say("solve %s mixed=%s persistent=%s tol=%g" % (case.name, mixed, persistent, tol))
     mesh, _, vals, rhs = _gpu_system(api, case)
-    solver = api.Solver(mesh, restart=50, max_iters=20000, rel_tol=tol, mixed=mixed, inner_tol=1e-5)
+    solver = api.Solver(mesh, restart=50, max_iters=20000, rel_tol=tol, mixed=mixed, inner_tol=1e-5,
+                        persistent=persistent)
     solver.setup(vals)
     x = torch.zeros_like(rhs)
     rep = solver.solve(rhs, x)
-    _say("  iters %d cycles %d relres %.3e" % (rep.iters, rep.cycles, rep.rel_res))
+    _say("  iters %d cycles %d relres %.3e path %d" % (rep.iters, rep.cycles, rep.rel_res, rep.persistent))
+    if persistent is False:
+        assert rep.persistent == 0
     assert rep.converged and rep.rel_res <= tol
     M, B = DC.oracle_system(case)
     assert _oracle_relres(B, x.cpu().numpy()) <= tol * 1.01
 
 
-def test_solver_reports_non_convergence_and_warm_start(api):
+def _fitting_restart(api, mesh, mixed):
+    """Largest of a few restarts whose Krylov state fits one workgroup's LDS."""
+    for restart in (40, 30, 20, 12, 8):
+        try:
+            api.Solver(mesh, restart=restart, mixed=mixed, persistent=True)
+            return restart
+        except api.DGError:
+            pass
+    return None
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", SOLVE_CASES, ids=[c.name for c in SOLVE_CASES])
+def test_persistent_and_per_kernel_paths_agree(api, case, mixed):
+    """The one-workgroup LDS solve (forced) runs the same GMRES as the
+    launch-per-kernel path: Arnoldi step counts equal up to the steps that the
+    different summation orders can move a stopping test by, and solutions that
+    agree to the tolerance."""
+    mesh, _, vals, rhs = _gpu_system(api, case)
+    restart = _fitting_restart(api, mesh, mixed)
+    if restart is None:
+        pytest.skip("%d unknowns do not fit one workgroup's LDS" % mesh.n_dofs)
+    out = {}
+    for persistent in (True, False):
+        s = api.Solver(mesh, restart=restart, max_iters=20000, rel_tol=case.tol, mixed=mixed, persistent=persistent)
+        s.setup(vals)
+        x = torch.zeros_like(rhs)
+        rep = s.solve(rhs, x)
+        assert rep.converged and rep.persistent == int(persistent)
+        out[persistent] = (rep, x)
+    (r1, x1), (r0, x0) = out[True], out[False]
+    _say("  %s mixed=%s restart %d: iters %d vs %d, cycles %d vs %d" % (case.name, mixed, restart, r1.iters,
+                                                                      r0.iters, r1.cycles, r0.cycles))
+    assert abs(r1.iters - r0.iters) <= max(2, 0.05 * r0.iters) and abs(r1.cycles - r0.cycles) <= 1
+    A = api.bsr_to_scipy(mesh, vals)
+    b = rhs.cpu().numpy()
+    # ||A (x1 - x0)|| <= ||F - A x1|| + ||F - A x0|| <= 2 tol ||F||
+    e = np.linalg.norm(A @ (x1 - x0).cpu().numpy()) / np.linalg.norm(b)
+    assert e <= 2.05 * case.tol
+
+
+def test_persistent_path_selection(api):
+    """C1's 384 unknowns with restart 32 (about 126 KB of LDS in FP64) take the
+    one-workgroup path by default; forcing it where the state does not fit
+    gfx950's 160 KB, or with options it lacks, is an error."""
+    c1 = api.Mesh.from_arrays(SMALL[0].mesh, SMALL[0].k)
+    big = api.Mesh.from_arrays(SOLVE_CASES[1].mesh, SOLVE_CASES[1].k)
+    assert big.n_dofs > 10000
+    with pytest.raises(api.DGError):
+        api.Solver(big, restart=30, persistent=True)
+    for kw in ({"restart": 129}, {"reorth": True}, {"profile": True}, {"restart": 50}):
+        with pytest.raises(api.DGError):
+            api.Solver(c1, persistent=True, **kw)
+    api.Solver(c1, persistent=True, restart=32)
+    api.Solver(c1, persistent=True, restart=64, mixed=True)
+    mesh, _, vals, rhs = _gpu_system(api, SMALL[0])
+    for persistent, expect in (("auto", 1), (False, 0)):
+        s = api.Solver(mesh, restart=32, rel_tol=1e-12, persistent=persistent)
+        s.setup(vals)
+        rep = s.solve(rhs, torch.zeros_like(rhs))
+        assert rep.converged and rep.persistent == expect
+
+
+@pytest.mark.parametrize("persistent", ["auto", False], ids=["auto", "per_kernel"])
+def test_solver_reports_non_convergence_and_warm_start(api, persistent):
     case = SMALL[0]
     mesh, _, vals, rhs = _gpu_system(api, case)
-    s = api.Solver(mesh, restart=10, max_iters=3, rel_tol=1e-12)
+    s = api.Solver(mesh, restart=10, max_iters=3, rel_tol=1e-12, persistent=persistent)
     s.setup(vals)
     x = torch.zeros_like(rhs)
     rep = s.solve(rhs, x)
     assert rep.status == api.DG_NOT_CONVERGED and rep.iters == 3 and rep.rel_res > 1e-12
     # restart from the returned iterate: the initial residual is the previous final one
-    s2 = api.Solver(mesh, restart=50, max_iters=5000, rel_tol=1e-12)
+    s2 = api.Solver(mesh, restart=50, max_iters=5000, rel_tol=1e-12, persistent=persistent)
     s2.setup(vals)
     rep2 = s2.solve(rhs, x)
     assert rep2.converged and abs(rep2.rel_res0 - rep.rel_res) <= 1e-9 * rep.rel_res
@@ -232,13 +300,14 @@ def test_c3_full_size_assembly_sampled(api):
     assert e32 <= 2e-6
 
 
-def test_solver_rejects_a_guess_worse_than_zero(api):
+@pytest.mark.parametrize("persistent", ["auto", False], ids=["auto", "per_kernel"])
+def test_solver_rejects_a_guess_worse_than_zero(api, persistent):
     """The true FP64 residual judges the initial guess: a guess with
     ||F - A x0|| > ||F|| (or non-finite) is replaced by x0 = 0, giving the
     zero-guess run exactly; a good guess is kept."""
     case = SMALL[0]
     mesh, _, vals, rhs = _gpu_system(api, case)
-    s = api.Solver(mesh, restart=50, max_iters=5000, rel_tol=1e-12)
+    s = api.Solver(mesh, restart=50, max_iters=5000, rel_tol=1e-12, persistent=persistent)
     s.setup(vals)
     x0 = torch.zeros_like(rhs)
     rep0 = s.solve(rhs, x0)
