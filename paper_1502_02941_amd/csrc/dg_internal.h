@@ -140,7 +140,9 @@ void solver_invalidate(dg_solver* s);
 // One-workgroup GMRES with its state in LDS (small.hip): byte offsets of each
 // array in the dynamic LDS block.
 struct SmallLayout {
-    int64_t V, w0, w1, r, x, rp, ci, H, hcol, cs, sn, gv, yv, red, flag, bytes;
+    int64_t V, w0, w1, r, x, rp, ci, H, hcol, cs, sn, gv, yv, red, flag;
+    int64_t ahat;   // A M^{-1} staged in LDS at this offset; -1: read from global memory
+    int64_t bytes;
 };
 constexpr int SMALL_MAX_RESTART = 128;
 struct SmallArgs {
@@ -157,9 +159,9 @@ struct SmallArgs {
     double rel_tol, inner_tol, guess_limit;
     SmallLayout L;
 };
-SmallLayout small_layout(int64_t T, int N, int64_t nnzb, int m, size_t ps);
+SmallLayout small_layout(int64_t T, int N, int64_t nnzb, int m, size_t ps, bool stage_ahat);
 int small_lds_limit();
-int small_prepare(int N, int mixed, int64_t lds_bytes);
+int small_prepare(int N, int mixed, const SmallLayout& L);
 int small_launch(int N, int mixed, const SmallArgs& a, hipStream_t st);
 // Error rule of dg_l2_error: Stroud q = k + 4; [w, xi, eta, phi[nqr][n]].
 std::vector<double> build_error_table(int k, int* nqr);

@@ -721,9 +721,11 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     // A system whose Krylov state fits one workgroup's LDS is solved by one
     // launch: the ~8 launches of every Arnoldi step would leave the chip idle.
     if (o->persistent != -1 && mm <= SMALL_MAX_RESTART && !o->reorth && !o->profile) {
-        const SmallLayout L = small_layout(s->T, s->N, m->nnzb, mm, ps);
-        if (L.bytes <= small_lds_limit()) {
-            const int r = small_prepare(s->N, s->mixed, L.bytes);
+        const int64_t lim = small_lds_limit();
+        SmallLayout L = small_layout(s->T, s->N, m->nnzb, mm, ps, true);
+        if (L.bytes > lim) L = small_layout(s->T, s->N, m->nnzb, mm, ps, false);
+        if (L.bytes <= lim) {
+            const int r = small_prepare(s->N, s->mixed, L);
             if (r != DG_OK) { solver_free(s); delete s; return r; }
             if (hipHostMalloc((void**)&s->h_rep, sizeof(dg_solve_report), hipHostMallocDefault) != hipSuccess) {
                 s->h_rep = nullptr;
