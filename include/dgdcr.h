@@ -131,6 +131,26 @@ int32_t dg_mesh_create(const double* nodes_xy, int64_t n_nodes, const int32_t* e
 int32_t dg_mesh_info_get(const dg_mesh* mesh, dg_mesh_info* out);
 void dg_mesh_destroy(dg_mesh* mesh);
 
+/* Uniform (red) refinement, the refinement step of the paper's driver
+ * (section 2.1: the initial mesh is refined before assembly): every triangle
+ * is split at its edge midpoints into four, and every listed boundary edge
+ * into two halves of the same type.  dg_mesh_refine_sizes writes the refined
+ * sizes (host int64[4]: n_nodes + n_edges, 4 n_elems, 2 n_dir_edges,
+ * 2 n_neu_edges).  dg_mesh_refine writes the refined arrays in the layout of
+ * dg_mesh_create into caller-owned device buffers of those sizes:
+ * dev_nodes [.][2] FP64, dev_elems [.][3], dev_dir [.][2], dev_neu [.][2]
+ * (int32, 0-based; dev_dir / dev_neu may be NULL when the list is empty).
+ * Old nodes keep their index, the midpoint of an edge gets n_nodes + its edge
+ * id (edges numbered in the order a walk over the elements and their edges
+ * (v0 v1), (v1 v2), (v2 v0) first meets them); triangle K = (a, b, c) becomes
+ * rows 4K..4K+3 = (a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca);
+ * boundary edge i = (a, b) becomes rows 2i, 2i+1 = (a, m), (m, b).
+ * Stream-ordered, no synchronisation.  DG_ERR_ARG if an index of the refined
+ * mesh would not fit int32. */
+int32_t dg_mesh_refine_sizes(const dg_mesh* mesh, int64_t* sizes);
+int32_t dg_mesh_refine(const dg_mesh* mesh, double* dev_nodes, int32_t* dev_elems, int32_t* dev_dir,
+                       int32_t* dev_neu, void* stream);
+
 /* Copies the BSR pattern into dev_row_ptr [n_elems+1] and dev_col_idx [nnzb]. */
 int32_t dg_mesh_structure(const dg_mesh* mesh, int32_t* dev_row_ptr, int32_t* dev_col_idx, void* stream);
 

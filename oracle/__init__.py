@@ -377,3 +377,38 @@ def newton(mesh: Mesh, k: int, blocks, c, tol=1e-10, max_newton=50, x0=None):
         HJ = sp.bsr_matrix((hj, np.arange(T), np.arange(T + 1)), shape=(T * n, T * n))
         x = x + spl.spsolve((A + HJ).tocsc(), -res)
     return x, max_newton, rel, False
+
+
+def uniform_refine(nodes, elems, dirichlet, neumann):
+    """Red refinement of a triangulation (the refinement step of the paper's
+    driver, section 2.1), in plain Python: each triangle (a, b, c) is cut at its
+    edge midpoints into (a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca),
+    and each listed boundary edge (a, b) into (a, m), (m, b).  A midpoint is a
+    new node numbered after the existing ones in the order the edges are first
+    met when the triangles are visited in order, each through its edges
+    (a, b), (b, c), (c, a).  Returns (nodes, elems, dirichlet, neumann)."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    new_nodes = [list(p) for p in nodes]
+    index_of = {}
+
+    def mid(a, b):
+        e = frozenset((int(a), int(b)))
+        if e not in index_of:
+            index_of[e] = len(new_nodes)
+            new_nodes.append([0.5 * (nodes[a][0] + nodes[b][0]), 0.5 * (nodes[a][1] + nodes[b][1])])
+        return index_of[e]
+
+    tris = []
+    for a, b, c in np.asarray(elems):
+        ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+        tris += [[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, bc, ca]]
+
+    def halves(edges):
+        out = []
+        for a, b in np.asarray(edges).reshape(-1, 2):
+            m = index_of[frozenset((int(a), int(b)))]
+            out += [[a, m], [m, b]]
+        return np.array(out, dtype=np.int32).reshape(-1, 2)
+
+    return (np.array(new_nodes, dtype=np.float64), np.array(tris, dtype=np.int32), halves(dirichlet),
+            halves(neumann))

@@ -101,7 +101,8 @@ EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_
            "dg_batch_create", "dg_batch_offsets", "dg_batch_run", "dg_batch_destroy", "dg_batch_progress",
            "dg_batch_set_progress", "dg_mlp_create", "dg_mlp_num_params", "dg_mlp_forward", "dg_mlp_loss_mse",
            "dg_mlp_backward", "dg_mlp_adam_step", "dg_mlp_params", "dg_mlp_destroy", "dg_warmstart_prolong",
-           "dg_mesh_error_points", "dg_l2_error", "dg_reaction_terms", "dg_newton_solve"]
+           "dg_mesh_error_points", "dg_l2_error", "dg_reaction_terms", "dg_newton_solve", "dg_mesh_refine_sizes",
+           "dg_mesh_refine"]
 
 _lib = None
 
@@ -121,6 +122,8 @@ def lib():
         L.dg_mesh_destroy.argtypes = [P]
         L.dg_mesh_destroy.restype = None
         L.dg_mesh_structure.argtypes = [P, P, P, P]
+        L.dg_mesh_refine_sizes.argtypes = [P, P]
+        L.dg_mesh_refine.argtypes = [P, P, P, P, P, P]
         L.dg_mesh_qpoints.argtypes = [P, P, P, P, P, P]
         L.dg_assemble.argtypes = [P, C.POINTER(_Problem), I32, C.c_uint32, P, P, P]
         L.dg_solver_create.argtypes = [P, C.POINTER(_SolverOpts), C.POINTER(P)]
@@ -259,6 +262,18 @@ class Problem:
         return p
 
 
+@dataclass
+class RefinedArrays:
+    """Device tensors of a refined mesh (dg_mesh_refine); host() gives numpy."""
+    nodes: torch.Tensor
+    elems: torch.Tensor
+    dirichlet: torch.Tensor
+    neumann: torch.Tensor
+
+    def host(self):
+        return RefinedArrays(*(t.cpu().numpy() for t in (self.nodes, self.elems, self.dirichlet, self.neumann)))
+
+
 class Mesh:
     """dg_mesh_create on host arrays (0-based; section 2.1 layout)."""
 
@@ -266,6 +281,10 @@ class Mesh:
         if device is not None:
             torch.cuda.set_device(device)
         L = lib()
+        if isinstance(nodes, torch.Tensor):
+            nodes, elems = nodes.cpu().numpy(), elems.cpu().numpy()
+            dirichlet = dirichlet.cpu().numpy() if isinstance(dirichlet, torch.Tensor) else dirichlet
+            neumann = neumann.cpu().numpy() if isinstance(neumann, torch.Tensor) else neumann
         nodes = np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1, 2)
         elems = np.ascontiguousarray(elems, dtype=np.int32).reshape(-1, 3)
         d = np.ascontiguousarray(dirichlet if dirichlet is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
@@ -292,6 +311,19 @@ class Mesh:
         if h is not None and _lib is not None:
             _lib.dg_mesh_destroy(h)
             self._h = None
+
+    def refine(self, stream=None):
+        """dg_mesh_refine: the uniformly refined mesh arrays as device tensors
+        (nodes, elems, dirichlet, neumann), in dg_mesh_create's layout."""
+        sz = (C.c_int64 * 4)()
+        _check(lib().dg_mesh_refine_sizes(self._h, sz), "dg_mesh_refine_sizes")
+        nodes = torch.empty(sz[0], 2, dtype=torch.float64, device="cuda")
+        elems = torch.empty(sz[1], 3, dtype=torch.int32, device="cuda")
+        d = torch.empty(sz[2], 2, dtype=torch.int32, device="cuda")
+        nm = torch.empty(sz[3], 2, dtype=torch.int32, device="cuda")
+        _check(lib().dg_mesh_refine(self._h, _dptr(nodes), _dptr(elems), _dptr(d) if sz[2] else None,
+                                    _dptr(nm) if sz[3] else None, _stream(stream)), "dg_mesh_refine")
+        return RefinedArrays(nodes, elems, d, nm)
 
     def structure(self, stream=None):
         rp = torch.empty(self.T + 1, dtype=torch.int32, device="cuda")

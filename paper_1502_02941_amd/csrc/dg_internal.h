@@ -129,6 +129,16 @@ struct dg_mesh {
     double* d_etab = nullptr;   // error rule (q = k + 4): w[nqr], xi[nqr], eta[nqr], phi[nqr][n]
     double* d_epart = nullptr;  // [ERR_BLOCKS + 1] partial sums of dg_l2_error
     int nqr = 0;
+    // uniform refinement (dg_mesh_refine): the caller's arrays and one id per edge
+    int64_t n_edges = 0;
+    double* d_nodes = nullptr;    // [n_nodes][2]
+    int32_t* d_elems = nullptr;   // [T][3]
+    int32_t* d_eid = nullptr;     // [T][3] edge id of local edge l = (v_l, v_l+1)
+    int32_t* d_owner = nullptr;   // [T][3] 1 where (K, l) is the first half-edge of its edge
+    int32_t* d_dir = nullptr;     // [n_dir][2] as given
+    int32_t* d_neu = nullptr;     // [n_neu][2] as given
+    int32_t* d_dir_eid = nullptr;
+    int32_t* d_neu_eid = nullptr;
 };
 
 namespace dg {

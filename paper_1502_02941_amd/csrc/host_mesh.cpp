@@ -285,6 +285,8 @@ static void free_device(dg_mesh* m)
     hipFree(m->d_bnd_elems);
     hipFree(m->d_tab64); hipFree(m->d_tab32); hipFree(m->d_p1map); hipFree(m->d_ten64); hipFree(m->d_ten32);
     hipFree(m->d_gt); hipFree(m->d_etab); hipFree(m->d_epart);
+    hipFree(m->d_nodes); hipFree(m->d_elems); hipFree(m->d_eid); hipFree(m->d_owner);
+    hipFree(m->d_dir); hipFree(m->d_neu); hipFree(m->d_dir_eid); hipFree(m->d_neu_eid);
 }
 
 template <typename T>
@@ -507,6 +509,50 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
                 for (int v = 0; v < 3; ++v) P[mm * 3 + v] += w * lam[v] * m->tab64[L.vphi + g * L.n + mm];
         }
         st = upload(&m->d_p1map, P);
+    }
+    if (st == DG_OK) {
+        // Edge ids for refinement: walking the elements in order and each
+        // element's edges (v0 v1), (v1 v2), (v2 v0), an edge gets the next id
+        // when it is met for the first time (a boundary edge, or an interior
+        // edge whose other element comes later).
+        std::vector<int32_t> eid(3 * T), owner(3 * T, 0);
+        int32_t ne = 0;
+        for (int64_t K = 0; K < T; ++K)
+            for (int l = 0; l < 3; ++l) {
+                const int32_t nb = m->nbr[3 * K + l];
+                if (nb < 0 || nb > K) {
+                    owner[3 * K + l] = 1;
+                    eid[3 * K + l] = ne++;
+                } else {
+                    eid[3 * K + l] = eid[3 * (int64_t)nb + ((m->nbr_edge[K] >> (2 * l)) & 3)];
+                }
+            }
+        m->n_edges = ne;
+        // ids of the listed boundary edges, in the caller's order
+        std::unordered_map<uint64_t, int32_t> bid;
+        bid.reserve((size_t)m->n_bnd);
+        for (int64_t i = 0; i < m->n_bnd; ++i) {
+            const int64_t K = m->bnd_el[i];
+            const int l = m->bnd_loc[i];
+            const uint64_t a = (uint64_t)elems[3 * K + l], b = (uint64_t)elems[3 * K + (l + 1) % 3];
+            bid.emplace((std::min(a, b) << 32) | std::max(a, b), eid[3 * K + l]);
+        }
+        auto ids = [&](const int32_t* e, int64_t cnt) {
+            std::vector<int32_t> v((size_t)cnt);
+            for (int64_t i = 0; i < cnt; ++i) {
+                const uint64_t a = (uint64_t)e[2 * i], b = (uint64_t)e[2 * i + 1];
+                v[i] = bid.at((std::min(a, b) << 32) | std::max(a, b));
+            }
+            return v;
+        };
+        st = upload(&m->d_nodes, std::vector<double>(xy, xy + 2 * n_nodes));
+        if (st == DG_OK) st = upload(&m->d_elems, std::vector<int32_t>(elems, elems + 3 * T));
+        if (st == DG_OK) st = upload(&m->d_eid, eid);
+        if (st == DG_OK) st = upload(&m->d_owner, owner);
+        if (st == DG_OK && n_dir > 0) st = upload(&m->d_dir, std::vector<int32_t>(dir, dir + 2 * n_dir));
+        if (st == DG_OK && n_neu > 0) st = upload(&m->d_neu, std::vector<int32_t>(neu, neu + 2 * n_neu));
+        if (st == DG_OK && n_dir > 0) st = upload(&m->d_dir_eid, ids(dir, n_dir));
+        if (st == DG_OK && n_neu > 0) st = upload(&m->d_neu_eid, ids(neu, n_neu));
     }
     if (st != DG_OK) { free_device(m); delete m; return st; }
     *out = m;

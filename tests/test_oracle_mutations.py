@@ -56,3 +56,43 @@ def test_mutant_is_caught(name, tmp_path):
                         "-x", "-q", "-p", "no:cacheprovider", "-k", "not brute_force"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "mutant %s survived every pin:\n%s" % (name, r.stdout[-2000:])
+
+
+# Planted mistakes in the oracle's Python part (its mesh refinement), run
+# against a copy of the package placed first on the import path.
+PY_MUTANTS = {
+    "refine_inner_child_clockwise": ("tris += [[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, bc, ca]]",
+                                     "tris += [[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, ca, bc]]"),
+    "refine_midpoint_half_weight": ("new_nodes.append([0.5 * (nodes[a][0] + nodes[b][0]), 0.5 * (nodes[a][1] + nodes[b][1])])",
+                                    "new_nodes.append([nodes[a][0] + 0.5 * nodes[b][0], 0.5 * (nodes[a][1] + nodes[b][1])])"),
+    "refine_boundary_half_reversed": ("out += [[a, m], [m, b]]", "out += [[m, a], [m, b]]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS) + ["unchanged_copy"])
+def test_python_mutant_is_caught(name, tmp_path):
+    """Each mutant fails a refinement pin; the unchanged copy passes them all
+    (so a failure means the pins, not the harness)."""
+    import shutil
+    old, new = PY_MUTANTS.get(name, ("def uniform_refine(", "def uniform_refine("))
+    pkg = os.path.join(ROOT, "oracle")
+    src = open(os.path.join(pkg, "__init__.py")).read()
+    assert src.count(old) == 1, "mutation anchor not found exactly once: %r" % old
+    dst = tmp_path / "oracle"
+    dst.mkdir()
+    for f in os.listdir(pkg):
+        if f.endswith((".c", ".so", ".py")) and f != "__init__.py":
+            shutil.copy(os.path.join(pkg, f), dst / f)
+    (dst / "__init__.py").write_text(src.replace(old, new))
+    # the mutant is imported first, so the pins (which pytest imports with the
+    # repository at the front of the path) find it already loaded
+    code = ("import sys; sys.path.insert(0, %r); import oracle; assert oracle.__file__.startswith(%r); "
+            "sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main([%r, '-x', '-q', '-p', 'no:cacheprovider', '-k', 'refine']))"
+            % (str(tmp_path), str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_pins.py")))
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True, text=True, timeout=600)
+    assert "passed" in r.stdout or "failed" in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]
+    if name == "unchanged_copy":
+        assert r.returncode == 0, r.stdout[-2000:]
+    else:
+        assert r.returncode != 0, "mutant %s survived every pin:\n%s" % (name, r.stdout[-2000:])

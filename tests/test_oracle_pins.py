@@ -117,6 +117,64 @@ def test_paper_fixture_refines_to_the_8x8_grid():
     assert tri(m) == tri(s)
 
 
+def _signed_areas(nodes, elems):
+    p = nodes[elems]
+    return 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                  - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+
+
+def _tri_set(nodes, elems):
+    return sorted(tuple(sorted(map(tuple, nodes[e]))) for e in elems)
+
+
+def test_oracle_refine_twice_from_the_paper_mesh_is_the_8x8_grid():
+    """Two red refinements of the paper's 2x2 mesh give the structured 8x8
+    grid (same triangles, exact coordinates) with its 32 Dirichlet edges."""
+    pm = W.paper_mesh()
+    m = (pm.nodes, pm.elems, pm.dirichlet, pm.neumann)
+    for _ in range(2):
+        m = O.uniform_refine(*m)
+    s = W.structured_mesh(8)
+    assert _tri_set(m[0], m[1]) == _tri_set(s.nodes, s.elems)
+    seg = lambda nd, e: sorted(tuple(sorted(map(tuple, nd[x]))) for x in e)
+    assert seg(m[0], m[2]) == seg(s.nodes, s.dirichlet) and len(m[3]) == 0
+
+
+@pytest.mark.parametrize("jitter", [0.0, 0.2])
+def test_oracle_refine_invariants(jitter):
+    """Children are counter-clockwise with a quarter of the parent's area each;
+    V' = V + E (every edge gets one midpoint, Euler: E = V + F - 1); boundary
+    halves are collinear and keep their type; the refined mesh is valid."""
+    base = W.structured_mesh(5, dirichlet=("left", "bottom"), neumann=("right", "top"), jitter=jitter, seed=3)
+    nodes, elems, d, nm = O.uniform_refine(base.nodes, base.elems, base.dirichlet, base.neumann)
+    T = len(base.elems)
+    n_edges = len(base.nodes) + T - 1
+    assert len(nodes) == len(base.nodes) + n_edges and len(elems) == 4 * T
+    assert len(d) == 2 * len(base.dirichlet) and len(nm) == 2 * len(base.neumann)
+    np.testing.assert_array_equal(nodes[:len(base.nodes)], base.nodes)
+    a0 = _signed_areas(base.nodes, base.elems)
+    a1 = _signed_areas(nodes, elems).reshape(T, 4)
+    assert (a1 > 0).all()
+    np.testing.assert_allclose(a1, np.repeat(a0[:, None] / 4, 4, axis=1), rtol=1e-12)
+    for old, new in ((base.dirichlet, d), (base.neumann, nm)):
+        for i, (a, b) in enumerate(old):
+            (p, q), (r, s) = new[2 * i], new[2 * i + 1]
+            assert p == a and s == b and q == r
+            np.testing.assert_array_equal(nodes[q], 0.5 * (base.nodes[a] + base.nodes[b]))
+    M = O.Mesh(nodes, elems, d, nm)
+    assert M.T == 4 * T and M.n_dir == len(d) and M.n_neu == len(nm)
+
+
+def test_oracle_refine_matches_the_input_generator():
+    """The mesh generator's own refinement (used to build inputs) and the
+    oracle's, written separately, give the same arrays."""
+    m = W.structured_mesh(4, dirichlet=("left",), neumann=("right", "top", "bottom"), jitter=0.2, seed=1)
+    r = W.uniform_refine(m)
+    o = O.uniform_refine(m.nodes, m.elems, m.dirichlet, m.neumann)
+    for x, y in zip((r.nodes, r.elems, r.dirichlet, r.neumann), o):
+        np.testing.assert_array_equal(x, y)
+
+
 def test_set_parameter_table():
     g = json.load(open(os.path.join(GOLDEN, "set_parameter_table.json")))
     for c in g["cases"]:
