@@ -303,6 +303,30 @@ int32_t dg_newton_solve(const dg_mesh* mesh, const dg_reaction* r, const dg_newt
                         const double* dev_vals64, const double* dev_rhs, double* dev_x, dg_newton_report* report,
                         void* stream);
 
+/* Backward Euler in time (section 3: the linear reaction coefficient alpha of
+ * its model stands for 1/dt of a time discretisation).  dev_vals64 = D + C + R
+ * assembled (FP64) with alpha = alpha_0 + inv_dt, dev_rhs = F, dev_x = u^0 on
+ * entry and u^{n_steps} on exit.  Step n solves, from the start u^n,
+ *   (D + C + R) u^{n+1} [+ H(u^{n+1})] = F + inv_dt M u^n,
+ * M the mass matrix (|det J_K| times the identity on element K for the
+ * orthonormal basis): by dg_solver_setup once and dg_solver_solve per step when
+ * r is NULL, else by dg_newton_solve with nopts per step.  Allocates one vector
+ * for the duration of the call; synchronises `stream`.  Stops at the first
+ * step that does not reach its tolerance (report->status, report->steps). */
+typedef struct {
+    int32_t status;       /* DG_OK or the first failing step's status */
+    int32_t steps;        /* time steps completed */
+    int64_t linear_iters; /* GMRES iterations over all steps */
+    int64_t newton_steps; /* Newton steps over all steps (0 without r) */
+    double rel_res;       /* relative residual of the last step's system */
+} dg_euler_report;
+int32_t dg_implicit_euler(const dg_mesh* mesh, const dg_reaction* r, const dg_newton_opts* nopts, dg_solver* solver,
+                          const double* dev_vals64, const double* dev_rhs, double inv_dt, int32_t n_steps,
+                          double* dev_x, dg_euler_report* report, void* stream);
+/* The step's load vector alone: dev_out = dev_rhs + inv_dt M dev_u (stream-ordered). */
+int32_t dg_euler_rhs(const dg_mesh* mesh, const double* dev_rhs, const double* dev_u, double inv_dt, double* dev_out,
+                     void* stream);
+
 /* y = b - A x in FP64 with the BSR values of the mesh (dev_b may be NULL: y = -A x). */
 int32_t dg_residual(const dg_mesh* mesh, const double* dev_vals64, const double* dev_b, const double* dev_x,
                     double* dev_y, void* stream);

@@ -352,15 +352,16 @@ def reaction_terms(mesh: Mesh, k: int, c, coef):
     return h, hj
 
 
-def newton(mesh: Mesh, k: int, blocks, c, tol=1e-10, max_newton=50, x0=None):
+def newton(mesh: Mesh, k: int, blocks, c, tol=1e-10, max_newton=50, x0=None, rhs=None):
     """Newton's method for (D + C + R) v + H(v) = F: J w = -Res, v <- v + w with
     Res = A v + H(v) - F and J = A + HJ(v); every linear system is solved
     directly.  Stops when ||Res|| / ||F|| <= tol (checked before each step).
+    F is blocks.rhs unless rhs is given.
     Returns (v, newton steps, final relative residual, converged)."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spl
     A = blocks.to_scipy().tocsr()
-    F = blocks.rhs
+    F = blocks.rhs if rhs is None else np.asarray(rhs, dtype=np.float64)
     n = (k + 1) * (k + 2) // 2
     T = mesh.T
     x = np.zeros(T * n) if x0 is None else np.array(x0, dtype=np.float64)
@@ -412,3 +413,24 @@ def uniform_refine(nodes, elems, dirichlet, neumann):
 
     return (np.array(new_nodes, dtype=np.float64), np.array(tris, dtype=np.int32), halves(dirichlet),
             halves(neumann))
+
+
+def implicit_euler(mesh: Mesh, k: int, blocks, mass, inv_dt, n_steps, x0=None, c=None, tol=1e-10, max_newton=50):
+    """Backward Euler: section 3 reads its linear reaction coefficient as 1/dt
+    of a time discretisation.  `blocks` holds D + C + R assembled with
+    alpha = alpha_0 + inv_dt and F; `mass` the mass matrix (R assembled with
+    alpha = 1).  Each step solves A u^{n+1} [+ H(u^{n+1})] = F + inv_dt M u^n
+    directly (by Newton's method from u^n when c is given).  Returns u^n_steps."""
+    import scipy.sparse.linalg as spl
+    A = blocks.to_scipy().tocsc()
+    M = mass.to_scipy().tocsr()
+    x = np.zeros(A.shape[0]) if x0 is None else np.array(x0, dtype=np.float64)
+    for _ in range(n_steps):
+        rhs = blocks.rhs + inv_dt * (M @ x)
+        if c is None:
+            x = spl.spsolve(A, rhs)
+        else:
+            x, _, _, ok = newton(mesh, k, blocks, c, tol=tol, max_newton=max_newton, x0=x, rhs=rhs)
+            if not ok:
+                raise OracleError("implicit_euler: Newton did not converge")
+    return x

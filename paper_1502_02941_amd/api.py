@@ -88,6 +88,11 @@ class _NewtonReport(C.Structure):
                 ("rel_res", C.c_double)]
 
 
+class _EulerReport(C.Structure):
+    _fields_ = [("status", C.c_int32), ("steps", C.c_int32), ("linear_iters", C.c_int64),
+                ("newton_steps", C.c_int64), ("rel_res", C.c_double)]
+
+
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32)
 
 
@@ -102,7 +107,7 @@ EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_
            "dg_batch_set_progress", "dg_mlp_create", "dg_mlp_num_params", "dg_mlp_forward", "dg_mlp_loss_mse",
            "dg_mlp_backward", "dg_mlp_adam_step", "dg_mlp_params", "dg_mlp_destroy", "dg_warmstart_prolong",
            "dg_mesh_error_points", "dg_l2_error", "dg_reaction_terms", "dg_newton_solve", "dg_mesh_refine_sizes",
-           "dg_mesh_refine"]
+           "dg_mesh_refine", "dg_implicit_euler", "dg_euler_rhs"]
 
 _lib = None
 
@@ -154,6 +159,8 @@ def lib():
         L.dg_reaction_terms.argtypes = [P, C.POINTER(_Reaction), P, P, P, P]
         L.dg_newton_solve.argtypes = [P, C.POINTER(_Reaction), C.POINTER(_NewtonOpts), P, P, P, P,
                                       C.POINTER(_NewtonReport), P]
+        L.dg_implicit_euler.argtypes = [P, P, P, P, P, P, D, I32, P, C.POINTER(_EulerReport), P]
+        L.dg_euler_rhs.argtypes = [P, P, P, D, P, P]
         L.dg_batch_destroy.argtypes = [P]
         L.dg_batch_destroy.restype = None
         L.dg_status_str.argtypes = [I32]
@@ -673,3 +680,32 @@ def newton_solve(mesh: Mesh, solver, vals64: torch.Tensor, rhs: torch.Tensor, x:
     _check(st, "dg_newton_solve")
     return {"status": rep.status, "newton_steps": rep.newton_steps, "linear_iters": rep.linear_iters,
             "rel_res": rep.rel_res}
+
+
+def euler_rhs(mesh: Mesh, rhs: torch.Tensor, u: torch.Tensor, inv_dt: float, out=None, stream=None):
+    """dg_euler_rhs: rhs + inv_dt M u (M the mass matrix)."""
+    if out is None:
+        out = torch.empty_like(rhs)
+    _check(lib().dg_euler_rhs(mesh._h, _dptr(rhs), _dptr(u), float(inv_dt), _dptr(out), _stream(stream)),
+           "dg_euler_rhs")
+    return out
+
+
+def implicit_euler(mesh: Mesh, solver, vals64: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor, inv_dt: float,
+                   n_steps: int, c=None, tol=1e-10, max_newton=50, stream=None):
+    """dg_implicit_euler: n_steps backward Euler steps from x = u^0 (x receives
+    u^n).  vals64 is assembled with alpha = alpha_0 + inv_dt; c (optional) are
+    the coefficients of the non-linear reaction r(u) = sum_p c[p-1] u^p, each
+    step then solved by Newton's method with tolerance tol."""
+    rep = _EulerReport()
+    if c is None:
+        st = lib().dg_implicit_euler(mesh._h, None, None, solver._h, _dptr(vals64), _dptr(rhs), float(inv_dt),
+                                     int(n_steps), _dptr(x), C.byref(rep), _stream(stream))
+    else:
+        r = _reaction(c)
+        o = _NewtonOpts(int(max_newton), 0, float(tol))
+        st = lib().dg_implicit_euler(mesh._h, C.byref(r), C.byref(o), solver._h, _dptr(vals64), _dptr(rhs),
+                                     float(inv_dt), int(n_steps), _dptr(x), C.byref(rep), _stream(stream))
+    _check(st, "dg_implicit_euler")
+    return {"status": rep.status, "steps": rep.steps, "linear_iters": rep.linear_iters,
+            "newton_steps": rep.newton_steps, "rel_res": rep.rel_res}

@@ -89,7 +89,7 @@ def test_batch_rejects_bad_instances_on_host():
 STRUCTS = {"dg_field": "_Field", "dg_problem": "_Problem", "dg_mesh_info": "_MeshInfo",
            "dg_solver_opts": "_SolverOpts", "dg_kernel_stats": "_KStats", "dg_solve_report": "_Report",
            "dg_instance": "_Instance", "dg_batch_opts": "_BatchOpts", "dg_reaction": "_Reaction",
-           "dg_newton_opts": "_NewtonOpts", "dg_newton_report": "_NewtonReport"}
+           "dg_newton_opts": "_NewtonOpts", "dg_newton_report": "_NewtonReport", "dg_euler_report": "_EulerReport"}
 
 
 def test_struct_layouts_match_header(tmp_path):

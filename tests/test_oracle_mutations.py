@@ -62,10 +62,15 @@ def test_mutant_is_caught(name, tmp_path):
 # against a copy of the package placed first on the import path.
 PY_MUTANTS = {
     "refine_inner_child_clockwise": ("tris += [[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, bc, ca]]",
-                                     "tris += [[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, ca, bc]]"),
+                                     "tris += [[a, ab, ca], [ab, b, bc], [ca, bc, c], [ab, ca, bc]]", "refine"),
     "refine_midpoint_half_weight": ("new_nodes.append([0.5 * (nodes[a][0] + nodes[b][0]), 0.5 * (nodes[a][1] + nodes[b][1])])",
-                                    "new_nodes.append([nodes[a][0] + 0.5 * nodes[b][0], 0.5 * (nodes[a][1] + nodes[b][1])])"),
-    "refine_boundary_half_reversed": ("out += [[a, m], [m, b]]", "out += [[m, a], [m, b]]"),
+                                    "new_nodes.append([nodes[a][0] + 0.5 * nodes[b][0], 0.5 * (nodes[a][1] + nodes[b][1])])",
+                                    "refine"),
+    "refine_boundary_half_reversed": ("out += [[a, m], [m, b]]", "out += [[m, a], [m, b]]", "refine"),
+    "euler_identity_mass": ("rhs = blocks.rhs + inv_dt * (M @ x)", "rhs = blocks.rhs + inv_dt * x", "euler"),
+    "euler_one_step_short": ("    for _ in range(n_steps):\n        rhs = blocks.rhs", "    for _ in range(n_steps - 1):\n        rhs = blocks.rhs", "euler"),
+    "newton_ignores_given_rhs": ("F = blocks.rhs if rhs is None else np.asarray(rhs, dtype=np.float64)",
+                                 "F = blocks.rhs", "euler"),
 }
 
 
@@ -74,7 +79,7 @@ def test_python_mutant_is_caught(name, tmp_path):
     """Each mutant fails a refinement pin; the unchanged copy passes them all
     (so a failure means the pins, not the harness)."""
     import shutil
-    old, new = PY_MUTANTS.get(name, ("def uniform_refine(", "def uniform_refine("))
+    old, new, sel = PY_MUTANTS.get(name, ("def uniform_refine(", "def uniform_refine(", "refine or euler"))
     pkg = os.path.join(ROOT, "oracle")
     src = open(os.path.join(pkg, "__init__.py")).read()
     assert src.count(old) == 1, "mutation anchor not found exactly once: %r" % old
@@ -88,8 +93,8 @@ def test_python_mutant_is_caught(name, tmp_path):
     # repository at the front of the path) find it already loaded
     code = ("import sys; sys.path.insert(0, %r); import oracle; assert oracle.__file__.startswith(%r); "
             "sys.path.insert(1, %r); import pytest; "
-            "sys.exit(pytest.main([%r, '-x', '-q', '-p', 'no:cacheprovider', '-k', 'refine']))"
-            % (str(tmp_path), str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_pins.py")))
+            "sys.exit(pytest.main([%r, '-x', '-q', '-p', 'no:cacheprovider', '-k', %r]))"
+            % (str(tmp_path), str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_pins.py"), sel))
     r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True, text=True, timeout=600)
     assert "passed" in r.stdout or "failed" in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]
     if name == "unchanged_copy":

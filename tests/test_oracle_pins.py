@@ -720,3 +720,60 @@ def test_newton_reproduces_polynomials_with_square_reaction(k, kappa):
     uh = O.eval_solution(M, k, x, np.repeat(np.arange(M.T), q * q), np.stack([X, Y], 1))
     ue = u(X, Y)
     assert np.abs(uh - ue).max() <= 1e-9 * np.abs(ue).max()
+
+
+# ------------------------------------------------------- backward Euler in time
+def _reaction_only(k, alpha, f0, n=3):
+    m = W.structured_mesh(n, jitter=0.2, seed=7)
+    M = omesh(m)
+    sigma = 1.0  # irrelevant: eps = 0 removes every penalty term
+    B = O.assemble(M, k, sigma=sigma, kappa=-1.0, eps=0.0, bx=0.0, by=0.0, alpha=alpha, f=f0)
+    Mass = O.assemble(M, k, sigma=sigma, kappa=-1.0, eps=0.0, bx=0.0, by=0.0, alpha=1.0, f=0.0, parts=O.PART_R)
+    return M, B, Mass
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_implicit_euler_reaction_only_is_the_backward_euler_ode(k):
+    """eps = 0, b = 0: every element follows u_t + a0 u = f0, and backward
+    Euler from u = 0 gives u^N = (1 - (1 + a0 dt)^-N) f0 / a0 in the constant
+    mode (u = sqrt(2) c_0), the other modes staying zero."""
+    a0, f0, dt, N = 2.0, 1.5, 0.1, 7
+    M, B, Mass = _reaction_only(k, a0 + 1.0 / dt, f0)
+    x = O.implicit_euler(M, k, B, Mass, 1.0 / dt, N)
+    n = (k + 1) * (k + 2) // 2
+    c = x.reshape(M.T, n)
+    exact = (1.0 - (1.0 + a0 * dt) ** -N) * f0 / a0
+    np.testing.assert_allclose(math.sqrt(2.0) * c[:, 0], exact, rtol=1e-12)
+    assert np.abs(c[:, 1:]).max(initial=0.0) <= 1e-13
+
+
+def test_implicit_euler_nonlinear_p0_is_the_scalar_recurrence():
+    """k = 0, eps = 0, b = 0, r(u) = u^2: each element's value follows
+    (u' - u)/dt + a0 u' + u'^2 = f0, whose positive root gives u' exactly."""
+    a0, f0, dt, N = 1.0, 3.0, 0.05, 6
+    M, B, Mass = _reaction_only(0, a0 + 1.0 / dt, f0)
+    x = O.implicit_euler(M, 0, B, Mass, 1.0 / dt, N, c=[0.0, 1.0], tol=1e-14)
+    u = 0.0
+    for _ in range(N):
+        p, q = a0 + 1.0 / dt, -(f0 + u / dt)
+        u = (-p + math.sqrt(p * p - 4.0 * q)) / 2.0
+    np.testing.assert_allclose(math.sqrt(2.0) * x, u, rtol=1e-12)
+
+
+def test_implicit_euler_reaches_the_steady_solution():
+    """A diffusion-convection problem with a0 = 1 and dt = 1: the backward
+    Euler iterates contract to the stationary DG solution (alpha = a0)."""
+    prob = W.sinsin_problem()
+    m = W.structured_mesh(4)
+    M = omesh(m)
+    sigma, kappa = O.default_penalty(O.SIPG, 1)
+    pts = M.volume_points(3)
+    f = O.Field.points(prob.f(pts[..., 0], pts[..., 1]))
+    kw = dict(sigma=sigma, kappa=kappa, eps=prob.eps, bx=prob.b[0], by=prob.b[1], f=f)
+    a0, inv_dt = prob.alpha, 1.0
+    B = O.assemble(M, 1, alpha=a0 + inv_dt, **kw)
+    Mass = O.assemble(M, 1, sigma=sigma, kappa=kappa, eps=0.0, bx=0.0, by=0.0, alpha=1.0, f=0.0, parts=O.PART_R)
+    Bs = O.assemble(M, 1, alpha=a0, **kw)
+    xs = spl.spsolve(Bs.to_scipy().tocsc(), Bs.rhs)
+    x = O.implicit_euler(M, 1, B, Mass, inv_dt, 80)
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
