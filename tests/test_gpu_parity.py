@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from paper_1502_02941_amd import workloads as W
 from tests import dgcases as DC
 
 pytestmark = pytest.mark.gpu
@@ -67,6 +68,34 @@ def test_superpenalty_assembly_matches_oracle(api, case):
     mesh, _, vals, rhs = _gpu_system(api, case)
     M, B = DC.oracle_system(case)
     assert DC.rel_fro(api.bsr_to_scipy(mesh, vals).tocsr(), B.to_scipy()) <= 1e-12
+    assert DC.rel_fro(rhs.cpu().numpy(), B.rhs) <= 1e-12
+
+
+@pytest.mark.parametrize("method", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_variable_eps_and_alpha_assembly_matches_oracle(api, k, method):
+    """eps(x, y) and alpha(x, y) affine (section 2.2 lets the coefficients be
+    functions), rotating b, mixed boundaries on a jittered mesh: the point
+    quadrature path against the oracle at 1e-12."""
+    m = W.structured_mesh(7, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=20 + k)
+    e, a = (0.05, 0.02, -0.03), (0.4, 0.3, 0.1)
+    sigma = 3.0 * k * (k + 1) if method != 1 else 1.0
+    kappa = {1: 1.0, 2: -1.0, 3: 0.0}[method]
+    mesh = api.Mesh.from_arrays(m, k)
+    F = api.Field
+    P = api.Problem(method, k, sigma, eps=F.affine(*e), bx=F.affine(0.5, 0.0, -1.0), by=F.affine(-0.5, 1.0, 0.0),
+                    alpha=F.affine(*a), f=F.gauss_sum([(0.3, 0.6, 0.1, 1.0), (0.7, 0.2, 0.05, -0.5)]),
+                    gD=0.25, gN=-0.5)
+    vals, rhs = api.assemble(mesh, P)
+    M = O.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann)
+    B = O.assemble(M, k, sigma=sigma, kappa=kappa, eps=O.Field.affine(*e), bx=O.Field.affine(0.5, 0.0, -1.0),
+                   by=O.Field.affine(-0.5, 1.0, 0.0), alpha=O.Field.affine(*a),
+                   f=O.Field.gauss_sum([(0.3, 0.6, 0.1, 1.0), (0.7, 0.2, 0.05, -0.5)]), gD=0.25, gN=-0.5)
+    Ag = api.bsr_to_scipy(mesh, vals).tocsr()
+    Ao = B.to_scipy()
+    assert DC.rel_fro(Ag, Ao) <= 1e-12
+    d, mx = DC.max_abs_diff(Ag, Ao)
+    assert d <= 1e-12 * mx
     assert DC.rel_fro(rhs.cpu().numpy(), B.rhs) <= 1e-12
 
 

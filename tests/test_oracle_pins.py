@@ -381,6 +381,62 @@ def test_polynomial_reproduction(k, kappa, bc):
         assert err < 1e-9, (prob.name, err)
 
 
+def variable_coefficient_polynomial(k, seed):
+    """u in P_k with affine eps(x, y) > 0 and alpha(x, y) (section 2.2 lets eps,
+    b and alpha be functions): f = alpha u - div(eps grad u) + b . grad u,
+    g^D = u, g^N = eps grad u . n, all exact."""
+    prob = W.polynomial_problem(k, 0.0, (0.7, -0.3), 0.0, seed=seed)
+    coef = prob.meta["coef"]
+    e = (0.05, 0.02, -0.03)    # eps >= 0.02 on the unit square
+    a = (0.4, 0.3, 0.1)
+
+    def lap(x, y):
+        s = 0 * x
+        for (i, j), c in coef.items():
+            if i > 1:
+                s = s + c * i * (i - 1) * x ** (i - 2) * y ** j
+            if j > 1:
+                s = s + c * j * (j - 1) * x ** i * y ** (j - 2)
+        return s
+
+    eps = lambda x, y: e[0] + e[1] * x + e[2] * y
+    alpha = lambda x, y: a[0] + a[1] * x + a[2] * y
+
+    def f(x, y):
+        ux, uy = prob.grad_u(x, y)
+        return alpha(x, y) * prob.u(x, y) - eps(x, y) * lap(x, y) - (e[1] * ux + e[2] * uy) + 0.7 * ux - 0.3 * uy
+
+    def gN(x, y, nx, ny):
+        ux, uy = prob.grad_u(x, y)
+        return eps(x, y) * (ux * nx + uy * ny)
+
+    return prob.u, f, gN, e, a
+
+
+@pytest.mark.parametrize("kappa", [-1.0, 0.0, 1.0])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_polynomial_reproduction_with_variable_eps_and_alpha(k, kappa):
+    """Consistency of eq. (ds) with eps(x, y) and alpha(x, y): the edge terms
+    take eps at each edge point (continuous eps), and a global u in P_k is
+    reproduced exactly (every integrand is integrated exactly)."""
+    u, f, gN, e, a = variable_coefficient_polynomial(k, seed=60 + k)
+    m = W.structured_mesh(3, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=k)
+    M = omesh(m)
+    q = k + 2
+    pts = M.volume_points(q)
+    bp, nrm = M.boundary_points(q)
+    sigma = 3.0 * k * (k + 1) if kappa != 1.0 else 1.0
+    B = O.assemble(M, k, sigma=sigma, kappa=kappa, eps=O.Field.affine(*e), bx=0.7, by=-0.3,
+                   alpha=O.Field.affine(*a), f=O.Field.points(f(pts[..., 0], pts[..., 1])),
+                   gD=O.Field.points(u(bp[..., 0], bp[..., 1])),
+                   gN=O.Field.points(gN(bp[..., 0], bp[..., 1], nrm[:, None, 0], nrm[:, None, 1])))
+    x = spl.spsolve(B.to_scipy().tocsc(), B.rhs)
+    X, Y = pts[..., 0].ravel(), pts[..., 1].ravel()
+    uh = O.eval_solution(M, k, x, np.repeat(np.arange(M.T), q * q), np.stack([X, Y], 1))
+    ue = u(X, Y)
+    assert np.abs(uh - ue).max() <= 1e-9 * np.abs(ue).max()
+
+
 def test_polynomial_reproduction_catches_literal_rhs_sign():
     """The paper prints -eps grad v . n g^D in l_h for every kappa; only the kappa
     reading (+kappa eps grad v.n g^D) is consistent for NIPG: with the literal
