@@ -39,7 +39,7 @@ def test_default_penalty_table():
 
 @pytest.mark.parametrize("what,code", [("clockwise", -2), ("missing_bc", -3), ("duplicate_bc", -3),
                                        ("interior_listed", -3), ("three_elems", -4), ("degree", -5),
-                                       ("nan", -7), ("node_range", -1)])
+                                       ("nan", -7), ("node_range", -1), ("no_elements", -1)])
 def test_mesh_validation_errors(what, code):
     m = W.structured_mesh(3)
     nodes, el, d, nm, k = m.nodes.copy(), m.elems.copy(), m.dirichlet.copy(), m.neumann.copy(), 1
@@ -59,6 +59,8 @@ def test_mesh_validation_errors(what, code):
         nodes[3, 0] = np.nan
     elif what == "node_range":
         el[0, 0] = 999
+    elif what == "no_elements":
+        el, d, nm = el[:0], d[:0], nm[:0]
     with pytest.raises(api.DGError) as e:
         api.Mesh(nodes, el, d, nm, k)
     assert e.value.status == code
