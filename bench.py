@@ -94,13 +94,13 @@ def measured_traffic(kernel, form):
 
 def assembly_bytes(mesh, prec_bytes, f_points=True):
     """Algorithmic HBM bytes of one assembly: BSR values + load vector written;
-    per element its vertex coordinates (6 FP64), J^{-T} of its three neighbours
-    (3 x 4 FP64), neighbour table (3 int32), packed neighbour edge ids (int32),
-    row pointer (int32), and the f values at the volume points (FP64) when f is
-    given by point values, each read once."""
+    per element its vertex coordinates (6 FP64), the neighbours' gradient maps
+    on its three edges (3 x 2 FP64), neighbour table (3 int32), packed neighbour
+    edge ids (int32), row pointer (int32), and the f values at the volume points
+    (FP64) when f is given by point values, each read once."""
     n = mesh.n_loc
     out = mesh.nnzb * n * n * prec_bytes + mesh.n_dofs * prec_bytes
-    inp = mesh.T * (6 * 8 + 3 * 4 * 8 + 3 * 4 + 4 + 4) + (mesh.T * mesh.n_q * 8 if f_points else 0)
+    inp = mesh.T * (6 * 8 + 3 * 2 * 8 + 3 * 4 + 4 + 4) + (mesh.T * mesh.n_q * 8 if f_points else 0)
     return out + inp
 
 

@@ -180,27 +180,27 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     constexpr int N = (K + 1) * (K + 2) / 2, NN = N * N;
     constexpr TabLayout L(K);
     const R t_first = ((const R*)a.tab)[L.et], t_last = ((const R*)a.tab)[L.et + L.nqe - 1];
-    // all global loads of the element first, so that they are in flight together
-    // (up to P2; at P3 the neighbour data is loaded per edge to save registers)
-    constexpr bool HOIST = K <= 2;
+    // all global loads of the element first, so that they are in flight together;
+    // the neighbours enter only through the element's own table of their
+    // gradient maps on the shared edges (no gathers)
     const double* p = a.xy + 6 * el;
     const double X1 = p[0], Y1 = p[1], X2 = p[2], Y2 = p[3], X3 = p[4], Y3 = p[5];
     int32_t nb[3];
     int32_t btype[3];
-    double gL[3][4];  // J^{-T} of the neighbours
+    // the table is loaded with the rest, except for P3 in FP64: there it is read
+    // per edge from the element's own row, which keeps 128 VGPRs without spills
+    constexpr bool HOIST = K <= 2 || sizeof(R) == 4;
+    double mL[6];
 #pragma unroll
     for (int l = 0; l < 3; ++l) nb[l] = a.nbr[3 * el + l];
+    if constexpr (HOIST) {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) mL[v] = a.mL[6 * el + v];
+    }
     const int32_t nbe = a.nbr_edge[el];
     const int64_t s0 = a.row_ptr[el];
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        if constexpr (HOIST) {
-            const double* gl = a.gt + 4 * (nb[l] >= 0 ? (int64_t)nb[l] : el);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) gL[l][v] = gl[v];
-        }
-        btype[l] = nb[l] >= 0 ? -1 : a.bnd_type[-nb[l] - 1];
-    }
+    for (int l = 0; l < 3; ++l) btype[l] = nb[l] >= 0 ? -1 : a.bnd_type[-nb[l] - 1];
 
     const double cD = (a.parts & DG_PART_D) ? 1.0 : 0.0;
     const double cC = (a.parts & DG_PART_C) ? 1.0 : 0.0;
@@ -298,13 +298,13 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
             const double hk = 0.5 * deps;
             const int lp = (nbe >> (2 * l)) & 3;
             if constexpr (!HOIST) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) gL[l][v] = a.gt[4 * (int64_t)nb[l] + v];
+                mL[2 * l] = a.mL[6 * el + 2 * l];
+                mL[2 * l + 1] = a.mL[6 * el + 2 * l + 1];
             }
             R c[5];
             c[0] = (R)(-s);
-            c[1] = (R)(-hk * (gL[l][0] * nx + gL[l][1] * ny));  // -1/2 eps |e| m_L
-            c[2] = (R)(-hk * (gL[l][2] * nx + gL[l][3] * ny));
+            c[1] = (R)(-hk * mL[2 * l]);  // -1/2 eps |e| m_L
+            c[2] = (R)(-hk * mL[2 * l + 1]);
             c[3] = (R)(-0.5 * deps * a.kappa * mKx);
             c[4] = (R)(-0.5 * deps * a.kappa * mKy);
             const R* Tl = col + (TenStage::EO + 5 * (3 * l + lp)) * NN;
@@ -335,7 +335,7 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
 }
 
 template <int K, typename R>
-__global__ __launch_bounds__(TEN_BLOCK) void assemble_tensor_kernel(const AsmArgs a, const R* __restrict__ ten)
+__global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const AsmArgs a, const R* __restrict__ ten)
 {
     constexpr TabLayout L(K);
     constexpr int N = L.n, NN = N * N, NQ = L.nq, EPW = 64 / N, WPB = TEN_BLOCK / 64;
@@ -532,7 +532,7 @@ extern "C" int32_t dg_assemble(const dg_mesh* m, const dg_problem* P, int32_t pr
         return st;
     AsmArgs a;
     a.xy = m->d_xy;
-    a.gt = m->d_gt;
+    a.mL = m->d_gt;
     a.nbr = m->d_nbr;
     a.nbr_edge = m->d_nbr_edge;
     a.row_ptr = m->d_row_ptr;

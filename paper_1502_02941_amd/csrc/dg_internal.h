@@ -84,7 +84,7 @@ struct FieldDev {
 
 struct AsmArgs {
     const double* xy;        // [T][6]: element vertex coordinates (x1,y1,x2,y2,x3,y3)
-    const double* gt;        // [T][4]: G = J^{-T} as (G11, G21, G12, G22), so G^T n = (g0 nx + g1 ny, g2 nx + g3 ny)
+    const double* mL;        // [T][6]: per local edge l with a neighbour L, G_L^T (|e| n) (G = J^{-T}); 0 on boundary edges
     const int32_t* nbr;      // [T][3]: neighbour across local edge l, or -(b+1) for boundary edge b
     const int32_t* nbr_edge; // [T]: bits 2l..2l+1 = neighbour's local edge index
     const int32_t* row_ptr;  // [T+1]
@@ -122,7 +122,7 @@ struct dg_mesh {
     int32_t* d_bnd_elems = nullptr;
     double* d_tab64 = nullptr;
     float* d_tab32 = nullptr;
-    double* d_gt = nullptr;     // [T][4] J^{-T} per element (see AsmArgs::gt)
+    double* d_gt = nullptr;     // [T][6] neighbour gradient maps on the edges (see AsmArgs::mL)
     double* d_ten64 = nullptr;  // [3][TenStage::COUNT] n x n staged tensors per kappa (k <= 3)
     float* d_ten32 = nullptr;
     double* d_p1map = nullptr;  // [3][3]: P1 coefficients from vertex values (k >= 1)

@@ -485,7 +485,24 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
             gt[4 * K + 2] = -j21 / det;  // G12
             gt[4 * K + 3] = j11 / det;   // G22
         }
-        st = upload(&m->d_gt, gt);
+        // per element and local edge l with a neighbour L: G_L^T (|e| n_K), the
+        // neighbour's gradient map applied to the scaled outward normal of the
+        // edge, |e| n = (dy, -dx) along the edge from vertex l to vertex l+1
+        std::vector<double> mL((size_t)6 * m->T, 0.0);
+        for (int64_t K = 0; K < m->T; ++K) {
+            const double* p = &m->xy6[6 * K];
+            const double j11 = p[2] - p[0], j12 = p[4] - p[0], j21 = p[3] - p[1], j22 = p[5] - p[1];
+            const double evx[3] = {j11, j12 - j11, -j12}, evy[3] = {j21, j22 - j21, -j22};
+            for (int l = 0; l < 3; ++l) {
+                const int32_t L = m->nbr[3 * K + l];
+                if (L < 0) continue;
+                const double nx = evy[l], ny = -evx[l];
+                const double* g = &gt[4 * (size_t)L];
+                mL[6 * K + 2 * l] = g[0] * nx + g[1] * ny;
+                mL[6 * K + 2 * l + 1] = g[2] * nx + g[3] * ny;
+            }
+        }
+        st = upload(&m->d_gt, mL);
     }
     if (st == DG_OK && degree <= 3) {
         const std::vector<double> ref = build_tensors(degree, m->tab64);
