@@ -149,3 +149,35 @@ def test_batch_rejects_guesses_worse_than_zero(api, split):
                 d = (b.segment(x, i) - b.segment(x0, i)).norm() / b.segment(x0, i).norm()
                 assert float(d) <= 1e-6
     assert not torch.equal(x, x_in)
+
+
+def test_batched_workload_at_full_instance_sizes_sampled(api):
+    """Every 8th instance of the seeded 4096-instance batched workload (P1/P2,
+    N up to 128, eps down to 1e-6) in the launch configuration the benchmark's
+    tuner picks (lockstep for every instance, restart 64 + 2N), FP32 cycles with
+    FP64 refinement: every report reaches 1e-10, and the solutions of sampled
+    instances are judged with the oracle's own FP64 matrix and load vector."""
+    insts = W.sample_instances(4096, seed=0)[::8]
+    meshes = {}
+    pairs = []
+    for i in insts:
+        if i.N not in meshes:
+            meshes[i.N] = W.structured_mesh(i.N)
+        pairs.append((meshes[i.N], api.instance_problem(i)))
+    _say("%d instances, N from %d to %d" % (len(insts), min(i.N for i in insts), max(i.N for i in insts)))
+    b = api.Batch(pairs, mixed=True, rel_tol=1e-10, inner_tol=1e-5, block_threads=256, slots=512, restart_min=64,
+                  restart_per_side=2.0, lockstep_min_dofs=0)
+    x, rep = b.alloc()
+    b.run(x, rep)
+    b.wait(_say)
+    torch.cuda.synchronize()
+    R = b.reports(rep)
+    assert (R["status"] == 0).all() and (R["rel_res"] <= 1e-10).all()
+    _say("  iterations: median %d, max %d" % (int(np.median(R["iters"])), int(R["iters"].max())))
+    xs = x.cpu().numpy()
+    order = sorted(range(len(insts)), key=lambda i: insts[i].N)
+    sample = order[:3] + order[len(order) // 4:len(order) // 4 + 1] + [max(order, key=lambda i: insts[i].eps)]
+    for i in sample:
+        rr = _oracle_relres(insts[i], xs[b.offsets[i]:b.offsets[i + 1]])
+        _say("  instance %d: k=%d N=%d eps=%.1e oracle rel-res %.2e" % (i, insts[i].k, insts[i].N, insts[i].eps, rr))
+        assert rr <= 1.01e-10
