@@ -233,6 +233,25 @@ __global__ __launch_bounds__(SBT) void small_gmres_kernel(const SmallArgs a)
         }
         return;
     }
+    // Up to degree 1, when one pass of waves 1.. covers every element, each lane
+    // keeps its rows of the operator blocks and the neighbour offsets in
+    // registers for the whole solve.
+    constexpr bool RC = N <= 3;
+    const bool regs = RC && T <= EPB1;
+    P rbl[RC ? 3 : 1][RC ? N : 1];
+    int rnb[3] = {-1, -1, -1};
+    if constexpr (RC) {
+        const int el = (wave - 1) * EPW + e_in;
+        if (regs && wave > 0 && lane_ok && el < T) {
+            const int s0 = rp[el], nnb = rp[el + 1] - s0 - 1, c0 = s0 - el;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                rnb[q] = q < nnb ? ci[s0 + 1 + q] * N : -1;
+#pragma unroll
+                for (int c = 0; c < N; ++c) rbl[q][c] = q < nnb ? Ahat[((c0 + q) * N + jj) * N + c] : (P)0;
+            }
+        }
+    }
     const double abs_tol = a.rel_tol * bnorm;
     int its = 0;
     for (;;) {
@@ -286,7 +305,38 @@ __global__ __launch_bounds__(SBT) void small_gmres_kernel(const SmallArgs a)
             // triangle has at most three neighbours: their loads are issued
             // together.  Waves 1.. take the elements while thread 0 of wave 0
             // applies the rotations of step j - 1.
-            for (int e0 = 0; e0 < T && wave > 0; e0 += EPB1) {
+            if constexpr (RC) {
+                const int el = (wave - 1) * EPW + e_in;
+                if (regs && wave > 0 && lane_ok && el < T) {
+                    const int row = el * N + jj;
+                    double s;
+                    if (j == 0) {
+                        s = (double)vj[row];
+                    } else {
+                        const P pv = (P)((double)wprev[row] * invh);
+                        vj[row] = pv;
+                        s = (double)pv;
+                    }
+                    const P* src = j == 0 ? vj : wprev;
+                    P xv[3][N];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+#pragma unroll
+                        for (int c = 0; c < N; ++c) xv[q][c] = rnb[q] >= 0 ? src[rnb[q] + c] : (P)0;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        if (j == 0) {
+#pragma unroll
+                            for (int c = 0; c < N; ++c) s += (double)rbl[q][c] * (double)xv[q][c];
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < N; ++c) s += (double)rbl[q][c] * (double)(P)((double)xv[q][c] * invh);
+                        }
+                    }
+                    w[row] = (P)s;
+                }
+            }
+            for (int e0 = 0; e0 < T && wave > 0 && !regs; e0 += EPB1) {
                 const int el = e0 + (wave - 1) * EPW + e_in;
                 if (!(lane_ok && el < T)) continue;
                 const int row = el * N + jj;
