@@ -120,7 +120,7 @@ def main():
     if args.profile_run:
         args.steps, args.warmup, args.no_cpu_baseline = 1, 0, True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the workload is a single-GPU problem and this build has no "
+        print("bench.py runs on one GPU only: each workload is a single-GPU problem and the library has no "
               "multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
