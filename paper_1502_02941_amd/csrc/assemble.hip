@@ -174,6 +174,16 @@ __device__ void upwind_points(const AsmArgs& a, int l, int lp, int j, double blA
     }
 }
 
+// A wave-uniform double held in scalar registers.  Selecting per lane between
+// two kernel arguments otherwise becomes one vector load from the argument
+// block per lane, whose wait also covers every store issued before it.
+__device__ __forceinline__ double scalar_value(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 template <int K, typename R>
 __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, const int64_t el, const int j)
 {
@@ -187,8 +197,11 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     const double X1 = p[0], Y1 = p[1], X2 = p[2], Y2 = p[3], X3 = p[4], Y3 = p[5];
     int32_t nb[3];
     int32_t btype[3];
-    // the table is loaded with the rest, except for P3 in FP64: there it is read
-    // per edge from the element's own row, which keeps 128 VGPRs without spills
+    // the table is loaded with the rest, except for P3 in FP64: there each
+    // edge's pair is loaded at the start of the previous edge, ahead of that
+    // edge's block stores (loads and stores share one completion counter, so
+    // a load issued after the stores would wait for them), which keeps 128
+    // VGPRs without spills
     constexpr bool HOIST = K <= 2 || sizeof(R) == 4;
     double mL[6];
 #pragma unroll
@@ -196,12 +209,16 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     if constexpr (HOIST) {
 #pragma unroll
         for (int v = 0; v < 6; ++v) mL[v] = a.mL[6 * el + v];
+    } else {
+        mL[0] = a.mL[6 * el];
+        mL[1] = a.mL[6 * el + 1];
     }
     const int32_t nbe = a.nbr_edge[el];
     const int64_t s0 = a.row_ptr[el];
 #pragma unroll
     for (int l = 0; l < 3; ++l) btype[l] = nb[l] >= 0 ? -1 : a.bnd_type[-nb[l] - 1];
 
+    const double sigma_int = scalar_value(a.sigma), sigma_dir = scalar_value(a.sigma_D);
     const double cD = (a.parts & DG_PART_D) ? 1.0 : 0.0;
     const double cC = (a.parts & DG_PART_C) ? 1.0 : 0.0;
     const double cR = (a.parts & DG_PART_R) ? 1.0 : 0.0;
@@ -259,13 +276,19 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     const double evx[3] = {dj11, dj12 - dj11, -dj12}, evy[3] = {dj21, dj22 - dj21, -dj22};
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
+        if constexpr (!HOIST) {
+            if (l < 2) {
+                mL[2 * l + 2] = a.mL[6 * el + 2 * l + 2];
+                mL[2 * l + 3] = a.mL[6 * el + 2 * l + 3];
+            }
+        }
         const bool interior = nb[l] >= 0;
         if (btype[l] == 1) continue;  // Neumann edge: load vector only
         // |e| n = (dy, -dx): every edge coefficient carries the factor |e| of ds
         const double nx = evy[l], ny = -evx[l];
         const double mKx = G11 * nx + G21 * ny, mKy = G12 * nx + G22 * ny;  // |e| G^T n
         const double c1 = interior ? 0.5 : 1.0;
-        const double sig = interior ? a.sigma : a.sigma_D;
+        const double sig = interior ? sigma_int : sigma_dir;
         // |e| * sigma / |e|^b0
         const double pl = a.b0 == 1.0 ? sig : sig * pow(sqrt(nx * nx + ny * ny), 1.0 - a.b0);
         // |e| b . n is linear along the edge: blA at vertex l, blA + dbl at vertex l+1.
@@ -297,10 +320,6 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         if (interior) {
             const double hk = 0.5 * deps;
             const int lp = (nbe >> (2 * l)) & 3;
-            if constexpr (!HOIST) {
-                mL[2 * l] = a.mL[6 * el + 2 * l];
-                mL[2 * l + 1] = a.mL[6 * el + 2 * l + 1];
-            }
             R c[5];
             c[0] = (R)(-s);
             c[1] = (R)(-hk * mL[2 * l]);  // -1/2 eps |e| m_L
@@ -340,12 +359,66 @@ __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const Asm
     constexpr TabLayout L(K);
     constexpr int N = L.n, NN = N * N, NQ = L.nq, EPW = 64 / N, WPB = TEN_BLOCK / 64;
     constexpr int NT = TenStage::COUNT * NN;
-    __shared__ R st[NT + NQ * (N + 3)];  // staged tensors, then the load vector's point tables
-    R* sw = st + NT;
+    constexpr int RPW = 16 / (int)sizeof(R);
+    constexpr int PER = (NT / RPW + TEN_BLOCK - 1) / TEN_BLOCK;  // 16-byte tensor words per thread
+    constexpr int NTP = PER * TEN_BLOCK * RPW;                   // tensor region padded to whole passes
+    __shared__ __align__(16) R st[NTP + NQ * (N + 3)];  // staged tensors, then the load vector's point tables
+    R* sw = st + NTP;
     const bool baff = a.bx.c[1] != 0.0 || a.bx.c[2] != 0.0 || a.by.c[1] != 0.0 || a.by.c[2] != 0.0;
-    const int nst = (baff ? TenStage::COUNT : TenStage::CONST_B) * NN;
-    for (int t = threadIdx.x; t < nst; t += TEN_BLOCK) st[t] = ten[t];
-    if (a.rhs) stage_point_tables<K, R>(a, sw, TEN_BLOCK);
+    // Staging: every load of a thread (the tensors in 16-byte words, then the
+    // load vector's point tables) is issued before its first LDS write, so the
+    // workgroup waits for one round trip instead of one per word; the empty asm
+    // with a memory clobber keeps the compiler from sinking loads into the
+    // guarded writes.  Both staged tensor sets are whole 16-byte words and each
+    // method's set starts on one (the host packs them contiguously from a
+    // hipMalloc base).
+    static_assert(NT % RPW == 0 && (TenStage::CONST_B * NN) % RPW == 0, "staged tensors are whole 16-byte words");
+    constexpr int PPT = (NQ * N + TEN_BLOCK - 1) / TEN_BLOCK;
+    static_assert(NQ <= TEN_BLOCK, "one point per thread");
+    const int nw = (baff ? TenStage::COUNT : TenStage::CONST_B) * NN / RPW;
+    const R* __restrict__ tab = (const R*)a.tab;
+    uint4 buf[PER];
+    R pt[3], pphi[PPT];
+    {
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(ten);
+        // a word past the staged set re-reads word 0 and lands in the tensor
+        // slots that a constant b leaves unread, or in the padding
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int t = threadIdx.x + p * TEN_BLOCK;
+            buf[p] = src[t < nw ? t : 0];
+        }
+        const int q = threadIdx.x < NQ ? threadIdx.x : 0;
+        pt[0] = tab[L.vw + q];
+        pt[1] = tab[L.vxi + q];
+        pt[2] = tab[L.veta + q];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int t = threadIdx.x + p * TEN_BLOCK;
+            pphi[p] = tab[L.vphi + (t < NQ * N ? t : 0)];
+        }
+    }
+    asm volatile("" ::: "memory");
+    {
+        uint4* dst = reinterpret_cast<uint4*>(st);
+#pragma unroll
+        for (int p = 0; p < PER; ++p) dst[threadIdx.x + p * TEN_BLOCK] = buf[p];
+        // point tables (same layout as stage_point_tables): weights, basis
+        // values, then the reference coordinates
+        if (a.rhs) {
+            const int q = threadIdx.x;
+            if (q < NQ) {
+                sw[q] = pt[0];
+                sw[NQ * (N + 1) + q] = pt[1];
+                sw[NQ * (N + 2) + q] = pt[2];
+            }
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const int t = threadIdx.x + p * TEN_BLOCK;
+                if (t < NQ * N) sw[NQ + t] = pphi[p];
+            }
+        }
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int e_in = lane / N;
