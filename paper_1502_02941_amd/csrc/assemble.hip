@@ -185,7 +185,8 @@ __device__ __forceinline__ double scalar_value(double v)
 }
 
 template <int K, typename R>
-__device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, const int64_t el, const int j)
+__device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, const R* sw, const int64_t el,
+                                               const int j)
 {
     constexpr int N = (K + 1) * (K + 2) / 2, NN = N * N;
     constexpr TabLayout L(K);
@@ -197,12 +198,11 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     const double X1 = p[0], Y1 = p[1], X2 = p[2], Y2 = p[3], X3 = p[4], Y3 = p[5];
     int32_t nb[3];
     int32_t btype[3];
-    // the table is loaded with the rest, except for P3 in FP64: there each
-    // edge's pair is loaded at the start of the previous edge, ahead of that
-    // edge's block stores (loads and stores share one completion counter, so
-    // a load issued after the stores would wait for them), which keeps 128
-    // VGPRs without spills
-    constexpr bool HOIST = K <= 2 || sizeof(R) == 4;
+    // the table is loaded with the rest, except for P3: there each edge's pair
+    // is loaded at the start of the previous edge's block, ahead of its stores
+    // (loads and stores share one completion counter, so a load issued after
+    // the stores would wait for them), which keeps 128 VGPRs without spills
+    constexpr bool HOIST = K <= 2;
     double mL[6];
 #pragma unroll
     for (int l = 0; l < 3; ++l) nb[l] = a.nbr[3 * el + l];
@@ -217,6 +217,21 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     const int64_t s0 = a.row_ptr[el];
 #pragma unroll
     for (int l = 0; l < 3; ++l) btype[l] = nb[l] >= 0 ? -1 : a.bnd_type[-nb[l] - 1];
+    // The volume term of the load vector (point tables in sw), computed before
+    // the matrix where registers allow: its loads of f then join the ones
+    // above in flight instead of being issued after the block stores, which
+    // they would wait for.  P3 computes it last and reads the coordinates
+    // again rather than holding them across the matrix.
+    const double xyv[6] = {X1, Y1, X2, Y2, X3, Y3};
+    auto load_vector = [&]() -> R {
+        constexpr int NQ = L.nq;
+        const bool fpts = a.f.kind == DG_QPOINTS;
+        return volume_rhs<K, R, double>(a, sw, fpts ? a.f.vals + el * NQ : nullptr, fpts, HOIST ? xyv : p, j);
+    };
+    R rv = R(0);
+    if constexpr (HOIST) {
+        if (a.rhs) rv = load_vector();
+    }
 
     const double sigma_int = scalar_value(a.sigma), sigma_dir = scalar_value(a.sigma_D);
     const double cD = (a.parts & DG_PART_D) ? 1.0 : 0.0;
@@ -232,9 +247,89 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     // G = J^{-T} = [[G11, G12], [G21, G22]]
     const double G11 = dj22 * inv, G12 = -dj21 * inv, G21 = -dj12 * inv, G22 = dj11 * inv;
     const R* col = st + j * N;
-
     R* __restrict__ vals = (R*)a.vals;
+    // edge vectors from vertex l to vertex l+1
+    const double evx[3] = {dj11, dj12 - dj11, -dj12}, evy[3] = {dj21, dj22 - dj21, -dj22};
+
+    // What edge l contributes to both its diagonal and off-diagonal terms.
+    // |e| n = (dy, -dx): every edge coefficient carries the factor |e| of ds.
+    // |e| b . n is linear along the edge: blA at vertex l, blA + dbl at vertex
+    // l+1.  Upwinding is decided at the quadrature points; when all of them have
+    // the same sign of b . n, the upwind weight max(-b . n, 0) is linear in t and
+    // integrates exactly through E (and t E); otherwise (mixed) the upwind term
+    // of the edge is summed point by point.
+    struct EdgeCoef {
+        double mKx, mKy;  // |e| G^T n
+        double s, s1;     // penalty + inflow weight at vertex l, and its slope along the edge
+        double blA, dbl;
+        bool mixed;
+    };
+    auto edge_coef = [&](int l) {
+        EdgeCoef e;
+        const double nx = evy[l], ny = -evx[l];
+        e.mKx = G11 * nx + G21 * ny;
+        e.mKy = G12 * nx + G22 * ny;
+        const double sig = nb[l] >= 0 ? sigma_int : sigma_dir;
+        // |e| * sigma / |e|^b0
+        const double pl = a.b0 == 1.0 ? sig : sig * pow(sqrt(nx * nx + ny * ny), 1.0 - a.b0);
+        const double xa = l == 0 ? X1 : (l == 1 ? X2 : X3), ya = l == 0 ? Y1 : (l == 1 ? Y2 : Y3);
+        e.blA = (a.bx.c[0] + bx1 * xa + bx2 * ya) * nx + (a.by.c[0] + by1 * xa + by2 * ya) * ny;
+        e.dbl = (bx1 * evx[l] + bx2 * evy[l]) * nx + (by1 * evx[l] + by2 * evy[l]) * ny;
+        const double bl0 = e.blA + (double)t_first * e.dbl, bl1 = e.blA + (double)t_last * e.dbl;
+        const bool inflow = bl0 < 0.0 && bl1 < 0.0;
+        e.mixed = (bl0 < 0.0) != (bl1 < 0.0);
+        e.s = deps * pl + cC * (inflow ? -e.blA : 0.0);
+        e.s1 = cC * (inflow ? -e.dbl : 0.0);
+        return e;
+    };
+
+    // Off-diagonal block of interior edge l, stored as soon as it is complete.
     int64_t slot = s0 + 1;
+    auto off_diagonal = [&](int l, const EdgeCoef& e) {
+        const double hk = 0.5 * deps;
+        const int lp = (nbe >> (2 * l)) & 3;
+        R c[5];
+        c[0] = (R)(-e.s);
+        c[1] = (R)(-hk * mL[2 * l]);  // -1/2 eps |e| m_L
+        c[2] = (R)(-hk * mL[2 * l + 1]);
+        c[3] = (R)(-0.5 * deps * a.kappa * e.mKx);
+        c[4] = (R)(-0.5 * deps * a.kappa * e.mKy);
+        const R* Tl = col + (TenStage::EO + 5 * (3 * l + lp)) * NN;
+        R acco[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) acco[i] = c[0] * Tl[i];
+#pragma unroll
+        for (int t = 1; t < 5; ++t) {
+            const R* T = Tl + t * NN;
+#pragma unroll
+            for (int i = 0; i < N; ++i) acco[i] += c[t] * T[i];
+        }
+        if (baff) {
+            const R c1t = (R)(-e.s1);
+            const R* T1 = col + (TenStage::F1 + 3 * l + lp) * NN;
+#pragma unroll
+            for (int i = 0; i < N; ++i) acco[i] += c1t * T1[i];
+            if (e.mixed) upwind_points<K, R>(a, l, lp, j, e.blA, e.dbl, -cC, acco);
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) vals[(slot * N + i) * N + j] = acco[i];
+        ++slot;
+    };
+    // The off-diagonal blocks first, then the diagonal block: their stores
+    // drain while the diagonal block is summed, and the two sets of
+    // accumulators are never live together.  Each block sums its terms in the
+    // same order as one pass over the edges would.
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if constexpr (!HOIST) {
+            if (l < 2) {
+                mL[2 * l + 2] = a.mL[6 * el + 2 * l + 2];
+                mL[2 * l + 3] = a.mL[6 * el + 2 * l + 3];
+            }
+        }
+        if (nb[l] >= 0) off_diagonal(l, edge_coef(l));
+    }
+
     R accd[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) accd[i] = R(0);
@@ -272,86 +367,31 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
             }
         }
     }
-    // edge vectors from vertex l to vertex l+1
-    const double evx[3] = {dj11, dj12 - dj11, -dj12}, evy[3] = {dj21, dj22 - dj21, -dj22};
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        if constexpr (!HOIST) {
-            if (l < 2) {
-                mL[2 * l + 2] = a.mL[6 * el + 2 * l + 2];
-                mL[2 * l + 3] = a.mL[6 * el + 2 * l + 3];
-            }
-        }
-        const bool interior = nb[l] >= 0;
         if (btype[l] == 1) continue;  // Neumann edge: load vector only
-        // |e| n = (dy, -dx): every edge coefficient carries the factor |e| of ds
-        const double nx = evy[l], ny = -evx[l];
-        const double mKx = G11 * nx + G21 * ny, mKy = G12 * nx + G22 * ny;  // |e| G^T n
-        const double c1 = interior ? 0.5 : 1.0;
-        const double sig = interior ? sigma_int : sigma_dir;
-        // |e| * sigma / |e|^b0
-        const double pl = a.b0 == 1.0 ? sig : sig * pow(sqrt(nx * nx + ny * ny), 1.0 - a.b0);
-        // |e| b . n is linear along the edge: blA at vertex l, blA + dbl at vertex l+1.
-        // Upwinding is decided at the quadrature points; when all of them have
-        // the same sign of b . n, the upwind weight max(-b . n, 0) is linear in
-        // t and integrates exactly through E (and t E); otherwise the upwind
-        // term of this edge is summed point by point below.
-        const double xa = l == 0 ? X1 : (l == 1 ? X2 : X3), ya = l == 0 ? Y1 : (l == 1 ? Y2 : Y3);
-        const double blA = (a.bx.c[0] + bx1 * xa + bx2 * ya) * nx + (a.by.c[0] + by1 * xa + by2 * ya) * ny;
-        const double dbl = (bx1 * evx[l] + bx2 * evy[l]) * nx + (by1 * evx[l] + by2 * evy[l]) * ny;
-        const double bl0 = blA + (double)t_first * dbl, bl1 = blA + (double)t_last * dbl;
-        const bool inflow = bl0 < 0.0 && bl1 < 0.0;
-        const bool mixed = (bl0 < 0.0) != (bl1 < 0.0);
-        const double s = deps * pl + cC * (inflow ? -blA : 0.0);
-        const double s1 = cC * (inflow ? -dbl : 0.0);
-        {
-            const double dc = deps * c1;
-            const R c0 = (R)s, cx = (R)(dc * mKx), cy = (R)(dc * mKy);
-            const R* T = col + (TenStage::ED + 3 * l) * NN;
+        const EdgeCoef e = edge_coef(l);
+        const double dc = deps * (nb[l] >= 0 ? 0.5 : 1.0);
+        const R c0 = (R)e.s, cx = (R)(dc * e.mKx), cy = (R)(dc * e.mKy);
+        const R* T = col + (TenStage::ED + 3 * l) * NN;
 #pragma unroll
-            for (int i = 0; i < N; ++i) accd[i] += c0 * T[i] + cx * T[NN + i] + cy * T[2 * NN + i];
-            if (baff) {
-                const R c1t = (R)s1;
-                const R* T1 = col + (TenStage::E1 + l) * NN;
+        for (int i = 0; i < N; ++i) accd[i] += c0 * T[i] + cx * T[NN + i] + cy * T[2 * NN + i];
+        if (baff) {
+            const R c1t = (R)e.s1;
+            const R* T1 = col + (TenStage::E1 + l) * NN;
 #pragma unroll
-                for (int i = 0; i < N; ++i) accd[i] += c1t * T1[i];
-            }
+            for (int i = 0; i < N; ++i) accd[i] += c1t * T1[i];
         }
-        if (interior) {
-            const double hk = 0.5 * deps;
-            const int lp = (nbe >> (2 * l)) & 3;
-            R c[5];
-            c[0] = (R)(-s);
-            c[1] = (R)(-hk * mL[2 * l]);  // -1/2 eps |e| m_L
-            c[2] = (R)(-hk * mL[2 * l + 1]);
-            c[3] = (R)(-0.5 * deps * a.kappa * mKx);
-            c[4] = (R)(-0.5 * deps * a.kappa * mKy);
-            const R* Tl = col + (TenStage::EO + 5 * (3 * l + lp)) * NN;
-            R acco[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) acco[i] = c[0] * Tl[i];
-#pragma unroll
-            for (int t = 1; t < 5; ++t) {
-                const R* T = Tl + t * NN;
-#pragma unroll
-                for (int i = 0; i < N; ++i) acco[i] += c[t] * T[i];
-            }
-            if (baff) {
-                const R c1t = (R)(-s1);
-                const R* T1 = col + (TenStage::F1 + 3 * l + lp) * NN;
-#pragma unroll
-                for (int i = 0; i < N; ++i) acco[i] += c1t * T1[i];
-                if (mixed) upwind_points<K, R>(a, l, lp, j, blA, dbl, -cC, acco);
-            }
-#pragma unroll
-            for (int i = 0; i < N; ++i) vals[(slot * N + i) * N + j] = acco[i];
-            ++slot;
-        }
-        if (baff && mixed) upwind_points<K, R>(a, l, l, j, blA, dbl, cC, accd, true);
+        if (baff && e.mixed) upwind_points<K, R>(a, l, l, j, e.blA, e.dbl, cC, accd, true);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) vals[(s0 * N + i) * N + j] = accd[i];
+    if (a.rhs) {
+        if constexpr (!HOIST) rv = load_vector();
+        ((R*)a.rhs)[el * N + j] = rv;
+    }
 }
+
 
 template <int K, typename R>
 __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const AsmArgs a, const R* __restrict__ ten)
@@ -425,12 +465,7 @@ __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const Asm
     const int j = lane - e_in * N;
     const int64_t el = ((int64_t)blockIdx.x * WPB + wave) * EPW + e_in;
     if (e_in >= EPW || el >= a.T) return;
-    tensor_element<K, R>(a, st, el, j);
-    if (a.rhs) {
-        const bool fpts = a.f.kind == DG_QPOINTS;
-        ((R*)a.rhs)[el * N + j] = volume_rhs<K, R, double>(a, sw, fpts ? a.f.vals + el * NQ : nullptr, fpts,
-                                                             a.xy + 6 * el, j);
-    }
+    tensor_element<K, R>(a, st, sw, el, j);
 }
 
 // eps and alpha constant (the affine form with zero slopes), b affine
