@@ -64,7 +64,7 @@ def lib():
         L.orc_mesh_edges.argtypes = [P, P, P, P, P, P]
         L.orc_volume_rule.argtypes = [C.c_int, P, P, P]
         L.orc_edge_rule.argtypes = [C.c_int, P, P]
-        L.orc_basis_eval.argtypes = [C.c_int, C.c_int, P, P, P, P, P]
+        L.orc_basis_eval.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P]
         L.orc_volume_points.argtypes = [P, C.c_int, C.c_int, P]
         L.orc_boundary_points.argtypes = [P, C.c_int, P, P]
         L.orc_assemble.argtypes = [P, P, C.c_uint32, P, P, P, P]
@@ -73,10 +73,11 @@ def lib():
         L.orc_gmres.argtypes = [P, C.c_int, P, P, P, P, P, C.c_int, D, C.c_int,
                                 C.POINTER(C.c_int), C.POINTER(D)]
         L.orc_gmres.restype = C.c_int
-        L.orc_eval_solution.argtypes = [P, C.c_int, P, I64, P, P, P]
-        L.orc_l2_error.argtypes = [P, C.c_int, P, C.c_int, P]
+        L.orc_eval_solution.argtypes = [P, C.c_int, C.c_int, P, I64, P, P, P]
+        L.orc_eval_solution.restype = C.c_int
+        L.orc_l2_error.argtypes = [P, C.c_int, C.c_int, P, C.c_int, P]
         L.orc_l2_error.restype = D
-        L.orc_reaction_terms.argtypes = [P, C.c_int, C.c_int, P, P, P, P]
+        L.orc_reaction_terms.argtypes = [P, C.c_int, C.c_int, C.c_int, P, P, P, P]
         L.orc_reaction_terms.restype = C.c_int
         _lib = L
     return _lib
@@ -95,7 +96,7 @@ class _Field(C.Structure):
 
 
 class _Problem(C.Structure):
-    _fields_ = [("degree", C.c_int32), ("sigma", C.c_double), ("sigma_D", C.c_double),
+    _fields_ = [("degree", C.c_int32), ("basis", C.c_int32), ("sigma", C.c_double), ("sigma_D", C.c_double),
                 ("kappa", C.c_double), ("b0", C.c_double),
                 ("eps", _Field), ("bx", _Field), ("by", _Field), ("alpha", _Field),
                 ("f", _Field), ("gD", _Field), ("gN", _Field)]
@@ -205,15 +206,20 @@ def edge_rule(q):
     return t, w
 
 
-def basis_eval(k, xi, eta):
-    """Dubiner basis values and reference gradients, each [npts][n_loc]."""
+# Element bases: the orthonormal Dubiner basis (the paper's default, base = 2
+# of set_parameter) and monomials xi^p eta^q in the same order (base = 1).
+DUBINER, MONOMIAL = 0, 1
+
+
+def basis_eval(k, xi, eta, basis=DUBINER):
+    """Basis values and reference gradients, each [npts][n_loc]."""
     xi = np.ascontiguousarray(xi, dtype=np.float64).ravel()
     eta = np.ascontiguousarray(eta, dtype=np.float64).ravel()
     n = (k + 1) * (k + 2) // 2
     v, dx, de = (np.zeros((len(xi), n)) for _ in range(3))
-    r = lib().orc_basis_eval(k, len(xi), _ptr(xi), _ptr(eta), _ptr(v), _ptr(dx), _ptr(de))
+    r = lib().orc_basis_eval(k, basis, len(xi), _ptr(xi), _ptr(eta), _ptr(v), _ptr(dx), _ptr(de))
     if r < 0:
-        raise OracleError("bad degree")
+        raise OracleError("bad degree or basis")
     return v, dx, de
 
 
@@ -221,8 +227,8 @@ class Blocks:
     """Assembled system: diagonal blocks, the two off-diagonal blocks of every
     interior edge, and the load vector."""
 
-    def __init__(self, mesh, k, diag, off_ij, off_ji, rhs):
-        self.mesh, self.k = mesh, k
+    def __init__(self, mesh, k, diag, off_ij, off_ji, rhs, basis=DUBINER):
+        self.mesh, self.k, self.basis = mesh, k, basis
         self.n = (k + 1) * (k + 2) // 2
         self.diag, self.off_ij, self.off_ji, self.rhs = diag, off_ij, off_ji, rhs
 
@@ -267,7 +273,7 @@ class Blocks:
 
 
 def assemble(mesh: Mesh, k: int, *, sigma, kappa, eps, bx, by, alpha, f, gD=None, gN=None,
-             sigma_D=None, b0=1.0, parts=PART_ALL) -> Blocks:
+             sigma_D=None, b0=1.0, parts=PART_ALL, basis=DUBINER) -> Blocks:
     """Assemble D+C+R (parts selected by the bit mask) and F.  Scalar arguments
     are promoted to CONST fields.  sigma_D defaults to 2*sigma (section 1)."""
 
@@ -278,6 +284,7 @@ def assemble(mesh: Mesh, k: int, *, sigma, kappa, eps, bx, by, alpha, f, gD=None
 
     P = _Problem()
     P.degree = k
+    P.basis = basis
     P.sigma = float(sigma)
     P.sigma_D = float(2.0 * sigma if sigma_D is None else sigma_D)
     P.kappa = float(kappa)
@@ -300,7 +307,7 @@ def assemble(mesh: Mesh, k: int, *, sigma, kappa, eps, bx, by, alpha, f, gD=None
     st = lib().orc_assemble(mesh._h, C.byref(P), parts, _ptr(diag), _ptr(off_ij), _ptr(off_ji), _ptr(rhs))
     if st != 0:
         raise OracleError("orc_assemble failed with status %d" % st)
-    return Blocks(mesh, k, diag, off_ij, off_ji, rhs)
+    return Blocks(mesh, k, diag, off_ij, off_ji, rhs, basis)
 
 
 def gmres(blocks: Blocks, rhs=None, x0=None, restart=50, tol=1e-10, max_iters=100000):
@@ -316,29 +323,30 @@ def gmres(blocks: Blocks, rhs=None, x0=None, restart=50, tol=1e-10, max_iters=10
     return x, its.value, rel.value, st == 0
 
 
-def eval_solution(mesh: Mesh, k: int, coef, elem, xy):
+def eval_solution(mesh: Mesh, k: int, coef, elem, xy, basis=DUBINER):
     elem = np.ascontiguousarray(elem, dtype=np.int32)
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
     coef = np.ascontiguousarray(coef, dtype=np.float64)
     out = np.zeros(len(elem))
-    lib().orc_eval_solution(mesh._h, k, _ptr(coef), len(elem), _ptr(elem), _ptr(xy), _ptr(out))
+    if lib().orc_eval_solution(mesh._h, k, basis, _ptr(coef), len(elem), _ptr(elem), _ptr(xy), _ptr(out)) != 0:
+        raise OracleError("orc_eval_solution: bad degree or basis")
     return out
 
 
-def l2_error(mesh: Mesh, k: int, coef, exact_fn, q=None):
+def l2_error(mesh: Mesh, k: int, coef, exact_fn, q=None, basis=DUBINER):
     """||u_h - u||_L2 with a Stroud rule of q (default k+4) points per direction;
     exact_fn(x, y) is evaluated at the oracle's own points."""
     q = k + 4 if q is None else q
     pts = mesh.volume_points(q)
     ex = np.ascontiguousarray(exact_fn(pts[..., 0], pts[..., 1]), dtype=np.float64)
     coef = np.ascontiguousarray(coef, dtype=np.float64)
-    return float(lib().orc_l2_error(mesh._h, k, _ptr(coef), q, _ptr(ex)))
+    return float(lib().orc_l2_error(mesh._h, k, basis, _ptr(coef), q, _ptr(ex)))
 
 
 # ----------------------------------------------------------------------------
 # Non-linear reaction and Newton's method (section 3).
 # ----------------------------------------------------------------------------
-def reaction_terms(mesh: Mesh, k: int, c, coef):
+def reaction_terms(mesh: Mesh, k: int, c, coef, basis=DUBINER):
     """H_i = int r(u_h) phi_i and the diagonal blocks HJ[K] (row = test) of its
     Jacobian, r(u) = sum_p c[p-1] u^p, with the assembly's volume rule."""
     n = (k + 1) * (k + 2) // 2
@@ -346,7 +354,7 @@ def reaction_terms(mesh: Mesh, k: int, c, coef):
     coef = np.ascontiguousarray(coef, dtype=np.float64)
     h = np.zeros(mesh.T * n)
     hj = np.zeros((mesh.T, n, n))
-    st = lib().orc_reaction_terms(mesh._h, k, len(c), _ptr(c), _ptr(coef), _ptr(h), _ptr(hj))
+    st = lib().orc_reaction_terms(mesh._h, k, basis, len(c), _ptr(c), _ptr(coef), _ptr(h), _ptr(hj))
     if st != 0:
         raise OracleError("orc_reaction_terms: %d" % st)
     return h, hj
@@ -368,7 +376,7 @@ def newton(mesh: Mesh, k: int, blocks, c, tol=1e-10, max_newton=50, x0=None, rhs
     fn = np.linalg.norm(F)
     rel = np.inf
     for it in range(max_newton + 1):
-        h, hj = reaction_terms(mesh, k, c, x)
+        h, hj = reaction_terms(mesh, k, c, x, basis=blocks.basis)
         res = A @ x + h - F
         rel = np.linalg.norm(res) / fn
         if rel <= tol:

@@ -37,6 +37,9 @@
  *   - upwinding is decided pointwise (per quadrature point), b.n < 0 strictly.
  *   - basis = orthonormal Dubiner basis on the reference triangle, vertex 1
  *     of an element row -> (0,0), vertex 2 -> (1,0), vertex 3 -> (0,1).
+ *   - the alternative basis the paper's set_parameter names ("1: monomials",
+ *     no formula) is xi^p eta^q on the same reference triangle, in the same
+ *     order (total degree d = p+q, then q = 0..d); its mass matrix is full.
  *   - quadrature: Stroud conical product with q=k+2 points per direction on
  *     triangles, Gauss-Legendre with k+2 points on edges.
  */
@@ -199,10 +202,22 @@ typedef struct {
     poly2 phi[ORC_MAXN];
 } basis_t;
 
-static void build_basis(int k, basis_t* B)
+enum { ORC_BASIS_DUBINER = 0, ORC_BASIS_MONOMIAL = 1 };
+
+static void build_basis(int k, int basis, basis_t* B)
 {
     B->k = k;
     B->n = (k + 1) * (k + 2) / 2;
+    if (basis == ORC_BASIS_MONOMIAL) {
+        int m = 0;
+        for (int d = 0; d <= k; ++d)
+            for (int q = 0; q <= d; ++q) {
+                poly_zero(&B->phi[m]);
+                B->phi[m].c[d - q][q] = 1.0;  /* xi^p eta^q, p = d - q */
+                ++m;
+            }
+        return;
+    }
     /* Q_p = P_p(a) (1-eta)^p :  Q_0 = 1, Q_1 = 2xi + eta - 1,
      * (p+1) Q_{p+1} = (2p+1)(2xi + eta - 1) Q_p - p (1-eta)^2 Q_{p-1}
      * (Legendre's recurrence multiplied through by (1-eta)^{p+1}). */
@@ -278,12 +293,16 @@ static void eval_basis(const basis_t* B, double xi, double eta, double* v, doubl
     }
 }
 
+static int basis_ok(int basis) { return basis == ORC_BASIS_DUBINER || basis == ORC_BASIS_MONOMIAL; }
+
 /* exported for the basis pins: values and reference gradients at points */
-int orc_basis_eval(int k, int npts, const double* xi, const double* eta, double* v, double* dxi, double* deta)
+int orc_basis_eval(int k, int basis, int npts, const double* xi, const double* eta, double* v, double* dxi,
+                   double* deta)
 {
     if (k < 0 || k > ORC_MAXK) return ORC_ERR_DEGREE;
+    if (!basis_ok(basis)) return ORC_ERR_ARG;
     basis_t B;
-    build_basis(k, &B);
+    build_basis(k, basis, &B);
     for (int p = 0; p < npts; ++p)
         eval_basis(&B, xi[p], eta[p], v + (size_t)p * B.n, dxi ? dxi + (size_t)p * B.n : NULL,
                    deta ? deta + (size_t)p * B.n : NULL);
@@ -534,6 +553,7 @@ static double field_at(const orc_field* F, double x, double y, int64_t pidx)
 
 typedef struct {
     int32_t degree;
+    int32_t basis;   /* ORC_BASIS_DUBINER or ORC_BASIS_MONOMIAL */
     double sigma;    /* penalty on interior edges */
     double sigma_D;  /* penalty on Dirichlet edges (the paper: twice sigma) */
     double kappa;    /* -1 SIPG, +1 NIPG, 0 IIPG */
@@ -593,8 +613,9 @@ int orc_assemble(const orc_mesh* M, const orc_problem* P, uint32_t parts,
 {
     const int k = P->degree;
     if (k < 0 || k > ORC_MAXK) return ORC_ERR_DEGREE;
+    if (!basis_ok(P->basis)) return ORC_ERR_ARG;
     basis_t B;
-    build_basis(k, &B);
+    build_basis(k, P->basis, &B);
     const int n = B.n;
     const int q = k + 2;
     double xi[ORC_MAXQ * ORC_MAXQ], eta[ORC_MAXQ * ORC_MAXQ], wv[ORC_MAXQ * ORC_MAXQ];
@@ -938,11 +959,12 @@ int orc_gmres(const orc_mesh* M, int k, const double* diag, const double* off_ij
 /* ------------------------------------------------------------------------ */
 
 /* u_h(x_p) for points p lying in elements elem[p] */
-int orc_eval_solution(const orc_mesh* M, int k, const double* coef, int64_t np, const int32_t* elem,
+int orc_eval_solution(const orc_mesh* M, int k, int basis, const double* coef, int64_t np, const int32_t* elem,
                       const double* xy, double* out)
 {
+    if (k < 0 || k > ORC_MAXK || !basis_ok(basis)) return ORC_ERR_ARG;
     basis_t B;
-    build_basis(k, &B);
+    build_basis(k, basis, &B);
     double v[ORC_MAXN], gx[ORC_MAXN], gy[ORC_MAXN];
     for (int64_t p = 0; p < np; ++p) {
         affine_t A;
@@ -956,10 +978,11 @@ int orc_eval_solution(const orc_mesh* M, int k, const double* coef, int64_t np, 
 }
 
 /* ||u_h - u||_{L2} with the q x q Stroud rule; exact = u at orc_volume_points(M,k,q) */
-double orc_l2_error(const orc_mesh* M, int k, const double* coef, int q, const double* exact)
+double orc_l2_error(const orc_mesh* M, int k, int basis, const double* coef, int q, const double* exact)
 {
+    if (k < 0 || k > ORC_MAXK || !basis_ok(basis)) return NAN;
     basis_t B;
-    build_basis(k, &B);
+    build_basis(k, basis, &B);
     double xi[ORC_MAXQ * ORC_MAXQ], eta[ORC_MAXQ * ORC_MAXQ], w[ORC_MAXQ * ORC_MAXQ];
     int nq = orc_volume_rule(q, xi, eta, w);
     double v[ORC_MAXN];
@@ -985,11 +1008,12 @@ double orc_l2_error(const orc_mesh* M, int k, const double* coef, int q, const d
 /* element-local: hj[K][i][j] is the diagonal block of element K (row = test */
 /* i, column = trial j).  Either output may be NULL.                          */
 /* ------------------------------------------------------------------------ */
-int orc_reaction_terms(const orc_mesh* M, int k, int np, const double* c, const double* coef, double* h, double* hj)
+int orc_reaction_terms(const orc_mesh* M, int k, int basis, int np, const double* c, const double* coef, double* h,
+                       double* hj)
 {
-    if (k < 0 || k > ORC_MAXK || np < 0 || np > 8) return ORC_ERR_ARG;
+    if (k < 0 || k > ORC_MAXK || np < 0 || np > 8 || !basis_ok(basis)) return ORC_ERR_ARG;
     basis_t B;
-    build_basis(k, &B);
+    build_basis(k, basis, &B);
     const int n = B.n, q = k + 2;
     double xi[ORC_MAXQ * ORC_MAXQ], eta[ORC_MAXQ * ORC_MAXQ], w[ORC_MAXQ * ORC_MAXQ];
     const int nq = orc_volume_rule(q, xi, eta, w);

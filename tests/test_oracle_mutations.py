@@ -38,6 +38,8 @@ MUTANTS = {
     "reaction_derivative_drops_power": ("dr += p * c[p - 1] * up;", "dr += c[p - 1] * up;"),
     "reaction_det_missing": ("const double dx = w[g] * A.det;", "const double dx = w[g];"),
     "reaction_power_off_by_one": ("r += c[p - 1] * up;", "r += c[p - 1] * up * u;"),
+    "monomial_exponents_swapped": ("B->phi[m].c[d - q][q] = 1.0;", "B->phi[m].c[q][d - q] = 1.0;"),
+    "monomial_basis_ignored": ("if (basis == ORC_BASIS_MONOMIAL) {", "if (0) {"),
 }
 
 

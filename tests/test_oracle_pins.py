@@ -833,3 +833,106 @@ def test_implicit_euler_reaches_the_steady_solution():
     xs = spl.spsolve(Bs.to_scipy().tocsc(), Bs.rhs)
     x = O.implicit_euler(M, 1, B, Mass, inv_dt, 80)
     assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+# ----------------------------------------------------------- monomial basis
+# The paper's set_parameter offers monomials as the alternative basis (base = 1)
+# without a formula; the reading here is xi^p eta^q on the reference triangle in
+# the Dubiner order (total degree d = p + q, then q = 0..d).
+def monomial_order(k):
+    return [(d - q, q) for d in range(k + 1) for q in range(d + 1)]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+def test_monomial_basis_values_and_gradients(k):
+    rng = np.random.default_rng(70 + k)
+    xi = rng.uniform(0, 1, 50)
+    eta = rng.uniform(0, 1, 50) * (1 - xi)
+    v, dx, de = O.basis_eval(k, xi, eta, basis=O.MONOMIAL)
+    for m, (p, q) in enumerate(monomial_order(k)):
+        np.testing.assert_allclose(v[:, m], xi ** p * eta ** q, rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(dx[:, m], p * xi ** max(p - 1, 0) * eta ** q if p else 0.0, rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(de[:, m], q * xi ** p * eta ** max(q - 1, 0) if q else 0.0, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_monomial_mass_matrix_closed_form(k):
+    """R_h with alpha = 1 on one triangle is det J times the reference Gram
+    matrix int xi^(p+p') eta^(q+q') = (p+p')! (q+q')! / (p+p'+q+q'+2)!."""
+    nodes = np.array([[0.2, 0.1], [1.1, 0.3], [0.4, 0.9]])
+    M = O.Mesh(nodes, np.array([[0, 1, 2]], dtype=np.int32), np.array([[0, 1], [1, 2], [2, 0]], dtype=np.int32),
+               np.zeros((0, 2), dtype=np.int32))
+    B = O.assemble(M, k, sigma=1.0, kappa=1.0, eps=0.0, bx=0.0, by=0.0, alpha=1.0, f=0.0, parts=O.PART_R,
+                   basis=O.MONOMIAL)
+    det = (1.1 - 0.2) * (0.9 - 0.1) - (0.4 - 0.2) * (0.3 - 0.1)
+    order = monomial_order(k)
+    f = math.factorial
+    G = np.array([[f(p + a) * f(q + b) / f(p + a + q + b + 2) for (a, b) in order] for (p, q) in order])
+    np.testing.assert_allclose(B.diag[0], det * G, rtol=1e-13, atol=1e-16)
+
+
+def dubiner_in_monomials(k):
+    """C with phi^Dubiner_i = sum_m C[i, m] xi^p_m eta^q_m, from values at
+    points (a square, well-posed fit)."""
+    rng = np.random.default_rng(5)
+    xi = rng.uniform(0, 1, 80)
+    eta = rng.uniform(0, 1, 80) * (1 - xi)
+    vd, _, _ = O.basis_eval(k, xi, eta)
+    vm = np.stack([xi ** p * eta ** q for (p, q) in monomial_order(k)], axis=1)
+    Ct, *_ = np.linalg.lstsq(vm, vd, rcond=None)
+    return Ct.T
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("kappa", [-1.0, 0.0, 1.0])
+def test_monomial_system_is_the_dubiner_system_in_another_basis(k, kappa):
+    """a_h and l_h are bilinear / linear, so with phi^D = C phi^M on every
+    element each block transforms as A^D = C A^M C^T and F^D = C F^M."""
+    m = W.structured_mesh(3, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=k)
+    M = omesh(m)
+    q = k + 2
+    pts = M.volume_points(q)
+    bp, nrm = M.boundary_points(q)
+    sigma = 3.0 * k * (k + 1) if kappa != 1.0 else 1.0
+    kw = dict(sigma=sigma, kappa=kappa, eps=O.Field.affine(0.05, 0.02, -0.03), bx=O.Field.affine(0.6, 0.0, -1.0),
+              by=O.Field.affine(-0.2, 1.0, 0.0), alpha=O.Field.affine(0.4, 0.3, 0.1),
+              f=O.Field.points(np.sin(3 * pts[..., 0]) + pts[..., 1]),
+              gD=O.Field.points(np.cos(bp[..., 0] + 2 * bp[..., 1])), gN=O.Field.points(bp[..., 0] * bp[..., 1]))
+    Bd = O.assemble(M, k, **kw)
+    Bm = O.assemble(M, k, basis=O.MONOMIAL, **kw)
+    C = dubiner_in_monomials(k)
+    scale = np.abs(Bd.diag).max()
+    for a, b in ((Bd.diag, Bm.diag), (Bd.off_ij, Bm.off_ij), (Bd.off_ji, Bm.off_ji)):
+        np.testing.assert_allclose(a, C @ b @ C.T, atol=1e-11 * scale)
+    np.testing.assert_allclose(Bd.rhs.reshape(M.T, -1), Bm.rhs.reshape(M.T, -1) @ C.T,
+                               atol=1e-11 * np.abs(Bd.rhs).max())
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_solution_does_not_depend_on_the_basis(k):
+    """u_h is defined by the space P_k(K), not by its basis: both bases give
+    the same u_h at every point and the same L2 error."""
+    prob = W.polynomial_problem(k + 1, 0.02, W.rotating_b(), 0.3, seed=80 + k)  # u outside P_k: a real error
+    m = W.structured_mesh(4, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.15, seed=k)
+    M = omesh(m)
+    q = k + 2
+    pts = M.volume_points(q)
+    bp, nrm = M.boundary_points(q)
+    sigma = 3.0 * k * (k + 1)
+    bx, by = O.Field.affine(*prob.b[1]), O.Field.affine(*prob.b[2])
+    kw = dict(sigma=sigma, kappa=-1.0, eps=prob.eps, bx=bx, by=by, alpha=prob.alpha,
+              f=O.Field.points(prob.f(pts[..., 0], pts[..., 1])), gD=O.Field.points(prob.u(bp[..., 0], bp[..., 1])),
+              gN=O.Field.points(prob.gN(bp[..., 0], bp[..., 1], nrm[:, None, 0], nrm[:, None, 1])))
+    sols = {}
+    for basis in (O.DUBINER, O.MONOMIAL):
+        B = O.assemble(M, k, basis=basis, **kw)
+        x = spl.spsolve(B.to_scipy().tocsc(), B.rhs)
+        rng = np.random.default_rng(1)
+        el = rng.integers(0, M.T, 300).astype(np.int32)
+        lam = rng.dirichlet((1, 1, 1), 300)
+        xy = np.einsum("pv,pvd->pd", lam, m.nodes[m.elems[el]])
+        sols[basis] = (O.eval_solution(M, k, x, el, xy, basis=basis),
+                       O.l2_error(M, k, x, prob.u, basis=basis))
+    (ud, ed), (um, em) = sols[O.DUBINER], sols[O.MONOMIAL]
+    np.testing.assert_allclose(um, ud, atol=1e-10 * np.abs(ud).max())
+    assert abs(em - ed) <= 1e-9 * ed and ed > 1e-6
