@@ -27,9 +27,11 @@
  *
  * Layouts:
  *  - element-local basis: orthonormal Dubiner basis of degree k on the
- *    reference triangle, n_loc = (k+1)(k+2)/2 functions ordered by total
- *    degree d = 0..k, then q = 0..d (p = d-q); vertex 1 of an element row maps
- *    to (0,0), vertex 2 to (1,0), vertex 3 to (0,1);
+ *    reference triangle (the paper's default, base = 2 of set_parameter), or
+ *    with dg_mesh_create_basis the monomials xi^p eta^q (base = 1); either way
+ *    n_loc = (k+1)(k+2)/2 functions ordered by total degree d = 0..k, then
+ *    q = 0..d (p = d-q); vertex 1 of an element row maps to (0,0), vertex 2
+ *    to (1,0), vertex 3 to (0,1);
  *  - dof index = element * n_loc + local index (element-major);
  *  - BSR: row_ptr[T+1], col_idx[nnzb] (int32); block row K holds the
  *    diagonal block first, then one block per interior neighbour in local
@@ -66,6 +68,9 @@ typedef enum {
 /* Method numbering of the paper's set_parameter routine (section 2.2, section 4). */
 typedef enum { DG_NIPG = 1, DG_SIPG = 2, DG_IIPG = 3 } dg_method;
 typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_prec;
+/* Element basis (section 4, set_parameter's `base`): 2 there is the
+ * orthonormal Dubiner basis, 1 the monomials. */
+typedef enum { DG_BASIS_DUBINER = 0, DG_BASIS_MONOMIAL = 1 } dg_basis;
 
 /* Parts of a_h = D_h + C_h + R_h (section 2.3 eq. (dgscheme)) selected by dg_assemble. */
 enum { DG_PART_D = 1, DG_PART_C = 2, DG_PART_R = 4, DG_PART_ALL = 7 };
@@ -106,6 +111,7 @@ typedef struct {
     int64_t n_elems, n_int_edges, n_dir_edges, n_neu_edges;
     int64_t nnzb, n_dofs;
     int32_t degree, n_loc, n_q, n_qe; /* n_q = (k+2)^2 volume points, n_qe = k+2 points per edge */
+    int32_t basis, reserved;          /* dg_basis of the mesh's tables */
     double h_max;                     /* largest edge length */
 } dg_mesh_info;
 
@@ -123,11 +129,20 @@ int32_t dg_default_penalty(int32_t method, int32_t degree, double* sigma, double
  * dir_edges [n_dir][2] and neu_edges [n_neu][2] (start, end node; either
  * direction accepted).  Checks orientation, boundary classification and
  * manifoldness, builds edge connectivity, the BSR pattern and the reference
- * tables for `degree`, and uploads them with synchronous copies on the
- * current device.  *out is NULL on error. */
+ * tables for `degree` in the Dubiner basis, and uploads them with
+ * synchronous copies on the current device.  *out is NULL on error. */
 int32_t dg_mesh_create(const double* nodes_xy, int64_t n_nodes, const int32_t* elems, int64_t n_elems,
                        const int32_t* dir_edges, int64_t n_dir, const int32_t* neu_edges, int64_t n_neu,
                        int32_t degree, dg_mesh** out);
+/* dg_mesh_create with the element basis chosen (set_parameter's `base`,
+ * section 4): DG_BASIS_DUBINER or DG_BASIS_MONOMIAL, else DG_ERR_ARG.  Every
+ * call taking the mesh then works in that basis (coefficients, BSR blocks,
+ * load vector); u_h itself does not depend on it.  With monomials the element
+ * mass matrix is full (dg_euler_rhs applies it).  The batched calls
+ * (dg_batch_*) build their own Dubiner meshes. */
+int32_t dg_mesh_create_basis(const double* nodes_xy, int64_t n_nodes, const int32_t* elems, int64_t n_elems,
+                             const int32_t* dir_edges, int64_t n_dir, const int32_t* neu_edges, int64_t n_neu,
+                             int32_t degree, int32_t basis, dg_mesh** out);
 int32_t dg_mesh_info_get(const dg_mesh* mesh, dg_mesh_info* out);
 void dg_mesh_destroy(dg_mesh* mesh);
 
@@ -309,7 +324,8 @@ int32_t dg_newton_solve(const dg_mesh* mesh, const dg_reaction* r, const dg_newt
  * entry and u^{n_steps} on exit.  Step n solves, from the start u^n,
  *   (D + C + R) u^{n+1} [+ H(u^{n+1})] = F + inv_dt M u^n,
  * M the mass matrix (|det J_K| times the identity on element K for the
- * orthonormal basis): by dg_solver_setup once and dg_solver_solve per step when
+ * orthonormal basis, |det J_K| times the reference Gram matrix for the
+ * monomials): by dg_solver_setup once and dg_solver_solve per step when
  * r is NULL, else by dg_newton_solve with nopts per step.  Allocates one vector
  * for the duration of the call; synchronises `stream`.  Stops at the first
  * step that does not reach its tolerance (report->status, report->steps). */
@@ -323,7 +339,8 @@ typedef struct {
 int32_t dg_implicit_euler(const dg_mesh* mesh, const dg_reaction* r, const dg_newton_opts* nopts, dg_solver* solver,
                           const double* dev_vals64, const double* dev_rhs, double inv_dt, int32_t n_steps,
                           double* dev_x, dg_euler_report* report, void* stream);
-/* The step's load vector alone: dev_out = dev_rhs + inv_dt M dev_u (stream-ordered). */
+/* The step's load vector alone: dev_out = dev_rhs + inv_dt M dev_u (stream-ordered;
+ * dev_out must not overlap dev_u). */
 int32_t dg_euler_rhs(const dg_mesh* mesh, const double* dev_rhs, const double* dev_u, double inv_dt, double* dev_out,
                      void* stream);
 
@@ -434,7 +451,8 @@ void dg_mlp_destroy(dg_mlp* mlp);
  * mode 0 = injection (each element takes its cell's value as a constant),
  * mode 1 = continuous piecewise-bilinear interpolation of the cell-centre
  * values with zero on the boundary, taken at the element vertices as a P1
- * function.  dev_x [B][ldx] FP64 coefficients (modes above P1 set to zero).
+ * function.  dev_x [B][ldx] FP64 coefficients in the mesh's basis (the
+ * functions of degree above 1 get zero).
  * Synchronises `stream`. */
 int32_t dg_warmstart_prolong(const dg_mesh* mesh, const float* dev_coarse, int32_t B, int32_t nc, int32_t mode,
                              double* dev_x, int64_t ldx, void* stream);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libdgdcr.so")
 DG_OK, DG_NOT_CONVERGED = 0, 1
 NIPG, SIPG, IIPG = 1, 2, 3
 F64, F32 = 0, 1
+DUBINER, MONOMIAL = 0, 1  # element bases (dg_basis)
 PART_D, PART_C, PART_R, PART_ALL = 1, 2, 4, 7
 CONST, AFFINE, GAUSS_SUM, QPOINTS = 0, 1, 2, 3
 MAX_DEGREE = 4
@@ -43,7 +44,8 @@ class _Problem(C.Structure):
 class _MeshInfo(C.Structure):
     _fields_ = [("n_elems", C.c_int64), ("n_int_edges", C.c_int64), ("n_dir_edges", C.c_int64),
                 ("n_neu_edges", C.c_int64), ("nnzb", C.c_int64), ("n_dofs", C.c_int64), ("degree", C.c_int32),
-                ("n_loc", C.c_int32), ("n_q", C.c_int32), ("n_qe", C.c_int32), ("h_max", C.c_double)]
+                ("n_loc", C.c_int32), ("n_q", C.c_int32), ("n_qe", C.c_int32), ("basis", C.c_int32),
+                ("reserved", C.c_int32), ("h_max", C.c_double)]
 
 
 class _SolverOpts(C.Structure):
@@ -100,7 +102,7 @@ REPORT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", n
                          ("rel_res", np.float64), ("rel_res0", np.float64), ("guess_rejected", np.int32),
                          ("persistent", np.int32)])
 
-EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_info_get", "dg_mesh_destroy", "dg_mesh_structure",
+EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_create_basis", "dg_mesh_info_get", "dg_mesh_destroy", "dg_mesh_structure",
            "dg_mesh_qpoints", "dg_assemble", "dg_solver_create", "dg_solver_setup", "dg_solver_solve",
            "dg_solver_destroy", "dg_residual", "dg_status_str", "dg_solver_profile",
            "dg_batch_create", "dg_batch_offsets", "dg_batch_run", "dg_batch_destroy", "dg_batch_progress",
@@ -123,6 +125,7 @@ def lib():
         P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.dg_default_penalty.argtypes = [I32, I32, C.POINTER(D), C.POINTER(D)]
         L.dg_mesh_create.argtypes = [P, I64, P, I64, P, I64, P, I64, I32, C.POINTER(P)]
+        L.dg_mesh_create_basis.argtypes = [P, I64, P, I64, P, I64, P, I64, I32, I32, C.POINTER(P)]
         L.dg_mesh_info_get.argtypes = [P, C.POINTER(_MeshInfo)]
         L.dg_mesh_destroy.argtypes = [P]
         L.dg_mesh_destroy.restype = None
@@ -282,9 +285,10 @@ class RefinedArrays:
 
 
 class Mesh:
-    """dg_mesh_create on host arrays (0-based; section 2.1 layout)."""
+    """dg_mesh_create_basis on host arrays (0-based; section 2.1 layout);
+    basis DUBINER (the paper's default) or MONOMIAL."""
 
-    def __init__(self, nodes, elems, dirichlet, neumann, degree: int, device=None):
+    def __init__(self, nodes, elems, dirichlet, neumann, degree: int, device=None, basis: int = DUBINER):
         if device is not None:
             torch.cuda.set_device(device)
         L = lib()
@@ -297,21 +301,21 @@ class Mesh:
         d = np.ascontiguousarray(dirichlet if dirichlet is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
         nm = np.ascontiguousarray(neumann if neumann is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
         h = C.c_void_p()
-        st = L.dg_mesh_create(nodes.ctypes.data, len(nodes), elems.ctypes.data, len(elems),
-                              d.ctypes.data if len(d) else None, len(d), nm.ctypes.data if len(nm) else None, len(nm),
-                              int(degree), C.byref(h))
-        _check(st, "dg_mesh_create")
+        st = L.dg_mesh_create_basis(nodes.ctypes.data, len(nodes), elems.ctypes.data, len(elems),
+                                    d.ctypes.data if len(d) else None, len(d),
+                                    nm.ctypes.data if len(nm) else None, len(nm), int(degree), int(basis), C.byref(h))
+        _check(st, "dg_mesh_create_basis")
         self._h = h
         info = _MeshInfo()
         _check(L.dg_mesh_info_get(h, C.byref(info)), "dg_mesh_info_get")
         self.info = {k: getattr(info, k) for k, _ in _MeshInfo._fields_}
         self.T, self.n_loc, self.nnzb, self.n_dofs = info.n_elems, info.n_loc, info.nnzb, info.n_dofs
-        self.degree, self.n_q, self.n_qe = info.degree, info.n_q, info.n_qe
+        self.degree, self.n_q, self.n_qe, self.basis = info.degree, info.n_q, info.n_qe, info.basis
         self.n_bnd = info.n_dir_edges + info.n_neu_edges
 
     @classmethod
-    def from_arrays(cls, m, degree):
-        return cls(m.nodes, m.elems, m.dirichlet, m.neumann, degree)
+    def from_arrays(cls, m, degree, basis=DUBINER):
+        return cls(m.nodes, m.elems, m.dirichlet, m.neumann, degree, basis=basis)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -667,7 +667,7 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
         std::copy(m.bnd_type.begin(), m.bnd_type.end(), bt.begin() + I.bnd_off);
     }
     meshes.clear();
-    std::vector<double> t1 = build_tables(1), t2 = build_tables(2);
+    std::vector<double> t1 = build_tables(1, DG_BASIS_DUBINER), t2 = build_tables(2, DG_BASIS_DUBINER);
     int s = DG_OK;
     if (s == DG_OK) s = up(&b->d_inst, hinst.data(), hinst.size());
     if (s == DG_OK) s = up(&b->d_order, order.data(), order.size());

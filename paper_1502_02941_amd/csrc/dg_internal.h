@@ -110,6 +110,8 @@ struct dg_mesh {
     std::vector<int32_t> nbr, nbr_edge, row_ptr, col_idx, bnd_el, bnd_loc, bnd_type;
     std::vector<int32_t> bnd_elems;  // elements with at least one boundary edge, ascending
     std::vector<double> tab64;
+    int32_t basis = DG_BASIS_DUBINER;
+    double phi0 = 0.0;  // value of the constant basis function (sqrt 2 or 1)
     // device copies (owned)
     double* d_xy = nullptr;
     int32_t* d_nbr = nullptr;
@@ -126,6 +128,7 @@ struct dg_mesh {
     double* d_ten64 = nullptr;  // [3][TenStage::COUNT] n x n staged tensors per kappa (k <= 3)
     float* d_ten32 = nullptr;
     double* d_p1map = nullptr;  // [3][3]: P1 coefficients from vertex values (k >= 1)
+    double* d_mref = nullptr;   // [n][n] reference mass matrix (monomial basis only)
     double* d_etab = nullptr;   // error rule (q = k + 4): w[nqr], xi[nqr], eta[nqr], phi[nqr][n]
     double* d_epart = nullptr;  // [ERR_BLOCKS + 1] partial sums of dg_l2_error
     int nqr = 0;
@@ -142,9 +145,10 @@ struct dg_mesh {
 };
 
 namespace dg {
-// Host-side reference tables for degree k (Golub-Welsch quadrature, Dubiner
-// basis in collapsed coordinates); returns TabLayout(k).size values.
-std::vector<double> build_tables(int k);
+// Host-side reference tables for degree k (Golub-Welsch quadrature; the
+// Dubiner basis in collapsed coordinates or the monomials, by dg_basis);
+// returns TabLayout(k).size values.
+std::vector<double> build_tables(int k, int basis);
 void solver_invalidate(dg_solver* s);
 
 // One-workgroup GMRES with its state in LDS (small.hip): byte offsets of each
@@ -174,7 +178,7 @@ int small_lds_limit();
 int small_prepare(int N, int mixed, const SmallLayout& L);
 int small_launch(int N, int mixed, const SmallArgs& a, hipStream_t st);
 // Error rule of dg_l2_error: Stroud q = k + 4; [w, xi, eta, phi[nqr][n]].
-std::vector<double> build_error_table(int k, int* nqr);
+std::vector<double> build_error_table(int k, int basis, int* nqr);
 constexpr int ERR_BLOCKS = 1024;
 // Reference tensors (TenLayout) of degree k from the tables of build_tables.
 std::vector<double> build_tensors(int k, const std::vector<double>& tab);

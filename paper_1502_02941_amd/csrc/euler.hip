@@ -7,7 +7,8 @@
 //
 // With the orthonormal reference basis (the integral of phi_i phi_j over the
 // reference triangle is delta_ij) the mass matrix of element K is
-// |det J_K| times the identity, so M u^n is an element-wise scaling.
+// |det J_K| times the identity, so M u^n is an element-wise scaling; with the
+// monomials it is |det J_K| times the reference Gram matrix G.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,6 +32,23 @@ __global__ __launch_bounds__(EB) void euler_rhs_kernel(const double* __restrict_
     out[t] = F[t] + inv_dt * det * u[t];
 }
 
+// the same with a full reference mass matrix G [N][N]: (M u)_t = det sum_j G[i][j] u_(K, j)
+__global__ __launch_bounds__(EB) void euler_rhs_gram_kernel(const double* __restrict__ xy, const double* __restrict__ F,
+                                                            const double* __restrict__ u, double inv_dt, int N,
+                                                            int64_t n, const double* __restrict__ G,
+                                                            double* __restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * EB + threadIdx.x;
+    if (t >= n) return;
+    const int64_t K = t / N;
+    const int i = (int)(t - K * N);
+    const double* p = xy + 6 * K;
+    const double det = (p[2] - p[0]) * (p[5] - p[1]) - (p[4] - p[0]) * (p[3] - p[1]);
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += G[i * N + j] * u[K * N + j];
+    out[t] = F[t] + inv_dt * det * s;
+}
+
 }  // namespace
 }  // namespace dg
 
@@ -41,8 +59,13 @@ extern "C" int32_t dg_euler_rhs(const dg_mesh* m, const double* F, const double*
 {
     if (!m || !F || !u || !out || !std::isfinite(inv_dt)) return DG_ERR_ARG;
     const int64_t n = m->T * m->n;
-    hipLaunchKernelGGL(euler_rhs_kernel, dim3((unsigned)((n + EB - 1) / EB)), dim3(EB), 0, (hipStream_t)stream,
-                       m->d_xy, F, u, inv_dt, m->n, n, out);
+    if (n == 0) return DG_OK;
+    if (m->basis == DG_BASIS_MONOMIAL)
+        hipLaunchKernelGGL(euler_rhs_gram_kernel, dim3((unsigned)((n + EB - 1) / EB)), dim3(EB), 0,
+                           (hipStream_t)stream, m->d_xy, F, u, inv_dt, m->n, n, (const double*)m->d_mref, out);
+    else
+        hipLaunchKernelGGL(euler_rhs_kernel, dim3((unsigned)((n + EB - 1) / EB)), dim3(EB), 0, (hipStream_t)stream,
+                           m->d_xy, F, u, inv_dt, m->n, n, out);
     return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
 }
 

@@ -125,7 +125,30 @@ static void dubiner_at(int k, double xi, double eta, double* v, double* dxi, dou
         }
 }
 
-std::vector<double> build_tables(int k)
+// Monomial basis xi^p eta^q, in the Dubiner order (d = p + q, then q = 0..d).
+static void monomial_at(int k, double xi, double eta, double* v, double* dxi, double* deta)
+{
+    int m = 0;
+    for (int d = 0; d <= k; ++d)
+        for (int q = 0; q <= d; ++q) {
+            const int p = d - q;
+            const double xp = std::pow(xi, p), eq = std::pow(eta, q);
+            v[m] = xp * eq;
+            dxi[m] = p > 0 ? p * std::pow(xi, p - 1) * eq : 0.0;
+            deta[m] = q > 0 ? q * xp * std::pow(eta, q - 1) : 0.0;
+            ++m;
+        }
+}
+
+static void basis_at(int k, int basis, double xi, double eta, double* v, double* dxi, double* deta)
+{
+    if (basis == DG_BASIS_MONOMIAL)
+        monomial_at(k, xi, eta, v, dxi, deta);
+    else
+        dubiner_at(k, xi, eta, v, dxi, deta);
+}
+
+std::vector<double> build_tables(int k, int basis)
 {
     const TabLayout T(k);
     std::vector<double> tab(T.size, 0.0);
@@ -141,7 +164,7 @@ std::vector<double> build_tables(int k)
             tab[T.vw + g] = 0.125 * gwa[i] * gwb[j];
             tab[T.vxi + g] = xi;
             tab[T.veta + g] = eta;
-            dubiner_at(k, xi, eta, v, dx, de);
+            basis_at(k, basis, xi, eta, v, dx, de);
             for (int m = 0; m < T.n; ++m) {
                 tab[T.vphi + g * T.n + m] = v[m];
                 tab[T.vdx + g * T.n + m] = dx[m];
@@ -159,7 +182,7 @@ std::vector<double> build_tables(int k)
             if (l == 0) { xi = t; eta = 0.0; }
             else if (l == 1) { xi = 1.0 - t; eta = t; }
             else { xi = 0.0; eta = 1.0 - t; }
-            dubiner_at(k, xi, eta, v, dx, de);
+            basis_at(k, basis, xi, eta, v, dx, de);
             for (int m = 0; m < T.n; ++m) {
                 tab[T.ephi + (l * q + g) * T.n + m] = v[m];
                 tab[T.edx + (l * q + g) * T.n + m] = dx[m];
@@ -257,7 +280,7 @@ std::vector<double> stage_tensors(int k, const std::vector<double>& ten, double 
     return st;
 }
 
-std::vector<double> build_error_table(int k, int* nqr)
+std::vector<double> build_error_table(int k, int basis, int* nqr)
 {
     const int q = k + 4, nq = q * q, n = (k + 1) * (k + 2) / 2;
     std::vector<double> t((size_t)nq * (3 + n));
@@ -271,7 +294,7 @@ std::vector<double> build_error_table(int k, int* nqr)
             t[g] = 0.125 * gwa[i] * gwb[j];
             t[nq + g] = xi;
             t[2 * nq + g] = eta;
-            dubiner_at(k, xi, eta, v, dx, de);
+            basis_at(k, basis, xi, eta, v, dx, de);
             for (int m = 0; m < n; ++m) t[3 * nq + (size_t)g * n + m] = v[m];
         }
     *nqr = nq;
@@ -284,6 +307,7 @@ static void free_device(dg_mesh* m)
     hipFree(m->d_col_idx); hipFree(m->d_bnd_type); hipFree(m->d_bnd_el); hipFree(m->d_bnd_loc);
     hipFree(m->d_bnd_elems);
     hipFree(m->d_tab64); hipFree(m->d_tab32); hipFree(m->d_p1map); hipFree(m->d_ten64); hipFree(m->d_ten32);
+    hipFree(m->d_mref);
     hipFree(m->d_gt); hipFree(m->d_etab); hipFree(m->d_epart);
     hipFree(m->d_nodes); hipFree(m->d_elems); hipFree(m->d_eid); hipFree(m->d_owner);
     hipFree(m->d_dir); hipFree(m->d_neu); hipFree(m->d_dir_eid); hipFree(m->d_neu_eid);
@@ -444,19 +468,21 @@ int build_host_mesh(const double* xy, int64_t n_nodes, const int32_t* elems, int
         for (int l = 0; l < 3; ++l)
             if (m->nbr[3 * K + l] >= 0) m->col_idx[s++] = m->nbr[3 * K + l];
     }
-    if (with_tables) m->tab64 = build_tables(degree);
+    if (with_tables) m->tab64 = build_tables(degree, m->basis);
     return DG_OK;
 }
 }  // namespace dg
 
-extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32_t* elems, int64_t T,
-                                  const int32_t* dir, int64_t n_dir, const int32_t* neu, int64_t n_neu,
-                                  int32_t degree, dg_mesh** out)
+extern "C" int32_t dg_mesh_create_basis(const double* xy, int64_t n_nodes, const int32_t* elems, int64_t T,
+                                        const int32_t* dir, int64_t n_dir, const int32_t* neu, int64_t n_neu,
+                                        int32_t degree, int32_t basis, dg_mesh** out)
 {
     if (!out) return DG_ERR_ARG;
     *out = nullptr;
+    if (basis != DG_BASIS_DUBINER && basis != DG_BASIS_MONOMIAL) return DG_ERR_ARG;
     dg_mesh* m = new (std::nothrow) dg_mesh();
     if (!m) return DG_ERR_OOM;
+    m->basis = basis;
     int st = build_host_mesh(xy, n_nodes, elems, T, dir, n_dir, neu, n_neu, degree, m, true);
     if (st != DG_OK) { delete m; return st; }
     std::vector<float> tab32(m->tab64.begin(), m->tab64.end());
@@ -472,7 +498,7 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
     if (st == DG_OK) st = upload(&m->d_bnd_elems, m->bnd_elems);
     if (st == DG_OK) st = upload(&m->d_tab64, m->tab64);
     if (st == DG_OK) st = upload(&m->d_tab32, tab32);
-    if (st == DG_OK) st = upload(&m->d_etab, build_error_table(degree, &m->nqr));
+    if (st == DG_OK) st = upload(&m->d_etab, build_error_table(degree, basis, &m->nqr));
     if (st == DG_OK) st = upload(&m->d_epart, std::vector<double>(ERR_BLOCKS + 1, 0.0));
     if (st == DG_OK) {
         std::vector<double> gt((size_t)4 * m->T);
@@ -516,16 +542,36 @@ extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32
         if (st == DG_OK) st = upload(&m->d_ten32, ten32);
     }
     if (st == DG_OK) {
-        // P[m][v] = int_ref lambda_v phi_m: coefficients of the linear function with vertex values u_v
+        // P[m][v]: coefficient of basis function m in the linear function with
+        // vertex values u_v (k >= 1).  Orthonormal basis: int_ref lambda_v phi_m.
+        // Monomials: lambda_1 = 1 - xi - eta, lambda_2 = xi, lambda_3 = eta.
         const TabLayout L(degree);
         std::vector<double> P(9, 0.0);
-        for (int g = 0; g < L.nq && degree >= 1; ++g) {
-            const double xi = m->tab64[L.vxi + g], eta = m->tab64[L.veta + g], w = m->tab64[L.vw + g];
-            const double lam[3] = {1.0 - xi - eta, xi, eta};
-            for (int mm = 0; mm < 3; ++mm)
-                for (int v = 0; v < 3; ++v) P[mm * 3 + v] += w * lam[v] * m->tab64[L.vphi + g * L.n + mm];
+        if (basis == DG_BASIS_MONOMIAL) {
+            if (degree >= 1) {
+                const double Pm[9] = {1.0, 0.0, 0.0, -1.0, 1.0, 0.0, -1.0, 0.0, 1.0};
+                P.assign(Pm, Pm + 9);
+            }
+        } else {
+            for (int g = 0; g < L.nq && degree >= 1; ++g) {
+                const double xi = m->tab64[L.vxi + g], eta = m->tab64[L.veta + g], w = m->tab64[L.vw + g];
+                const double lam[3] = {1.0 - xi - eta, xi, eta};
+                for (int mm = 0; mm < 3; ++mm)
+                    for (int v = 0; v < 3; ++v) P[mm * 3 + v] += w * lam[v] * m->tab64[L.vphi + g * L.n + mm];
+            }
         }
         st = upload(&m->d_p1map, P);
+        m->phi0 = m->tab64[L.vphi];  // the constant function: sqrt 2 (Dubiner) or 1 (monomial)
+        if (st == DG_OK && basis == DG_BASIS_MONOMIAL) {
+            // reference Gram matrix int_ref phi_i phi_j (the volume rule is exact for it)
+            std::vector<double> G((size_t)L.n * L.n, 0.0);
+            for (int g = 0; g < L.nq; ++g)
+                for (int i = 0; i < L.n; ++i)
+                    for (int j = 0; j < L.n; ++j)
+                        G[(size_t)i * L.n + j] +=
+                            m->tab64[L.vw + g] * m->tab64[L.vphi + g * L.n + i] * m->tab64[L.vphi + g * L.n + j];
+            st = upload(&m->d_mref, G);
+        }
     }
     if (st == DG_OK) {
         // Edge ids for refinement: walking the elements in order and each
@@ -589,8 +635,17 @@ extern "C" int32_t dg_mesh_info_get(const dg_mesh* m, dg_mesh_info* out)
     out->n_loc = m->n;
     out->n_q = m->nq;
     out->n_qe = m->nqe;
+    out->basis = m->basis;
+    out->reserved = 0;
     out->h_max = m->hmax;
     return DG_OK;
+}
+
+extern "C" int32_t dg_mesh_create(const double* xy, int64_t n_nodes, const int32_t* elems, int64_t T,
+                                  const int32_t* dir, int64_t n_dir, const int32_t* neu, int64_t n_neu,
+                                  int32_t degree, dg_mesh** out)
+{
+    return dg_mesh_create_basis(xy, n_nodes, elems, T, dir, n_dir, neu, n_neu, degree, DG_BASIS_DUBINER, out);
 }
 
 extern "C" void dg_mesh_destroy(dg_mesh* m)

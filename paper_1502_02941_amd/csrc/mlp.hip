@@ -183,12 +183,13 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ gr,
 
 // P0 -> P1 initial guess on a mesh from values on an nc x nc grid of cells of
 // the unit square.  mode 0: each element takes its cell's value (constant
-// mode only: c0 = value / sqrt(2)); mode 1: the continuous piecewise bilinear
+// mode only: c0 = value / phi0, phi0 the constant basis function: sqrt 2 for
+// the orthonormal basis, 1 for the monomials); mode 1: the continuous piecewise bilinear
 // interpolant of the cell-centre values (zero on the boundary) at the three
 // vertices, then the element's P1 coefficients c_m = sum_v P[m][v] u_v.
 __global__ void prolong_kernel(const double* __restrict__ xy, int64_t T, int nloc, const float* __restrict__ coarse,
-                               int B, int nc, int mode, const double* __restrict__ P, double* __restrict__ x,
-                               int64_t ldx)
+                               int B, int nc, int mode, const double* __restrict__ P, double phi0,
+                               double* __restrict__ x, int64_t ldx)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)B * T) return;
@@ -200,7 +201,7 @@ __global__ void prolong_kernel(const double* __restrict__ xy, int64_t T, int nlo
     if (mode == 0) {
         const double cx = (p[0] + p[2] + p[4]) / 3.0, cy = (p[1] + p[3] + p[5]) / 3.0;
         const int i = min(nc - 1, max(0, (int)floor(cx * nc))), j = min(nc - 1, max(0, (int)floor(cy * nc)));
-        out[0] = (double)cv[j * nc + i] / sqrt(2.0);
+        out[0] = (double)cv[j * nc + i] / phi0;
         return;
     }
     double u[3];
@@ -410,7 +411,7 @@ extern "C" int32_t dg_warmstart_prolong(const dg_mesh* mesh, const float* dev_co
     hipStream_t s = (hipStream_t)stream;
     const int64_t tot = (int64_t)B * mesh->T;
     hipLaunchKernelGGL(prolong_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, mesh->d_xy, mesh->T,
-                       mesh->n, dev_coarse, B, nc, mode, (const double*)mesh->d_p1map, dev_x, ldx);
+                       mesh->n, dev_coarse, B, nc, mode, (const double*)mesh->d_p1map, mesh->phi0, dev_x, ldx);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? DG_OK : DG_ERR_HIP;
 }

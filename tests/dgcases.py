@@ -35,7 +35,7 @@ class Case:
         return O.default_penalty(self.method, self.k)
 
 
-def oracle_system(c: Case):
+def oracle_system(c: Case, basis=O.DUBINER):
     M = O.Mesh(c.mesh.nodes, c.mesh.elems, c.mesh.dirichlet, c.mesh.neumann)
     q = c.k + 2
     sigma, kappa = c.penalty()
@@ -57,7 +57,7 @@ def oracle_system(c: Case):
     else:
         bx, by = O.Field.const(c.b[0]), O.Field.const(c.b[1])
     B = O.assemble(M, c.k, sigma=sigma, kappa=kappa, sigma_D=c.sigma_D, b0=c.b0, eps=c.eps, bx=bx, by=by, alpha=c.alpha,
-                   **kw)
+                   basis=basis, **kw)
     return M, B
 
 

@@ -121,3 +121,11 @@ def test_struct_layouts_match_header(tmp_path):
     assert api.REPORT_DTYPE.itemsize == ctypes.sizeof(api._Report)
     for fname, (_, off) in api.REPORT_DTYPE.fields.items():
         assert off == getattr(api._Report, {"reorth": "reorth_passes"}.get(fname, fname)).offset
+
+
+def test_mesh_create_rejects_unknown_basis():
+    m = W.structured_mesh(3)
+    for bad in (-1, 2, 7):
+        with pytest.raises(api.DGError) as e:
+            api.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann, 1, basis=bad)
+        assert e.value.status == -1
