@@ -222,7 +222,12 @@ typedef struct {
                              restart <= 512 and reorth = profile = 0.  0: automatic, taken for supported
                              systems of at most 4096 unknowns; 1: always (DG_ERR_ARG if unsupported);
                              -1: never */
-    int32_t reserved;
+    int32_t block;        /* Arnoldi vectors per Gram-Schmidt pass of the kernel-per-step path: 1 = one
+                             (w = A M^{-1} v_j, then h = V^T w and w -= V h); 2 = two (w0 = A M^{-1} v_j and
+                             w1 = A M^{-1} w0 projected together, the 2 x 2 block orthonormalised by
+                             Cholesky QR, the two Hessenberg columns recovered from the block), which
+                             reads the basis half as often; 0 = automatic (2, or 1 when reorth is set).
+                             DG_ERR_ARG for other values or for 2 with reorth. */
 } dg_solver_opts;
 
 typedef struct {

@@ -51,7 +51,7 @@ class _MeshInfo(C.Structure):
 class _SolverOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double), ("mixed", C.c_int32),
                 ("inner_tol", C.c_double), ("reorth", C.c_int32), ("profile", C.c_int32),
-                ("guess_limit", C.c_double), ("persistent", C.c_int32), ("reserved", C.c_int32)]
+                ("guess_limit", C.c_double), ("persistent", C.c_int32), ("block", C.c_int32)]
 
 
 class _KStats(C.Structure):
@@ -407,14 +407,15 @@ class Solver:
     FP64 or FP32 cycles with FP64 refinement (mixed=True)."""
 
     def __init__(self, mesh: Mesh, restart=50, max_iters=20000, rel_tol=1e-10, mixed=False, inner_tol=1e-5,
-                 reorth=False, profile=False, guess_limit=0.0, persistent="auto"):
+                 reorth=False, profile=False, guess_limit=0.0, persistent="auto", block=0):
         """persistent: "auto" (one workgroup for small degree-1/2 systems),
         True (always; an error where unsupported) or False (one launch per
-        GMRES kernel)."""
+        GMRES kernel).  block: Arnoldi vectors per Gram-Schmidt pass of the
+        kernel-per-step path (0 automatic, 1 or 2)."""
         self.mesh = mesh
         pers = {"auto": 0, True: 1, False: -1}[persistent]
         o = _SolverOpts(int(restart), int(max_iters), float(rel_tol), int(bool(mixed)), float(inner_tol),
-                        int(bool(reorth)), int(bool(profile)), float(guess_limit), pers, 0)
+                        int(bool(reorth)), int(bool(profile)), float(guess_limit), pers, int(block))
         h = C.c_void_p()
         _check(lib().dg_solver_create(mesh._h, C.byref(o), C.byref(h)), "dg_solver_create")
         self._h = h

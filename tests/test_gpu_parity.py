@@ -353,3 +353,59 @@ def test_solver_rejects_a_guess_worse_than_zero(api, persistent):
     good = x0 * (1 + 1e-6)
     rep = s.solve(rhs, good)
     assert rep.guess_rejected == 0 and rep.rel_res0 < 1e-5 and rep.iters < rep0.iters
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", SOLVE_CASES, ids=[c.name for c in SOLVE_CASES])
+def test_two_vector_blocks_match_one_vector_steps(api, case, mixed):
+    """The kernel-per-step GMRES with one Arnoldi vector per Gram-Schmidt pass
+    and with two (w, A w projected together, Cholesky QR of the block): both
+    reach the tolerance judged by the oracle, in nearly the same number of
+    steps (the Krylov spaces are the same; only rounding differs)."""
+    mesh = api.Mesh.from_arrays(case.mesh, case.k)
+    vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
+    M, B = DC.oracle_system(case)
+    its = {}
+    for block in (1, 2):
+        s = api.Solver(mesh, restart=50, max_iters=20000, rel_tol=case.tol, mixed=mixed, inner_tol=1e-5,
+                       persistent=False, block=block)
+        s.setup(vals)
+        x = torch.zeros_like(rhs)
+        rep = s.solve(rhs, x)
+        rel = _oracle_relres(B, x.cpu().numpy())
+        _say("  %s block %d mixed %s: %d its %d cycles, oracle rel-res %.2e" % (case.name, block, mixed, rep.iters,
+                                                                             rep.cycles, rel))
+        assert rep.status == 0 and rel <= case.tol * 1.01
+        its[block] = rep.iters
+    assert abs(its[2] - its[1]) <= max(4, 0.05 * its[1])
+
+
+@pytest.mark.parametrize("restart", [2, 3, 7])
+def test_two_vector_blocks_with_short_and_odd_restarts(api, restart):
+    """Restart lengths that end a cycle inside a block (odd) or allow only one
+    column per cycle still converge and agree with one-vector steps."""
+    case = SOLVE_CASES[0]
+    mesh = api.Mesh.from_arrays(case.mesh, case.k)
+    vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
+    M, B = DC.oracle_system(case)
+    res = {}
+    for block in (1, 2):
+        s = api.Solver(mesh, restart=restart, max_iters=200000, rel_tol=1e-9, persistent=False, block=block)
+        s.setup(vals)
+        x = torch.zeros_like(rhs)
+        rep = s.solve(rhs, x)
+        res[block] = (rep.status, rep.iters, _oracle_relres(B, x.cpu().numpy()))
+        _say("  restart %d block %d: %s" % (restart, block, res[block]))
+        assert rep.status == 0 and res[block][2] <= 1e-9
+    assert abs(res[2][1] - res[1][1]) <= max(8, 0.1 * res[1][1])
+
+
+def test_two_vector_blocks_reject_reorth(api):
+    mesh = api.Mesh.from_arrays(SOLVE_CASES[0].mesh, SOLVE_CASES[0].k)
+    with pytest.raises(api.DGError) as e:
+        api.Solver(mesh, restart=20, reorth=True, block=2)
+    assert e.value.status == -1
+    for bad in (-1, 3):
+        with pytest.raises(api.DGError):
+            api.Solver(mesh, restart=20, block=bad)
+    api.Solver(mesh, restart=20, reorth=True)  # automatic: one vector per pass with reorth
