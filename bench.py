@@ -77,6 +77,10 @@ def copy_probe(torch):
     log("profile run done")
 
 
+# the kernels behind the solver profiler's classes on the default (two-vector block) path
+BLOCK_KERNELS = {"multidot": "multidot2_kernel", "update": "update2_kernel", "spmv_hat": "spmv_hat_kernel<6>"}
+
+
 def measured_traffic(kernel, form):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/traffic.json), or None when there is none for this kernel and
@@ -240,7 +244,8 @@ def main():
         "dtype": "f64" if best == "fp64" else "f32 Arnoldi cycles + f64 residual/update (f64 assembly)",
         "data": "synthetic (manufactured boundary-layer solution on a structured mesh)",
         "config": {"workload": "256x256 structured, P2 SIPG (131072 triangles, 786432 dofs), eps=1e-6, "
-                               "b=(1,0), alpha=0, boundary-layer u; block-Jacobi GMRES(%d)" % args.restart,
+                               "b=(1,0), alpha=0, boundary-layer u; block-Jacobi GMRES(%d), two Arnoldi vectors "
+                               "per Gram-Schmidt pass" % args.restart,
                    "restart": args.restart, "form": best, "reorth": args.reorth},
         "forms": {f: {"solves_per_s": args.steps / results[f]["seconds"],
                       "ms_per_step": results[f]["seconds"] / args.steps * 1e3,
@@ -248,7 +253,9 @@ def main():
                       "reorth_passes": results[f]["reorth"], "rel_res": results[f]["rel_res"],
                       "converged": results[f]["converged"], "kernels": kstats(f)} for f in forms},
         "assembly": asm,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "launched": "%s<%s>" % (BLOCK_KERNELS.get(dom, dom), "double" if best == "fp64" else "float"),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, best),
                      "launches": launches, "avg_us": ms / launches * 1e3,
                      "bytes_per_launch_avg": nbytes / launches},
