@@ -397,6 +397,9 @@ typedef struct {
     int64_t lockstep_min_dofs; /* instances with at least this many unknowns use the lockstep solver */
     double lockstep_mem_gb;   /* lockstep workspace budget per chunk of instances (<= 0: 64 GB) */
     double guess_limit;       /* per instance, as dg_solver_opts.guess_limit */
+    int32_t lockstep_block;   /* lockstep solver: Arnoldi vectors per Gram-Schmidt pass, as dg_solver_opts.block
+                                 (0 = automatic = 2, 1 or 2; DG_ERR_ARG otherwise) */
+    int32_t reserved;
 } dg_batch_opts;
 
 typedef struct dg_batch dg_batch;

@@ -342,8 +342,9 @@ __global__ __launch_bounds__(LS_BT) void ls_cycle_init_kernel(const LsArgs A)
 // ---------------------------------------------------------------------------
 // Arnoldi step kernels
 // ---------------------------------------------------------------------------
+// w = Ahat v_J, or with second = 1 the two-vector block's w1 = Ahat w
 template <typename P>
-__global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A)
+__global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int second)
 {
     ElemLane e;
     if (!ls_elem_lane(A, e)) return;
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A)
     const int N = e.n;
     const int32_t* rp = A.row_ptr + I.rp_off;
     const int32_t* ci = A.col_idx + I.ci_off;
-    const P* v = (const P*)A.V + I.v_off + (int64_t)S.J * I.n;
+    const P* v = second ? (const P*)A.w + I.x_off : (const P*)A.V + I.v_off + (int64_t)S.J * I.n;
     const P* Ah = (const P*)A.Ahat + I.ahat_off;
     const int s0 = rp[e.el], s1 = rp[e.el + 1];
     const int64_t c0 = (int64_t)s0 - e.el;
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A)
         const P* xv = v + (int64_t)ci[sl] * N;
         for (int c = 0; c < N; ++c) s += (double)blk[c] * (double)xv[c];
     }
-    ((P*)A.w)[I.x_off + e.el * N + e.j] = (P)s;
+    ((P*)(second ? A.w1 : A.w))[I.x_off + e.el * N + e.j] = (P)s;
 }
 
 // partial V_c . w (c <= J) and w . w (c = J+1) over one row chunk
@@ -409,15 +410,17 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot_kernel(const LsArgs A)
     }
 }
 
-// one block per instance: h[c] = sum over chunks
-__global__ __launch_bounds__(LS_BT) void ls_reduce_kernel(const LsArgs A)
+// one block per instance: h[c] = sum over chunks (J + 2 columns, or 2 (J + 1)
+// for a two-vector block)
+__global__ __launch_bounds__(LS_BT) void ls_reduce_kernel(const LsArgs A, int block2)
 {
     const int i = blockIdx.x;
     const LsState& S = A.state[i];
     if (!ls_running(S)) return;
     const LsInst& I = A.inst[i];
     const double* part = A.part + I.part_off;
-    for (int c = threadIdx.x; c < S.J + 2; c += LS_BT) {
+    const int ncols = block2 ? 2 * (S.J + 1) : S.J + 2;
+    for (int c = threadIdx.x; c < ncols; c += LS_BT) {
         double s = 0.0;
         for (int ch = 0; ch < I.nchunks; ++ch) s += part[(int64_t)c * I.nchunks + ch];
         A.hcol[I.hc_off + c] = s;
@@ -565,6 +568,315 @@ __global__ __launch_bounds__(LS_BT) void ls_normalize_kernel(const LsArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// Two-vector blocks (as in the single-system solver): w0 = Ahat v_J and
+// w1 = Ahat w0 are projected against v_0..v_J in one pass over the basis and
+// updated in a second, the 2 x 2 Gram matrix of the results is factored by
+// Cholesky, and the two Hessenberg columns follow from the block relations.
+// ---------------------------------------------------------------------------
+constexpr int LS_CT2 = 8;  // columns per tile with two right-hand sides
+
+// partial V_c . w_r (c <= J, r = 0, 1) over one row chunk, at part[(r (J+1) + c) nchunks + chunk]
+template <typename P>
+__global__ __launch_bounds__(LS_BT) void ls_multidot2_kernel(const LsArgs A)
+{
+    __shared__ double sh[LS_BT / 64][2 * LS_CT2];
+    const int64_t b = blockIdx.x;
+    const int i = ls_find(A.rblk, A.count, b);
+    const LsState& S = A.state[i];
+    if (!ls_running(S)) return;
+    const LsInst& I = A.inst[i];
+    const int64_t ch = b - A.rblk[i];
+    const int J = S.J, ncols = J + 1;
+    const P* V = (const P*)A.V + I.v_off;
+    const P* w0 = (const P*)A.w + I.x_off;
+    const P* w1 = (const P*)A.w1 + I.x_off;
+    const int64_t r0 = ch * LS_CH, r1 = min(r0 + LS_CH, I.n);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* part = A.part + I.part_off;
+    for (int t0 = 0; t0 < ncols; t0 += LS_CT2) {
+        const P* col[LS_CT2];
+#pragma unroll
+        for (int c = 0; c < LS_CT2; ++c) col[c] = (t0 + c <= J) ? V + (int64_t)(t0 + c) * I.n : w0;  // past J: discarded
+        double a0[LS_CT2], a1[LS_CT2];
+#pragma unroll
+        for (int c = 0; c < LS_CT2; ++c) a0[c] = a1[c] = 0.0;
+        for (int64_t t = r0 + threadIdx.x; t < r1; t += LS_BT) {
+            const double x0 = (double)w0[t], x1 = (double)w1[t];
+#pragma unroll
+            for (int c = 0; c < LS_CT2; ++c) {
+                const double v = (double)col[c][t];
+                a0[c] += v * x0;
+                a1[c] += v * x1;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < LS_CT2; ++c) {
+            const double v0 = ls_wave_sum(a0[c]), v1 = ls_wave_sum(a1[c]);
+            if (lane == 0) {
+                sh[wave][c] = v0;
+                sh[wave][LS_CT2 + c] = v1;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * LS_CT2) {
+            const int rr = threadIdx.x / LS_CT2, c = threadIdx.x - rr * LS_CT2;
+            if (t0 + c < ncols)
+                part[((int64_t)rr * ncols + t0 + c) * I.nchunks + ch] =
+                    (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+        }
+        __syncthreads();
+    }
+}
+
+// w_r -= sum_{c<=J} R_r[c] V_c (R_0 = hcol[0..J], R_1 = hcol[J+1..2J+1]) and the
+// Gram partials u0.u0, u0.u1, u1.u1 at red[red_off + k nchunks + chunk]
+template <typename P>
+__global__ __launch_bounds__(LS_BT) void ls_update2_kernel(const LsArgs A)
+{
+    __shared__ double sh[LS_BT / 64];
+    const int64_t b = blockIdx.x;
+    const int i = ls_find(A.rblk, A.count, b);
+    const LsState& S = A.state[i];
+    if (!ls_running(S)) return;
+    const LsInst& I = A.inst[i];
+    const int64_t ch = b - A.rblk[i];
+    const int J = S.J;
+    const P* V = (const P*)A.V + I.v_off;
+    P* w0 = (P*)A.w + I.x_off;
+    P* w1 = (P*)A.w1 + I.x_off;
+    const double* R0 = A.hcol + I.hc_off;
+    const double* R1 = R0 + (J + 1);
+    const int64_t r0 = ch * LS_CH, r1 = min(r0 + LS_CH, I.n);
+    const int64_t n = I.n;
+    double g00 = 0.0, g01 = 0.0, g11 = 0.0;
+    constexpr int E = 4;
+    for (int64_t t0 = r0 + threadIdx.x; t0 < r1; t0 += (int64_t)LS_BT * E) {
+        double u0[E], u1[E];
+        bool in[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t t = t0 + (int64_t)e * LS_BT;
+            in[e] = t < r1;
+            u0[e] = in[e] ? (double)w0[t] : 0.0;
+            u1[e] = in[e] ? (double)w1[t] : 0.0;
+        }
+        int c = 0;
+        for (; c + 3 <= J; c += 4) {
+            const double p0 = R0[c], p1 = R0[c + 1], p2 = R0[c + 2], p3 = R0[c + 3];
+            const double q0 = R1[c], q1 = R1[c + 1], q2 = R1[c + 2], q3 = R1[c + 3];
+            const P* v0 = V + (int64_t)c * n;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t t = t0 + (int64_t)e * LS_BT;
+                if (in[e]) {
+                    const double a = (double)v0[t], bb = (double)v0[t + n], cc = (double)v0[t + 2 * n],
+                                 d = (double)v0[t + 3 * n];
+                    u0[e] -= p0 * a + p1 * bb + p2 * cc + p3 * d;
+                    u1[e] -= q0 * a + q1 * bb + q2 * cc + q3 * d;
+                }
+            }
+        }
+        for (; c <= J; ++c) {
+            const double p0 = R0[c], q0 = R1[c];
+            const P* vc = V + (int64_t)c * n;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t t = t0 + (int64_t)e * LS_BT;
+                if (in[e]) {
+                    const double a = (double)vc[t];
+                    u0[e] -= p0 * a;
+                    u1[e] -= q0 * a;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (in[e]) {
+                const int64_t t = t0 + (int64_t)e * LS_BT;
+                const P a = (P)u0[e], bb = (P)u1[e];
+                w0[t] = a;
+                w1[t] = bb;
+                g00 += (double)a * (double)a;
+                g01 += (double)a * (double)bb;
+                g11 += (double)bb * (double)bb;
+            }
+        }
+    }
+    g00 = ls_block_sum(g00, sh);
+    g01 = ls_block_sum(g01, sh);
+    g11 = ls_block_sum(g11, sh);
+    if (threadIdx.x == 0) {
+        double* red = A.red + I.red_off;
+        red[ch] = g00;
+        red[I.nchunks + ch] = g01;
+        red[2 * I.nchunks + ch] = g11;
+    }
+}
+
+// previous Givens rotations applied to colv[0..count] in LDS (thread 0 runs the
+// chain; the rotations are staged in chunks by the 64 threads)
+__device__ void ls_rotate(double* colv, int count, const double* __restrict__ cs, const double* __restrict__ sn,
+                          double* sc, double* ss)
+{
+    double a = colv[0];
+    for (int i0 = 0; i0 < count; i0 += LS_GV) {
+        const int cnt = min(count - i0, LS_GV);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 64) {
+            sc[t] = cs[i0 + t];
+            ss[t] = sn[i0 + t];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int t = 0; t < cnt; ++t) {
+                const double bv = colv[i0 + t + 1];
+                colv[i0 + t] = sc[t] * a + ss[t] * bv;
+                a = -ss[t] * a + sc[t] * bv;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) colv[count] = a;
+    __syncthreads();
+}
+
+// one block of 64 threads per instance: Gram sums, Cholesky, the two raw
+// Hessenberg columns (Hr, leading dimension m + 2) and, rotated, into H;
+// residual estimates and stop tests.  Dynamic LDS: two columns of max_m + 4.
+__global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int step)
+{
+    extern __shared__ double dyn[];
+    __shared__ double sc[LS_GV], ss[LS_GV];
+    __shared__ double fac[3];
+    __shared__ int flags[2];  // take the second column, stop after the first
+    const int i = blockIdx.x;
+    LsState& S = A.state[i];
+    if (!ls_running(S)) return;
+    const LsInst& I = A.inst[i];
+    const int j = S.J, mcyc = S.mcyc, ldh = I.m + 1, ldr = I.m + 2;
+    double* colA = dyn;
+    double* colB = dyn + (I.m + 4);
+    double* H = A.H + I.H_off;
+    double* Hr = A.Hr + I.Hr_off;
+    double* cs = A.cs + I.h_off;
+    double* sn = A.sn + I.h_off;
+    double* g = A.g + I.h_off;
+    const double* R0 = A.hcol + I.hc_off;
+    const double* R1 = R0 + (j + 1);
+    const double* red = A.red + I.red_off;
+    double a00 = 0.0, a01 = 0.0, a11 = 0.0;
+    for (int c = threadIdx.x; c < I.nchunks; c += 64) {
+        a00 += red[c];
+        a01 += red[I.nchunks + c];
+        a11 += red[2 * I.nchunks + c];
+    }
+    a00 = ls_wave_sum(a00);
+    a01 = ls_wave_sum(a01);
+    a11 = ls_wave_sum(a11);
+    for (int t = threadIdx.x; t <= j; t += 64) colA[t] = R0[t];
+    if (threadIdx.x == 0) {
+        const double r11 = sqrt(a00);
+        const bool brk1 = !(r11 > 1e-300) || !isfinite(r11);
+        const double r12 = brk1 ? 0.0 : a01 / r11;
+        const double d = a11 - r12 * r12;
+        const double r22 = d > 0.0 ? sqrt(d) : 0.0;
+        const bool ok2 = !brk1 && isfinite(r22) && r22 > 1e-8 * sqrt(a11);
+        fac[0] = r11;
+        fac[1] = r12;
+        fac[2] = r22;
+        colA[j + 1] = r11;
+        S.q1 = brk1 ? 0.0 : 1.0 / r11;
+        S.q2a = ok2 ? 1.0 / r22 : 0.0;
+        S.q2b = ok2 ? -r12 / (r11 * r22) : 0.0;
+        flags[0] = ok2 ? 1 : 0;
+        flags[1] = brk1 ? 1 : 0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t <= j + 1; t += 64) Hr[t + (int64_t)j * ldr] = colA[t];
+    __syncthreads();
+    const bool want2 = !flags[1] && j + 1 < mcyc;
+    if (want2) {
+        const double r11 = fac[0];
+        for (int t = threadIdx.x; t <= j + 1; t += 64) {
+            double acc = 0.0;
+            for (int c = t > 0 ? t - 1 : 0; c <= j; ++c) acc += Hr[t + (int64_t)c * ldr] * R0[c];
+            colB[t] = ((t <= j ? R1[t] : fac[1]) - acc) / r11;
+        }
+        if (threadIdx.x == 0) colB[j + 2] = fac[2] / r11;
+        __syncthreads();
+        for (int t = threadIdx.x; t <= j + 2; t += 64) Hr[t + (int64_t)(j + 1) * ldr] = colB[t];
+    }
+    ls_rotate(colA, j, cs, sn, sc, ss);
+    if (threadIdx.x == 0) {
+        const double a = colA[j], bv = colA[j + 1];
+        const double d = sqrt(a * a + bv * bv);
+        cs[j] = d == 0.0 ? 1.0 : a / d;
+        sn[j] = d == 0.0 ? 0.0 : bv / d;
+        colA[j] = d;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        if (flags[1] || fabs(g[j + 1]) <= S.cyctol || j + 1 >= mcyc || !want2) flags[1] = 1;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t <= j; t += 64) H[t + (int64_t)j * ldh] = colA[t];
+    if (flags[1]) {
+        if (threadIdx.x == 0) {
+            S.jb = j;
+            S.bstep = step;
+            S.J = j + 1;
+            S.stop = 1;
+            atomicSub(A.counters + 1, 1);
+        }
+        return;
+    }
+    ls_rotate(colB, j + 1, cs, sn, sc, ss);
+    if (threadIdx.x == 0) {
+        const int k = j + 1;
+        const double a = colB[k], bv = colB[k + 1];
+        const double d = sqrt(a * a + bv * bv);
+        cs[k] = d == 0.0 ? 1.0 : a / d;
+        sn[k] = d == 0.0 ? 0.0 : bv / d;
+        colB[k] = d;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        S.jb = j;
+        S.bstep = step;
+        S.J = k + 1;
+        if (!flags[0] || fabs(g[k + 1]) <= S.cyctol || k + 1 >= mcyc) {
+            S.stop = 1;
+            atomicSub(A.counters + 1, 1);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t <= j + 1; t += 64) H[t + (int64_t)(j + 1) * ldh] = colB[t];
+}
+
+// v_{jb+1} = q1 u0 and, unless the cycle stopped, v_{jb+2} = q2a u1 + q2b u0,
+// for instances whose block of this step took both columns
+template <typename P>
+__global__ __launch_bounds__(LS_BT) void ls_normalize2_kernel(const LsArgs A, int step)
+{
+    const int64_t b = blockIdx.x;
+    const int i = ls_find(A.rblk, A.count, b);
+    const LsState& S = A.state[i];
+    if (!S.active || S.bstep != step || S.J != S.jb + 2) return;
+    const LsInst& I = A.inst[i];
+    const int64_t ch = b - A.rblk[i];
+    const bool second = !S.stop;
+    const double a = S.q1, qa = S.q2a, qb = S.q2b;
+    P* o1 = (P*)A.V + I.v_off + (int64_t)(S.jb + 1) * I.n;
+    P* o2 = o1 + I.n;
+    const P* w0 = (const P*)A.w + I.x_off;
+    const P* w1 = (const P*)A.w1 + I.x_off;
+    const int64_t r1 = min((ch + 1) * (int64_t)LS_CH, I.n);
+    for (int64_t t = ch * LS_CH + threadIdx.x; t < r1; t += LS_BT) {
+        const double u0 = (double)w0[t];
+        o1[t] = (P)(u0 * a);
+        if (second) o2[t] = (P)((double)w1[t] * qa + u0 * qb);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // end of a cycle: y = R^{-1} g, u = V y, x += D^{-1} u
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(LS_BT) void ls_trisolve_kernel(const LsArgs A)
@@ -659,6 +971,7 @@ static int ls_solve_p(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m
     hipLaunchKernelGGL(ls_bnorm_kernel, gr, be, 0, st, A);
     int first = 1;
     int h[2];
+    int step = 1;  // host step index of the two-vector blocks, unique over the whole solve
     for (;;) {
         hipLaunchKernelGGL(ls_zero_counters, dim3(1), dim3(1), 0, st, A.counters);
         hipLaunchKernelGGL(ls_residual_kernel, ge, be, 0, st, A);
@@ -669,10 +982,25 @@ static int ls_solve_p(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m
         if (fn) fn(user, done_before + (A.count - h[0]), total);
         if (h[0] == 0) break;
         hipLaunchKernelGGL((ls_cycle_init_kernel<P>), gr, be, 0, st, A);
-        for (int j = 0; j < max_m; ++j) {
-            hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A);
+        const size_t dyn = sizeof(double) * 2 * (size_t)(max_m + 4);
+        for (int j = 0; A.block == 2 && j < max_m; j += 2, ++step) {
+            hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, 0);
+            hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, 1);
+            hipLaunchKernelGGL((ls_multidot2_kernel<P>), gr, be, 0, st, A);
+            hipLaunchKernelGGL(ls_reduce_kernel, gi, be, 0, st, A, 1);
+            hipLaunchKernelGGL((ls_update2_kernel<P>), gr, be, 0, st, A);
+            hipLaunchKernelGGL(ls_block_givens_kernel, gi, dim3(64), dyn, st, A, step);
+            hipLaunchKernelGGL((ls_normalize2_kernel<P>), gr, be, 0, st, A, step);
+            if ((j & 7) == 6) {  // every 8 steps: stop early once every cycle has ended
+                DG_HIP_CHECK(hipMemcpyAsync(h, A.counters, sizeof(h), hipMemcpyDeviceToHost, st));
+                DG_HIP_CHECK(hipStreamSynchronize(st));
+                if (h[1] <= 0) break;
+            }
+        }
+        for (int j = 0; A.block != 2 && j < max_m; ++j) {
+            hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, 0);
             hipLaunchKernelGGL((ls_multidot_kernel<P>), gr, be, 0, st, A);
-            hipLaunchKernelGGL(ls_reduce_kernel, gi, be, 0, st, A);
+            hipLaunchKernelGGL(ls_reduce_kernel, gi, be, 0, st, A, 0);
             hipLaunchKernelGGL((ls_update_kernel<P>), gr, be, 0, st, A);
             hipLaunchKernelGGL(ls_givens_kernel, gi, dim3(64), 0, st, A);
             hipLaunchKernelGGL((ls_normalize_kernel<P>), gr, be, 0, st, A);

@@ -181,3 +181,34 @@ def test_batched_workload_at_full_instance_sizes_sampled(api):
         rr = _oracle_relres(insts[i], xs[b.offsets[i]:b.offsets[i + 1]])
         _say("  instance %d: k=%d N=%d eps=%.1e oracle rel-res %.2e" % (i, insts[i].k, insts[i].N, insts[i].eps, rr))
         assert rr <= 1.01e-10
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_lockstep_two_vector_blocks_match_one_vector_steps(api, mixed):
+    """Every instance on the lockstep solver, with one and with two Arnoldi
+    vectors per Gram-Schmidt pass: both reach 1e-10 (judged by the oracle) in
+    nearly the same number of steps per instance."""
+    insts = _instances(16, seed=23)
+    its = {}
+    for block in (1, 2):
+        b = api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], mixed=mixed,
+                      rel_tol=1e-10, inner_tol=1e-5, lockstep_min_dofs=0, lockstep_block=block)
+        x, rep = b.alloc()
+        b.run(x, rep)
+        torch.cuda.synchronize()
+        R = b.reports(rep)
+        xs = x.cpu().numpy()
+        for i, inst in enumerate(insts):
+            assert R[i]["status"] == 0, (block, i, R[i])
+            rr = _oracle_relres(inst, xs[b.offsets[i]:b.offsets[i + 1]])
+            assert rr <= 1.01e-10, (block, i, rr)
+        its[block] = np.array(R["iters"])
+        _say("  block %d mixed %s iters %s" % (block, mixed, list(its[block])))
+    assert np.all(np.abs(its[2] - its[1]) <= np.maximum(6, 0.1 * its[1]))
+
+
+def test_batch_rejects_unknown_lockstep_block(api):
+    insts = _instances(2, seed=3)
+    with pytest.raises(api.DGError) as e:
+        api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], lockstep_block=3)
+    assert e.value.status == -1
