@@ -325,7 +325,13 @@ def bench_c4(args, api, W, torch):
             cyc = max(int(R["cycles"][i]), 1)
             its_i = float(R["iters"][i])
             per = its_i / cyc
-            orth = cyc * (per * (per + 1) + 4 * per) * n * ps        # dots + updates over the basis
+            # dots + updates over the basis: the lockstep path takes two Arnoldi vectors per pass
+            # ((j + 3) + (j + 5) vectors per block of two steps), the persistent path one
+            # ((j + 2) + (j + 3) per step)
+            if n >= best["lockstep_min_dofs"]:
+                orth = cyc * (per * per / 2.0 + 3.0 * per) * n * ps
+            else:
+                orth = cyc * (per * (per + 1) + 4 * per) * n * ps
             spmv = its_i * ((nnzb - T) * nl * nl * ps + 2.0 * n * ps)
             resid = (cyc + 1) * (nnzb * nl * nl * 8 + 3 * n * 8)
             asm = nnzb * nl * nl * 8 + n * 8 + T * 72
