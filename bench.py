@@ -77,8 +77,14 @@ def copy_probe(torch):
     log("profile run done")
 
 
-# the kernels behind the solver profiler's classes on the default (two-vector block) path
-BLOCK_KERNELS = {"multidot": "multidot2_kernel", "update": "update2_kernel", "spmv_hat": "spmv_hat_kernel<6>"}
+def launched_kernel(cls, prec, block):
+    """The HIP kernel behind one of the solver profiler's classes (P2: 6 basis
+    functions per element) for Arnoldi blocks of `block` vectors."""
+    if cls == "spmv_hat":
+        return "spmv_hat_kernel<6, %s>" % prec
+    if block > 1 and cls in ("multidot", "update"):
+        return "%s_block_kernel<%s, %d>" % (cls, prec, block)
+    return "%s_kernel<%s>" % (cls, prec)
 
 
 def measured_traffic(kernel, form):
@@ -115,6 +121,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--restart", type=int, default=2 * N_GRID + 64)
     ap.add_argument("--reorth", type=int, default=0, help="1: conditional second Gram-Schmidt pass")
+    ap.add_argument("--block", type=int, default=0, choices=(0, 1, 2, 3, 4),
+                    help="Arnoldi vectors per Gram-Schmidt pass (0: the solver's choice, 3 without reorth)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c2", choices=("c1", "c2", "c3", "c4", "c5", "nl"))
     ap.add_argument("--count", type=int, default=None, help="c4 / c5: number of instances (4096 / 512)")
@@ -153,9 +161,9 @@ def main():
     forms = ("fp64",) if args.profile_run else ("mixed", "fp64")
     solvers = {
         "mixed": api.Solver(mesh, restart=args.restart, max_iters=20000, rel_tol=1e-10, mixed=True, inner_tol=1e-6,
-                            reorth=bool(args.reorth), profile=True),
+                            reorth=bool(args.reorth), profile=True, block=args.block),
         "fp64": api.Solver(mesh, restart=args.restart, max_iters=20000, rel_tol=1e-10, mixed=False,
-                           reorth=bool(args.reorth), profile=True),
+                           reorth=bool(args.reorth), profile=True, block=args.block),
     }
     stream = torch.cuda.current_stream()
 
@@ -225,6 +233,7 @@ def main():
         return out
 
     best = min(forms, key=lambda f: results[f]["seconds"] if results[f]["converged"] else 1e30)
+    block = 1 if args.reorth else (args.block or 3)
     other = [f for f in forms if f != best][0]
     kb = kstats(best)
     dom = max(kb, key=lambda k: kb[k]["total_ms"])
@@ -244,9 +253,9 @@ def main():
         "dtype": "f64" if best == "fp64" else "f32 Arnoldi cycles + f64 residual/update (f64 assembly)",
         "data": "synthetic (manufactured boundary-layer solution on a structured mesh)",
         "config": {"workload": "256x256 structured, P2 SIPG (131072 triangles, 786432 dofs), eps=1e-6, "
-                               "b=(1,0), alpha=0, boundary-layer u; block-Jacobi GMRES(%d), two Arnoldi vectors "
-                               "per Gram-Schmidt pass" % args.restart,
-                   "restart": args.restart, "form": best, "reorth": args.reorth},
+                               "b=(1,0), alpha=0, boundary-layer u; block-Jacobi GMRES(%d), %d Arnoldi vector(s) "
+                               "per Gram-Schmidt pass" % (args.restart, block),
+                   "restart": args.restart, "form": best, "reorth": args.reorth, "block": block},
         "forms": {f: {"solves_per_s": args.steps / results[f]["seconds"],
                       "ms_per_step": results[f]["seconds"] / args.steps * 1e3,
                       "iters": results[f]["iters"], "cycles": results[f]["cycles"],
@@ -254,7 +263,7 @@ def main():
                       "converged": results[f]["converged"], "kernels": kstats(f)} for f in forms},
         "assembly": asm,
         "roofline": {"bound": "hbm", "kernel": dom,
-                     "launched": "%s<%s>" % (BLOCK_KERNELS.get(dom, dom), "double" if best == "fp64" else "float"),
+                     "launched": launched_kernel(dom, "double" if best == "fp64" else "float", block),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, best),
                      "launches": launches, "avg_us": ms / launches * 1e3,

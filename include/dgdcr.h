@@ -226,8 +226,13 @@ typedef struct {
                              (w = A M^{-1} v_j, then h = V^T w and w -= V h); 2 = two (w0 = A M^{-1} v_j and
                              w1 = A M^{-1} w0 projected together, the 2 x 2 block orthonormalised by
                              Cholesky QR, the two Hessenberg columns recovered from the block), which
-                             reads the basis half as often; 0 = automatic (2, or 1 when reorth is set).
-                             DG_ERR_ARG for other values or for 2 with reorth. */
+                             reads the basis half as often; 3 or 4 = three or four (w_i = A M^{-1} w_{i-1}
+                             as well, an S x S block, the basis read once per S steps; the block's Gram
+                             matrix is worse conditioned, so a hard system can need more steps, as four
+                             vectors do on the 256 x 256 P2 boundary-layer system); 0 = automatic (3, or
+                             1 when reorth is set).  A block whose Gram matrix has an unresolvable pivot
+                             (Cholesky pivot <= 1e-8 of the vector's norm) ends the cycle at the last
+                             column it determines.  DG_ERR_ARG for other values or for 2 to 4 with reorth. */
 } dg_solver_opts;
 
 typedef struct {

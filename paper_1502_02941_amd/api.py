@@ -412,7 +412,7 @@ class Solver:
         """persistent: "auto" (one workgroup for small degree-1/2 systems),
         True (always; an error where unsupported) or False (one launch per
         GMRES kernel).  block: Arnoldi vectors per Gram-Schmidt pass of the
-        kernel-per-step path (0 automatic, 1 or 2)."""
+        kernel-per-step path (0 automatic = 3, or 1 to 4)."""
         self.mesh = mesh
         pers = {"auto": 0, True: 1, False: -1}[persistent]
         o = _SolverOpts(int(restart), int(max_iters), float(rel_tol), int(bool(mixed)), float(inner_tol),

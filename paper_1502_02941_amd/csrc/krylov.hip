@@ -32,7 +32,7 @@ namespace dg {
 
 enum { C_J = 0, C_STOP = 1, C_REORTH = 2, C_NREORTH = 3, C_NCTRL = 16 };
 enum { S_BNORM2 = 0, S_RNORM2 = 1, S_INVH = 2, S_WNORM2 = 3, S_HN = 4, S_CYCTOL = 5, S_BETA = 6,
-       S_Q1 = 7, S_Q2A = 8, S_Q2B = 9, S_NSCAL = 12 };
+       S_QB = 7, S_NSCAL = 24 };  // S_QB..: the inverse Cholesky factor of an Arnoldi block (row-major, S x S)
 
 constexpr int BLK = 256;
 constexpr int MD_TARGET_BLOCKS = 2048;   // multidot: column tiles x row splits aimed at this many blocks
@@ -425,59 +425,75 @@ __global__ __launch_bounds__(BLK) void normalize_kernel(P* __restrict__ V, const
 }
 
 // ---------------------------------------------------------------------------
-// Two-vector Arnoldi blocks.  From the last basis vector v_j a block forms
-// w0 = Ahat v_j and w1 = Ahat w0, projects both against v_0..v_j with one pass
-// over the basis (R = V^T [w0 w1]) and updates them with a second pass
-// (U = [w0 w1] - V R, with the 2 x 2 Gram matrix U^T U), so the basis is read
-// twice per two Arnoldi steps instead of twice per step.  The Cholesky factor
-// (r11, r12; r22) of the Gram matrix turns U into v_{j+1}, v_{j+2}, and the
-// Hessenberg columns follow from Ahat v_j = w0 = V R_0 + r11 v_{j+1} and
-// Ahat v_{j+1} = (w1 - Ahat V R_0) / r11 with Ahat V = V H.
+// Arnoldi blocks of S = 2, 3 or 4 vectors.  From the last basis vector v_j a block
+// forms w_0 = Ahat v_j and w_i = Ahat w_{i-1} (i < S), projects them against
+// v_0..v_j with one pass over the basis (R = V^T W) and updates them with a
+// second pass (U = W - V R, with the S x S Gram matrix U^T U), so the basis is
+// read twice per S Arnoldi steps instead of twice per step.  With the upper
+// Cholesky factor C of U^T U the new basis vectors are Q = U C^{-1}, and
+// W = V R + Q C gives the Hessenberg columns: Ahat v_j = w_0 = V R_0 + c_00 q_0
+// and, for i < S - 1, Ahat q_i = sum_{l<=i} (w_{l+1} - Ahat V R_l) (C^{-1})_{li}
+// with Ahat V = V H.
 // ---------------------------------------------------------------------------
-
-// partial V_c . w_r (c = 0..j, r = 0, 1), stored at partials[(r (j+1) + c) splits + split].
-// Tiles of CT2 = 8 columns (measured on 786432 unknowns: 8 columns and 4096
-// target blocks took 14% less time over a cycle than 16 columns and 2048).
-constexpr int CT2 = 8;
-constexpr int MD2_TARGET_BLOCKS = 4096;
+constexpr int BS_MAX = 4;
+// the block's vectors w_0..w_{S-1}, passed by value
 template <typename P>
-__global__ __launch_bounds__(BLK) void multidot2_kernel(const P* __restrict__ V, const P* __restrict__ w0,
-                                                        const P* __restrict__ w1, int64_t n, int j,
-                                                        int64_t rows_per_split, const int* ctrl,
-                                                        double* __restrict__ partials)
+struct BlockVecs {
+    P* w[BS_MAX];
+};
+
+// partial V_c . w_r (c = 0..j, r < S), stored at partials[(r (j+1) + c) splits + split].
+// Tiles of md_block_ct(S) columns over about md_block_target(S) workgroups:
+// measured on 786432 unknowns over a 538-step cycle, 8 columns and 4096
+// workgroups took 14% less time than 16 and 2048 with two vectors, while
+// with three 16 and 2048 took 12% less than 8 and 4096 (each block re-reads
+// its S vectors once per tile), and four vectors were within 2% either way.
+constexpr int md_block_ct(int S) { return S == 3 ? 16 : 8; }
+constexpr int md_block_target(int S) { return S == 3 ? 2048 : 4096; }
+template <typename P, int S>
+__global__ __launch_bounds__(BLK) void multidot_block_kernel(const P* __restrict__ V, BlockVecs<P> W, int64_t n,
+                                                             int j, int64_t rows_per_split, const int* ctrl,
+                                                             double* __restrict__ partials)
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
-    __shared__ double sh[4][2 * CT2];
+    constexpr int CT2 = md_block_ct(S);
+    __shared__ double sh[4][S * CT2];
+    const P* wv[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) wv[q] = W.w[q];
     const int ncols = j + 1;
     const int c0 = blockIdx.x * CT2;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
     const int64_t r1 = r0 + rows_per_split < n ? r0 + rows_per_split : n;
     const P* col[CT2];
 #pragma unroll
-    for (int c = 0; c < CT2; ++c) col[c] = (c0 + c < ncols) ? V + (int64_t)(c0 + c) * n : w0;  // past j: discarded
-    double a0[CT2], a1[CT2];
+    for (int c = 0; c < CT2; ++c) col[c] = (c0 + c < ncols) ? V + (int64_t)(c0 + c) * n : wv[0];  // past j: discarded
+    double a[S][CT2];
 #pragma unroll
-    for (int c = 0; c < CT2; ++c) a0[c] = a1[c] = 0.0;
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int c = 0; c < CT2; ++c) a[q][c] = 0.0;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += BLK) {
-        const double x0 = (double)w0[r], x1 = (double)w1[r];
+        double x[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) x[q] = (double)wv[q][r];
 #pragma unroll
         for (int c = 0; c < CT2; ++c) {
             const double v = (double)col[c][r];
-            a0[c] += v * x0;
-            a1[c] += v * x1;
+#pragma unroll
+            for (int q = 0; q < S; ++q) a[q][c] += v * x[q];
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int c = 0; c < CT2; ++c) {
-        const double v0 = wave_sum(a0[c]), v1 = wave_sum(a1[c]);
-        if (lane == 0) {
-            sh[wave][c] = v0;
-            sh[wave][CT2 + c] = v1;
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int c = 0; c < CT2; ++c) {
+            const double v = wave_sum(a[q][c]);
+            if (lane == 0) sh[wave][q * CT2 + c] = v;
         }
-    }
     __syncthreads();
-    if (threadIdx.x < 2 * CT2) {
+    if (threadIdx.x < S * CT2) {
         const int rr = threadIdx.x / CT2, c = threadIdx.x - rr * CT2;
         if (c0 + c < ncols)
             partials[((int64_t)rr * ncols + c0 + c) * gridDim.y + blockIdx.y] =
@@ -485,91 +501,138 @@ __global__ __launch_bounds__(BLK) void multidot2_kernel(const P* __restrict__ V,
     }
 }
 
-// w_r -= sum_{c<=j} R[r][c] V_c for r = 0, 1 (R = [R_0 | R_1], each j+1 long),
-// and the Gram partials of the results: partials[k * gridDim.x + block] for
-// k = 0: u0.u0, 1: u0.u1, 2: u1.u1
-template <typename P>
-__global__ __launch_bounds__(BLK) void update2_kernel(const P* __restrict__ V, P* __restrict__ w0, P* __restrict__ w1,
-                                                      int64_t n, int j, const int* ctrl, double* partials,
-                                                      const double* __restrict__ R)
+// w_r -= sum_{c<=j} R_r[c] V_c for r < S (R_r = R + r (j+1)) in the first
+// nchunk workgroups, with the Gram partials of the results, pair k = (p, q),
+// p <= q in the order (0,0), (0,1), (1,1), (0,2), (1,2), (2,2), (0,3), ..., at
+// partials[k * nchunk + block].  The workgroups after them take one row t <= j
+// per wave of the Hessenberg products the block's columns need,
+// HX[l][t] = sum_{c<j} Hrow[t][c] R_l[c] (l < S - 1; Hrow holds the raw
+// Hessenberg matrix row-major, so a row is read coalesced); column j is not
+// formed yet and is added by the block's Givens kernel.
+template <typename P, int S>
+__global__ __launch_bounds__(BLK) void update_block_kernel(const P* __restrict__ V, BlockVecs<P> W, int64_t n, int j,
+                                                           const int* ctrl, double* partials,
+                                                           const double* __restrict__ R, int nchunk,
+                                                           const double* __restrict__ Hrow, int ldr,
+                                                           double* __restrict__ HX, int ldx)
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
+    constexpr int NG = S * (S + 1) / 2;
+    if ((int)blockIdx.x >= nchunk) {
+        const int lane = threadIdx.x & 63;
+        const int t = ((int)blockIdx.x - nchunk) * (BLK / 64) + (threadIdx.x >> 6);
+        if (t > j) return;
+        const double* hr = Hrow + (int64_t)t * ldr;
+        double acc[S - 1];
+#pragma unroll
+        for (int l = 0; l < S - 1; ++l) acc[l] = 0.0;
+        for (int c = (t > 0 ? t - 1 : 0) + lane; c < j; c += 64) {
+            const double h = hr[c];
+#pragma unroll
+            for (int l = 0; l < S - 1; ++l) acc[l] += h * R[l * (j + 1) + c];
+        }
+#pragma unroll
+        for (int l = 0; l < S - 1; ++l) {
+            const double v = wave_sum(acc[l]);
+            if (lane == 0) HX[l * ldx + t] = v;
+        }
+        return;
+    }
     __shared__ double sh[4];
-    const double* R0 = R;
-    const double* R1 = R + (j + 1);
+    P* wv[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) wv[q] = W.w[q];
     const int64_t base = (int64_t)blockIdx.x * (BLK * UPD_E) + threadIdx.x;
-    double u0[UPD_E], u1[UPD_E];
+    double u[S][UPD_E];
     bool in[UPD_E];
 #pragma unroll
     for (int e = 0; e < UPD_E; ++e) {
         const int64_t t = base + (int64_t)e * BLK;
         in[e] = t < n;
-        u0[e] = in[e] ? (double)w0[t] : 0.0;
-        u1[e] = in[e] ? (double)w1[t] : 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) u[q][e] = in[e] ? (double)wv[q][t] : 0.0;
     }
     int c = 0;
     for (; c + 3 <= j; c += 4) {
-        const double p0 = R0[c], p1 = R0[c + 1], p2 = R0[c + 2], p3 = R0[c + 3];
-        const double q0 = R1[c], q1 = R1[c + 1], q2 = R1[c + 2], q3 = R1[c + 3];
+        double h[S][4];
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) h[q][m] = R[q * (j + 1) + c + m];
         const P* v0 = V + (int64_t)c * n;
 #pragma unroll
         for (int e = 0; e < UPD_E; ++e) {
             const int64_t t = base + (int64_t)e * BLK;
             if (in[e]) {
-                const double a = (double)v0[t], b = (double)v0[t + n], cc = (double)v0[t + 2 * n],
-                             d = (double)v0[t + 3 * n];
-                u0[e] -= p0 * a + p1 * b + p2 * cc + p3 * d;
-                u1[e] -= q0 * a + q1 * b + q2 * cc + q3 * d;
+                const double a0 = (double)v0[t], a1 = (double)v0[t + n], a2 = (double)v0[t + 2 * n],
+                             a3 = (double)v0[t + 3 * n];
+#pragma unroll
+                for (int q = 0; q < S; ++q) u[q][e] -= h[q][0] * a0 + h[q][1] * a1 + h[q][2] * a2 + h[q][3] * a3;
             }
         }
     }
     for (; c <= j; ++c) {
-        const double p0 = R0[c], q0 = R1[c];
+        double h[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) h[q] = R[q * (j + 1) + c];
         const P* vc = V + (int64_t)c * n;
 #pragma unroll
         for (int e = 0; e < UPD_E; ++e) {
             const int64_t t = base + (int64_t)e * BLK;
             if (in[e]) {
-                const double a = (double)vc[t];
-                u0[e] -= p0 * a;
-                u1[e] -= q0 * a;
+                const double a0 = (double)vc[t];
+#pragma unroll
+                for (int q = 0; q < S; ++q) u[q][e] -= h[q] * a0;
             }
         }
     }
-    double g00 = 0.0, g01 = 0.0, g11 = 0.0;
+    double gs[NG];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) gs[k] = 0.0;
 #pragma unroll
     for (int e = 0; e < UPD_E; ++e) {
         if (in[e]) {
             const int64_t t = base + (int64_t)e * BLK;
-            const P a = (P)u0[e], b = (P)u1[e];
-            w0[t] = a;
-            w1[t] = b;
-            g00 += (double)a * (double)a;
-            g01 += (double)a * (double)b;
-            g11 += (double)b * (double)b;
+            double r[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const P pv = (P)u[q][e];
+                wv[q][t] = pv;
+                r[q] = (double)pv;
+            }
+            int k = 0;
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+#pragma unroll
+                for (int p = 0; p <= q; ++p) gs[k++] += r[p] * r[q];
         }
     }
-    const double s00 = block_sum(g00, sh);
-    const double s01 = block_sum(g01, sh);
-    const double s11 = block_sum(g11, sh);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = s00;
-        partials[gridDim.x + blockIdx.x] = s01;
-        partials[2 * gridDim.x + blockIdx.x] = s11;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        const double bs = block_sum(gs[k], sh);
+        if (threadIdx.x == 0) partials[k * nchunk + blockIdx.x] = bs;
     }
 }
 
-// One workgroup: Gram reduction, Cholesky, Hessenberg columns j and j+1 (raw
-// copies in Hr, leading dimension ldr; rotated in H, leading dimension ldh),
-// the previous Givens rotations applied to them in turn, the new rotations,
-// residual estimates and stop tests.  Column j+1 is taken only when column j
-// did not stop the cycle; when r22 is not resolvable (the second vector lies
-// in the span to working accuracy) the cycle stops after column j+1.
+// One workgroup: Gram reduction, Cholesky (pivot i is resolvable when c_ii >
+// 1e-8 sqrt(G_ii), pivot 0 when c_00 > 1e-300), the block's Hessenberg
+// columns (raw copies in the row-major Hr, leading dimension ldr; rotated in H, leading
+// dimension ldh), the previous Givens rotations applied to them in turn, new
+// rotations, residual estimates and stop tests.  A block with p < S
+// resolvable pivots takes columns j..j+p and ends the cycle (the next vector
+// lies in the span to working accuracy); (C^{-1}) goes to scal for the
+// normalisation.
 constexpr int BG_T = 1024;
-__device__ void bg_rotate(double* colv, int count, const double* __restrict__ cs, const double* __restrict__ sn,
-                          double* sc, double* ss)
+// Rotations 0..count-1 (cs, sn) applied to columns 0..ncol-1 of colv, lane i
+// of the first wave taking column i; each column is a chain of dependent
+// steps, so the LDS loads of eight steps are issued together.
+constexpr int BG_UNROLL = 8;
+__device__ void bg_rotate_cols(double (*colv)[TS_MAXJ + 4], int ncol, int count, const double* __restrict__ cs,
+                               const double* __restrict__ sn, double* sc, double* ss)
 {
-    double a = colv[0];
+    const int i = threadIdx.x;
+    __syncthreads();
+    double a = i < ncol ? colv[i][0] : 0.0;
     for (int i0 = 0; i0 < count; i0 += GV_CHUNK) {
         const int cnt = count - i0 < GV_CHUNK ? count - i0 : GV_CHUNK;
         __syncthreads();
@@ -578,151 +641,214 @@ __device__ void bg_rotate(double* colv, int count, const double* __restrict__ cs
             ss[t] = sn[i0 + t];
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int t = 0; t < cnt; ++t) {
-                const double b = colv[i0 + t + 1];
-                colv[i0 + t] = sc[t] * a + ss[t] * b;
+        if (i < ncol) {
+            double* cv = colv[i] + i0;
+            int t = 0;
+            for (; t + BG_UNROLL <= cnt; t += BG_UNROLL) {
+                double c[BG_UNROLL], s[BG_UNROLL], b[BG_UNROLL], o[BG_UNROLL];
+#pragma unroll
+                for (int u = 0; u < BG_UNROLL; ++u) {
+                    c[u] = sc[t + u];
+                    s[u] = ss[t + u];
+                    b[u] = cv[t + u + 1];  // not yet written: this batch writes cv[t .. t + 7]
+                }
+#pragma unroll
+                for (int u = 0; u < BG_UNROLL; ++u) {
+                    o[u] = c[u] * a + s[u] * b[u];
+                    a = -s[u] * a + c[u] * b[u];
+                }
+#pragma unroll
+                for (int u = 0; u < BG_UNROLL; ++u) cv[t + u] = o[u];
+            }
+            for (; t < cnt; ++t) {
+                const double b = cv[t + 1];
+                cv[t] = sc[t] * a + ss[t] * b;
                 a = -ss[t] * a + sc[t] * b;
             }
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) colv[count] = a;
+    if (i < ncol) colv[i][count] = a;
     __syncthreads();
 }
 
+template <int S>
 __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const double* __restrict__ gp, int nparts,
                                                             const double* __restrict__ R, double* __restrict__ Hr,
-                                                            int ldr, double* __restrict__ H, int ldh,
+                                                            int ldr, const double* __restrict__ HX, int ldx,
+                                                            double* __restrict__ H, int ldh,
                                                             double* __restrict__ cs, double* __restrict__ sn,
                                                             double* __restrict__ g, double* scal, int j, int mcyc)
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
-    __shared__ double red[3][BG_T / 64];
-    __shared__ double colA[TS_MAXJ + 4], colB[TS_MAXJ + 4];
+    constexpr int NG = S * (S + 1) / 2;
+    __shared__ double red[NG][BG_T / 64];
+    __shared__ double colv[S][TS_MAXJ + 4];
     __shared__ double sc[GV_CHUNK], ss[GV_CHUNK];
-    __shared__ double fac[3];
-    __shared__ int take2, stop1;
+    __shared__ double G[S][S], Cf[S][S], Ci[S][S];  // in LDS: thread 0 indexes them dynamically
+    __shared__ int ncol_s, cut_s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double a00 = 0.0, a01 = 0.0, a11 = 0.0;
-    for (int t = threadIdx.x; t < nparts; t += BG_T) {
-        a00 += gp[t];
-        a01 += gp[nparts + t];
-        a11 += gp[2 * nparts + t];
+    {
+        double acc[NG];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) acc[k] = 0.0;
+        for (int t = threadIdx.x; t < nparts; t += BG_T)
+#pragma unroll
+            for (int k = 0; k < NG; ++k) acc[k] += gp[k * nparts + t];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const double v = wave_sum(acc[k]);
+            if (lane == 0) red[k][wave] = v;
+        }
     }
-    a00 = wave_sum(a00);
-    a01 = wave_sum(a01);
-    a11 = wave_sum(a11);
-    if (lane == 0) {
-        red[0][wave] = a00;
-        red[1][wave] = a01;
-        red[2][wave] = a11;
-    }
-    const double* R0 = R;
-    const double* R1 = R + (j + 1);
-    for (int i = threadIdx.x; i <= j; i += BG_T) colA[i] = R0[i];
+    for (int i = threadIdx.x; i <= j; i += BG_T) colv[0][i] = R[i];
     __syncthreads();
     if (threadIdx.x == 0) {
-        double G00 = 0.0, G01 = 0.0, G11 = 0.0;
-        for (int w = 0; w < BG_T / 64; ++w) {
-            G00 += red[0][w];
-            G01 += red[1][w];
-            G11 += red[2][w];
+        int k = 0;
+        for (int q = 0; q < S; ++q)
+            for (int p = 0; p <= q; ++p) {
+                double v = 0.0;
+                for (int w = 0; w < BG_T / 64; ++w) v += red[k][w];
+                G[p][q] = G[q][p] = v;
+                ++k;
+            }
+        // upper Cholesky factor, stopping at the first pivot that is not resolvable
+        int pok = 0;
+        for (int p = 0; p < S; ++p)
+            for (int q = 0; q < S; ++q) Cf[p][q] = Ci[p][q] = 0.0;
+        for (int i = 0; i < S; ++i) {
+            double d = G[i][i];
+            for (int m = 0; m < i; ++m) d -= Cf[m][i] * Cf[m][i];
+            const double cii = d > 0.0 ? sqrt(d) : 0.0;
+            const bool ok = isfinite(cii) && (i == 0 ? cii > 1e-300 : cii > 1e-8 * sqrt(G[i][i]));
+            Cf[i][i] = isfinite(cii) ? cii : 0.0;
+            if (!ok) break;
+            for (int q = i + 1; q < S; ++q) {
+                double v = G[i][q];
+                for (int m = 0; m < i; ++m) v -= Cf[m][i] * Cf[m][q];
+                Cf[i][q] = v / cii;
+            }
+            ++pok;
         }
-        const double r11 = sqrt(G00);
-        const bool brk1 = !(r11 > 1e-300) || !isfinite(r11);
-        const double r12 = brk1 ? 0.0 : G01 / r11;
-        const double d = G11 - r12 * r12;
-        const double r22 = d > 0.0 ? sqrt(d) : 0.0;
-        const bool ok2 = !brk1 && isfinite(r22) && r22 > 1e-8 * sqrt(G11);
-        fac[0] = r11;
-        fac[1] = r12;
-        fac[2] = r22;
-        colA[j + 1] = r11;
-        scal[S_Q1] = brk1 ? 0.0 : 1.0 / r11;
-        scal[S_Q2A] = ok2 ? 1.0 / r22 : 0.0;
-        scal[S_Q2B] = ok2 ? -r12 / (r11 * r22) : 0.0;
-        scal[S_HN] = r11;
-        take2 = ok2 ? 1 : 0;
-        stop1 = brk1 ? 1 : 0;
+        // inverse of the resolvable leading triangle
+        for (int i = 0; i < pok; ++i) {
+            Ci[i][i] = 1.0 / Cf[i][i];
+            for (int q = i + 1; q < pok; ++q) {
+                double v = 0.0;
+                for (int m = i; m < q; ++m) v += Ci[i][m] * Cf[m][q];
+                Ci[i][q] = -v / Cf[q][q];
+            }
+        }
+        int ncol = S < mcyc - j ? S : mcyc - j;
+        if (pok < S && ncol > pok + 1) ncol = pok + 1;
+        ncol_s = ncol;
+        cut_s = pok < S ? 1 : 0;
+        colv[0][j + 1] = Cf[0][0];
+        for (int p = 0; p < S; ++p)
+            for (int q = 0; q < S; ++q) scal[S_QB + p * S + q] = Ci[p][q];
     }
     __syncthreads();
-    // raw column j
-    for (int i = threadIdx.x; i <= j + 1; i += BG_T) Hr[i + (int64_t)j * ldr] = colA[i];
+    const int ncol = ncol_s;
+    for (int i = threadIdx.x; i <= j + 1; i += BG_T) Hr[(int64_t)i * ldr + j] = colv[0][i];
     __syncthreads();
-    // raw column j+1 (before colA is rotated): (R_1 + r12 e_{j+1} + r22 e_{j+2} - Hr(0:j+1, 0:j) R_0) / r11
-    const bool want2 = !stop1 && j + 1 < mcyc;
-    if (want2) {
-        const double r11 = fac[0];
-        for (int i = threadIdx.x; i <= j + 1; i += BG_T) {
-            double t = 0.0;
-            for (int c = i > 0 ? i - 1 : 0; c <= j; ++c) t += Hr[i + (int64_t)c * ldr] * R0[c];
-            const double base = i <= j ? R1[i] : fac[1];
-            colB[i] = (base - t) / r11;
+    // columns j+1 .. j+ncol-1, from the raw column j and the earlier raw columns
+    if (ncol > 1) {
+        for (int t = threadIdx.x; t <= j + ncol; t += BG_T) {
+            double hx[S - 1];
+#pragma unroll
+            for (int l = 0; l < S - 1; ++l) hx[l] = 0.0;
+            if (t <= j + 1) {  // (Hr R_l)[t]: columns below j from HX, column j here
+                const double h = colv[0][t];
+#pragma unroll
+                for (int l = 0; l < S - 1; ++l) hx[l] = (t <= j ? HX[l * ldx + t] : 0.0) + h * R[l * (j + 1) + j];
+            }
+            for (int i = 1; i < ncol; ++i) {
+                if (t > j + i + 1) continue;
+                double v = 0.0;
+                for (int l = 0; l < i; ++l) {
+                    const int m = l + 1;
+                    const double cm = t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0);
+                    v += (cm - hx[l]) * Ci[l][i - 1];
+                }
+                colv[i][t] = v;
+            }
         }
-        if (threadIdx.x == 0) colB[j + 2] = fac[2] / r11;
         __syncthreads();
-        for (int i = threadIdx.x; i <= j + 2; i += BG_T) Hr[i + (int64_t)(j + 1) * ldr] = colB[i];
+        for (int i = 1; i < ncol; ++i)
+            for (int t = threadIdx.x; t <= j + i + 1; t += BG_T) Hr[(int64_t)t * ldr + j + i] = colv[i][t];
     }
-    // column j: previous rotations, new rotation, estimate
-    bg_rotate(colA, j, cs, sn, sc, ss);
-    if (threadIdx.x == 0) {
-        const double a = colA[j], b = colA[j + 1];
-        const double d = sqrt(a * a + b * b);
-        cs[j] = d == 0.0 ? 1.0 : a / d;
-        sn[j] = d == 0.0 ? 0.0 : b / d;
-        colA[j] = d;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        const bool stop = stop1 || fabs(g[j + 1]) <= scal[S_CYCTOL] || j + 1 >= mcyc;
-        if (stop) stop1 = 1;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= j; i += BG_T) H[i + (int64_t)j * ldh] = colA[i];
-    if (stop1 || !want2) {
+    // the rotations of earlier blocks on all columns at once, then the columns
+    // in turn: this block's earlier rotations, new rotation, estimate, stop test
+    bg_rotate_cols(colv, ncol, j, cs, sn, sc, ss);
+    __shared__ int stop_s;
+    for (int i = 0; i < ncol; ++i) {
+        const int k = j + i;
         if (threadIdx.x == 0) {
-            ctrl[C_J] = j + 1;
-            ctrl[C_REORTH] = 0;
-            ctrl[C_STOP] = 1;
+            double* cv = colv[i];
+            double a = cv[j];
+            for (int t = j; t < k; ++t) {
+                const double b = cv[t + 1];
+                cv[t] = cs[t] * a + sn[t] * b;
+                a = -sn[t] * a + cs[t] * b;
+            }
+            const double b = cv[k + 1];
+            const double d = sqrt(a * a + b * b);
+            cs[k] = d == 0.0 ? 1.0 : a / d;
+            sn[k] = d == 0.0 ? 0.0 : b / d;
+            colv[i][k] = d;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            const bool last = i == ncol - 1;
+            stop_s = (fabs(g[k + 1]) <= scal[S_CYCTOL] || k + 1 >= mcyc || (last && cut_s)) ? 1 : 0;
         }
-        return;
+        __syncthreads();
+        for (int t = threadIdx.x; t <= k; t += BG_T) H[t + (int64_t)k * ldh] = colv[i][t];
+        if (stop_s) {
+            if (threadIdx.x == 0) {
+                ctrl[C_J] = k + 1;
+                ctrl[C_REORTH] = 0;
+                ctrl[C_STOP] = 1;
+            }
+            return;
+        }
+        __syncthreads();  // every thread has read stop_s before thread 0 sets it again
     }
-    // column j+1
-    bg_rotate(colB, j + 1, cs, sn, sc, ss);
     if (threadIdx.x == 0) {
-        const int k = j + 1;
-        const double a = colB[k], b = colB[k + 1];
-        const double d = sqrt(a * a + b * b);
-        cs[k] = d == 0.0 ? 1.0 : a / d;
-        sn[k] = d == 0.0 ? 0.0 : b / d;
-        colB[k] = d;
-        g[k + 1] = -sn[k] * g[k];
-        g[k] = cs[k] * g[k];
-        ctrl[C_J] = k + 1;
+        ctrl[C_J] = j + ncol;
         ctrl[C_REORTH] = 0;
-        if (!take2 || fabs(g[k + 1]) <= scal[S_CYCTOL] || k + 1 >= mcyc) ctrl[C_STOP] = 1;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= j + 1; i += BG_T) H[i + (int64_t)(j + 1) * ldh] = colB[i];
 }
 
-// v_{j+1} = u0 / r11 and v_{j+2} = u1 / r22 - r12 / (r11 r22) u0, each when the
-// block took its column (ctrl[C_J] already advanced by the block kernel)
-template <typename P>
-__global__ __launch_bounds__(BLK) void normalize2_kernel(P* __restrict__ V, const P* __restrict__ w0,
-                                                         const P* __restrict__ w1, int64_t n, int j, const int* ctrl,
-                                                         const double* scal)
+// q_i = sum_{l<=i} u_l (C^{-1})_{li} into V_{j+1+i} for the columns the block
+// took (ctrl[C_J] = j + t): i <= t - 2, and i = t - 1 unless the cycle stopped
+template <typename P, int S>
+__global__ __launch_bounds__(BLK) void normalize_block_kernel(P* __restrict__ V, BlockVecs<P> W, int64_t n, int j,
+                                                              const int* ctrl, const double* scal)
 {
-    const int J = ctrl[C_J];
-    if (J != j + 2) return;  // the block took only column j (the cycle stopped there) or did not run
-    const bool second = !ctrl[C_STOP];
-    const double a = scal[S_Q1], b = scal[S_Q2A], c = scal[S_Q2B];
-    P* o1 = V + (int64_t)(j + 1) * n;
-    P* o2 = V + (int64_t)(j + 2) * n;
-    for (int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
-        const double u0 = (double)w0[t];
-        o1[t] = (P)(u0 * a);
-        if (second) o2[t] = (P)((double)w1[t] * b + u0 * c);
+    const int t = ctrl[C_J] - j;  // columns the block took (<= 0: the cycle had stopped before it)
+    const int nq = ctrl[C_STOP] ? t - 1 : t;
+    if (t < 1 || t > S || nq < 1) return;
+    const P* wv[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) wv[q] = W.w[q];
+    double ci[S][S];
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+        for (int q = 0; q < S; ++q) ci[p][q] = scal[S_QB + p * S + q];
+    P* out = V + (int64_t)(j + 1) * n;
+    for (int64_t r = (int64_t)blockIdx.x * BLK + threadIdx.x; r < n; r += (int64_t)gridDim.x * BLK) {
+        double u[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) u[q] = (double)wv[q][r];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (i < nq) {
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l <= i; ++l) v += u[l] * ci[l][i];
+                out[(int64_t)i * n + r] = (P)v;
+            }
+        }
     }
 }
 
@@ -863,13 +989,16 @@ struct dg_solver {
     void* V = nullptr;      // [(m+1)][n] in P
     void* w = nullptr;      // [n] in P
     void* u = nullptr;      // [n] in P
+    void* w2 = nullptr;     // [n] in P: the third vector of blocks of 3 or more
+    void* w3 = nullptr;     // [n] in P: the fourth vector of blocks of 4
     double* r = nullptr;    // [n] FP64
     double* partials = nullptr;
     double* hcol = nullptr;
     double* hcol2 = nullptr;
-    double* Rb = nullptr;   // [2][restart + 2]: a two-vector block's projections
-    double* Hr = nullptr;   // [restart + 1][restart + 2]: raw Hessenberg columns of the block path
-    int block = 1;          // Arnoldi vectors per Gram-Schmidt pass (1 or 2)
+    double* Rb = nullptr;   // [block][restart + 2]: an Arnoldi block's projections
+    double* Hr = nullptr;   // [restart + 2][restart + 1]: raw Hessenberg matrix of the block path, row-major
+    double* HX = nullptr;   // [block - 1][restart + 2]: its products with a block's projections
+    int block = 1;          // Arnoldi vectors per Gram-Schmidt pass (1 to 4)
     double* H = nullptr;
     double* cs = nullptr;
     double* sn = nullptr;
@@ -892,8 +1021,8 @@ struct dg_solver {
     double pms[8] = {0}, pbytes[8] = {0};
     // multidot split for iteration j: (column tiles, row splits, rows per split)
     void md_shape(int j, int* tiles, int* splits, int64_t* rows) const;
-    // the same for the two-vector block starting at column j
-    void md_shape2(int j, int* tiles, int* splits, int64_t* rows) const;
+    // the same for the Arnoldi block of S vectors starting at column j
+    void md_shape2(int j, int S, int* tiles, int* splits, int64_t* rows) const;
 };
 
 void dg_solver::md_shape(int j, int* tiles, int* splits, int64_t* rows) const
@@ -910,11 +1039,12 @@ void dg_solver::md_shape(int j, int* tiles, int* splits, int64_t* rows) const
     *rows = r;
 }
 
-void dg_solver::md_shape2(int j, int* tiles, int* splits, int64_t* rows) const
+void dg_solver::md_shape2(int j, int S, int* tiles, int* splits, int64_t* rows) const
 {
-    const int nt = (j + 1 + dg::CT2 - 1) / dg::CT2;
+    const int ct = dg::md_block_ct(S);
+    const int nt = (j + 1 + ct - 1) / ct;
     const int64_t max_splits = std::max<int64_t>(1, n / dg::MD_MIN_ROWS);
-    int64_t sp = (dg::MD2_TARGET_BLOCKS + nt - 1) / nt;
+    int64_t sp = (dg::md_block_target(S) + nt - 1) / nt;
     sp = std::max<int64_t>(1, std::min<int64_t>(sp, max_splits));
     int64_t r = (n + sp - 1) / sp;
     r = (r + dg::BLK - 1) / dg::BLK * dg::BLK;
@@ -978,7 +1108,7 @@ static void solver_free(dg_solver* s)
     hipFree(s->rflags);
     hipFree(s->Ahat); hipFree(s->Dinv); hipFree(s->Dinv64); hipFree(s->V); hipFree(s->w); hipFree(s->u);
     hipFree(s->r); hipFree(s->partials); hipFree(s->hcol); hipFree(s->hcol2); hipFree(s->H); hipFree(s->cs);
-    hipFree(s->Rb); hipFree(s->Hr);
+    hipFree(s->Rb); hipFree(s->Hr); hipFree(s->HX); hipFree(s->w2); hipFree(s->w3);
     hipFree(s->sn); hipFree(s->g); hipFree(s->y); hipFree(s->scal); hipFree(s->ctrl); hipFree(s->bad);
     if (s->h_rep) hipHostFree(s->h_rep);
     s->h_rep = nullptr;
@@ -993,7 +1123,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
         return DG_ERR_ARG;
     if (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)) return DG_ERR_ARG;
     if (o->persistent < -1 || o->persistent > 1) return DG_ERR_ARG;
-    if (o->block < 0 || o->block > 2 || (o->block == 2 && o->reorth)) return DG_ERR_ARG;
+    if (o->block < 0 || o->block > BS_MAX || (o->block > 1 && o->reorth)) return DG_ERR_ARG;
     dg_solver* s = new (std::nothrow) dg_solver();
     if (!s) return DG_ERR_OOM;
     s->m = m;
@@ -1004,7 +1134,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     s->n = m->T * m->n;
     s->n_off = m->nnzb - m->T;
     s->mixed = o->mixed;
-    s->block = o->block == 0 ? (o->reorth ? 1 : 2) : o->block;
+    s->block = o->block == 0 ? (o->reorth ? 1 : 3) : o->block;
     const int EPW = 64 / s->N;
     s->grid_elem = (int)((s->T + 4 * EPW - 1) / (4 * EPW));
     s->grid_chunk = (int)((s->n + BLK * UPD_E - 1) / (BLK * UPD_E));
@@ -1018,10 +1148,12 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
         int64_t rows;
         s->md_shape(j, &nt, &sp, &rows);
         maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 2));
-        s->md_shape2(j, &nt, &sp, &rows);
-        maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * 2);
+        for (int S = 2; S <= BS_MAX; ++S) {
+            s->md_shape2(j, S, &nt, &sp, &rows);
+            maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * S);
+        }
     }
-    maxgrid = std::max<int64_t>(maxgrid, 3 * (int64_t)s->grid_chunk);
+    maxgrid = std::max<int64_t>(maxgrid, BS_MAX * (BS_MAX + 1) / 2 * (int64_t)s->grid_chunk);
     bool ok = true;
     auto al = [&](void** p, size_t bytes) { if (ok && hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) { *p = nullptr; ok = false; } };
     al(&s->Ahat, ps * NN * std::max<int64_t>(s->n_off, 1));
@@ -1034,10 +1166,13 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     al((void**)&s->partials, sizeof(double) * (size_t)maxgrid);
     al((void**)&s->hcol, sizeof(double) * (mm + 2));
     al((void**)&s->hcol2, sizeof(double) * (mm + 2));
-    if (s->block == 2) {
-        al((void**)&s->Rb, sizeof(double) * 2 * (size_t)(mm + 2));
+    if (s->block > 1) {
+        al((void**)&s->Rb, sizeof(double) * s->block * (size_t)(mm + 2));
         al((void**)&s->Hr, sizeof(double) * (size_t)(mm + 2) * (mm + 1));
+        al((void**)&s->HX, sizeof(double) * (s->block - 1) * (size_t)(mm + 2));
     }
+    if (s->block > 2) al(&s->w2, ps * s->n);
+    if (s->block > 3) al(&s->w3, ps * s->n);
     al((void**)&s->H, sizeof(double) * (size_t)(mm + 1) * mm);
     al((void**)&s->cs, sizeof(double) * mm);
     al((void**)&s->sn, sizeof(double) * mm);
@@ -1121,6 +1256,50 @@ extern "C" int32_t dg_solver_setup(dg_solver* s, const double* A64, void* stream
     return r;
 }
 
+// One restart cycle on the block path: blocks of S Arnoldi vectors from
+// columns 0, S, 2S, ... until a block's kernels record the stop.
+template <int N, typename P, int S>
+static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_bytes)
+{
+    const dg_mesh* m = s->m;
+    const int mm = s->o.restart;
+    const double ps = (double)sizeof(P), nb = (double)s->n;
+    P* V = (P*)s->V;
+    BlockVecs<P> W{{(P*)s->w, (P*)s->u, (P*)s->w2, (P*)s->w3}};  // u is free until the cycle's combine
+    P* const* wv = W.w;
+    for (int j = 0; j < mcyc; j += S) {
+        int nt, sp;
+        int64_t rows;
+        s->md_shape2(j, S, &nt, &sp, &rows);
+        const double md_bytes = (j + 1.0 + S) * nb * ps, up_bytes = (j + 1.0 + 2 * S) * nb * ps;
+        for (int q = 0; q < S; ++q) {
+            const bool pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
+            hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
+                               m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, wv[q], s->T, s->ctrl,
+                               (const P*)(q ? wv[q - 1] : nullptr));
+            prof_end(s, st, pr);
+        }
+        bool pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
+        hipLaunchKernelGGL((multidot_block_kernel<P, S>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, W, s->n, j,
+                           rows, (const int*)s->ctrl, s->partials);
+        prof_end(s, st, pr);
+        hipLaunchKernelGGL(reduce_cols_kernel, dim3((S * (j + 1) + 3) / 4), dim3(BLK), 0, st,
+                           (const double*)s->partials, S * (j + 1), sp, j, (const int*)s->ctrl, s->Rb, 0);
+        pr = prof_begin(s, st, PK_UPDATE, up_bytes, j, 0);
+        const int hrows = (j + 1 + BLK / 64 - 1) / (BLK / 64);  // workgroups of the Hessenberg products
+        hipLaunchKernelGGL((update_block_kernel<P, S>), dim3(s->grid_chunk + hrows), dim3(BLK), 0, st, (const P*)V, W,
+                           s->n, j, (const int*)s->ctrl, s->partials, (const double*)s->Rb, s->grid_chunk,
+                           (const double*)s->Hr, mm + 1, s->HX, mm + 2);
+        prof_end(s, st, pr);
+        hipLaunchKernelGGL((block_givens_kernel<S>), dim3(1), dim3(BG_T), 0, st, s->ctrl, (const double*)s->partials,
+                           s->grid_chunk, (const double*)s->Rb, s->Hr, mm + 1, (const double*)s->HX, mm + 2, s->H,
+                           mm + 1, s->cs, s->sn, s->g,
+                           s->scal, j, mcyc);
+        hipLaunchKernelGGL((normalize_block_kernel<P, S>), dim3(s->grid_vec), dim3(BLK), 0, st, V, W, s->n, j,
+                           (const int*)s->ctrl, (const double*)s->scal);
+    }
+}
+
 template <int N, typename P>
 static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* rep, hipStream_t st)
 {
@@ -1196,36 +1375,9 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
         hipLaunchKernelGGL((cycle_init_kernel<P>), dim3(s->grid_vec), dim3(BLK), 0, st, V, s->r, s->n, s->ctrl,
                            s->scal, s->g, cyc_rel, abs_tol);
         const double spmv_bytes = (double)s->n_off * N * N * ps + 2.0 * nb * ps + idx_bytes;
-        P* w1 = (P*)s->u;  // the block's second vector (u is free until the cycle's combine)
-        for (int j = 0; s->block == 2 && j < mcyc; j += 2) {
-            int nt, sp;
-            int64_t rows;
-            s->md_shape2(j, &nt, &sp, &rows);
-            const double md_bytes = (j + 3.0) * nb * ps, up_bytes = (j + 5.0) * nb * ps;
-            pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
-            hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
-                               m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, w, s->T, s->ctrl, (const P*)nullptr);
-            prof_end(s, st, pr);
-            pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
-            hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
-                               m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, w1, s->T, s->ctrl, (const P*)w);
-            prof_end(s, st, pr);
-            pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
-            hipLaunchKernelGGL((multidot2_kernel<P>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, (const P*)w,
-                               (const P*)w1, s->n, j, rows, (const int*)s->ctrl, s->partials);
-            prof_end(s, st, pr);
-            hipLaunchKernelGGL(reduce_cols_kernel, dim3((2 * (j + 1) + 3) / 4), dim3(BLK), 0, st,
-                               (const double*)s->partials, 2 * (j + 1), sp, j, (const int*)s->ctrl, s->Rb, 0);
-            pr = prof_begin(s, st, PK_UPDATE, up_bytes, j, 0);
-            hipLaunchKernelGGL((update2_kernel<P>), dim3(s->grid_chunk), dim3(BLK), 0, st, (const P*)V, w, w1, s->n, j,
-                               (const int*)s->ctrl, s->partials, (const double*)s->Rb);
-            prof_end(s, st, pr);
-            hipLaunchKernelGGL(block_givens_kernel, dim3(1), dim3(BG_T), 0, st, s->ctrl, (const double*)s->partials,
-                               s->grid_chunk, (const double*)s->Rb, s->Hr, mm + 2, s->H, mm + 1, s->cs, s->sn, s->g,
-                               s->scal, j, mcyc);
-            hipLaunchKernelGGL((normalize2_kernel<P>), dim3(s->grid_vec), dim3(BLK), 0, st, V, (const P*)w,
-                               (const P*)w1, s->n, j, (const int*)s->ctrl, (const double*)s->scal);
-        }
+        if (s->block == 2) block_cycle<N, P, 2>(s, st, mcyc, spmv_bytes);
+        if (s->block == 3) block_cycle<N, P, 3>(s, st, mcyc, spmv_bytes);
+        if (s->block == 4) block_cycle<N, P, 4>(s, st, mcyc, spmv_bytes);
         for (int j = 0; s->block == 1 && j < mcyc; ++j) {
             int nt, sp;
             int64_t rows;
