@@ -26,6 +26,7 @@ constexpr int LS_BT = 256;       // threads per block
 constexpr int LS_CH = 1024;      // rows per row chunk (one workgroup each); measured fastest of 512..16384
 constexpr int LS_CT = 16;        // Gram-Schmidt columns reduced together (8: same, 32: slower)
 constexpr int LS_GV = 512;       // Givens staging chunk
+constexpr int LS_BATCH = 8;      // loads issued together in the serial loops of the block kernels
 
 __device__ __forceinline__ double ls_wave_sum(double v)
 {
@@ -421,8 +422,17 @@ __global__ __launch_bounds__(LS_BT) void ls_reduce_kernel(const LsArgs A, int bl
     const double* part = A.part + I.part_off;
     const int ncols = block2 ? 2 * (S.J + 1) : S.J + 2;
     for (int c = threadIdx.x; c < ncols; c += LS_BT) {
+        const double* pc = part + (int64_t)c * I.nchunks;
         double s = 0.0;
-        for (int ch = 0; ch < I.nchunks; ++ch) s += part[(int64_t)c * I.nchunks + ch];
+        int ch = 0;
+        for (; ch + LS_BATCH <= I.nchunks; ch += LS_BATCH) {  // loads issued together, summed in order
+            double v[LS_BATCH];
+#pragma unroll
+            for (int u = 0; u < LS_BATCH; ++u) v[u] = pc[ch + u];
+#pragma unroll
+            for (int u = 0; u < LS_BATCH; ++u) s += v[u];
+        }
+        for (; ch < I.nchunks; ++ch) s += pc[ch];
         A.hcol[I.hc_off + c] = s;
     }
 }
@@ -715,10 +725,15 @@ __global__ __launch_bounds__(LS_BT) void ls_update2_kernel(const LsArgs A)
 
 // previous Givens rotations applied to colv[0..count] in LDS (thread 0 runs the
 // chain; the rotations are staged in chunks by the 64 threads)
-__device__ void ls_rotate(double* colv, int count, const double* __restrict__ cs, const double* __restrict__ sn,
-                          double* sc, double* ss)
+// Rotations 0..count-1 applied to col0 and, when ncol = 2, col1: lane l takes
+// column l, the LDS loads of LS_BATCH steps issued together
+__device__ void ls_rotate(double* col0, double* col1, int ncol, int count, const double* __restrict__ cs,
+                          const double* __restrict__ sn, double* sc, double* ss)
 {
-    double a = colv[0];
+    const int l = threadIdx.x;
+    double* colv = l == 0 ? col0 : col1;
+    __syncthreads();
+    double a = l < ncol ? colv[0] : 0.0;
     for (int i0 = 0; i0 < count; i0 += LS_GV) {
         const int cnt = min(count - i0, LS_GV);
         __syncthreads();
@@ -727,16 +742,33 @@ __device__ void ls_rotate(double* colv, int count, const double* __restrict__ cs
             ss[t] = sn[i0 + t];
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int t = 0; t < cnt; ++t) {
-                const double bv = colv[i0 + t + 1];
-                colv[i0 + t] = sc[t] * a + ss[t] * bv;
+        if (l < ncol) {
+            double* cv = colv + i0;
+            int t = 0;
+            for (; t + LS_BATCH <= cnt; t += LS_BATCH) {
+                double c[LS_BATCH], s[LS_BATCH], b[LS_BATCH], o[LS_BATCH];
+#pragma unroll
+                for (int u = 0; u < LS_BATCH; ++u) {
+                    c[u] = sc[t + u];
+                    s[u] = ss[t + u];
+                    b[u] = cv[t + u + 1];  // not yet written: this batch writes cv[t .. t + LS_BATCH - 1]
+                }
+#pragma unroll
+                for (int u = 0; u < LS_BATCH; ++u) {
+                    o[u] = c[u] * a + s[u] * b[u];
+                    a = -s[u] * a + c[u] * b[u];
+                }
+#pragma unroll
+                for (int u = 0; u < LS_BATCH; ++u) cv[t + u] = o[u];
+            }
+            for (; t < cnt; ++t) {
+                const double bv = cv[t + 1];
+                cv[t] = sc[t] * a + ss[t] * bv;
                 a = -ss[t] * a + sc[t] * bv;
             }
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) colv[count] = a;
+    if (l < ncol) colv[count] = a;
     __syncthreads();
 }
 
@@ -799,14 +831,25 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
         const double r11 = fac[0];
         for (int t = threadIdx.x; t <= j + 1; t += 64) {
             double acc = 0.0;
-            for (int c = t > 0 ? t - 1 : 0; c <= j; ++c) acc += Hr[t + (int64_t)c * ldr] * R0[c];
+            int c = t > 0 ? t - 1 : 0;
+            for (; c + LS_BATCH <= j + 1; c += LS_BATCH) {  // loads issued together, summed in order
+                double h[LS_BATCH], r[LS_BATCH];
+#pragma unroll
+                for (int u = 0; u < LS_BATCH; ++u) {
+                    h[u] = Hr[t + (int64_t)(c + u) * ldr];
+                    r[u] = R0[c + u];
+                }
+#pragma unroll
+                for (int u = 0; u < LS_BATCH; ++u) acc += h[u] * r[u];
+            }
+            for (; c <= j; ++c) acc += Hr[t + (int64_t)c * ldr] * R0[c];
             colB[t] = ((t <= j ? R1[t] : fac[1]) - acc) / r11;
         }
         if (threadIdx.x == 0) colB[j + 2] = fac[2] / r11;
         __syncthreads();
         for (int t = threadIdx.x; t <= j + 2; t += 64) Hr[t + (int64_t)(j + 1) * ldr] = colB[t];
     }
-    ls_rotate(colA, j, cs, sn, sc, ss);
+    ls_rotate(colA, colB, want2 ? 2 : 1, j, cs, sn, sc, ss);  // earlier blocks' rotations on both columns
     if (threadIdx.x == 0) {
         const double a = colA[j], bv = colA[j + 1];
         const double d = sqrt(a * a + bv * bv);
@@ -829,9 +872,13 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
         }
         return;
     }
-    ls_rotate(colB, j + 1, cs, sn, sc, ss);
     if (threadIdx.x == 0) {
         const int k = j + 1;
+        {  // the first column's rotation on the second
+            const double a = colB[j], bv = colB[k];
+            colB[j] = cs[j] * a + sn[j] * bv;
+            colB[k] = -sn[j] * a + cs[j] * bv;
+        }
         const double a = colB[k], bv = colB[k + 1];
         const double d = sqrt(a * a + bv * bv);
         cs[k] = d == 0.0 ? 1.0 : a / d;
