@@ -224,11 +224,44 @@ __global__ __launch_bounds__(BLK) void spmv_hat_kernel(const P* __restrict__ Aha
     const int s0 = rp[el], s1 = rp[el + 1];
     const int64_t c0 = (int64_t)s0 - el;
     P s = v[el * N + i];
-    for (int sl = s0 + 1; sl < s1; ++sl) {
-        const P* blk = Ahat + ((c0 + (sl - s0 - 1)) * N + i) * N;
-        const P* xv = v + (int64_t)ci[sl] * N;
+    if constexpr (N <= 6) {
+        // A triangle has at most three neighbours: the loads of all three are
+        // issued before the first product (absent ones read block 0 and
+        // element 0, always allocated, and are not added), the sums keep the
+        // neighbour order.
+        constexpr int NB = 3;
+        const int nb = s1 - s0 - 1;
+        P bl[NB][N], xx[NB][N];
 #pragma unroll
-        for (int c = 0; c < N; ++c) s += blk[c] * xv[c];
+        for (int q = 0; q < NB; ++q) {
+            const bool has = q < nb;
+            const P* blk = Ahat + (has ? ((c0 + q) * N + i) * N : 0);
+            const P* xv = v + (has ? (int64_t)ci[s0 + 1 + q] * N : 0);
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                bl[q][c] = blk[c];
+                xx[q][c] = xv[c];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (q < nb) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) s += bl[q][c] * xx[q][c];
+            }
+        for (int sl = s0 + 1 + NB; sl < s1; ++sl) {  // not reached on triangle meshes
+            const P* blk = Ahat + ((c0 + (sl - s0 - 1)) * N + i) * N;
+            const P* xv = v + (int64_t)ci[sl] * N;
+#pragma unroll
+            for (int c = 0; c < N; ++c) s += blk[c] * xv[c];
+        }
+    } else {
+        for (int sl = s0 + 1; sl < s1; ++sl) {
+            const P* blk = Ahat + ((c0 + (sl - s0 - 1)) * N + i) * N;
+            const P* xv = v + (int64_t)ci[sl] * N;
+#pragma unroll
+            for (int c = 0; c < N; ++c) s += blk[c] * xv[c];
+        }
     }
     w[el * N + i] = s;
 }

@@ -1,6 +1,6 @@
 """Degenerate inputs on the GPU: a mesh of one triangle (no interior edge,
 one block), two triangles with Neumann data only, a zero load vector and a
-non-finite one, through both solver paths."""
+non-finite one, through both solver paths and every Arnoldi block size."""
 import sys
 
 import numpy as np
@@ -36,9 +36,12 @@ TWO = W.MeshArrays(np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]]),
 
 
 def _solve_both(api, mesh, vals, rhs, tol):
+    """Both solver paths; the kernel-per-step one with 1 to 4 Arnoldi vectors
+    per Gram-Schmidt pass (one triangle: the preconditioned operator is the
+    identity, so every block breaks down at its first Cholesky pivot)."""
     out = []
-    for persistent in ("auto", False):
-        s = api.Solver(mesh, restart=16, max_iters=200, rel_tol=tol, persistent=persistent)
+    for persistent, block in (("auto", 0), (False, 1), (False, 2), (False, 3), (False, 4)):
+        s = api.Solver(mesh, restart=16, max_iters=200, rel_tol=tol, persistent=persistent, block=block)
         s.setup(vals)
         x = torch.zeros_like(rhs)
         rep = s.solve(rhs, x)
@@ -76,8 +79,8 @@ def test_zero_and_non_finite_load_vectors(api, mixed):
     case = DC.Case("zero", m, 1, 2, 0.1, (1.0, 0.0), 1.0, 0.0)
     vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
     assert float(rhs.abs().max()) == 0.0
-    for persistent in ("auto", False):
-        s = api.Solver(mesh, restart=16, rel_tol=1e-10, mixed=mixed, persistent=persistent)
+    for persistent, block in (("auto", 0), (False, 1), (False, 2), (False, 3), (False, 4)):
+        s = api.Solver(mesh, restart=16, rel_tol=1e-10, mixed=mixed, persistent=persistent, block=block)
         s.setup(vals)
         x = torch.full_like(rhs, 3.0)
         rep = s.solve(rhs, x)
