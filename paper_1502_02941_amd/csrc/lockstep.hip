@@ -614,7 +614,7 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot2_kernel(const LsArgs A)
             const double x0 = (double)w0[t], x1 = (double)w1[t];
 #pragma unroll
             for (int c = 0; c < LS_CT2; ++c) {
-                const double v = (double)col[c][t];
+                const double v = (double)__builtin_nontemporal_load(col[c] + t);  // streamed
                 a0[c] += v * x0;
                 a1[c] += v * x1;
             }
@@ -679,8 +679,10 @@ __global__ __launch_bounds__(LS_BT) void ls_update2_kernel(const LsArgs A)
             for (int e = 0; e < E; ++e) {
                 const int64_t t = t0 + (int64_t)e * LS_BT;
                 if (in[e]) {
-                    const double a = (double)v0[t], bb = (double)v0[t + n], cc = (double)v0[t + 2 * n],
-                                 d = (double)v0[t + 3 * n];
+                    const double a = (double)__builtin_nontemporal_load(v0 + t),  // streamed
+                                 bb = (double)__builtin_nontemporal_load(v0 + t + n),
+                                 cc = (double)__builtin_nontemporal_load(v0 + t + 2 * n),
+                                 d = (double)__builtin_nontemporal_load(v0 + t + 3 * n);
                     u0[e] -= p0 * a + p1 * bb + p2 * cc + p3 * d;
                     u1[e] -= q0 * a + q1 * bb + q2 * cc + q3 * d;
                 }
@@ -693,7 +695,7 @@ __global__ __launch_bounds__(LS_BT) void ls_update2_kernel(const LsArgs A)
             for (int e = 0; e < E; ++e) {
                 const int64_t t = t0 + (int64_t)e * LS_BT;
                 if (in[e]) {
-                    const double a = (double)vc[t];
+                    const double a = (double)__builtin_nontemporal_load(vc + t);
                     u0[e] -= p0 * a;
                     u1[e] -= q0 * a;
                 }
