@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--restart", type=int, default=2 * N_GRID + 64)
     ap.add_argument("--reorth", type=int, default=0, help="1: conditional second Gram-Schmidt pass")
+    ap.add_argument("--lockstep-block", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="c4: Arnoldi vectors per Gram-Schmidt pass of the lockstep solver (0: the batch's choice, 3)")
     ap.add_argument("--block", type=int, default=0, choices=(0, 1, 2, 3, 4),
                     help="Arnoldi vectors per Gram-Schmidt pass (0: the solver's choice, 3 without reorth)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -301,7 +303,7 @@ def bench_c4(args, api, W, torch):
         best = autotune.tune_batch(api, pairs, mixed=mixed, log=log)
         log("%s: tuned %s in %.1f s" % (form, best, time.perf_counter() - t0))
         t0 = time.perf_counter()
-        b = api.Batch(pairs, mixed=mixed, rel_tol=1e-10, inner_tol=1e-5, **best)
+        b = api.Batch(pairs, mixed=mixed, rel_tol=1e-10, inner_tol=1e-5, lockstep_block=args.lockstep_block, **best)
         log("%s: batch created in %.1f s" % (form, time.perf_counter() - t0))
         x, rep = b.alloc()
         for _ in range(args.warmup):
@@ -334,11 +336,12 @@ def bench_c4(args, api, W, torch):
             cyc = max(int(R["cycles"][i]), 1)
             its_i = float(R["iters"][i])
             per = its_i / cyc
-            # dots + updates over the basis: the lockstep path takes two Arnoldi vectors per pass
-            # ((j + 3) + (j + 5) vectors per block of two steps), the persistent path one
-            # ((j + 2) + (j + 3) per step)
+            # dots + updates over the basis: the lockstep path takes S Arnoldi vectors per pass
+            # ((j + 1 + S) + (j + 1 + 2S) vectors per block of S steps, summed over the blocks of a
+            # cycle: per^2 / S + (2 + 2S) per / S), the persistent path one ((j + 2) + (j + 3) per step)
             if n >= best["lockstep_min_dofs"]:
-                orth = cyc * (per * per / 2.0 + 3.0 * per) * n * ps
+                lsb = args.lockstep_block or 3
+                orth = cyc * (per * per / lsb + (2.0 + 2.0 * lsb) * per / lsb) * n * ps
             else:
                 orth = cyc * (per * (per + 1) + 4 * per) * n * ps
             spmv = its_i * ((nnzb - T) * nl * nl * ps + 2.0 * n * ps)

@@ -403,7 +403,7 @@ typedef struct {
     double lockstep_mem_gb;   /* lockstep workspace budget per chunk of instances (<= 0: 64 GB) */
     double guess_limit;       /* per instance, as dg_solver_opts.guess_limit */
     int32_t lockstep_block;   /* lockstep solver: Arnoldi vectors per Gram-Schmidt pass, as dg_solver_opts.block
-                                 (0 = automatic = 2, 1 or 2; DG_ERR_ARG otherwise) */
+                                 (0 = automatic = 3, 1, 2 or 3; DG_ERR_ARG otherwise) */
     int32_t reserved;
 } dg_batch_opts;
 

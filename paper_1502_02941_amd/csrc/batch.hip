@@ -510,7 +510,7 @@ struct dg_batch {
         int64_t* d_rblk = nullptr;
     };
     std::vector<Chunk> chunks;
-    void *ls_V = nullptr, *ls_Ahat = nullptr, *ls_DinvP = nullptr, *ls_w = nullptr, *ls_w1 = nullptr;
+    void *ls_V = nullptr, *ls_Ahat = nullptr, *ls_DinvP = nullptr, *ls_w = nullptr, *ls_w1 = nullptr, *ls_w2 = nullptr;
     double* ls_Hr = nullptr;
     double *ls_Dinv64 = nullptr, *ls_part = nullptr, *ls_red = nullptr, *ls_red2 = nullptr, *ls_hcol = nullptr;
     double *ls_H = nullptr, *ls_cs = nullptr, *ls_sn = nullptr, *ls_g = nullptr, *ls_y = nullptr, *ls_r = nullptr;
@@ -532,7 +532,7 @@ static void batch_free(dg_batch* b)
     hipFree(b->ls_V); hipFree(b->ls_Ahat); hipFree(b->ls_DinvP); hipFree(b->ls_w); hipFree(b->ls_Dinv64);
     hipFree(b->ls_part); hipFree(b->ls_red); hipFree(b->ls_red2); hipFree(b->ls_hcol); hipFree(b->ls_H);
     hipFree(b->ls_cs); hipFree(b->ls_sn); hipFree(b->ls_g); hipFree(b->ls_y); hipFree(b->ls_r);
-    hipFree(b->ls_w1); hipFree(b->ls_Hr);
+    hipFree(b->ls_w1); hipFree(b->ls_w2); hipFree(b->ls_Hr);
     hipFree(b->ls_counters);
 }
 
@@ -578,7 +578,7 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
     *out = nullptr;
     if (!in || count <= 0 || !o) return DG_ERR_ARG;
     if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512) return DG_ERR_ARG;
-    if (o->lockstep_block < 0 || o->lockstep_block > 2) return DG_ERR_ARG;
+    if (o->lockstep_block < 0 || o->lockstep_block > 3) return DG_ERR_ARG;
     if (o->restart_max < 1 || o->restart_max > B_MAXM || o->restart_min < 1 || !(o->rel_tol > 0) ||
         o->max_iters < 0 || (o->mixed != 0 && o->mixed != 1) || (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)))
         return DG_ERR_ARG;
@@ -754,6 +754,10 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
     // lockstep chunks: cost order, greedy under the memory budget
     if (s == DG_OK && !lock.empty()) {
         const double budget = (o->lockstep_mem_gb > 0 ? o->lockstep_mem_gb : 64.0) * 1e9;
+        // partials, projections and Gram sums sized for blocks of lsb vectors
+        // (at least two: the one-vector path fits in the same room)
+        const int lsb = (o->lockstep_block == 0 || o->lockstep_block == 3) ? 3 : 2;
+        const size_t lsg = (size_t)lsb * (lsb + 1) / 2;
         size_t mx_dinv = 0, mx_ahat = 0, mx_V = 0, mx_part = 0, mx_red = 0, mx_red2 = 0, mx_hc = 0, mx_h = 0, mx_H = 0;
         size_t mx_Hr = 0;
         size_t i0 = 0;
@@ -770,7 +774,8 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
                 const int64_t n = I.T * N;
                 const int64_t nch = ls_row_chunks(n), neb = ls_elem_blocks(I.k, I.T);
                 const double add = (double)i_V[id] * ps + (double)i_ahat[id] * ps + (double)i_dinv[id] * (8 + ps) +
-                                   (double)(I.m + 2) * nch * 8 * 2 + 3.0 * nch * 8 + (double)(I.m + 1) * (I.m + 6) * 8 +
+                                   (double)(I.m + 2) * nch * 8 * lsb + (double)lsg * nch * 8 +
+                                   (double)(I.m + 1) * (I.m + 6) * 8 +
                                    (double)(I.m + 2) * (I.m + 1) * 8;
                 if (!li.empty() && bytes + add > budget) break;
                 LsInst L{};
@@ -779,10 +784,9 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
                 L.rp_off = I.rp_off; L.ci_off = I.ci_off; L.val_off = I.val_off; L.x_off = I.x_off;
                 L.dinv_off = dinv; L.ahat_off = ahat; L.v_off = V; L.part_off = part;
                 L.red_off = red; L.red2_off = red2; L.hc_off = hc; L.h_off = hh; L.H_off = H; L.Hr_off = Hr;
-                // partials, projections and reductions sized for two-vector blocks:
-                // 2 (m + 1) columns of partials, 3 Gram sums per row chunk
-                dinv += i_dinv[id]; ahat += i_ahat[id]; V += i_V[id]; part += (size_t)2 * (I.m + 2) * nch;
-                red += 3 * (size_t)nch; red2 += neb; hc += 2 * ((size_t)I.m + 2); hh += I.m + 1;
+                // lsb (m + 2) columns of partials, lsb (lsb + 1) / 2 Gram sums per row chunk
+                dinv += i_dinv[id]; ahat += i_ahat[id]; V += i_V[id]; part += (size_t)lsb * (I.m + 2) * nch;
+                red += lsg * (size_t)nch; red2 += neb; hc += (size_t)lsb * ((size_t)I.m + 2); hh += I.m + 1;
                 H += (size_t)(I.m + 1) * I.m; Hr += (size_t)(I.m + 2) * (I.m + 1);
                 eb.push_back(eb.back() + neb);
                 rb.push_back(rb.back() + nch);
@@ -816,6 +820,7 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
         al((void**)&b->ls_Dinv64, mx_dinv * 8);
         al(&b->ls_w, (size_t)tot_x * ps);
         al(&b->ls_w1, (size_t)tot_x * ps);
+        if (lsb == 3) al(&b->ls_w2, (size_t)tot_x * ps);
         al((void**)&b->ls_Hr, mx_Hr * 8);
         al((void**)&b->ls_r, (size_t)tot_x * 8);
         al((void**)&b->ls_part, mx_part * 8);
@@ -893,8 +898,9 @@ extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev
         L.r = b->ls_r;
         L.w = b->ls_w;
         L.w1 = b->ls_w1;
+        L.w2 = b->ls_w2;
         L.Hr = b->ls_Hr;
-        L.block = b->o.lockstep_block == 1 ? 1 : 2;
+        L.block = b->o.lockstep_block == 0 ? 3 : b->o.lockstep_block;
         L.V = b->ls_V;
         L.Ahat = b->ls_Ahat;
         L.DinvP = b->ls_DinvP;

@@ -17,14 +17,14 @@ struct LsInst {
     int64_t rp_off, ci_off, val_off, x_off;               // batch arrays
     int64_t dinv_off, ahat_off, v_off, part_off;          // chunk buffers
     int64_t red_off, red2_off, hc_off, h_off, H_off;
-    int64_t Hr_off;            // raw Hessenberg columns of the two-vector blocks
+    int64_t Hr_off;            // raw Hessenberg columns of the Arnoldi blocks
 };
 
 struct LsState {
     int32_t active, stop, J, mcyc, its, cycles, status, pad;
     double bnorm, beta, cyctol, invh;
-    int32_t jb, bstep;         // two-vector blocks: first column and host step of the last block taken
-    double q1, q2a, q2b;       // v_{jb+1} = q1 u0, v_{jb+2} = q2a u1 + q2b u0
+    int32_t jb, bstep;         // Arnoldi blocks: first column and host step of the last block taken
+    double ci[9];              // its inverse Cholesky factor, row-major block x block: q_i = sum_l u_l ci[l][i]
 };
 
 struct LsArgs {
@@ -40,7 +40,8 @@ struct LsArgs {
     double* x;
     double* r;
     void* w;
-    void* w1;             // the second vector of a two-vector block
+    void* w1;             // the second vector of an Arnoldi block
+    void* w2;             // the third (blocks of 3)
     void* V;
     void* Ahat;
     void* DinvP;
@@ -59,7 +60,7 @@ struct LsArgs {
     int* counters;
     double rel_tol, inner_tol, guess_limit;
     int32_t max_iters, mixed;
-    int32_t block;        // Arnoldi vectors per Gram-Schmidt pass: 1 or 2
+    int32_t block;        // Arnoldi vectors per Gram-Schmidt pass: 1, 2 or 3
 };
 
 int ls_solve(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m, int mixed, hipStream_t st,

@@ -345,7 +345,7 @@ __global__ __launch_bounds__(LS_BT) void ls_cycle_init_kernel(const LsArgs A)
 // ---------------------------------------------------------------------------
 // w = Ahat v_J, or with second = 1 the two-vector block's w1 = Ahat w
 template <typename P>
-__global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int second)
+__global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src)
 {
     ElemLane e;
     if (!ls_elem_lane(A, e)) return;
@@ -355,7 +355,9 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int seco
     const int N = e.n;
     const int32_t* rp = A.row_ptr + I.rp_off;
     const int32_t* ci = A.col_idx + I.ci_off;
-    const P* v = second ? (const P*)A.w + I.x_off : (const P*)A.V + I.v_off + (int64_t)S.J * I.n;
+    // src 0: Ahat v_J into w; src r > 0: a block's w_r = Ahat w_{r-1}
+    const P* v = src == 0 ? (const P*)A.V + I.v_off + (int64_t)S.J * I.n
+                          : (const P*)(src == 1 ? A.w : A.w1) + I.x_off;
     const P* Ah = (const P*)A.Ahat + I.ahat_off;
     const int s0 = rp[e.el], s1 = rp[e.el + 1];
     const int64_t c0 = (int64_t)s0 - e.el;
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int seco
         const P* xv = v + (int64_t)ci[sl] * N;
         for (int c = 0; c < N; ++c) s += (double)blk[c] * (double)xv[c];
     }
-    ((P*)(second ? A.w1 : A.w))[I.x_off + e.el * N + e.j] = (P)s;
+    ((P*)(src == 0 ? A.w : src == 1 ? A.w1 : A.w2))[I.x_off + e.el * N + e.j] = (P)s;
 }
 
 // partial V_c . w (c <= J) and w . w (c = J+1) over one row chunk
@@ -413,14 +415,14 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot_kernel(const LsArgs A)
 
 // one block per instance: h[c] = sum over chunks (J + 2 columns, or 2 (J + 1)
 // for a two-vector block)
-__global__ __launch_bounds__(LS_BT) void ls_reduce_kernel(const LsArgs A, int block2)
+__global__ __launch_bounds__(LS_BT) void ls_reduce_kernel(const LsArgs A, int nrhs)
 {
     const int i = blockIdx.x;
     const LsState& S = A.state[i];
     if (!ls_running(S)) return;
     const LsInst& I = A.inst[i];
     const double* part = A.part + I.part_off;
-    const int ncols = block2 ? 2 * (S.J + 1) : S.J + 2;
+    const int ncols = nrhs ? nrhs * (S.J + 1) : S.J + 2;  // a block's S (J + 1) dots, or one step's J + 2
     for (int c = threadIdx.x; c < ncols; c += LS_BT) {
         const double* pc = part + (int64_t)c * I.nchunks;
         double s = 0.0;
@@ -578,57 +580,68 @@ __global__ __launch_bounds__(LS_BT) void ls_normalize_kernel(const LsArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// Two-vector blocks (as in the single-system solver): w0 = Ahat v_J and
-// w1 = Ahat w0 are projected against v_0..v_J in one pass over the basis and
-// updated in a second, the 2 x 2 Gram matrix of the results is factored by
-// Cholesky, and the two Hessenberg columns follow from the block relations.
+// Arnoldi blocks of S = 2 or 3 vectors (as in the single-system solver):
+// w_0 = Ahat v_J and w_i = Ahat w_{i-1} are projected against v_0..v_J in one
+// pass over the basis and updated in a second, the S x S Gram matrix of the
+// results is factored by Cholesky, and the S Hessenberg columns follow from
+// the block relations W = V R + Q C.
 // ---------------------------------------------------------------------------
-constexpr int LS_CT2 = 8;  // columns per tile with two right-hand sides
+constexpr int LS_CT2 = 8;  // columns per tile of the block dot kernel
 
-// partial V_c . w_r (c <= J, r = 0, 1) over one row chunk, at part[(r (J+1) + c) nchunks + chunk]
 template <typename P>
-__global__ __launch_bounds__(LS_BT) void ls_multidot2_kernel(const LsArgs A)
+__device__ __forceinline__ P* ls_block_vec(const LsArgs& A, int r)
 {
-    __shared__ double sh[LS_BT / 64][2 * LS_CT2];
+    return (P*)(r == 0 ? A.w : r == 1 ? A.w1 : A.w2);
+}
+
+// partial V_c . w_r (c <= J, r < S) over one row chunk, at part[(r (J+1) + c) nchunks + chunk]
+template <typename P, int S>
+__global__ __launch_bounds__(LS_BT) void ls_multidot_block_kernel(const LsArgs A)
+{
+    __shared__ double sh[LS_BT / 64][S * LS_CT2];
     const int64_t b = blockIdx.x;
     const int i = ls_find(A.rblk, A.count, b);
-    const LsState& S = A.state[i];
-    if (!ls_running(S)) return;
+    const LsState& St = A.state[i];
+    if (!ls_running(St)) return;
     const LsInst& I = A.inst[i];
     const int64_t ch = b - A.rblk[i];
-    const int J = S.J, ncols = J + 1;
+    const int J = St.J, ncols = J + 1;
     const P* V = (const P*)A.V + I.v_off;
-    const P* w0 = (const P*)A.w + I.x_off;
-    const P* w1 = (const P*)A.w1 + I.x_off;
+    const P* wv[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) wv[q] = ls_block_vec<P>(A, q) + I.x_off;
     const int64_t r0 = ch * LS_CH, r1 = min(r0 + LS_CH, I.n);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double* part = A.part + I.part_off;
     for (int t0 = 0; t0 < ncols; t0 += LS_CT2) {
         const P* col[LS_CT2];
 #pragma unroll
-        for (int c = 0; c < LS_CT2; ++c) col[c] = (t0 + c <= J) ? V + (int64_t)(t0 + c) * I.n : w0;  // past J: discarded
-        double a0[LS_CT2], a1[LS_CT2];
+        for (int c = 0; c < LS_CT2; ++c) col[c] = (t0 + c <= J) ? V + (int64_t)(t0 + c) * I.n : wv[0];  // past J: discarded
+        double a[S][LS_CT2];
 #pragma unroll
-        for (int c = 0; c < LS_CT2; ++c) a0[c] = a1[c] = 0.0;
+        for (int q = 0; q < S; ++q)
+#pragma unroll
+            for (int c = 0; c < LS_CT2; ++c) a[q][c] = 0.0;
         for (int64_t t = r0 + threadIdx.x; t < r1; t += LS_BT) {
-            const double x0 = (double)w0[t], x1 = (double)w1[t];
+            double x[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) x[q] = (double)wv[q][t];
 #pragma unroll
             for (int c = 0; c < LS_CT2; ++c) {
                 const double v = (double)__builtin_nontemporal_load(col[c] + t);  // streamed
-                a0[c] += v * x0;
-                a1[c] += v * x1;
+#pragma unroll
+                for (int q = 0; q < S; ++q) a[q][c] += v * x[q];
             }
         }
 #pragma unroll
-        for (int c = 0; c < LS_CT2; ++c) {
-            const double v0 = ls_wave_sum(a0[c]), v1 = ls_wave_sum(a1[c]);
-            if (lane == 0) {
-                sh[wave][c] = v0;
-                sh[wave][LS_CT2 + c] = v1;
+        for (int q = 0; q < S; ++q)
+#pragma unroll
+            for (int c = 0; c < LS_CT2; ++c) {
+                const double v = ls_wave_sum(a[q][c]);
+                if (lane == 0) sh[wave][q * LS_CT2 + c] = v;
             }
-        }
         __syncthreads();
-        if (threadIdx.x < 2 * LS_CT2) {
+        if (threadIdx.x < S * LS_CT2) {
             const int rr = threadIdx.x / LS_CT2, c = threadIdx.x - rr * LS_CT2;
             if (t0 + c < ncols)
                 part[((int64_t)rr * ncols + t0 + c) * I.nchunks + ch] =
@@ -638,42 +651,49 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot2_kernel(const LsArgs A)
     }
 }
 
-// w_r -= sum_{c<=J} R_r[c] V_c (R_0 = hcol[0..J], R_1 = hcol[J+1..2J+1]) and the
-// Gram partials u0.u0, u0.u1, u1.u1 at red[red_off + k nchunks + chunk]
-template <typename P>
-__global__ __launch_bounds__(LS_BT) void ls_update2_kernel(const LsArgs A)
+// w_r -= sum_{c<=J} R_r[c] V_c (R_r = hcol + r (J+1)) and the Gram partials of
+// the results, pair k = (p, q), p <= q in the order (0,0), (0,1), (1,1), (0,2),
+// (1,2), (2,2), at red[red_off + k nchunks + chunk]
+template <typename P, int S>
+__global__ __launch_bounds__(LS_BT) void ls_update_block_kernel(const LsArgs A)
 {
+    constexpr int NG = S * (S + 1) / 2;
     __shared__ double sh[LS_BT / 64];
     const int64_t b = blockIdx.x;
     const int i = ls_find(A.rblk, A.count, b);
-    const LsState& S = A.state[i];
-    if (!ls_running(S)) return;
+    const LsState& St = A.state[i];
+    if (!ls_running(St)) return;
     const LsInst& I = A.inst[i];
     const int64_t ch = b - A.rblk[i];
-    const int J = S.J;
+    const int J = St.J;
     const P* V = (const P*)A.V + I.v_off;
-    P* w0 = (P*)A.w + I.x_off;
-    P* w1 = (P*)A.w1 + I.x_off;
-    const double* R0 = A.hcol + I.hc_off;
-    const double* R1 = R0 + (J + 1);
+    P* wv[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) wv[q] = ls_block_vec<P>(A, q) + I.x_off;
+    const double* R = A.hcol + I.hc_off;
     const int64_t r0 = ch * LS_CH, r1 = min(r0 + LS_CH, I.n);
     const int64_t n = I.n;
-    double g00 = 0.0, g01 = 0.0, g11 = 0.0;
+    double gs[NG];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) gs[k] = 0.0;
     constexpr int E = 4;
     for (int64_t t0 = r0 + threadIdx.x; t0 < r1; t0 += (int64_t)LS_BT * E) {
-        double u0[E], u1[E];
+        double u[S][E];
         bool in[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int64_t t = t0 + (int64_t)e * LS_BT;
             in[e] = t < r1;
-            u0[e] = in[e] ? (double)w0[t] : 0.0;
-            u1[e] = in[e] ? (double)w1[t] : 0.0;
+#pragma unroll
+            for (int q = 0; q < S; ++q) u[q][e] = in[e] ? (double)wv[q][t] : 0.0;
         }
         int c = 0;
         for (; c + 3 <= J; c += 4) {
-            const double p0 = R0[c], p1 = R0[c + 1], p2 = R0[c + 2], p3 = R0[c + 3];
-            const double q0 = R1[c], q1 = R1[c + 1], q2 = R1[c + 2], q3 = R1[c + 3];
+            double h[S][4];
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) h[q][m] = R[q * (J + 1) + c + m];
             const P* v0 = V + (int64_t)c * n;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -683,21 +703,23 @@ __global__ __launch_bounds__(LS_BT) void ls_update2_kernel(const LsArgs A)
                                  bb = (double)__builtin_nontemporal_load(v0 + t + n),
                                  cc = (double)__builtin_nontemporal_load(v0 + t + 2 * n),
                                  d = (double)__builtin_nontemporal_load(v0 + t + 3 * n);
-                    u0[e] -= p0 * a + p1 * bb + p2 * cc + p3 * d;
-                    u1[e] -= q0 * a + q1 * bb + q2 * cc + q3 * d;
+#pragma unroll
+                    for (int q = 0; q < S; ++q) u[q][e] -= h[q][0] * a + h[q][1] * bb + h[q][2] * cc + h[q][3] * d;
                 }
             }
         }
         for (; c <= J; ++c) {
-            const double p0 = R0[c], q0 = R1[c];
+            double h[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) h[q] = R[q * (J + 1) + c];
             const P* vc = V + (int64_t)c * n;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int64_t t = t0 + (int64_t)e * LS_BT;
                 if (in[e]) {
                     const double a = (double)__builtin_nontemporal_load(vc + t);
-                    u0[e] -= p0 * a;
-                    u1[e] -= q0 * a;
+#pragma unroll
+                    for (int q = 0; q < S; ++q) u[q][e] -= h[q] * a;
                 }
             }
         }
@@ -705,35 +727,36 @@ __global__ __launch_bounds__(LS_BT) void ls_update2_kernel(const LsArgs A)
         for (int e = 0; e < E; ++e) {
             if (in[e]) {
                 const int64_t t = t0 + (int64_t)e * LS_BT;
-                const P a = (P)u0[e], bb = (P)u1[e];
-                w0[t] = a;
-                w1[t] = bb;
-                g00 += (double)a * (double)a;
-                g01 += (double)a * (double)bb;
-                g11 += (double)bb * (double)bb;
+                double r[S];
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const P pv = (P)u[q][e];
+                    wv[q][t] = pv;
+                    r[q] = (double)pv;
+                }
+                int k = 0;
+#pragma unroll
+                for (int q = 0; q < S; ++q)
+#pragma unroll
+                    for (int pp = 0; pp <= q; ++pp) gs[k++] += r[pp] * r[q];
             }
         }
     }
-    g00 = ls_block_sum(g00, sh);
-    g01 = ls_block_sum(g01, sh);
-    g11 = ls_block_sum(g11, sh);
-    if (threadIdx.x == 0) {
-        double* red = A.red + I.red_off;
-        red[ch] = g00;
-        red[I.nchunks + ch] = g01;
-        red[2 * I.nchunks + ch] = g11;
+    double* red = A.red + I.red_off;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        const double v = ls_block_sum(gs[k], sh);
+        if (threadIdx.x == 0) red[(int64_t)k * I.nchunks + ch] = v;
     }
 }
 
-// previous Givens rotations applied to colv[0..count] in LDS (thread 0 runs the
-// chain; the rotations are staged in chunks by the 64 threads)
-// Rotations 0..count-1 applied to col0 and, when ncol = 2, col1: lane l takes
-// column l, the LDS loads of LS_BATCH steps issued together
-__device__ void ls_rotate(double* col0, double* col1, int ncol, int count, const double* __restrict__ cs,
-                          const double* __restrict__ sn, double* sc, double* ss)
+// Rotations 0..count-1 applied to columns 0..ncol-1 (column l at base + l ld):
+// lane l takes column l, the LDS loads of LS_BATCH steps issued together
+__device__ void ls_rotate_cols(double* base, int ld, int ncol, int count, const double* __restrict__ cs,
+                               const double* __restrict__ sn, double* sc, double* ss)
 {
     const int l = threadIdx.x;
-    double* colv = l == 0 ? col0 : col1;
+    double* colv = base + (int64_t)(l < ncol ? l : 0) * ld;
     __syncthreads();
     double a = l < ncol ? colv[0] : 0.0;
     for (int i0 = 0; i0 < count; i0 += LS_GV) {
@@ -774,154 +797,203 @@ __device__ void ls_rotate(double* col0, double* col1, int ncol, int count, const
     __syncthreads();
 }
 
-// one block of 64 threads per instance: Gram sums, Cholesky, the two raw
-// Hessenberg columns (Hr, leading dimension m + 2) and, rotated, into H;
-// residual estimates and stop tests.  Dynamic LDS: two columns of max_m + 4.
-__global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int step)
+// one block of 64 threads per instance: Gram sums, Cholesky (pivot i is
+// resolvable when c_ii > 1e-8 sqrt(G_ii), pivot 0 when c_00 > 1e-300), the
+// block's raw Hessenberg columns (Hr, leading dimension m + 2) and, rotated,
+// into H; residual estimates and stop tests.  A block with p < S resolvable
+// pivots takes columns J..J+p and ends the cycle; C^{-1} goes to the state for
+// the normalisation.  Dynamic LDS: S columns of max_m + 4.
+template <int S>
+__global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int step, int ldc)
 {
+    constexpr int NG = S * (S + 1) / 2;
     extern __shared__ double dyn[];
     __shared__ double sc[LS_GV], ss[LS_GV];
-    __shared__ double fac[3];
-    __shared__ int flags[2];  // take the second column, stop after the first
+    __shared__ double G[S][S], Cf[S][S], Ci[S][S];  // in LDS: thread 0 indexes them dynamically
+    __shared__ int ncol_s, cut_s, stop_s;
     const int i = blockIdx.x;
-    LsState& S = A.state[i];
-    if (!ls_running(S)) return;
+    LsState& St = A.state[i];
+    if (!ls_running(St)) return;
     const LsInst& I = A.inst[i];
-    const int j = S.J, mcyc = S.mcyc, ldh = I.m + 1, ldr = I.m + 2;
-    double* colA = dyn;
-    double* colB = dyn + (I.m + 4);
+    const int j = St.J, mcyc = St.mcyc, ldh = I.m + 1, ldr = I.m + 2;
     double* H = A.H + I.H_off;
     double* Hr = A.Hr + I.Hr_off;
     double* cs = A.cs + I.h_off;
     double* sn = A.sn + I.h_off;
     double* g = A.g + I.h_off;
-    const double* R0 = A.hcol + I.hc_off;
-    const double* R1 = R0 + (j + 1);
+    const double* R = A.hcol + I.hc_off;
     const double* red = A.red + I.red_off;
-    double a00 = 0.0, a01 = 0.0, a11 = 0.0;
-    for (int c = threadIdx.x; c < I.nchunks; c += 64) {
-        a00 += red[c];
-        a01 += red[I.nchunks + c];
-        a11 += red[2 * I.nchunks + c];
-    }
-    a00 = ls_wave_sum(a00);
-    a01 = ls_wave_sum(a01);
-    a11 = ls_wave_sum(a11);
-    for (int t = threadIdx.x; t <= j; t += 64) colA[t] = R0[t];
+    double acc[NG];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) acc[k] = 0.0;
+    for (int c = threadIdx.x; c < I.nchunks; c += 64)
+#pragma unroll
+        for (int k = 0; k < NG; ++k) acc[k] += red[(int64_t)k * I.nchunks + c];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) acc[k] = ls_wave_sum(acc[k]);
+    for (int t = threadIdx.x; t <= j; t += 64) dyn[t] = R[t];
     if (threadIdx.x == 0) {
-        const double r11 = sqrt(a00);
-        const bool brk1 = !(r11 > 1e-300) || !isfinite(r11);
-        const double r12 = brk1 ? 0.0 : a01 / r11;
-        const double d = a11 - r12 * r12;
-        const double r22 = d > 0.0 ? sqrt(d) : 0.0;
-        const bool ok2 = !brk1 && isfinite(r22) && r22 > 1e-8 * sqrt(a11);
-        fac[0] = r11;
-        fac[1] = r12;
-        fac[2] = r22;
-        colA[j + 1] = r11;
-        S.q1 = brk1 ? 0.0 : 1.0 / r11;
-        S.q2a = ok2 ? 1.0 / r22 : 0.0;
-        S.q2b = ok2 ? -r12 / (r11 * r22) : 0.0;
-        flags[0] = ok2 ? 1 : 0;
-        flags[1] = brk1 ? 1 : 0;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t <= j + 1; t += 64) Hr[t + (int64_t)j * ldr] = colA[t];
-    __syncthreads();
-    const bool want2 = !flags[1] && j + 1 < mcyc;
-    if (want2) {
-        const double r11 = fac[0];
-        for (int t = threadIdx.x; t <= j + 1; t += 64) {
-            double acc = 0.0;
-            int c = t > 0 ? t - 1 : 0;
-            for (; c + LS_BATCH <= j + 1; c += LS_BATCH) {  // loads issued together, summed in order
-                double h[LS_BATCH], r[LS_BATCH];
-#pragma unroll
-                for (int u = 0; u < LS_BATCH; ++u) {
-                    h[u] = Hr[t + (int64_t)(c + u) * ldr];
-                    r[u] = R0[c + u];
-                }
-#pragma unroll
-                for (int u = 0; u < LS_BATCH; ++u) acc += h[u] * r[u];
+        int k = 0;
+        for (int q = 0; q < S; ++q)
+            for (int p = 0; p <= q; ++p) {
+                G[p][q] = G[q][p] = acc[k];
+                ++k;
             }
-            for (; c <= j; ++c) acc += Hr[t + (int64_t)c * ldr] * R0[c];
-            colB[t] = ((t <= j ? R1[t] : fac[1]) - acc) / r11;
+        int pok = 0;  // leading resolvable pivots
+        for (int p = 0; p < S; ++p)
+            for (int q = 0; q < S; ++q) Cf[p][q] = Ci[p][q] = 0.0;
+        for (int ii = 0; ii < S; ++ii) {
+            double d = G[ii][ii];
+            for (int m = 0; m < ii; ++m) d -= Cf[m][ii] * Cf[m][ii];
+            const double cii = d > 0.0 ? sqrt(d) : 0.0;
+            const bool ok = isfinite(cii) && (ii == 0 ? cii > 1e-300 : cii > 1e-8 * sqrt(G[ii][ii]));
+            Cf[ii][ii] = isfinite(cii) ? cii : 0.0;
+            if (!ok) break;
+            for (int q = ii + 1; q < S; ++q) {
+                double v = G[ii][q];
+                for (int m = 0; m < ii; ++m) v -= Cf[m][ii] * Cf[m][q];
+                Cf[ii][q] = v / cii;
+            }
+            ++pok;
         }
-        if (threadIdx.x == 0) colB[j + 2] = fac[2] / r11;
+        for (int ii = 0; ii < pok; ++ii) {
+            Ci[ii][ii] = 1.0 / Cf[ii][ii];
+            for (int q = ii + 1; q < pok; ++q) {
+                double v = 0.0;
+                for (int m = ii; m < q; ++m) v += Ci[ii][m] * Cf[m][q];
+                Ci[ii][q] = -v / Cf[q][q];
+            }
+        }
+        int ncol = S < mcyc - j ? S : mcyc - j;
+        if (pok < S && ncol > pok + 1) ncol = pok + 1;
+        ncol_s = ncol;
+        cut_s = pok < S ? 1 : 0;
+        dyn[j + 1] = Cf[0][0];
+        for (int p = 0; p < S; ++p)
+            for (int q = 0; q < S; ++q) St.ci[p * S + q] = Ci[p][q];
+    }
+    __syncthreads();
+    const int ncol = ncol_s;
+    for (int t = threadIdx.x; t <= j + 1; t += 64) Hr[t + (int64_t)j * ldr] = dyn[t];
+    __syncthreads();
+    // columns J+1 .. J+ncol-1 from the raw column J and the earlier raw columns
+    if (ncol > 1) {
+        for (int t = threadIdx.x; t <= j + ncol; t += 64) {
+            double hx[S - 1];
+#pragma unroll
+            for (int l = 0; l < S - 1; ++l) hx[l] = 0.0;
+            if (t <= j + 1) {  // (Hr R_l)[t], loads issued LS_BATCH at a time, summed in order
+                int c = t > 0 ? t - 1 : 0;
+                for (; c + LS_BATCH <= j + 1; c += LS_BATCH) {
+                    double h[LS_BATCH];
+#pragma unroll
+                    for (int u = 0; u < LS_BATCH; ++u) h[u] = Hr[t + (int64_t)(c + u) * ldr];
+#pragma unroll
+                    for (int u = 0; u < LS_BATCH; ++u)
+#pragma unroll
+                        for (int l = 0; l < S - 1; ++l) hx[l] += h[u] * R[l * (j + 1) + c + u];
+                }
+                for (; c <= j; ++c) {
+                    const double h = Hr[t + (int64_t)c * ldr];
+#pragma unroll
+                    for (int l = 0; l < S - 1; ++l) hx[l] += h * R[l * (j + 1) + c];
+                }
+            }
+            for (int ii = 1; ii < ncol; ++ii) {
+                if (t > j + ii + 1) continue;
+                double v = 0.0;
+                for (int l = 0; l < ii; ++l) {
+                    const int m = l + 1;
+                    const double cm = t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0);
+                    v += (cm - hx[l]) * Ci[l][ii - 1];
+                }
+                dyn[ii * ldc + t] = v;
+            }
+        }
         __syncthreads();
-        for (int t = threadIdx.x; t <= j + 2; t += 64) Hr[t + (int64_t)(j + 1) * ldr] = colB[t];
+        for (int ii = 1; ii < ncol; ++ii)
+            for (int t = threadIdx.x; t <= j + ii + 1; t += 64) Hr[t + (int64_t)(j + ii) * ldr] = dyn[ii * ldc + t];
     }
-    ls_rotate(colA, colB, want2 ? 2 : 1, j, cs, sn, sc, ss);  // earlier blocks' rotations on both columns
-    if (threadIdx.x == 0) {
-        const double a = colA[j], bv = colA[j + 1];
-        const double d = sqrt(a * a + bv * bv);
-        cs[j] = d == 0.0 ? 1.0 : a / d;
-        sn[j] = d == 0.0 ? 0.0 : bv / d;
-        colA[j] = d;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        if (flags[1] || fabs(g[j + 1]) <= S.cyctol || j + 1 >= mcyc || !want2) flags[1] = 1;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t <= j; t += 64) H[t + (int64_t)j * ldh] = colA[t];
-    if (flags[1]) {
+    // earlier blocks' rotations on all columns at once, then the columns in turn
+    ls_rotate_cols(dyn, ldc, ncol, j, cs, sn, sc, ss);
+    for (int ii = 0; ii < ncol; ++ii) {
+        const int k = j + ii;
+        double* cv = dyn + ii * ldc;
         if (threadIdx.x == 0) {
-            S.jb = j;
-            S.bstep = step;
-            S.J = j + 1;
-            S.stop = 1;
-            atomicSub(A.counters + 1, 1);
+            double a = cv[j];
+            for (int t = j; t < k; ++t) {
+                const double bv = cv[t + 1];
+                cv[t] = cs[t] * a + sn[t] * bv;
+                a = -sn[t] * a + cs[t] * bv;
+            }
+            const double bv = cv[k + 1];
+            const double d = sqrt(a * a + bv * bv);
+            cs[k] = d == 0.0 ? 1.0 : a / d;
+            sn[k] = d == 0.0 ? 0.0 : bv / d;
+            cv[k] = d;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            stop_s = (fabs(g[k + 1]) <= St.cyctol || k + 1 >= mcyc || (ii == ncol - 1 && cut_s)) ? 1 : 0;
         }
-        return;
+        __syncthreads();
+        for (int t = threadIdx.x; t <= k; t += 64) H[t + (int64_t)k * ldh] = cv[t];
+        if (stop_s) {
+            if (threadIdx.x == 0) {
+                St.jb = j;
+                St.bstep = step;
+                St.J = k + 1;
+                St.stop = 1;
+                atomicSub(A.counters + 1, 1);
+            }
+            return;
+        }
+        __syncthreads();  // every thread has read stop_s before thread 0 sets it again
     }
     if (threadIdx.x == 0) {
-        const int k = j + 1;
-        {  // the first column's rotation on the second
-            const double a = colB[j], bv = colB[k];
-            colB[j] = cs[j] * a + sn[j] * bv;
-            colB[k] = -sn[j] * a + cs[j] * bv;
-        }
-        const double a = colB[k], bv = colB[k + 1];
-        const double d = sqrt(a * a + bv * bv);
-        cs[k] = d == 0.0 ? 1.0 : a / d;
-        sn[k] = d == 0.0 ? 0.0 : bv / d;
-        colB[k] = d;
-        g[k + 1] = -sn[k] * g[k];
-        g[k] = cs[k] * g[k];
-        S.jb = j;
-        S.bstep = step;
-        S.J = k + 1;
-        if (!flags[0] || fabs(g[k + 1]) <= S.cyctol || k + 1 >= mcyc) {
-            S.stop = 1;
-            atomicSub(A.counters + 1, 1);
-        }
+        St.jb = j;
+        St.bstep = step;
+        St.J = j + ncol;
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t <= j + 1; t += 64) H[t + (int64_t)(j + 1) * ldh] = colB[t];
 }
 
-// v_{jb+1} = q1 u0 and, unless the cycle stopped, v_{jb+2} = q2a u1 + q2b u0,
-// for instances whose block of this step took both columns
-template <typename P>
-__global__ __launch_bounds__(LS_BT) void ls_normalize2_kernel(const LsArgs A, int step)
+// q_i = sum_{l<=i} u_l (C^{-1})_{li} into V_{jb+1+i} for the instances whose
+// block was taken this step, for the columns it took (t = J - jb): i <= t - 2,
+// and i = t - 1 unless the cycle stopped
+template <typename P, int S>
+__global__ __launch_bounds__(LS_BT) void ls_normalize_block_kernel(const LsArgs A, int step)
 {
     const int64_t b = blockIdx.x;
     const int i = ls_find(A.rblk, A.count, b);
-    const LsState& S = A.state[i];
-    if (!S.active || S.bstep != step || S.J != S.jb + 2) return;
+    const LsState& St = A.state[i];
+    if (!St.active || St.bstep != step) return;
+    const int tk = St.J - St.jb;
+    const int nq = St.stop ? tk - 1 : tk;
+    if (nq < 1 || tk > S) return;
     const LsInst& I = A.inst[i];
     const int64_t ch = b - A.rblk[i];
-    const bool second = !S.stop;
-    const double a = S.q1, qa = S.q2a, qb = S.q2b;
-    P* o1 = (P*)A.V + I.v_off + (int64_t)(S.jb + 1) * I.n;
-    P* o2 = o1 + I.n;
-    const P* w0 = (const P*)A.w + I.x_off;
-    const P* w1 = (const P*)A.w1 + I.x_off;
+    double ci[S][S];
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+        for (int q = 0; q < S; ++q) ci[p][q] = St.ci[p * S + q];
+    const P* wv[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) wv[q] = ls_block_vec<P>(A, q) + I.x_off;
+    P* out = (P*)A.V + I.v_off + (int64_t)(St.jb + 1) * I.n;
     const int64_t r1 = min((ch + 1) * (int64_t)LS_CH, I.n);
     for (int64_t t = ch * LS_CH + threadIdx.x; t < r1; t += LS_BT) {
-        const double u0 = (double)w0[t];
-        o1[t] = (P)(u0 * a);
-        if (second) o2[t] = (P)((double)w1[t] * qa + u0 * qb);
+        double u[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) u[q] = (double)wv[q][t];
+#pragma unroll
+        for (int ii = 0; ii < S; ++ii) {
+            if (ii < nq) {
+                double v = 0.0;
+#pragma unroll
+                for (int l = 0; l <= ii; ++l) v += u[l] * ci[l][ii];
+                out[(int64_t)ii * I.n + t] = (P)v;
+            }
+        }
     }
 }
 
@@ -1010,6 +1082,31 @@ int ls_init(const LsArgs& A, hipStream_t st)
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
+// one restart cycle of blocks of S Arnoldi vectors over every running
+// instance; step numbers the blocks over the whole solve
+template <typename P, int S>
+static int ls_block_steps(const LsArgs& A, dim3 ge, dim3 gr, dim3 gi, dim3 be, int max_m, int& step, int* h,
+                          hipStream_t st)
+{
+    const int ldc = max_m + 4;
+    const size_t dyn = sizeof(double) * S * (size_t)ldc;
+    constexpr int CHECK = S == 2 ? 4 : 3;  // blocks between checks for the end of every cycle
+    for (int j = 0, blk = 0; j < max_m; j += S, ++step, ++blk) {
+        for (int q = 0; q < S; ++q) hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, q);
+        hipLaunchKernelGGL((ls_multidot_block_kernel<P, S>), gr, be, 0, st, A);
+        hipLaunchKernelGGL(ls_reduce_kernel, gi, be, 0, st, A, S);
+        hipLaunchKernelGGL((ls_update_block_kernel<P, S>), gr, be, 0, st, A);
+        hipLaunchKernelGGL((ls_block_givens_kernel<S>), gi, dim3(64), dyn, st, A, step, ldc);
+        hipLaunchKernelGGL((ls_normalize_block_kernel<P, S>), gr, be, 0, st, A, step);
+        if (blk % CHECK == CHECK - 1) {  // stop early once every cycle has ended
+            DG_HIP_CHECK(hipMemcpyAsync(h, A.counters, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+            DG_HIP_CHECK(hipStreamSynchronize(st));
+            if (h[1] <= 0) break;
+        }
+    }
+    return DG_OK;
+}
+
 template <typename P>
 static int ls_solve_p(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m, hipStream_t st, dg_progress_fn fn,
                       void* user, int done_before, int total)
@@ -1020,7 +1117,7 @@ static int ls_solve_p(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m
     hipLaunchKernelGGL(ls_bnorm_kernel, gr, be, 0, st, A);
     int first = 1;
     int h[2];
-    int step = 1;  // host step index of the two-vector blocks, unique over the whole solve
+    int step = 1;  // host step index of the Arnoldi blocks, unique over the whole solve
     for (;;) {
         hipLaunchKernelGGL(ls_zero_counters, dim3(1), dim3(1), 0, st, A.counters);
         hipLaunchKernelGGL(ls_residual_kernel, ge, be, 0, st, A);
@@ -1031,22 +1128,11 @@ static int ls_solve_p(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m
         if (fn) fn(user, done_before + (A.count - h[0]), total);
         if (h[0] == 0) break;
         hipLaunchKernelGGL((ls_cycle_init_kernel<P>), gr, be, 0, st, A);
-        const size_t dyn = sizeof(double) * 2 * (size_t)(max_m + 4);
-        for (int j = 0; A.block == 2 && j < max_m; j += 2, ++step) {
-            hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, 0);
-            hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, 1);
-            hipLaunchKernelGGL((ls_multidot2_kernel<P>), gr, be, 0, st, A);
-            hipLaunchKernelGGL(ls_reduce_kernel, gi, be, 0, st, A, 1);
-            hipLaunchKernelGGL((ls_update2_kernel<P>), gr, be, 0, st, A);
-            hipLaunchKernelGGL(ls_block_givens_kernel, gi, dim3(64), dyn, st, A, step);
-            hipLaunchKernelGGL((ls_normalize2_kernel<P>), gr, be, 0, st, A, step);
-            if ((j & 7) == 6) {  // every 8 steps: stop early once every cycle has ended
-                DG_HIP_CHECK(hipMemcpyAsync(h, A.counters, sizeof(h), hipMemcpyDeviceToHost, st));
-                DG_HIP_CHECK(hipStreamSynchronize(st));
-                if (h[1] <= 0) break;
-            }
-        }
-        for (int j = 0; A.block != 2 && j < max_m; ++j) {
+        const int rb = A.block == 2   ? ls_block_steps<P, 2>(A, ge, gr, gi, be, max_m, step, h, st)
+                       : A.block == 3 ? ls_block_steps<P, 3>(A, ge, gr, gi, be, max_m, step, h, st)
+                                      : DG_OK;
+        if (rb != DG_OK) return rb;
+        for (int j = 0; A.block == 1 && j < max_m; ++j) {
             hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, 0);
             hipLaunchKernelGGL((ls_multidot_kernel<P>), gr, be, 0, st, A);
             hipLaunchKernelGGL(ls_reduce_kernel, gi, be, 0, st, A, 0);
