@@ -344,6 +344,46 @@ __global__ __launch_bounds__(LS_BT) void ls_cycle_init_kernel(const LsArgs A)
 // Arnoldi step kernels
 // ---------------------------------------------------------------------------
 // w = Ahat v_J, or with second = 1 the two-vector block's w1 = Ahat w
+// Row j of element el of Ahat v for blocks of N <= 6: a triangle has at most
+// three neighbours, and the loads of all three are issued before the first
+// product (absent ones read the row `own`, which always exists, and are not
+// added); the sums keep the neighbour order.
+template <typename P, int N>
+__device__ __forceinline__ double ls_spmv_row(const P* Ah, const int32_t* rp, const int32_t* ci, const P* v,
+                                              const P* own, int64_t el, int j)
+{
+    const int s0 = rp[el], s1 = rp[el + 1];
+    const int64_t c0 = (int64_t)s0 - el;
+    double s = (double)v[el * N + j];
+    constexpr int NB = 3;
+    const int nb = s1 - s0 - 1;
+    P bl[NB][N], xx[NB][N];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const bool has = q < nb;
+        const P* blk = has ? Ah + ((c0 + q) * N + j) * N : own;
+        const P* xv = has ? v + (int64_t)ci[s0 + 1 + q] * N : v + el * N;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            bl[q][c] = blk[c];
+            xx[q][c] = xv[c];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        if (q < nb) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) s += (double)bl[q][c] * (double)xx[q][c];
+        }
+    for (int sl = s0 + 1 + NB; sl < s1; ++sl) {  // not reached on triangle meshes
+        const P* blk = Ah + ((c0 + (sl - s0 - 1)) * N + j) * N;
+        const P* xv = v + (int64_t)ci[sl] * N;
+#pragma unroll
+        for (int c = 0; c < N; ++c) s += (double)blk[c] * (double)xv[c];
+    }
+    return s;
+}
+
 template <typename P>
 __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src)
 {
@@ -359,13 +399,22 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src)
     const P* v = src == 0 ? (const P*)A.V + I.v_off + (int64_t)S.J * I.n
                           : (const P*)(src == 1 ? A.w : A.w1) + I.x_off;
     const P* Ah = (const P*)A.Ahat + I.ahat_off;
-    const int s0 = rp[e.el], s1 = rp[e.el + 1];
-    const int64_t c0 = (int64_t)s0 - e.el;
-    double s = (double)v[e.el * N + e.j];
-    for (int sl = s0 + 1; sl < s1; ++sl) {
-        const P* blk = Ah + ((c0 + (sl - s0 - 1)) * N + e.j) * N;
-        const P* xv = v + (int64_t)ci[sl] * N;
-        for (int c = 0; c < N; ++c) s += (double)blk[c] * (double)xv[c];
+    const P* own = (const P*)A.DinvP + I.dinv_off + (e.el * N + e.j) * N;  // a row that always exists
+    double s;
+    switch (N) {  // uniform over the workgroup: one instance per element block
+    case 1: s = ls_spmv_row<P, 1>(Ah, rp, ci, v, own, e.el, e.j); break;
+    case 3: s = ls_spmv_row<P, 3>(Ah, rp, ci, v, own, e.el, e.j); break;
+    case 6: s = ls_spmv_row<P, 6>(Ah, rp, ci, v, own, e.el, e.j); break;
+    default: {
+        const int s0 = rp[e.el], s1 = rp[e.el + 1];
+        const int64_t c0 = (int64_t)s0 - e.el;
+        s = (double)v[e.el * N + e.j];
+        for (int sl = s0 + 1; sl < s1; ++sl) {
+            const P* blk = Ah + ((c0 + (sl - s0 - 1)) * N + e.j) * N;
+            const P* xv = v + (int64_t)ci[sl] * N;
+            for (int c = 0; c < N; ++c) s += (double)blk[c] * (double)xv[c];
+        }
+    }
     }
     ((P*)(src == 0 ? A.w : src == 1 ? A.w1 : A.w2))[I.x_off + e.el * N + e.j] = (P)s;
 }
