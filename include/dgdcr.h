@@ -213,7 +213,9 @@ typedef struct {
     int32_t mixed;        /* 0: FP64 cycles; 1: FP32 cycles + FP64 refinement */
     double inner_tol;     /* mixed only: per-cycle relative reduction target (e.g. 1e-5) */
     int32_t reorth;       /* 1: second classical Gram-Schmidt pass when the first loses > 1/sqrt(2) of the norm */
-    int32_t profile;      /* 1: time the heavy kernels with HIP events on the solve stream (dg_solver_profile) */
+    int32_t profile;      /* 1: time the heavy kernels with HIP events on the solve stream (dg_solver_profile);
+                             2: only the Gram-Schmidt dot kernel (two events per launch instead of ten per
+                             block, for timing the solve with its dominant kernel); DG_ERR_ARG above 2 */
     double guess_limit;   /* the initial guess is replaced by zero when ||F - A x0|| > guess_limit ||F||
                              or is not finite; <= 0 selects 1 + 1e-8 (no worse than the zero guess;
                              the margin absorbs the rounding of the two norms); +inf keeps any finite guess */

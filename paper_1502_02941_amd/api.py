@@ -416,7 +416,7 @@ class Solver:
         self.mesh = mesh
         pers = {"auto": 0, True: 1, False: -1}[persistent]
         o = _SolverOpts(int(restart), int(max_iters), float(rel_tol), int(bool(mixed)), float(inner_tol),
-                        int(bool(reorth)), int(bool(profile)), float(guess_limit), pers, int(block))
+                        int(bool(reorth)), int(profile), float(guess_limit), pers, int(block))
         h = C.c_void_p()
         _check(lib().dg_solver_create(mesh._h, C.byref(o), C.byref(h)), "dg_solver_create")
         self._h = h
@@ -434,7 +434,8 @@ class Solver:
         _check(lib().dg_solver_setup(self._h, _dptr(vals64), _stream(stream)), "dg_solver_setup")
 
     def profile(self, reset=False):
-        """{kernel: (launches, ms, bytes)} from the built-in profiler (profile=True)."""
+        """{kernel: (launches, ms, bytes)} from the built-in profiler (profile=True, or 2 for the
+        Gram-Schmidt dot kernel alone)."""
         arr = (_KStats * 16)()
         cnt = C.c_int32()
         _check(lib().dg_solver_profile(self._h, arr, 16, C.byref(cnt), int(bool(reset))), "dg_solver_profile")

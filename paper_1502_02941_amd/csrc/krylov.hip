@@ -1109,7 +1109,7 @@ static hipEvent_t prof_event(dg_solver* s)
 // brackets one launch: returns true if recording (call prof_end after the launch)
 static bool prof_begin(dg_solver* s, hipStream_t st, int cls, double bytes, int j, int pass)
 {
-    if (!s->o.profile) return false;
+    if (!s->o.profile || (s->o.profile == 2 && cls != PK_MULTIDOT)) return false;
     dg_solver::Rec r{cls, bytes, j, pass, prof_event(s), prof_event(s)};
     if (!r.e0 || !r.e1) return false;
     hipEventRecord(r.e0, st);
@@ -1162,7 +1162,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     if (o->restart < 1 || o->restart > 4096 || o->max_iters < 0 || !(o->rel_tol > 0) || (o->mixed != 0 && o->mixed != 1))
         return DG_ERR_ARG;
     if (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)) return DG_ERR_ARG;
-    if (o->persistent < -1 || o->persistent > 1) return DG_ERR_ARG;
+    if (o->persistent < -1 || o->persistent > 1 || o->profile < 0 || o->profile > 2) return DG_ERR_ARG;
     if (o->block < 0 || o->block > BS_MAX || (o->block > 1 && o->reorth)) return DG_ERR_ARG;
     dg_solver* s = new (std::nothrow) dg_solver();
     if (!s) return DG_ERR_OOM;
