@@ -440,3 +440,28 @@ def test_two_vector_blocks_reject_reorth(api):
         with pytest.raises(api.DGError):
             api.Solver(mesh, restart=20, block=bad)
     api.Solver(mesh, restart=20, reorth=True)  # automatic: one vector per pass with reorth
+
+
+def test_profile_levels(api):
+    """opts.profile: 1 times every heavy kernel class, 2 the Gram-Schmidt dot
+    kernel alone (the solve is the same: equal iterations and residual);
+    other values are rejected."""
+    case = SOLVE_CASES[0]
+    mesh = api.Mesh.from_arrays(case.mesh, case.k)
+    vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
+    out = {}
+    for level in (1, 2):
+        s = api.Solver(mesh, restart=40, rel_tol=1e-10, persistent=False, profile=level)
+        s.setup(vals)
+        x = torch.zeros_like(rhs)
+        rep = s.solve(rhs, x)
+        kern = {k: v for k, v in s.profile(reset=True).items() if v[0] > 0}
+        out[level] = (rep.iters, rep.rel_res, kern)
+        _say("  profile %d: %d its, classes %s" % (level, rep.iters, sorted(kern)))
+    assert out[1][0] == out[2][0] and out[1][1] == out[2][1]
+    assert {"spmv_hat", "multidot", "update"} <= set(out[1][2])
+    assert set(out[2][2]) == {"multidot"}
+    assert out[2][2]["multidot"][0] == out[1][2]["multidot"][0]
+    for bad in (-1, 3):
+        with pytest.raises(api.DGError):
+            api.Solver(mesh, restart=40, profile=bad)
