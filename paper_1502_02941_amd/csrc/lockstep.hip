@@ -637,6 +637,41 @@ __global__ __launch_bounds__(LS_BT) void ls_normalize_kernel(const LsArgs A)
 // ---------------------------------------------------------------------------
 constexpr int LS_CT2 = 8;  // columns per tile of the block dot kernel
 
+// Sums NV per-lane values over the 64 lanes of a wave: while the count is even
+// each exchange step keeps half of them (the half picked by the step's lane
+// bit) and adds the partner's copy of that half, so the work halves per step;
+// the rest are summed over the remaining lane bits.  On return lanes with
+// (lane & full) == 0 hold the totals of values base .. base + n - 1 in a[0..n).
+template <int NV>
+__device__ __forceinline__ void ls_butterfly_sum(double (&a)[NV], int lane, int& base, int& n, int& full)
+{
+    base = 0;
+    n = NV;
+    full = 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        if (n % 2 == 0) {
+            const int half = n / 2;
+            const bool up = (lane & o) != 0;
+#pragma unroll
+            for (int i = 0; i < NV / 2; ++i) {
+                if (i < half) {
+                    const double send = up ? a[i] : a[half + i];
+                    const double recv = __shfl_xor(send, o);
+                    a[i] = (up ? a[half + i] : a[i]) + recv;
+                }
+            }
+            if (up) base += half;
+            n = half;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i < n) a[i] += __shfl_xor(a[i], o);
+            full |= o;
+        }
+    }
+}
+
 template <typename P>
 __device__ __forceinline__ P* ls_block_vec(const LsArgs& A, int r)
 {
@@ -682,13 +717,18 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot_block_kernel(const LsArgs A
                 for (int q = 0; q < S; ++q) a[q][c] += v * x[q];
             }
         }
+        double flat[S * LS_CT2];
 #pragma unroll
         for (int q = 0; q < S; ++q)
 #pragma unroll
-            for (int c = 0; c < LS_CT2; ++c) {
-                const double v = ls_wave_sum(a[q][c]);
-                if (lane == 0) sh[wave][q * LS_CT2 + c] = v;
-            }
+            for (int c = 0; c < LS_CT2; ++c) flat[q * LS_CT2 + c] = a[q][c];
+        int base, nv, full;
+        ls_butterfly_sum<S * LS_CT2>(flat, lane, base, nv, full);
+        if ((lane & full) == 0) {
+#pragma unroll
+            for (int k = 0; k < S * LS_CT2; ++k)
+                if (k < nv) sh[wave][base + k] = flat[k];
+        }
         __syncthreads();
         if (threadIdx.x < S * LS_CT2) {
             const int rr = threadIdx.x / LS_CT2, c = threadIdx.x - rr * LS_CT2;
