@@ -485,6 +485,41 @@ struct BlockVecs {
 // with three 16 and 2048 took 12% less than 8 and 4096 (each block re-reads
 // its S vectors once per tile), and four vectors were within 2% either way.
 constexpr int md_block_ct(int S) { return S == 3 ? 16 : 8; }
+
+// Sums NV per-lane values over the 64 lanes of a wave: while the count is even
+// each exchange step keeps half of them (the half picked by the step's lane
+// bit) and adds the partner's copy of that half, so the work halves per step;
+// the rest are summed over the remaining lane bits.  On return lanes with
+// (lane & full) == 0 hold the totals of values base .. base + n - 1 in a[0..n).
+template <int NV>
+__device__ __forceinline__ void wave_butterfly_sum(double (&a)[NV], int lane, int& base, int& n, int& full)
+{
+    base = 0;
+    n = NV;
+    full = 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        if (n % 2 == 0) {
+            const int half = n / 2;
+            const bool up = (lane & o) != 0;
+#pragma unroll
+            for (int i = 0; i < NV / 2; ++i) {
+                if (i < half) {
+                    const double send = up ? a[i] : a[half + i];
+                    const double recv = __shfl_xor(send, o);
+                    a[i] = (up ? a[half + i] : a[i]) + recv;
+                }
+            }
+            if (up) base += half;
+            n = half;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i < n) a[i] += __shfl_xor(a[i], o);
+            full |= o;
+        }
+    }
+}
 constexpr int md_block_target(int S) { return S == 3 ? 2048 : 4096; }
 template <typename P, int S>
 __global__ __launch_bounds__(BLK) void multidot_block_kernel(const P* __restrict__ V, BlockVecs<P> W, int64_t n,
@@ -521,13 +556,28 @@ __global__ __launch_bounds__(BLK) void multidot_block_kernel(const P* __restrict
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if constexpr (S <= 3) {  // (at S = 4 the exchanges' indexing spills to scratch)
+        double flat[S * CT2];
 #pragma unroll
-    for (int q = 0; q < S; ++q)
+        for (int q = 0; q < S; ++q)
 #pragma unroll
-        for (int c = 0; c < CT2; ++c) {
-            const double v = wave_sum(a[q][c]);
-            if (lane == 0) sh[wave][q * CT2 + c] = v;
+            for (int c = 0; c < CT2; ++c) flat[q * CT2 + c] = a[q][c];
+        int base, nv, full;
+        wave_butterfly_sum<S * CT2>(flat, lane, base, nv, full);
+        if ((lane & full) == 0) {
+#pragma unroll
+            for (int k = 0; k < S * CT2; ++k)
+                if (k < nv) sh[wave][base + k] = flat[k];
         }
+    } else {
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+#pragma unroll
+            for (int c = 0; c < CT2; ++c) {
+                const double v = wave_sum(a[q][c]);
+                if (lane == 0) sh[wave][q * CT2 + c] = v;
+            }
+    }
     __syncthreads();
     if (threadIdx.x < S * CT2) {
         const int rr = threadIdx.x / CT2, c = threadIdx.x - rr * CT2;
