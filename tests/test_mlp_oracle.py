@@ -1,4 +1,6 @@
 """Pins of the MLP oracle: finite differences, BF16 rounding, Adam's first step."""
+import math
+
 import numpy as np
 import pytest
 
@@ -46,3 +48,55 @@ def test_adam_first_step_is_signed_lr():
     g = np.array([0.3, -2.0, 1e-3])
     p, _, _ = OM.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=0.0)
     np.testing.assert_allclose(p, -0.01 * np.sign(g), rtol=1e-12)
+
+
+# A 2-3-2 network whose hidden pre-activations are ln 3, 0 and -ln 3, where
+# the logistic function takes the values 3/4, 1/2 and 1/4, so every value
+# below is worked out by hand from silu(z) = z / (1 + e^{-z}):
+#   x = (1, 2);  W1 = [[0.5, -0.25], [1, 1], [-2, 0.5]],  W1 x = (0, 3, -1)
+#   b1 = (ln 3, -3, 1 - ln 3)                 ->  z = (ln 3, 0, -ln 3)
+#   h = silu(z) = (3/4 ln 3, 0, -1/4 ln 3)      (no activation on the last layer)
+#   W2 = [[1, 5, 2], [-1, 0.5, 4]], b2 = (1/8, -1)
+#   y = W2 h + b2 = (1/4 ln 3 + 1/8, -7/4 ln 3 - 1)
+# Every input and weight is a BF16 number.  With BF16 rounding of the hidden
+# activations: 3/4 ln 3 = 0.8239592... = 1.6479184... * 2^-1 and 1.6479184 * 128
+# = 210.93 rounds to 211, so bf16(h_0) = 211/256; -1/4 ln 3 = -1.0986123 * 2^-2
+# and 1.0986123 * 128 = 140.62 rounds to 141, so bf16(h_2) = -141/512; then
+# y = (211/256 - 282/512 + 1/8, -211/256 - 564/512 - 1) = (0.3984375, -2.92578125).
+LN3 = math.log(3.0)
+HAND_WIDTHS = [2, 3, 2]
+HAND_X = np.array([[1.0, 2.0]])
+HAND_W1 = np.array([[0.5, -0.25], [1.0, 1.0], [-2.0, 0.5]])
+HAND_B1 = np.array([LN3, -3.0, 1.0 - LN3])
+HAND_W2 = np.array([[1.0, 5.0, 2.0], [-1.0, 0.5, 4.0]])
+HAND_B2 = np.array([0.125, -1.0])
+
+
+def _hand_params():
+    return np.concatenate([HAND_W1.ravel(), HAND_B1, HAND_W2.ravel(), HAND_B2])
+
+
+def test_forward_matches_hand_computed_network():
+    Y, (H, Z) = OM.forward(_hand_params(), HAND_WIDTHS, HAND_X, bf16_round=False)
+    np.testing.assert_allclose(Z[0], [[LN3, 0.0, -LN3]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(H[1], [[0.75 * LN3, 0.0, -0.25 * LN3]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Y, [[0.25 * LN3 + 0.125, -1.75 * LN3 - 1.0]], rtol=0, atol=1e-15)
+
+
+def test_bf16_forward_matches_hand_rounded_network():
+    Y, (H, _) = OM.forward(_hand_params(), HAND_WIDTHS, HAND_X, bf16_round=True)
+    assert H[1][0, 0] == 211.0 / 256.0 and H[1][0, 1] == 0.0 and H[1][0, 2] == -141.0 / 512.0
+    np.testing.assert_allclose(Y, [[0.3984375, -2.92578125]], rtol=0, atol=1e-15)
+
+
+def test_backward_matches_hand_computed_gradients():
+    """Gradients of y_0 (dY = (1, 0)) in closed form: dW2[0] = h, db2 = (1, 0),
+    dh = W2[0] = (1, 5, 2), dz = dh * silu'(z) with silu'(z) = s (1 + z (1 - s)),
+    s = 3/4, 1/2, 1/4; dW1 = dz x^T, db1 = dz."""
+    p = _hand_params()
+    Y, cache = OM.forward(p, HAND_WIDTHS, HAND_X, bf16_round=False)
+    g = OM.backward(p, HAND_WIDTHS, cache, np.array([[1.0, 0.0]]), bf16_round=False)
+    dz = np.array([0.75 * (1.0 + LN3 * 0.25), 5.0 * 0.5, 2.0 * 0.25 * (1.0 - LN3 * 0.75)])
+    want = np.concatenate([np.outer(dz, HAND_X[0]).ravel(), dz,
+                           np.array([[0.75 * LN3, 0.0, -0.25 * LN3], [0.0, 0.0, 0.0]]).ravel(), [1.0, 0.0]])
+    np.testing.assert_allclose(g, want, rtol=0, atol=1e-14)

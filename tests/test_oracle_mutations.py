@@ -103,3 +103,43 @@ def test_python_mutant_is_caught(name, tmp_path):
         assert r.returncode == 0, r.stdout[-2000:]
     else:
         assert r.returncode != 0, "mutant %s survived every pin:\n%s" % (name, r.stdout[-2000:])
+
+
+# Planted mistakes in the perceptron oracle (oracle/mlp.py): the pins of
+# tests/test_mlp_oracle.py (hand-computed network, closed-form gradients,
+# BF16 rounding, finite differences) must catch each.
+MLP_MUTANTS = {
+    "sigmoid_for_silu": ("return z / (1.0 + np.exp(-z))", "return 1.0 / (1.0 + np.exp(-z))"),
+    "bias_dropped": ("z = H[-1] @ r(W).T + b", "z = H[-1] @ r(W).T"),
+    "activation_on_last_layer": ("        if l < len(layers) - 1:\n            H.append(r(silu(z)))",
+                                 "        H.append(r(silu(z)))\n        Z[-1] = silu(z)"),
+    "silu_derivative_is_sigmoid_derivative": ("return s * (1.0 + z * (1.0 - s))", "return s * (1.0 - s)"),
+    "bf16_truncates": ("u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000", "u = u & 0xFFFF0000"),
+    "weight_gradient_uses_next_activation": ("grads.append((r(dz).T @ H[l], dz.sum(axis=0)))",
+                                             "grads.append((r(dz).T @ H[min(l + 1, len(H) - 1)], dz.sum(axis=0)))"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MLP_MUTANTS) + ["unchanged_copy"])
+def test_mlp_mutant_is_caught(name, tmp_path):
+    import shutil
+    old, new = MLP_MUTANTS.get(name, ("import numpy as np", "import numpy as np"))
+    pkg = os.path.join(ROOT, "oracle")
+    src = open(os.path.join(pkg, "mlp.py")).read()
+    assert src.count(old) == 1, "mutation anchor not found exactly once: %r" % old
+    dst = tmp_path / "oracle"
+    dst.mkdir()
+    for f in os.listdir(pkg):
+        if f.endswith((".c", ".so", ".py")) and f != "mlp.py":
+            shutil.copy(os.path.join(pkg, f), dst / f)
+    (dst / "mlp.py").write_text(src.replace(old, new))
+    code = ("import sys; sys.path.insert(0, %r); import oracle.mlp; assert oracle.mlp.__file__.startswith(%r); "
+            "sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main([%r, '-x', '-q', '-p', 'no:cacheprovider']))"
+            % (str(tmp_path), str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_mlp_oracle.py")))
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True, text=True, timeout=600)
+    assert "passed" in r.stdout or "failed" in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]
+    if name == "unchanged_copy":
+        assert r.returncode == 0, r.stdout[-2000:]
+    else:
+        assert r.returncode != 0, "mutant %s survived every pin:\n%s" % (name, r.stdout[-2000:])
