@@ -268,6 +268,15 @@ int32_t dg_solver_setup(dg_solver* solver, const double* dev_vals64, void* strea
 int32_t dg_solver_solve(dg_solver* solver, const double* dev_rhs, double* dev_x, dg_solve_report* report,
                         void* stream);
 void dg_solver_destroy(dg_solver* solver);
+/* The right block-Jacobi preconditioner of the last dg_solver_setup, for
+ * inspection: dev_dinv64 [n_elems][n_loc][n_loc] (FP64) receives the inverse
+ * of every diagonal block of A (M = blockdiag(A), section 2.3 eq. (system)),
+ * row-major; dev_ahat [nnzb - n_elems][n_loc][n_loc] receives A M^{-1}
+ * without its identity diagonal blocks, block rows in order and the
+ * neighbour blocks of a row in the BSR order (block (K, L) = A_KL M_L^{-1}),
+ * in the cycle precision (FP64, or FP32 when opts.mixed).  Either may be
+ * NULL.  Stream-ordered copies; DG_ERR_ARG before a successful setup. */
+int32_t dg_solver_preconditioner(dg_solver* solver, double* dev_dinv64, void* dev_ahat, void* stream);
 
 /* Per-kernel statistics gathered when opts.profile = 1: for each heavy kernel
  * of the solve (spmv_hat, multidot, update, residual64, combine), the number
@@ -433,6 +442,18 @@ int32_t dg_batch_set_progress(dg_batch* batch, dg_progress_fn fn, void* user);
 /* Number of instances the running (or last) dg_batch_run has started, read
  * with a copy on a separate non-blocking stream while the launch runs. */
 int32_t dg_batch_progress(dg_batch* batch, int32_t* started);
+/* Instance `instance` of the last dg_batch_run, for inspection.
+ * dg_batch_system copies its FP64 BSR values (dev_vals64 [nnzb][n_loc][n_loc],
+ * the layout of dg_assemble on the instance's mesh) and load vector
+ * (dev_rhs [n_dofs]); either may be NULL.  dg_batch_preconditioner writes its
+ * block-Jacobi preconditioner in the layout of dg_solver_preconditioner
+ * (dev_dinv64 FP64, dev_ahat in the cycle precision), recomputed from those
+ * FP64 values by the same kernels as the path that solved it (the persistent
+ * workgroup's setup, or the lockstep setup launch of its chunk, which also
+ * rewrites the chunk's own copies with the same values).  Stream-ordered;
+ * DG_ERR_ARG for an index out of range or before the first dg_batch_run. */
+int32_t dg_batch_system(const dg_batch* batch, int32_t instance, double* dev_vals64, double* dev_rhs, void* stream);
+int32_t dg_batch_preconditioner(dg_batch* batch, int32_t instance, double* dev_dinv64, void* dev_ahat, void* stream);
 void dg_batch_destroy(dg_batch* batch);
 
 /* ------------------------------------------------------------------------

@@ -110,7 +110,8 @@ EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_create_basis", "dg_m
            "dg_batch_set_progress", "dg_mlp_create", "dg_mlp_num_params", "dg_mlp_forward", "dg_mlp_loss_mse",
            "dg_mlp_backward", "dg_mlp_adam_step", "dg_mlp_params", "dg_mlp_destroy", "dg_warmstart_prolong",
            "dg_mesh_error_points", "dg_l2_error", "dg_reaction_terms", "dg_newton_solve", "dg_mesh_refine_sizes",
-           "dg_mesh_refine", "dg_implicit_euler", "dg_euler_rhs"]
+           "dg_mesh_refine", "dg_implicit_euler", "dg_euler_rhs", "dg_solver_preconditioner", "dg_batch_system",
+           "dg_batch_preconditioner"]
 
 _lib = None
 
@@ -165,6 +166,9 @@ def lib():
                                       C.POINTER(_NewtonReport), P]
         L.dg_implicit_euler.argtypes = [P, P, P, P, P, P, D, I32, P, C.POINTER(_EulerReport), P]
         L.dg_euler_rhs.argtypes = [P, P, P, D, P, P]
+        L.dg_solver_preconditioner.argtypes = [P, P, P, P]
+        L.dg_batch_system.argtypes = [P, I32, P, P, P]
+        L.dg_batch_preconditioner.argtypes = [P, I32, P, P, P]
         L.dg_batch_destroy.argtypes = [P]
         L.dg_batch_destroy.restype = None
         L.dg_status_str.argtypes = [I32]
@@ -421,6 +425,7 @@ class Solver:
         _check(lib().dg_solver_create(mesh._h, C.byref(o), C.byref(h)), "dg_solver_create")
         self._h = h
         self._vals = None
+        self.mixed = bool(mixed)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -440,6 +445,17 @@ class Solver:
         cnt = C.c_int32()
         _check(lib().dg_solver_profile(self._h, arr, 16, C.byref(cnt), int(bool(reset))), "dg_solver_profile")
         return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes) for i in range(cnt.value)}
+
+    def preconditioner(self, stream=None):
+        """dg_solver_preconditioner: (D^-1 [T, n, n] FP64, A D^-1 without its
+        identity blocks [nnzb - T, n, n] in the cycle precision)."""
+        m = self.mesh
+        dinv = torch.empty(m.T, m.n_loc, m.n_loc, dtype=torch.float64, device="cuda")
+        ahat = torch.empty(max(m.nnzb - m.T, 0), m.n_loc, m.n_loc, dtype=torch.float32 if self.mixed else torch.float64,
+                           device="cuda")
+        _check(lib().dg_solver_preconditioner(self._h, _dptr(dinv), _dptr(ahat) if ahat.numel() else None,
+                                              _stream(stream)), "dg_solver_preconditioner")
+        return dinv, ahat
 
     def solve(self, rhs: torch.Tensor, x: torch.Tensor, stream=None) -> Report:
         r = _Report()
@@ -471,6 +487,7 @@ class Batch:
                  lockstep_mem_gb=64.0, guess_limit=0.0, log=None, lockstep_block=0):
         L = lib()
         self.count = len(instances)
+        self.mixed = bool(mixed)
         arr = (_Instance * self.count)()
         self._keep = []
         for i, (m, prob) in enumerate(instances):
@@ -549,6 +566,24 @@ class Batch:
                     last_v = v
                 last_t = now
         ev.synchronize()
+
+    def system(self, i, n_loc, nnzb, stream=None):
+        """dg_batch_system: FP64 BSR values [nnzb, n_loc, n_loc] and load vector of instance i."""
+        n = int(self.offsets[i + 1] - self.offsets[i])
+        vals = torch.empty(nnzb, n_loc, n_loc, dtype=torch.float64, device="cuda")
+        rhs = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(lib().dg_batch_system(self._h, int(i), _dptr(vals), _dptr(rhs), _stream(stream)), "dg_batch_system")
+        return vals, rhs
+
+    def preconditioner(self, i, n_loc, nnzb, stream=None):
+        """dg_batch_preconditioner: (D^-1 FP64, A D^-1 off-diagonal blocks in the cycle precision) of instance i."""
+        T = int(self.offsets[i + 1] - self.offsets[i]) // n_loc
+        dinv = torch.empty(T, n_loc, n_loc, dtype=torch.float64, device="cuda")
+        ahat = torch.empty(max(nnzb - T, 1), n_loc, n_loc, dtype=torch.float32 if self.mixed else torch.float64,
+                           device="cuda")
+        _check(lib().dg_batch_preconditioner(self._h, int(i), _dptr(dinv), _dptr(ahat), _stream(stream)),
+               "dg_batch_preconditioner")
+        return dinv, ahat[:max(nnzb - T, 0)]
 
     @staticmethod
     def reports(rep: torch.Tensor):

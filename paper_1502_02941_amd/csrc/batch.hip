@@ -168,6 +168,73 @@ __device__ __forceinline__ bool invert_rows(double (&m)[N], const int r, const i
     return ok;
 }
 
+// 2a. Block-Jacobi setup of one instance by the whole workgroup, lane =
+// (element, row): the FP64 inverse of every diagonal block into Dinv64, then
+// A D^{-1} without its identity diagonal blocks into Ahat ([nnzb - T][N][N],
+// block row order) and D^{-1} into DinvP (skipped when null), both in the
+// cycle precision P.  Returns false, uniformly over the workgroup, when a
+// pivot of some block was zero or not finite (Ahat is then not formed).
+template <int K, typename P, int BT>
+__device__ bool batch_setup(const double* __restrict__ A64, const int32_t* __restrict__ rp,
+                            const int32_t* __restrict__ ci, const int64_t T, double* __restrict__ Dinv64,
+                            P* __restrict__ Ahat, P* __restrict__ DinvP, BatchSmem<BT>& sm)
+{
+    constexpr int N = (K + 1) * (K + 2) / 2, EPW = 64 / N, WPB = BT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int e_in = lane / N, jj = lane - e_in * N;
+    const bool lane_ok = e_in < EPW;
+    if (tid == 0) sm.flag[1] = 0;
+    __syncthreads();
+    for (int64_t e0 = 0; e0 < T; e0 += (int64_t)WPB * EPW) {
+        const int64_t el = e0 + wave * EPW + e_in;
+        const bool act = lane_ok && el < T;
+        double mrow[N];
+        const double* D = A64 + ((int64_t)(act ? rp[el] : 0) * N + jj) * N;
+#pragma unroll
+        for (int q = 0; q < N; ++q) mrow[q] = act ? D[q] : (q == jj ? 1.0 : 0.0);
+        int lr;
+        // every lane of the wavefront takes part in the shuffles; idle lanes invert the identity
+        const bool ok = invert_rows<N>(mrow, jj, lane_ok ? e_in * N : (lane / N) * N, lr);
+        if (act) {
+            if (!ok) sm.flag[1] = 1;
+            double* o = Dinv64 + (el * N + lr) * N;
+#pragma unroll
+            for (int q = 0; q < N; ++q) o[q] = mrow[q];
+        }
+    }
+    __syncthreads();
+    if (sm.flag[1]) return false;  // the flag is next written after the caller's next barrier
+    for (int64_t e0 = 0; e0 < T; e0 += (int64_t)WPB * EPW) {
+        const int64_t el = e0 + wave * EPW + e_in;
+        if (!(lane_ok && el < T)) continue;
+        const int i = jj;
+        const int s0 = rp[el], s1 = rp[el + 1];
+        const int64_t c0 = (int64_t)s0 - el;
+        for (int sl = s0 + 1; sl < s1; ++sl) {
+            const double* arow = A64 + ((int64_t)sl * N + i) * N;
+            const double* d = Dinv64 + (int64_t)ci[sl] * N * N;
+            P* out = Ahat + ((c0 + (sl - s0 - 1)) * N + i) * N;
+            double ar[N];
+#pragma unroll
+            for (int k2 = 0; k2 < N; ++k2) ar[k2] = arow[k2];
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) s += ar[k2] * d[k2 * N + c];
+                out[c] = (P)s;
+            }
+        }
+        if (DinvP) {
+            const double* dd = Dinv64 + (el * N + i) * N;
+#pragma unroll
+            for (int c = 0; c < N; ++c) DinvP[(el * N + i) * N + c] = (P)dd[c];
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
 template <int K, typename P, int BT>
 __device__ void run_instance(const BatchArgs& A, const BatchInst& I, const int id, const SlotPtrs& S,
                              BatchSmem<BT>& sm)
@@ -189,28 +256,8 @@ __device__ void run_instance(const BatchArgs& A, const BatchInst& I, const int i
 
     const double* A64 = A.A64 + I.val_off;
     const double* rhs = A.rhs + I.x_off;
-    if (tid == 0) sm.flag[1] = 0;
-    __syncthreads();
-    // ---- 2. block-Jacobi setup: lane (element, row) ----
-    for (int64_t e0 = 0; e0 < T; e0 += (int64_t)WPB * EPW) {
-        const int64_t el = e0 + wave * EPW + e_in;
-        const bool act = lane_ok && el < T;
-        double mrow[N];
-        const double* D = A64 + ((int64_t)(act ? rp[el] : 0) * N + jj) * N;
-#pragma unroll
-        for (int q = 0; q < N; ++q) mrow[q] = act ? D[q] : (q == jj ? 1.0 : 0.0);
-        int lr;
-        // every lane of the wavefront takes part in the shuffles; idle lanes invert the identity
-        const bool ok = invert_rows<N>(mrow, jj, lane_ok ? e_in * N : (lane / N) * N, lr);
-        if (act) {
-            if (!ok) sm.flag[1] = 1;
-            double* o = S.Dinv64 + (el * N + lr) * N;
-#pragma unroll
-            for (int q = 0; q < N; ++q) o[q] = mrow[q];
-        }
-    }
-    __syncthreads();
-    if (sm.flag[1]) {
+    // ---- 2. block-Jacobi setup ----
+    if (!batch_setup<K, P, BT>(A64, rp, ci, T, S.Dinv64, (P*)S.Ahat, DinvP, sm)) {
         if (tid == 0) {
             dg_solve_report r{};
             r.status = DG_ERR_NONFINITE;
@@ -219,32 +266,6 @@ __device__ void run_instance(const BatchArgs& A, const BatchInst& I, const int i
         __syncthreads();
         return;
     }
-    for (int64_t e0 = 0; e0 < T; e0 += (int64_t)WPB * EPW) {
-        const int64_t el = e0 + wave * EPW + e_in;
-        if (!(lane_ok && el < T)) continue;
-        const int i = jj;
-        const int s0 = rp[el], s1 = rp[el + 1];
-        const int64_t c0 = (int64_t)s0 - el;
-        for (int sl = s0 + 1; sl < s1; ++sl) {
-            const double* arow = A64 + ((int64_t)sl * N + i) * N;
-            const double* d = S.Dinv64 + (int64_t)ci[sl] * N * N;
-            P* out = (P*)S.Ahat + ((c0 + (sl - s0 - 1)) * N + i) * N;
-            double ar[N];
-#pragma unroll
-            for (int k2 = 0; k2 < N; ++k2) ar[k2] = arow[k2];
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double s = 0.0;
-#pragma unroll
-                for (int k2 = 0; k2 < N; ++k2) s += ar[k2] * d[k2 * N + c];
-                out[c] = (P)s;
-            }
-        }
-        const double* dd = S.Dinv64 + (el * N + i) * N;
-#pragma unroll
-        for (int c = 0; c < N; ++c) DinvP[(el * N + i) * N + c] = (P)dd[c];
-    }
-    __syncthreads();
 
     // ---- 3. GMRES cycles ----
     double acc = 0.0;
@@ -472,6 +493,21 @@ __global__ __launch_bounds__(BT) void batch_kernel(const BatchArgs A)
     }
 }
 
+// The block-Jacobi setup of one persistent-path instance again, by the same
+// device function and on the same FP64 values, into caller buffers (the
+// slots keep only the last instance each ran).
+template <typename P, int BT>
+__global__ __launch_bounds__(BT) void batch_setup_kernel(const BatchArgs A, int id, double* Dinv64, P* Ahat)
+{
+    __shared__ BatchSmem<BT> sm;
+    const BatchInst& I = A.inst[id];
+    const double* A64 = A.A64 + I.val_off;
+    const int32_t* rp = A.row_ptr + I.rp_off;
+    const int32_t* ci = A.col_idx + I.ci_off;
+    if (I.k == 1) batch_setup<1, P, BT>(A64, rp, ci, I.T, Dinv64, Ahat, (P*)nullptr, sm);
+    else batch_setup<2, P, BT>(A64, rp, ci, I.T, Dinv64, Ahat, (P*)nullptr, sm);
+}
+
 __global__ void reset_queue_kernel(int* q) { __hip_atomic_store(q, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM); }
 
 }  // namespace dg
@@ -517,6 +553,12 @@ struct dg_batch {
     int* ls_counters = nullptr;
     dg_progress_fn progress_fn = nullptr;
     void* progress_user = nullptr;
+    // per instance: lockstep chunk (-1: persistent path) and offsets of its
+    // inverse diagonal blocks and A D^{-1} in the chunk buffers
+    std::vector<int32_t> where_chunk;
+    std::vector<int64_t> where_dinv, where_ahat;
+    std::vector<BatchInst> h_inst;  // host copy of d_inst
+    int64_t ran = 0;  // dg_batch_run calls so far
 };
 
 static void batch_free(dg_batch* b)
@@ -673,6 +715,7 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
     std::vector<double> t1 = build_tables(1, DG_BASIS_DUBINER), t2 = build_tables(2, DG_BASIS_DUBINER);
     int s = DG_OK;
     if (s == DG_OK) s = up(&b->d_inst, hinst.data(), hinst.size());
+    b->h_inst = hinst;
     if (s == DG_OK) s = up(&b->d_order, order.data(), order.size());
     if (s == DG_OK) s = up(&b->d_xy, xy.data(), xy.size());
     if (s == DG_OK) s = up(&b->d_nbr, nbr.data(), nbr.size());
@@ -752,6 +795,9 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
     }
     if (s == DG_OK && b->nslots > 0) s = up(&b->d_slots, slots.data(), slots.size());
     // lockstep chunks: cost order, greedy under the memory budget
+    b->where_chunk.assign(count, -1);
+    b->where_dinv.assign(count, 0);
+    b->where_ahat.assign(count, 0);
     if (s == DG_OK && !lock.empty()) {
         const double budget = (o->lockstep_mem_gb > 0 ? o->lockstep_mem_gb : 64.0) * 1e9;
         // partials, projections and Gram sums sized for blocks of lsb vectors
@@ -793,6 +839,9 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
                 max_m = std::max(max_m, (int)I.m);
                 bytes += add;
                 li.push_back(L);
+                b->where_chunk[id] = (int32_t)b->chunks.size();
+                b->where_dinv[id] = L.dinv_off;
+                b->where_ahat[id] = L.ahat_off;
                 ++i1;
             }
             dg_batch::Chunk c;
@@ -846,10 +895,8 @@ extern "C" int32_t dg_batch_offsets(const dg_batch* b, int64_t* x_offsets)
     return DG_OK;
 }
 
-extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev_reports, void* stream)
+static BatchArgs batch_args(const dg_batch* b, double* dev_x, dg_solve_report* dev_reports)
 {
-    if (!b || !dev_x || !dev_reports) return DG_ERR_ARG;
-    hipStream_t st = (hipStream_t)stream;
     BatchArgs A;
     A.inst = b->d_inst;
     A.args = b->d_args;
@@ -868,9 +915,60 @@ extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev
     A.inner_tol = b->o.inner_tol;
     A.max_iters = b->o.max_iters;
     A.mixed = b->o.mixed;
+    return A;
+}
+
+static LsArgs ls_args(const dg_batch* b, const dg_batch::Chunk& c, double* dev_x, dg_solve_report* dev_reports)
+{
+    LsArgs L{};
+    L.count = c.count;
+    L.inst = c.d_inst;
+    L.state = c.d_state;
+    L.eblk = c.d_eblk;
+    L.rblk = c.d_rblk;
+    L.row_ptr = b->d_rp;
+    L.col_idx = b->d_ci;
+    L.A64 = b->d_A64;
+    L.rhs = b->d_rhs;
+    L.x = dev_x;
+    L.r = b->ls_r;
+    L.w = b->ls_w;
+    L.w1 = b->ls_w1;
+    L.w2 = b->ls_w2;
+    L.Hr = b->ls_Hr;
+    L.block = b->o.lockstep_block == 0 ? 3 : b->o.lockstep_block;
+    L.V = b->ls_V;
+    L.Ahat = b->ls_Ahat;
+    L.DinvP = b->ls_DinvP;
+    L.Dinv64 = b->ls_Dinv64;
+    L.part = b->ls_part;
+    L.red = b->ls_red;
+    L.red2 = b->ls_red2;
+    L.hcol = b->ls_hcol;
+    L.H = b->ls_H;
+    L.cs = b->ls_cs;
+    L.sn = b->ls_sn;
+    L.g = b->ls_g;
+    L.y = b->ls_y;
+    L.reports = dev_reports;
+    L.counters = b->ls_counters;
+    L.rel_tol = b->o.rel_tol;
+    L.guess_limit = guess_limit_of(b->o.guess_limit);
+    L.inner_tol = b->o.inner_tol;
+    L.max_iters = b->o.max_iters;
+    L.mixed = b->o.mixed;
+    return L;
+}
+
+extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev_reports, void* stream)
+{
+    if (!b || !dev_x || !dev_reports) return DG_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const BatchArgs A = batch_args(b, dev_x, dev_reports);
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, st, b->d_queue);
     hipLaunchKernelGGL(batch_assemble_kernel, dim3((unsigned)b->total_blocks), dim3(256), 0, st,
                        (const BatchInst*)b->d_inst, (const AsmArgs*)b->d_args, b->count, b->d_A64, b->d_rhs);
+    b->ran++;
     const int bt = b->o.block_threads ? b->o.block_threads : 512;
     if (b->n_persistent > 0) {
         if (b->o.mixed) {
@@ -884,43 +982,7 @@ extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev
     }
     int done = 0;
     for (auto& c : b->chunks) {
-        LsArgs L{};
-        L.count = c.count;
-        L.inst = c.d_inst;
-        L.state = c.d_state;
-        L.eblk = c.d_eblk;
-        L.rblk = c.d_rblk;
-        L.row_ptr = b->d_rp;
-        L.col_idx = b->d_ci;
-        L.A64 = b->d_A64;
-        L.rhs = b->d_rhs;
-        L.x = dev_x;
-        L.r = b->ls_r;
-        L.w = b->ls_w;
-        L.w1 = b->ls_w1;
-        L.w2 = b->ls_w2;
-        L.Hr = b->ls_Hr;
-        L.block = b->o.lockstep_block == 0 ? 3 : b->o.lockstep_block;
-        L.V = b->ls_V;
-        L.Ahat = b->ls_Ahat;
-        L.DinvP = b->ls_DinvP;
-        L.Dinv64 = b->ls_Dinv64;
-        L.part = b->ls_part;
-        L.red = b->ls_red;
-        L.red2 = b->ls_red2;
-        L.hcol = b->ls_hcol;
-        L.H = b->ls_H;
-        L.cs = b->ls_cs;
-        L.sn = b->ls_sn;
-        L.g = b->ls_g;
-        L.y = b->ls_y;
-        L.reports = dev_reports;
-        L.counters = b->ls_counters;
-        L.rel_tol = b->o.rel_tol;
-        L.guess_limit = guess_limit_of(b->o.guess_limit);
-        L.inner_tol = b->o.inner_tol;
-        L.max_iters = b->o.max_iters;
-        L.mixed = b->o.mixed;
+        const LsArgs L = ls_args(b, c, dev_x, dev_reports);
         int r = ls_init(L, st);
         if (r == DG_OK) r = ls_solve(L, c.n_eblk, c.n_rblk, c.max_m, b->o.mixed, st, b->progress_fn, b->progress_user,
                                      done, b->count - b->n_persistent);
@@ -928,6 +990,63 @@ extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev
         done += c.count;
     }
     return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
+}
+
+extern "C" int32_t dg_batch_system(const dg_batch* b, int32_t instance, double* dev_vals64, double* dev_rhs,
+                                   void* stream)
+{
+    if (!b || instance < 0 || instance >= b->count || b->ran == 0) return DG_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const BatchInst& I = b->h_inst[instance];
+    const int64_t N = (I.k + 1) * (I.k + 2) / 2;
+    if (dev_vals64)
+        DG_HIP_CHECK(hipMemcpyAsync(dev_vals64, b->d_A64 + I.val_off, sizeof(double) * I.nnzb * N * N,
+                                    hipMemcpyDeviceToDevice, st));
+    if (dev_rhs)
+        DG_HIP_CHECK(hipMemcpyAsync(dev_rhs, b->d_rhs + I.x_off, sizeof(double) * I.T * N, hipMemcpyDeviceToDevice, st));
+    return DG_OK;
+}
+
+extern "C" int32_t dg_batch_preconditioner(dg_batch* b, int32_t instance, double* dev_dinv64, void* dev_ahat,
+                                           void* stream)
+{
+    if (!b || instance < 0 || instance >= b->count || b->ran == 0 || !dev_dinv64 || !dev_ahat) return DG_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const BatchInst& I = b->h_inst[instance];
+    const int64_t N = (I.k + 1) * (I.k + 2) / 2;
+    const size_t ps = b->o.mixed ? sizeof(float) : sizeof(double);
+    const int ci = b->where_chunk[instance];
+    if (ci < 0) {
+        const BatchArgs A = batch_args(b, nullptr, nullptr);
+        const int bt = b->o.block_threads ? b->o.block_threads : 512;
+        if (b->o.mixed) {
+            if (bt == 256)
+                hipLaunchKernelGGL((batch_setup_kernel<float, 256>), dim3(1), dim3(256), 0, st, A, instance, dev_dinv64,
+                                   (float*)dev_ahat);
+            else
+                hipLaunchKernelGGL((batch_setup_kernel<float, 512>), dim3(1), dim3(512), 0, st, A, instance, dev_dinv64,
+                                   (float*)dev_ahat);
+        } else {
+            if (bt == 256)
+                hipLaunchKernelGGL((batch_setup_kernel<double, 256>), dim3(1), dim3(256), 0, st, A, instance,
+                                   dev_dinv64, (double*)dev_ahat);
+            else
+                hipLaunchKernelGGL((batch_setup_kernel<double, 512>), dim3(1), dim3(512), 0, st, A, instance,
+                                   dev_dinv64, (double*)dev_ahat);
+        }
+        DG_HIP_CHECK(hipGetLastError());
+        return DG_OK;
+    }
+    const dg_batch::Chunk& c = b->chunks[ci];
+    const LsArgs L = ls_args(b, c, nullptr, nullptr);
+    const int r = ls_setup(L, c.n_eblk, b->o.mixed, st);
+    if (r != DG_OK) return r;
+    DG_HIP_CHECK(hipMemcpyAsync(dev_dinv64, b->ls_Dinv64 + b->where_dinv[instance], sizeof(double) * I.T * N * N,
+                                hipMemcpyDeviceToDevice, st));
+    if (I.nnzb > I.T)
+        DG_HIP_CHECK(hipMemcpyAsync(dev_ahat, (char*)b->ls_Ahat + ps * b->where_ahat[instance],
+                                    ps * (I.nnzb - I.T) * N * N, hipMemcpyDeviceToDevice, st));
+    return DG_OK;
 }
 
 extern "C" int32_t dg_batch_set_progress(dg_batch* b, dg_progress_fn fn, void* user)

@@ -1624,3 +1624,15 @@ extern "C" int32_t dg_solver_profile(dg_solver* s, dg_kernel_stats* out, int32_t
         for (int k = 0; k < PK_N; ++k) { s->pl[k] = 0; s->pms[k] = 0.0; s->pbytes[k] = 0.0; }
     return DG_OK;
 }
+
+extern "C" int32_t dg_solver_preconditioner(dg_solver* s, double* dinv64, void* ahat, void* stream)
+{
+    if (!s || !s->ready) return DG_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t NN = (size_t)s->N * s->N;
+    if (dinv64) DG_HIP_CHECK(hipMemcpyAsync(dinv64, s->Dinv64, sizeof(double) * NN * s->T, hipMemcpyDeviceToDevice, st));
+    if (ahat && s->n_off > 0)
+        DG_HIP_CHECK(hipMemcpyAsync(ahat, s->Ahat, (s->mixed ? sizeof(float) : sizeof(double)) * NN * s->n_off,
+                                    hipMemcpyDeviceToDevice, st));
+    return DG_OK;
+}

@@ -68,5 +68,7 @@ int ls_solve(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m, int mix
 int64_t ls_elem_blocks(int k, int64_t T);
 int64_t ls_row_chunks(int64_t n);
 int ls_init(const LsArgs& A, hipStream_t st);
+// block-Jacobi setup of every instance of a chunk: Dinv64, Ahat and DinvP (cycle precision)
+int ls_setup(const LsArgs& A, int64_t n_eblk, int mixed, hipStream_t st);
 
 }  // namespace dg

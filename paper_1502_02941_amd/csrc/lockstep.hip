@@ -1168,6 +1168,16 @@ int ls_init(const LsArgs& A, hipStream_t st)
     return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
 }
 
+int ls_setup(const LsArgs& A, int64_t n_eblk, int mixed, hipStream_t st)
+{
+    if (A.count <= 0) return DG_OK;
+    const dim3 be(LS_BT), ge((unsigned)n_eblk);
+    hipLaunchKernelGGL(ls_invert_kernel, ge, be, 0, st, A);
+    if (mixed) hipLaunchKernelGGL((ls_form_kernel<float>), ge, be, 0, st, A);
+    else hipLaunchKernelGGL((ls_form_kernel<double>), ge, be, 0, st, A);
+    return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
+}
+
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
@@ -1201,8 +1211,8 @@ static int ls_solve_p(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m
                       void* user, int done_before, int total)
 {
     const dim3 be(LS_BT), ge((unsigned)n_eblk), gr((unsigned)n_rblk), gi((unsigned)A.count);
-    hipLaunchKernelGGL(ls_invert_kernel, ge, be, 0, st, A);
-    hipLaunchKernelGGL((ls_form_kernel<P>), ge, be, 0, st, A);
+    const int rs = ls_setup(A, n_eblk, A.mixed, st);
+    if (rs != DG_OK) return rs;
     hipLaunchKernelGGL(ls_bnorm_kernel, gr, be, 0, st, A);
     int first = 1;
     int h[2];

@@ -42,10 +42,10 @@ def test_forward_backward_match_oracle(api, widths, B):
     Yo, cache = OM.forward(p0, widths, X, bf16_round=True)
     lo, dYo = OM.mse(Yo, T)
     go = OM.backward(p0, widths, cache, dYo, bf16_round=True)
-    assert rel(y.cpu().numpy(), Yo) <= 5e-3
-    assert abs(float(loss.item()) - lo) <= 5e-3 * lo
-    assert rel(dy.cpu().numpy(), dYo) <= 5e-3
-    assert rel(g.cpu().numpy(), go) <= 1e-2
+    ey, el = rel(y.cpu().numpy(), Yo), abs(float(loss.item()) - lo) / lo
+    ed, eg = rel(dy.cpu().numpy(), dYo), rel(g.cpu().numpy(), go)
+    print("widths %s, B %d: Y %.2e, loss %.2e, dY %.2e, gradients %.2e" % (widths, B, ey, el, ed, eg), flush=True)
+    assert ey <= 1e-3 and el <= 1e-3 and ed <= 1e-3 and eg <= 1e-3
     np.testing.assert_array_equal(p.cpu().numpy(), p0)
 
 
