@@ -278,6 +278,26 @@ void dg_solver_destroy(dg_solver* solver);
  * NULL.  Stream-ordered copies; DG_ERR_ARG before a successful setup. */
 int32_t dg_solver_preconditioner(dg_solver* solver, double* dev_dinv64, void* dev_ahat, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * block-Jacobi setup and GMRES of dg_solver_setup + dg_solver_solve for a
+ * system small enough for the one-workgroup solve (opts.persistent = 1), with
+ * no solver object and no allocation, no synchronisation and no memset, so
+ * the call can be captured in a graph.  Same kernels, same results (bitwise)
+ * and the same report as that path, the report written to dev_report
+ * (device memory, caller-owned) when the kernels have run.  The setup's
+ * outputs (D^{-1} FP64, A M^{-1} and D^{-1} in the cycle precision) go to a
+ * fixed 4 MiB device array of the library that each device it runs on holds
+ * until the process ends; calls on one device share it, so calls that overlap
+ * on one device (other streams, or threads) race.  DG_ERR_ARG (nothing
+ * launched) for restart > 128, reorth or profile set, a system whose setup
+ * does not fit 4 MiB (n_elems n_loc^2 (8 + 2 p) + (nnzb - n_elems) n_loc^2 p
+ * bytes with p = 8, or 4 when mixed, plus alignment) or whose Krylov state
+ * does not fit one workgroup's LDS.  The report's status is
+ * DG_ERR_NONFINITE when a diagonal block is singular or not finite. */
+int32_t dg_solve_small_noalloc(const dg_mesh* mesh, const dg_solver_opts* opts, const double* dev_vals64,
+                               const double* dev_rhs, double* dev_x, dg_solve_report* dev_report, void* stream);
+
 /* Per-kernel statistics gathered when opts.profile = 1: for each heavy kernel
  * of the solve (spmv_hat, multidot, update, residual64, combine), the number
  * of launches that did work, their summed duration between HIP events

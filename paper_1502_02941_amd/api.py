@@ -111,7 +111,7 @@ EXPORTS = ["dg_default_penalty", "dg_mesh_create", "dg_mesh_create_basis", "dg_m
            "dg_mlp_backward", "dg_mlp_adam_step", "dg_mlp_params", "dg_mlp_destroy", "dg_warmstart_prolong",
            "dg_mesh_error_points", "dg_l2_error", "dg_reaction_terms", "dg_newton_solve", "dg_mesh_refine_sizes",
            "dg_mesh_refine", "dg_implicit_euler", "dg_euler_rhs", "dg_solver_preconditioner", "dg_batch_system",
-           "dg_batch_preconditioner"]
+           "dg_batch_preconditioner", "dg_solve_small_noalloc"]
 
 _lib = None
 
@@ -167,6 +167,7 @@ def lib():
         L.dg_implicit_euler.argtypes = [P, P, P, P, P, P, D, I32, P, C.POINTER(_EulerReport), P]
         L.dg_euler_rhs.argtypes = [P, P, P, D, P, P]
         L.dg_solver_preconditioner.argtypes = [P, P, P, P]
+        L.dg_solve_small_noalloc.argtypes = [P, C.POINTER(_SolverOpts), P, P, P, P, P]
         L.dg_batch_system.argtypes = [P, I32, P, P, P]
         L.dg_batch_preconditioner.argtypes = [P, I32, P, P, P]
         L.dg_batch_destroy.argtypes = [P]
@@ -463,6 +464,19 @@ class Solver:
         _check(st, "dg_solver_solve")
         return Report(r.status, r.iters, r.cycles, r.rel_res, r.rel_res0, r.reorth_passes, r.guess_rejected,
                       r.persistent)
+
+
+def solve_small_noalloc(mesh: Mesh, vals64: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor, report: torch.Tensor,
+                        restart=50, max_iters=20000, rel_tol=1e-10, mixed=False, inner_tol=1e-5, guess_limit=0.0,
+                        stream=None):
+    """dg_solve_small_noalloc: setup + one-workgroup GMRES with no allocation;
+    report: a device uint8 tensor of REPORT_DTYPE.itemsize bytes (read it with
+    Batch.reports)."""
+    assert vals64.dtype == torch.float64 and report.numel() == REPORT_DTYPE.itemsize
+    o = _SolverOpts(int(restart), int(max_iters), float(rel_tol), int(bool(mixed)), float(inner_tol), 0, 0,
+                    float(guess_limit), 1, 1)
+    return _check(lib().dg_solve_small_noalloc(mesh._h, C.byref(o), _dptr(vals64), _dptr(rhs), _dptr(x),
+                                               _dptr(report), _stream(stream)), "dg_solve_small_noalloc")
 
 
 def bsr_to_scipy(mesh: Mesh, vals: torch.Tensor, row_ptr=None, col_idx=None):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdgdcr.so")
 SOURCES = ["host_mesh.cpp", "assemble.hip", "krylov.hip", "small.hip", "batch.hip", "lockstep.hip", "mlp.hip",
-           "newton.hip", "refine.hip", "euler.hip"]
+           "newton.hip", "refine.hip", "euler.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include")]

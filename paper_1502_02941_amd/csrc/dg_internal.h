@@ -167,7 +167,9 @@ struct SmallArgs {
     const void* Dinv;      // D^{-1} blocks, cycle precision
     const double* b;
     double* x;             // initial guess in, solution out
-    dg_solve_report* rep;  // host-mapped pinned memory
+    dg_solve_report* rep;  // host-mapped pinned memory, or device memory
+    const int* bad;        // non-null: set by the block-Jacobi setup when a pivot failed (the solve then
+                           // only reports DG_ERR_NONFINITE)
     int64_t T;
     int32_t nnzb, m, max_iters, mixed;
     double rel_tol, inner_tol, guess_limit;
@@ -177,6 +179,11 @@ SmallLayout small_layout(int64_t T, int N, int64_t nnzb, int m, size_t ps, bool 
 int small_lds_limit();
 int small_prepare(int N, int mixed, const SmallLayout& L);
 int small_launch(int N, int mixed, const SmallArgs& a, hipStream_t st);
+// Block-Jacobi setup kernels of the solver (krylov.hip) on caller buffers:
+// dinv64 [T][N][N] FP64, ahat [nnzb - T][N][N] and dinvp [T][N][N] in the cycle
+// precision; *bad is set to 1 (never cleared) when a pivot fails.
+int launch_block_jacobi(int N, int mixed, const double* A64, const int32_t* rp, const int32_t* ci, int64_t T,
+                        double* dinv64, void* ahat, void* dinvp, int* bad, hipStream_t st);
 // Error rule of dg_l2_error: Stroud q = k + 4; [w, xi, eta, phi[nqr][n]].
 std::vector<double> build_error_table(int k, int basis, int* nqr);
 constexpr int ERR_BLOCKS = 1024;

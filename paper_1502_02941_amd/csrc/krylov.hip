@@ -1305,27 +1305,51 @@ extern "C" void dg_solver_destroy(dg_solver* s)
     delete s;
 }
 
-template <int N>
-static int setup_n(dg_solver* s, hipStream_t st)
+static int setup_all(dg_solver* s, hipStream_t st)
 {
     const dg_mesh* m = s->m;
     DG_HIP_CHECK(hipMemsetAsync(s->bad, 0, sizeof(int), st));
-    constexpr int TPB = inv_tpb<N>();
-    hipLaunchKernelGGL((invert_diag_kernel<N>), dim3((unsigned)((s->T + TPB - 1) / TPB)), dim3(TPB), 0, st, s->A64,
-                       m->d_row_ptr, s->T, s->Dinv64, s->bad);
-    DG_HIP_CHECK(hipGetLastError());
-    if (s->mixed)
-        hipLaunchKernelGGL((form_ahat_kernel<N, float>), dim3(s->grid_elem), dim3(BLK), 0, st, s->A64, m->d_row_ptr,
-                           m->d_col_idx, s->Dinv64, s->T, (float*)s->Ahat, (float*)s->Dinv);
-    else
-        hipLaunchKernelGGL((form_ahat_kernel<N, double>), dim3(s->grid_elem), dim3(BLK), 0, st, s->A64, m->d_row_ptr,
-                           m->d_col_idx, s->Dinv64, s->T, (double*)s->Ahat, (double*)s->Dinv);
-    DG_HIP_CHECK(hipGetLastError());
+    const int r = launch_block_jacobi(s->N, s->mixed, s->A64, m->d_row_ptr, m->d_col_idx, s->T, s->Dinv64, s->Ahat,
+                                      s->Dinv, s->bad, st);
+    if (r != DG_OK) return r;
     int bad = 0;
     DG_HIP_CHECK(hipMemcpyAsync(&bad, s->bad, sizeof(int), hipMemcpyDeviceToHost, st));
     DG_HIP_CHECK(hipStreamSynchronize(st));
     return bad ? DG_ERR_NONFINITE : DG_OK;
 }
+
+namespace dg {
+template <int N>
+static int block_jacobi_n(int mixed, const double* A64, const int32_t* rp, const int32_t* ci, int64_t T,
+                          double* dinv64, void* ahat, void* dinvp, int* bad, hipStream_t st)
+{
+    constexpr int TPB = inv_tpb<N>();
+    const int EPW = 64 / N;
+    const int grid = (int)((T + 4 * EPW - 1) / (4 * EPW));
+    hipLaunchKernelGGL((invert_diag_kernel<N>), dim3((unsigned)((T + TPB - 1) / TPB)), dim3(TPB), 0, st, A64, rp, T,
+                       dinv64, bad);
+    if (mixed)
+        hipLaunchKernelGGL((form_ahat_kernel<N, float>), dim3(grid), dim3(BLK), 0, st, A64, rp, ci, (const double*)dinv64,
+                           T, (float*)ahat, (float*)dinvp);
+    else
+        hipLaunchKernelGGL((form_ahat_kernel<N, double>), dim3(grid), dim3(BLK), 0, st, A64, rp, ci,
+                           (const double*)dinv64, T, (double*)ahat, (double*)dinvp);
+    return hipGetLastError() == hipSuccess ? DG_OK : DG_ERR_HIP;
+}
+
+int launch_block_jacobi(int N, int mixed, const double* A64, const int32_t* rp, const int32_t* ci, int64_t T,
+                        double* dinv64, void* ahat, void* dinvp, int* bad, hipStream_t st)
+{
+    switch (N) {
+    case 1: return block_jacobi_n<1>(mixed, A64, rp, ci, T, dinv64, ahat, dinvp, bad, st);
+    case 3: return block_jacobi_n<3>(mixed, A64, rp, ci, T, dinv64, ahat, dinvp, bad, st);
+    case 6: return block_jacobi_n<6>(mixed, A64, rp, ci, T, dinv64, ahat, dinvp, bad, st);
+    case 10: return block_jacobi_n<10>(mixed, A64, rp, ci, T, dinv64, ahat, dinvp, bad, st);
+    case 15: return block_jacobi_n<15>(mixed, A64, rp, ci, T, dinv64, ahat, dinvp, bad, st);
+    }
+    return DG_ERR_DEGREE;
+}
+}  // namespace dg
 
 extern "C" int32_t dg_solver_setup(dg_solver* s, const double* A64, void* stream)
 {
@@ -1333,15 +1357,7 @@ extern "C" int32_t dg_solver_setup(dg_solver* s, const double* A64, void* stream
     s->A64 = A64;
     s->ready = 0;
     hipStream_t st = (hipStream_t)stream;
-    int r;
-    switch (s->N) {
-    case 1: r = setup_n<1>(s, st); break;
-    case 3: r = setup_n<3>(s, st); break;
-    case 6: r = setup_n<6>(s, st); break;
-    case 10: r = setup_n<10>(s, st); break;
-    case 15: r = setup_n<15>(s, st); break;
-    default: return DG_ERR_DEGREE;
-    }
+    const int r = setup_all(s, st);
     if (r == DG_OK) s->ready = 1;
     return r;
 }

@@ -201,6 +201,15 @@ __global__ __launch_bounds__(SBT) void small_gmres_kernel(const SmallArgs a)
     const P* Ahat = STAGE ? (const P*)(lds + L.ahat) : (const P*)a.Ahat;
     const P* Dinv = (const P*)a.Dinv;
 
+    if (a.bad && *a.bad) {  // the setup found a singular or non-finite diagonal block
+        if (tid == 0) {
+            dg_solve_report rb{};
+            rb.status = DG_ERR_NONFINITE;
+            rb.persistent = 1;
+            *a.rep = rb;
+        }
+        return;
+    }
     for (int i = tid; i <= T; i += SBT) rp[i] = a.rp[i];
     for (int i = tid; i < a.nnzb; i += SBT) ci[i] = a.ci[i];
     if (STAGE) {
@@ -217,6 +226,7 @@ __global__ __launch_bounds__(SBT) void small_gmres_kernel(const SmallArgs a)
     const double bnorm = sqrt(group_sum(acc, red));  // its barriers publish rp, ci, Ahat and xs
     dg_solve_report rep{};
     rep.status = DG_NOT_CONVERGED;
+    rep.persistent = 1;
     if (!isfinite(bnorm)) {
         // the caller's x is left as it was
         if (tid == 0) {
