@@ -13,7 +13,10 @@ timing.  The roofline entry is for the step's dominant kernel, the
 Gram-Schmidt dot kernel, timed in the timed region by the solver's built-in
 HIP-event profiler on the launch stream (profile=2: that kernel alone); the
 per-kernel breakdown comes from one more, untimed, solve of each form with
-every heavy kernel timed.
+every heavy kernel timed.  The line also carries, under "learned_c5", the
+comparison the metric names (learned + mixed vs plain FP64) on the
+learned-warm-start workload: 512 held-out 64 x 64 P1 instances, plain FP64,
+mixed, and mixed from the network's guess, each timed over K whole batches.
 
 Other workloads (not the default line):
   --workload c4: 4096 instances (seed 0), P1/P2 50/50, N x N grids with N ~ U{16..128},
@@ -292,9 +295,51 @@ def main():
     }
     log("best form %s; dominant kernel %s (timed: multidot): %d launches, avg %.1f us, %.0f GB/s" % (
         best, dom, launches, ms / launches * 1e3, achieved))
+    line["learned_c5"] = c5_legs(args, api, W, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(m, prob, int(results["fp64"]["iters"][0]) if "fp64" in results else 538)
     print(json.dumps(line), flush=True)
+
+
+def c5_legs(args, api, W, torch):
+    """The comparison the metric names, learned + mixed against plain FP64, on
+    the learned-warm-start workload (512 held-out 64 x 64 P1 instances, seed 2):
+    plain FP64 from zero, mixed from zero, and mixed from the network's guess
+    (network + prolongation + judge + batched assembly and solve, each form
+    timed over `steps` whole batches after one untimed batch)."""
+    from paper_1502_02941_amd import learned as L
+    model = L.load(os.path.join(ROOT, "paper_1502_02941_amd", "data", "c5_mlp.npz"))
+    t0 = time.perf_counter()
+    out = L.evaluate(model, count=512, seed=2, reps=max(args.steps, 1), forms=L.HEADLINE_FORMS, log=log)
+    keep = ("solves_per_s", "seconds", "iters_median", "iters_p90", "iters_mean", "rejected", "converged",
+            "max_rel_res")
+    forms = {k: {kk: out[k][kk] for kk in keep} for k, _, _, _ in L.HEADLINE_FORMS}
+    log("learned-warm-start legs: %.1f s" % (time.perf_counter() - t0))
+    return {"workload": "512 held-out instances (seed 2), 64x64 P1 SIPG (24576 dofs each), Gaussian-sum f; "
+                        "batched assemble + solve to rel-res 1e-10; step = the whole batch",
+            "steps": max(args.steps, 1), "forms": forms,
+            "mixed_learned_vs_plain_fp64": forms["mixed+learned"]["solves_per_s"] / forms["fp64"]["solves_per_s"],
+            "mixed_learned_vs_mixed": forms["mixed+learned"]["solves_per_s"] / forms["mixed"]["solves_per_s"],
+            "coarse_rel_err_median": out["coarse_rel_err_median"], "guess_ms": out["guess_ms"]}
+
+
+def host_info():
+    """The host's CPU model and the number of logical CPUs this process may
+    use (the oracle itself runs on one of them)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count()
+    return {"cpu_model": model, "host_cpus": n}
 
 
 def bench_c4(args, api, W, torch):
@@ -521,7 +566,7 @@ def cpu_baseline_nl(W, n=32):
     _, its, rel, conv = O.newton(M, DEGREE, B, [0.0, 1.0], tol=1e-10, max_newton=50)
     t = time.perf_counter() - t0
     return {"value": 1.0 / t, "unit": "non-linear solves/s (32x32 instance of the same problem)", "cores": 1,
-            "kind": "oracle", "sample": "same problem on a %dx%d mesh (%d triangles): assembly + %d Newton steps with "
+            "kind": "oracle", **host_info(), "sample": "same problem on a %dx%d mesh (%d triangles): assembly + %d Newton steps with "
                                         "direct solves, %.2f s" % (n, n, M.T, its, t)}
 
 
@@ -542,7 +587,7 @@ def cpu_baseline_c1(m, prob, reps=20):
                        gD=O.Field.points(prob.u(bp[..., 0], bp[..., 1])))
         O.gmres(B, restart=C1_RESTART, tol=1e-12, max_iters=5000)
         ts.append(time.perf_counter() - t0)
-    return {"value": float(np.median(ts) * 1e3), "unit": "ms per solve", "cores": 1, "kind": "oracle",
+    return {"value": float(np.median(ts) * 1e3), "unit": "ms per solve", "cores": 1, "kind": "oracle", **host_info(),
             "sample": "the full problem, median of %d runs" % reps}
 
 
@@ -620,7 +665,7 @@ def cpu_baseline_c3(api, W, n=128):
     O.assemble(M, 3, sigma=sigma, kappa=kappa, eps=1e-4, bx=O.Field.affine(0.5, 0.0, -1.0),
                by=O.Field.affine(-0.5, 1.0, 0.0), alpha=0.5, f=1.0, gD=0.0, gN=0.0)
     t = time.perf_counter() - t0
-    return {"value": M.T / t / 1e6, "unit": "Melem/s (FP64 assembly)", "cores": 1, "kind": "oracle",
+    return {"value": M.T / t / 1e6, "unit": "Melem/s (FP64 assembly)", "cores": 1, "kind": "oracle", **host_info(),
             "sample": "same problem on a %dx%d jittered mesh (%d triangles), %.2f s" % (n, n, M.T, t)}
 
 
@@ -672,7 +717,7 @@ def cpu_baseline_c5(count, sample=8):
         _, its, rel, conv = O.gmres(B, restart=2 * L.FINE + 64, tol=1e-10, max_iters=20000)
         ok += conv
     dt = time.perf_counter() - t0
-    return {"value": len(insts) / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+    return {"value": len(insts) / dt, "unit": "solves/s", "cores": 1, "kind": "oracle", **host_info(),
             "sample": "first %d held-out instances (assemble + GMRES from zero), %.1f s, %d converged"
                       % (len(insts), dt, ok)}
 
@@ -701,18 +746,20 @@ def cpu_baseline_c4(insts, sample=12):
     dt = time.perf_counter() - t0
     share = sizes[pick].sum() / sizes.sum()
     return {"value": len(pick) / dt * share * len(insts) / len(pick), "unit": "solves/s (scaled to batch dofs)",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "kind": "oracle", **host_info(),
             "sample": "%d instances from the lower half of the size order (%.2f%% of the batch dofs), %.1f s, "
                       "%d converged; solves/s = batch size / (sample time / dof share)"
                       % (len(pick), 100 * share, dt, ok)}
 
 
 def cpu_baseline(m, prob, iters):
-    """The CPU oracle (single thread, FP64) on a bounded sample of the same
-    workload: full assembly of the 256x256 P2 system, then 20 GMRES iterations;
-    the solve rate is extrapolated from the measured per-iteration time and
-    the GPU's iteration count is not used (the oracle's own count at this size
-    is not run to completion)."""
+    """The CPU oracle (one thread, FP64) on a bounded sample of the same
+    workload: full assembly of the 256x256 P2 system, then two single-cycle
+    GMRES runs of 10 and 40 iterations.  Modified Gram-Schmidt makes iteration
+    j cost about alpha + beta j; the two runs fix alpha and beta, and the solve
+    time is extrapolated to `iters` iterations in one cycle (the FP64 GPU
+    solve's count: the oracle's GMRES spans the same Krylov space one vector
+    at a time, and the two counts agree on every size both complete)."""
     import numpy as np
     import oracle as O
     M = O.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann)
@@ -735,7 +782,7 @@ def cpu_baseline(m, prob, iters):
     J = iters
     t_solve = J * alpha + beta * J * (J + 1) / 2.0
     return {"value": 1.0 / (t_asm + t_solve), "unit": "solves/s (assemble + GMRES, extrapolated)", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", **host_info(),
             "sample": "full 256x256 P2 assembly (%.2f s, %.3f Melem/s) + single-cycle GMRES runs of 10 and 40 "
                       "iterations (%.2f s, %.2f s) fitting t(j) = %.4f + %.2e j s per iteration, extrapolated to "
                       "the %d iterations of one cycle that the FP64 GPU solve takes (%.1f s)"

@@ -435,7 +435,8 @@ typedef struct {
     double guess_limit;       /* per instance, as dg_solver_opts.guess_limit */
     int32_t lockstep_block;   /* lockstep solver: Arnoldi vectors per Gram-Schmidt pass, as dg_solver_opts.block
                                  (0 = automatic = 3, 1, 2 or 3; DG_ERR_ARG otherwise) */
-    int32_t reserved;
+    int32_t lockstep_eager;   /* lockstep solver: 0 (default) records each restart cycle of a chunk once as a HIP
+                                 graph and replays it; 1 launches the cycle's kernels one by one (same results) */
 } dg_batch_opts;
 
 typedef struct dg_batch dg_batch;
@@ -452,7 +453,8 @@ int32_t dg_batch_offsets(const dg_batch* batch, int64_t* x_offsets);
  * ([count], device) receives one report per instance.  Without lockstep
  * instances it is stream-ordered with no host synchronisation (so it can be
  * captured in a HIP graph); the lockstep solver synchronises the stream once
- * per restart cycle and every 8 Arnoldi steps to read two counters. */
+ * per restart cycle, and only then, to read two counters (the cycle itself is
+ * one HIP graph replay unless opts.lockstep_eager is set). */
 int32_t dg_batch_run(dg_batch* batch, double* dev_x, dg_solve_report* dev_reports, void* stream);
 /* Progress callback for the lockstep part, called on the host thread of
  * dg_batch_run after every restart cycle with the number of lockstep

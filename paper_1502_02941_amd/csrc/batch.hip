@@ -544,6 +544,7 @@ struct dg_batch {
         LsState* d_state = nullptr;
         int64_t* d_eblk = nullptr;
         int64_t* d_rblk = nullptr;
+        LsGraph graph;  // its restart cycle as a HIP graph (unless opts.lockstep_eager)
     };
     std::vector<Chunk> chunks;
     void *ls_V = nullptr, *ls_Ahat = nullptr, *ls_DinvP = nullptr, *ls_w = nullptr, *ls_w1 = nullptr, *ls_w2 = nullptr;
@@ -569,7 +570,10 @@ static void batch_free(dg_batch* b)
     if (b->progress_stream) hipStreamDestroy(b->progress_stream);
     for (void* p : b->slot_mem) hipFree(p);
     b->slot_mem.clear();
-    for (auto& c : b->chunks) { hipFree(c.d_inst); hipFree(c.d_state); hipFree(c.d_eblk); hipFree(c.d_rblk); }
+    for (auto& c : b->chunks) {
+        ls_graph_release(c.graph);
+        hipFree(c.d_inst); hipFree(c.d_state); hipFree(c.d_eblk); hipFree(c.d_rblk);
+    }
     b->chunks.clear();
     hipFree(b->ls_V); hipFree(b->ls_Ahat); hipFree(b->ls_DinvP); hipFree(b->ls_w); hipFree(b->ls_Dinv64);
     hipFree(b->ls_part); hipFree(b->ls_red); hipFree(b->ls_red2); hipFree(b->ls_hcol); hipFree(b->ls_H);
@@ -621,6 +625,7 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
     if (!in || count <= 0 || !o) return DG_ERR_ARG;
     if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512) return DG_ERR_ARG;
     if (o->lockstep_block < 0 || o->lockstep_block > 3) return DG_ERR_ARG;
+    if (o->lockstep_eager != 0 && o->lockstep_eager != 1) return DG_ERR_ARG;
     if (o->restart_max < 1 || o->restart_max > B_MAXM || o->restart_min < 1 || !(o->rel_tol > 0) ||
         o->max_iters < 0 || (o->mixed != 0 && o->mixed != 1) || (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)))
         return DG_ERR_ARG;
@@ -985,7 +990,7 @@ extern "C" int32_t dg_batch_run(dg_batch* b, double* dev_x, dg_solve_report* dev
         const LsArgs L = ls_args(b, c, dev_x, dev_reports);
         int r = ls_init(L, st);
         if (r == DG_OK) r = ls_solve(L, c.n_eblk, c.n_rblk, c.max_m, b->o.mixed, st, b->progress_fn, b->progress_user,
-                                     done, b->count - b->n_persistent);
+                                     done, b->count - b->n_persistent, b->o.lockstep_eager ? nullptr : &c.graph);
         if (r != DG_OK) return r;
         done += c.count;
     }

@@ -63,8 +63,27 @@ struct LsArgs {
     int32_t block;        // Arnoldi vectors per Gram-Schmidt pass: 1, 2 or 3
 };
 
+// One restart cycle of a lockstep chunk recorded as a HIP graph: recorded on
+// the first cycle that needs it and replayed for every later cycle while the
+// caller's solution and report buffers stay the same (the kernels' arguments
+// hold those pointers).  Capture runs on a stream of its own (default
+// priority, non-blocking); the graph is launched on the caller's stream.
+struct LsGraph {
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* key_x = nullptr;
+    const void* key_rep = nullptr;
+};
+void ls_graph_release(LsGraph& g);
+
+// Solves every instance of a chunk.  The host reads two counters once per
+// restart cycle and nothing in between: every cycle launches all
+// ceil(max_m / block) Arnoldi blocks, and the kernels of an instance whose
+// cycle has ended return at once (the heavy ones also when every cycle of the
+// chunk has ended).  With `graph`, each cycle after the first check is one
+// replay of the recorded cycle.
 int ls_solve(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m, int mixed, hipStream_t st,
-             dg_progress_fn fn, void* user, int done_before, int total);
+             dg_progress_fn fn, void* user, int done_before, int total, LsGraph* graph);
 int64_t ls_elem_blocks(int k, int64_t T);
 int64_t ls_row_chunks(int64_t n);
 int ls_init(const LsArgs& A, hipStream_t st);

@@ -60,6 +60,11 @@ __device__ __forceinline__ int ls_find(const int64_t* __restrict__ pre, int coun
 }
 
 __device__ __forceinline__ bool ls_running(const LsState& s) { return s.active && !s.stop; }
+// every cycle of the chunk has ended (counters[1] counts the running ones; it
+// only falls while a cycle's Arnoldi blocks run): the launches of the rest of
+// the cycle have nothing to do.  Only kernels that run before the block's
+// Givens kernel may use it, since that kernel takes the count to zero.
+__device__ __forceinline__ bool ls_all_ended(const LsArgs& A) { return A.counters[1] <= 0; }
 
 // Gauss-Jordan inverse with partial pivoting of an N x N block held by N
 // lanes (row r in m[]); pivots found / broadcast with shuffles, interchanges
@@ -387,6 +392,7 @@ __device__ __forceinline__ double ls_spmv_row(const P* Ah, const int32_t* rp, co
 template <typename P>
 __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src)
 {
+    if (ls_all_ended(A)) return;
     ElemLane e;
     if (!ls_elem_lane(A, e)) return;
     const LsState& S = A.state[e.inst];
@@ -423,6 +429,7 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src)
 template <typename P>
 __global__ __launch_bounds__(LS_BT) void ls_multidot_kernel(const LsArgs A)
 {
+    if (ls_all_ended(A)) return;
     __shared__ double sh[LS_BT / 64][LS_CT];
     const int64_t b = blockIdx.x;
     const int i = ls_find(A.rblk, A.count, b);
@@ -491,6 +498,7 @@ __global__ __launch_bounds__(LS_BT) void ls_reduce_kernel(const LsArgs A, int nr
 template <typename P>
 __global__ __launch_bounds__(LS_BT) void ls_update_kernel(const LsArgs A)
 {
+    if (ls_all_ended(A)) return;
     __shared__ double sh[LS_BT / 64];
     const int64_t b = blockIdx.x;
     const int i = ls_find(A.rblk, A.count, b);
@@ -682,6 +690,7 @@ __device__ __forceinline__ P* ls_block_vec(const LsArgs& A, int r)
 template <typename P, int S>
 __global__ __launch_bounds__(LS_BT) void ls_multidot_block_kernel(const LsArgs A)
 {
+    if (ls_all_ended(A)) return;
     __shared__ double sh[LS_BT / 64][S * LS_CT2];
     const int64_t b = blockIdx.x;
     const int i = ls_find(A.rblk, A.count, b);
@@ -746,6 +755,7 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot_block_kernel(const LsArgs A
 template <typename P, int S>
 __global__ __launch_bounds__(LS_BT) void ls_update_block_kernel(const LsArgs A)
 {
+    if (ls_all_ended(A)) return;
     constexpr int NG = S * (S + 1) / 2;
     __shared__ double sh[LS_BT / 64];
     const int64_t b = blockIdx.x;
@@ -1181,83 +1191,129 @@ int ls_setup(const LsArgs& A, int64_t n_eblk, int mixed, hipStream_t st)
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
-// one restart cycle of blocks of S Arnoldi vectors over every running
-// instance; step numbers the blocks over the whole solve
+struct LsDims {
+    dim3 be, ge, gr, gi;
+    int max_m;
+};
+
+// the launches of one restart cycle, from the normalised residual to the
+// next residual check: every Arnoldi block (numbered 1, 2, ... within the
+// cycle; an instance whose cycle has ended skips the rest), the least-squares
+// solve and update of x, then the true residual and the next cycle's state
 template <typename P, int S>
-static int ls_block_steps(const LsArgs& A, dim3 ge, dim3 gr, dim3 gi, dim3 be, int max_m, int& step, int* h,
-                          hipStream_t st)
+static void ls_cycle_blocks(const LsArgs& A, const LsDims& d, hipStream_t st)
 {
-    const int ldc = max_m + 4;
+    const int ldc = d.max_m + 4;
     const size_t dyn = sizeof(double) * S * (size_t)ldc;
-    constexpr int CHECK = S == 2 ? 4 : 3;  // blocks between checks for the end of every cycle
-    for (int j = 0, blk = 0; j < max_m; j += S, ++step, ++blk) {
-        for (int q = 0; q < S; ++q) hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, q);
-        hipLaunchKernelGGL((ls_multidot_block_kernel<P, S>), gr, be, 0, st, A);
-        hipLaunchKernelGGL(ls_reduce_kernel, gi, be, 0, st, A, S);
-        hipLaunchKernelGGL((ls_update_block_kernel<P, S>), gr, be, 0, st, A);
-        hipLaunchKernelGGL((ls_block_givens_kernel<S>), gi, dim3(64), dyn, st, A, step, ldc);
-        hipLaunchKernelGGL((ls_normalize_block_kernel<P, S>), gr, be, 0, st, A, step);
-        if (blk % CHECK == CHECK - 1) {  // stop early once every cycle has ended
-            DG_HIP_CHECK(hipMemcpyAsync(h, A.counters, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
-            DG_HIP_CHECK(hipStreamSynchronize(st));
-            if (h[1] <= 0) break;
-        }
+    for (int j = 0, step = 1; j < d.max_m; j += S, ++step) {
+        for (int q = 0; q < S; ++q) hipLaunchKernelGGL((ls_spmv_kernel<P>), d.ge, d.be, 0, st, A, q);
+        hipLaunchKernelGGL((ls_multidot_block_kernel<P, S>), d.gr, d.be, 0, st, A);
+        hipLaunchKernelGGL(ls_reduce_kernel, d.gi, d.be, 0, st, A, S);
+        hipLaunchKernelGGL((ls_update_block_kernel<P, S>), d.gr, d.be, 0, st, A);
+        hipLaunchKernelGGL((ls_block_givens_kernel<S>), d.gi, dim3(64), dyn, st, A, step, ldc);
+        hipLaunchKernelGGL((ls_normalize_block_kernel<P, S>), d.gr, d.be, 0, st, A, step);
     }
+}
+
+template <typename P>
+static void ls_cycle(const LsArgs& A, const LsDims& d, hipStream_t st)
+{
+    hipLaunchKernelGGL((ls_cycle_init_kernel<P>), d.gr, d.be, 0, st, A);
+    if (A.block == 2) ls_cycle_blocks<P, 2>(A, d, st);
+    else if (A.block == 3) ls_cycle_blocks<P, 3>(A, d, st);
+    else
+        for (int j = 0; j < d.max_m; ++j) {
+            hipLaunchKernelGGL((ls_spmv_kernel<P>), d.ge, d.be, 0, st, A, 0);
+            hipLaunchKernelGGL((ls_multidot_kernel<P>), d.gr, d.be, 0, st, A);
+            hipLaunchKernelGGL(ls_reduce_kernel, d.gi, d.be, 0, st, A, 0);
+            hipLaunchKernelGGL((ls_update_kernel<P>), d.gr, d.be, 0, st, A);
+            hipLaunchKernelGGL(ls_givens_kernel, d.gi, dim3(64), 0, st, A);
+            hipLaunchKernelGGL((ls_normalize_kernel<P>), d.gr, d.be, 0, st, A);
+        }
+    hipLaunchKernelGGL(ls_trisolve_kernel, d.gi, d.be, 0, st, A);
+    hipLaunchKernelGGL((ls_combine_kernel<P>), d.gr, d.be, 0, st, A);
+    hipLaunchKernelGGL((ls_dinv_update_kernel<P>), d.ge, d.be, 0, st, A);
+    hipLaunchKernelGGL(ls_zero_counters, dim3(1), dim3(1), 0, st, A.counters);
+    hipLaunchKernelGGL(ls_residual_kernel, d.ge, d.be, 0, st, A);
+    hipLaunchKernelGGL(ls_check_kernel, d.gi, d.be, 0, st, A, 0);
+}
+
+void ls_graph_release(LsGraph& g)
+{
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.cap) hipStreamDestroy(g.cap);
+    g = LsGraph{};
+}
+
+// records one cycle of this chunk on the capture stream and instantiates it
+template <typename P>
+static int ls_record(const LsArgs& A, const LsDims& d, LsGraph& G)
+{
+    if (!G.cap) DG_HIP_CHECK(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+    if (G.exec) {
+        DG_HIP_CHECK(hipGraphExecDestroy(G.exec));
+        G.exec = nullptr;
+    }
+    G.key_x = G.key_rep = nullptr;
+    DG_HIP_CHECK(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+    ls_cycle<P>(A, d, G.cap);
+    const hipError_t le = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(G.cap, &graph);
+    if (le != hipSuccess || ce != hipSuccess || !graph) {
+        if (graph) hipGraphDestroy(graph);
+        return DG_ERR_HIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        G.exec = nullptr;
+        return DG_ERR_HIP;
+    }
+    G.key_x = A.x;
+    G.key_rep = A.reports;
     return DG_OK;
 }
 
 template <typename P>
 static int ls_solve_p(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m, hipStream_t st, dg_progress_fn fn,
-                      void* user, int done_before, int total)
+                      void* user, int done_before, int total, LsGraph* graph)
 {
-    const dim3 be(LS_BT), ge((unsigned)n_eblk), gr((unsigned)n_rblk), gi((unsigned)A.count);
+    const LsDims d{dim3(LS_BT), dim3((unsigned)n_eblk), dim3((unsigned)n_rblk), dim3((unsigned)A.count), max_m};
     const int rs = ls_setup(A, n_eblk, A.mixed, st);
     if (rs != DG_OK) return rs;
-    hipLaunchKernelGGL(ls_bnorm_kernel, gr, be, 0, st, A);
-    int first = 1;
+    hipLaunchKernelGGL(ls_bnorm_kernel, d.gr, d.be, 0, st, A);
+    hipLaunchKernelGGL(ls_zero_counters, dim3(1), dim3(1), 0, st, A.counters);
+    hipLaunchKernelGGL(ls_residual_kernel, d.ge, d.be, 0, st, A);
+    hipLaunchKernelGGL(ls_check_kernel, d.gi, d.be, 0, st, A, 1);
+    DG_HIP_CHECK(hipGetLastError());
     int h[2];
-    int step = 1;  // host step index of the Arnoldi blocks, unique over the whole solve
     for (;;) {
-        hipLaunchKernelGGL(ls_zero_counters, dim3(1), dim3(1), 0, st, A.counters);
-        hipLaunchKernelGGL(ls_residual_kernel, ge, be, 0, st, A);
-        hipLaunchKernelGGL(ls_check_kernel, gi, be, 0, st, A, first);
-        first = 0;
+        // the one host read of the cycle: instances still active after the check
         DG_HIP_CHECK(hipMemcpyAsync(h, A.counters, sizeof(h), hipMemcpyDeviceToHost, st));
         DG_HIP_CHECK(hipStreamSynchronize(st));
         if (fn) fn(user, done_before + (A.count - h[0]), total);
         if (h[0] == 0) break;
-        hipLaunchKernelGGL((ls_cycle_init_kernel<P>), gr, be, 0, st, A);
-        const int rb = A.block == 2   ? ls_block_steps<P, 2>(A, ge, gr, gi, be, max_m, step, h, st)
-                       : A.block == 3 ? ls_block_steps<P, 3>(A, ge, gr, gi, be, max_m, step, h, st)
-                                      : DG_OK;
-        if (rb != DG_OK) return rb;
-        for (int j = 0; A.block == 1 && j < max_m; ++j) {
-            hipLaunchKernelGGL((ls_spmv_kernel<P>), ge, be, 0, st, A, 0);
-            hipLaunchKernelGGL((ls_multidot_kernel<P>), gr, be, 0, st, A);
-            hipLaunchKernelGGL(ls_reduce_kernel, gi, be, 0, st, A, 0);
-            hipLaunchKernelGGL((ls_update_kernel<P>), gr, be, 0, st, A);
-            hipLaunchKernelGGL(ls_givens_kernel, gi, dim3(64), 0, st, A);
-            hipLaunchKernelGGL((ls_normalize_kernel<P>), gr, be, 0, st, A);
-            if ((j & 7) == 7) {  // every 8 steps: stop early once every cycle has ended
-                DG_HIP_CHECK(hipMemcpyAsync(h, A.counters, sizeof(h), hipMemcpyDeviceToHost, st));
-                DG_HIP_CHECK(hipStreamSynchronize(st));
-                if (h[1] <= 0) break;
+        if (graph) {
+            if (!graph->exec || graph->key_x != (const void*)A.x || graph->key_rep != (const void*)A.reports) {
+                const int r = ls_record<P>(A, d, *graph);
+                if (r != DG_OK) return r;
             }
+            DG_HIP_CHECK(hipGraphLaunch(graph->exec, st));
+        } else {
+            ls_cycle<P>(A, d, st);
+            DG_HIP_CHECK(hipGetLastError());
         }
-        hipLaunchKernelGGL(ls_trisolve_kernel, gi, be, 0, st, A);
-        hipLaunchKernelGGL((ls_combine_kernel<P>), gr, be, 0, st, A);
-        hipLaunchKernelGGL((ls_dinv_update_kernel<P>), ge, be, 0, st, A);
-        DG_HIP_CHECK(hipGetLastError());
     }
     return DG_OK;
 }
 
 int ls_solve(const LsArgs& A, int64_t n_eblk, int64_t n_rblk, int max_m, int mixed, hipStream_t st,
-             dg_progress_fn fn, void* user, int done_before, int total)
+             dg_progress_fn fn, void* user, int done_before, int total, LsGraph* graph)
 {
     if (A.count <= 0) return DG_OK;
-    return mixed ? ls_solve_p<float>(A, n_eblk, n_rblk, max_m, st, fn, user, done_before, total)
-                 : ls_solve_p<double>(A, n_eblk, n_rblk, max_m, st, fn, user, done_before, total);
+    return mixed ? ls_solve_p<float>(A, n_eblk, n_rblk, max_m, st, fn, user, done_before, total, graph)
+                 : ls_solve_p<double>(A, n_eblk, n_rblk, max_m, st, fn, user, done_before, total, graph);
 }
 
 int64_t ls_elem_blocks(int k, int64_t T)

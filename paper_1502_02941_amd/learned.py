@@ -231,8 +231,14 @@ class WarmStart:
 # evaluated only to show what the guess would do to GMRES without the judge.
 NO_JUDGE = math.inf
 
-FORMS = (("fp64", False, False, 0.0), ("mixed", True, False, 0.0), ("fp64+learned", False, True, 0.0),
-         ("mixed+learned", True, True, 0.0), ("mixed+learned(no judge)", True, True, NO_JUDGE))
+# (name, mixed cycles, initial guess, judge limit): the guess is zero, the
+# network's ("net"), or the exact cell means of the solution itself ("exact":
+# what a perfect coarse predictor would give; needs the "fp64" form first)
+FORMS = (("fp64", False, None, 0.0), ("mixed", True, None, 0.0), ("fp64+learned", False, "net", 0.0),
+         ("mixed+learned", True, "net", 0.0), ("mixed+learned(no judge)", True, "net", NO_JUDGE),
+         ("mixed+exact coarse(no judge)", True, "exact", NO_JUDGE))
+# the forms of the comparison "learned + mixed vs plain FP64"
+HEADLINE_FORMS = FORMS[:2] + FORMS[3:4]
 
 
 def evaluate(model, count=512, seed=2, reps=3, forms=FORMS, log=None):
@@ -244,14 +250,20 @@ def evaluate(model, count=512, seed=2, reps=3, forms=FORMS, log=None):
     ws = WarmStart(model, count)
     out = {}
     truth = None
-    for name, mixed, learned, limit in forms:
+    for name, mixed, guess, limit in forms:
         fam = Family(insts, mixed=mixed, guess_limit=limit)
         x = torch.empty(count, N_DOFS, dtype=torch.float64, device="cuda")
         _, rep = fam.batch.alloc()
+        if guess == "exact":
+            if truth is None:
+                raise ValueError("the exact-coarse form needs a solved form before it")
+            exact = torch.from_numpy(truth.astype(np.float32)).cuda()
 
         def run():
-            if learned:
+            if guess == "net":
                 ws.guess(feats, x)
+            elif guess == "exact":
+                A.warmstart_prolong(ws.mesh, exact, COARSE, ws.mode, x)
             else:
                 x.zero_()
             fam.solve(x, rep)

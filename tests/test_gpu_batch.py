@@ -213,3 +213,49 @@ def test_batch_rejects_unknown_lockstep_block(api):
     with pytest.raises(api.DGError) as e:
         api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], lockstep_block=4)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("block", [1, 3])
+def test_lockstep_cycle_graph_matches_eager_and_oracle(api, mixed, block):
+    """Every instance on the lockstep solver, whose restart cycle is recorded
+    once as a HIP graph and replayed (the default): the solutions and reports
+    are bitwise those of launching the cycle's kernels one by one, on a second
+    run (replays of the same graph) and on a run into other buffers (a new
+    recording) too, and every solution reaches 1e-10 judged by the oracle.
+    Short restarts make each instance run several cycles."""
+    insts = _instances(12, seed=31)
+    pairs = [(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts]
+    kw = dict(mixed=mixed, rel_tol=1e-10, inner_tol=1e-5, lockstep_min_dofs=0, lockstep_block=block,
+              restart_min=12, restart_per_side=0.5)
+    _say("lockstep cycle graph: mixed=%s block %d" % (mixed, block))
+    be = api.Batch(pairs, lockstep_eager=True, **kw)
+    xe, repe = be.alloc()
+    be.run(xe, repe)
+    torch.cuda.synchronize()
+    Re = be.reports(repe)
+    assert (Re["status"] == 0).all(), Re
+    assert Re["cycles"].max() >= 3
+    bg = api.Batch(pairs, **kw)
+    runs = [bg.alloc(), None, bg.alloc()]
+    runs[1] = runs[0]
+    for r, (xg, repg) in enumerate(runs):
+        xg.fill_(0.0)
+        bg.run(xg, repg)
+        torch.cuda.synchronize()
+        Rg = bg.reports(repg)
+        assert torch.equal(xg, xe), r
+        for key in ("status", "iters", "cycles", "rel_res", "rel_res0", "guess_rejected"):
+            assert np.array_equal(Rg[key], Re[key]), (r, key)
+    xs = runs[2][0].cpu().numpy()
+    for i, inst in enumerate(insts):
+        rr = _oracle_relres(inst, xs[bg.offsets[i]:bg.offsets[i + 1]])
+        assert rr <= 1.01e-10, (i, rr)
+    _say("  cycles %s, iters %s" % (list(Re["cycles"]), list(Re["iters"])))
+
+
+def test_batch_rejects_unknown_lockstep_eager(api):
+    insts = _instances(2, seed=3)
+    with pytest.raises(api.DGError) as e:
+        api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], lockstep_eager=2)
+    assert e.value.status == -1
