@@ -362,22 +362,26 @@ def bench_c4(args, api, W, torch):
         best = autotune.tune_batch(api, pairs, mixed=mixed, log=log)
         log("%s: tuned %s in %.1f s" % (form, best, time.perf_counter() - t0))
         t0 = time.perf_counter()
-        b = api.Batch(pairs, mixed=mixed, rel_tol=1e-10, inner_tol=1e-5, lockstep_block=args.lockstep_block, **best)
+        b = api.Batch(pairs, mixed=mixed, rel_tol=1e-10, inner_tol=1e-5, lockstep_block=args.lockstep_block, log=log,
+                      **best)
         log("%s: batch created in %.1f s" % (form, time.perf_counter() - t0))
         x, rep = b.alloc()
-        for _ in range(args.warmup):
+        for w in range(args.warmup):
+            tw = time.perf_counter()
             x.zero_()
             b.run(x, rep)
             b.wait(log)
+            log("%s: warm-up batch %d: %.2f s" % (form, w + 1, time.perf_counter() - tw))
         torch.cuda.synchronize()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev[0].record()
-        for _ in range(args.steps):
+        for k in range(args.steps):
             x.zero_()
             b.run(x, rep)
             b.wait(log)
+            log("%s: timed batch %d done at %.2f s" % (form, k + 1, time.perf_counter() - t0))
         ev[1].record()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0

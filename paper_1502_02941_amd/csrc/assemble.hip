@@ -184,12 +184,26 @@ __device__ __forceinline__ double scalar_value(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Blocks written through LDS: with STAGED, a wave puts each block of its
+// elements (column j from each lane) into its own LDS buffer and writes them
+// out as whole 16-byte words, consecutive lanes on consecutive words, instead
+// of one 4- or 8-byte value per lane scattered over the block rows.
+template <int K, typename R>
+struct StagedStores {
+    static constexpr int N = (K + 1) * (K + 2) / 2, NN = N * N, EPW = 64 / N;
+    static constexpr bool on = (NN * (int)sizeof(R)) % 16 == 0 && K == 2;  // P3: slower (LDS and latency bound)
+    static constexpr int WORDS = on ? NN * (int)sizeof(R) / 16 : 1;  // 16-byte words per block
+    static constexpr int BUF = on ? EPW * NN : 0;            // R per wave
+};
+
 template <int K, typename R>
 __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, const R* sw, const int64_t el,
-                                               const int j)
+                                               const int j, R* wb = nullptr, bool valid = true, int e_in = 0)
 {
     constexpr int N = (K + 1) * (K + 2) / 2, NN = N * N;
     constexpr TabLayout L(K);
+    using SS = StagedStores<K, R>;
+    constexpr bool STAGED = SS::on;
     const R t_first = ((const R*)a.tab)[L.et], t_last = ((const R*)a.tab)[L.et + L.nqe - 1];
     // all global loads of the element first, so that they are in flight together;
     // the neighbours enter only through the element's own table of their
@@ -283,9 +297,42 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         return e;
     };
 
-    // Off-diagonal block of interior edge l, stored as soon as it is complete.
+    // STAGED: every lane of the wave calls this for the same block (slot < 0
+    // where the lane's element has no such block or is not a real element)
+    auto put_block = [&](const R* acc, int32_t slot_l) {
+        const int lane = (int)(threadIdx.x & 63);
+        if (slot_l >= 0) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) wb[e_in * NN + i * N + j] = acc[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        constexpr int TOT = SS::EPW * SS::WORDS, IT = (TOT + 63) / 64;
+        int32_t se[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {  // every lane active: slot of the element of word lane + 64 it
+            const int c = lane + 64 * it;
+            const int e = (c < TOT ? c : TOT - 1) / SS::WORDS;
+            se[it] = __shfl(slot_l, e * N, 64);
+        }
+        R* __restrict__ vals = (R*)a.vals;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int c = lane + 64 * it;
+            if (c < TOT && se[it] >= 0) {
+                const int e = c / SS::WORDS, w = c - e * SS::WORDS;
+                const uint4 v = reinterpret_cast<const uint4*>(wb + e * NN)[w];
+                reinterpret_cast<uint4*>(vals + (int64_t)se[it] * NN)[w] = v;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    // Off-diagonal block of interior edge l (into acco).
     int64_t slot = s0 + 1;
-    auto off_diagonal = [&](int l, const EdgeCoef& e) {
+    auto off_block = [&](int l, const EdgeCoef& e, R* acco) {
         const double hk = 0.5 * deps;
         const int lp = (nbe >> (2 * l)) & 3;
         R c[5];
@@ -295,7 +342,6 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         c[3] = (R)(-0.5 * deps * a.kappa * e.mKx);
         c[4] = (R)(-0.5 * deps * a.kappa * e.mKy);
         const R* Tl = col + (TenStage::EO + 5 * (3 * l + lp)) * NN;
-        R acco[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) acco[i] = c[0] * Tl[i];
 #pragma unroll
@@ -311,6 +357,11 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
             for (int i = 0; i < N; ++i) acco[i] += c1t * T1[i];
             if (e.mixed) upwind_points<K, R>(a, l, lp, j, e.blA, e.dbl, -cC, acco);
         }
+    };
+    // ... stored as soon as it is complete
+    auto off_diagonal = [&](int l, const EdgeCoef& e) {
+        R acco[N];
+        off_block(l, e, acco);
 #pragma unroll
         for (int i = 0; i < N; ++i) vals[(slot * N + i) * N + j] = acco[i];
         ++slot;
@@ -327,7 +378,17 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
                 mL[2 * l + 3] = a.mL[6 * el + 2 * l + 3];
             }
         }
-        if (nb[l] >= 0) off_diagonal(l, edge_coef(l));
+        if constexpr (STAGED) {  // every lane takes part in every edge's block write
+            R acco[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) acco[i] = R(0);
+            const bool has = nb[l] >= 0;
+            if (has) off_block(l, edge_coef(l), acco);
+            put_block(acco, valid && has ? (int32_t)slot : -1);
+            if (has) ++slot;
+        } else if (nb[l] >= 0) {
+            off_diagonal(l, edge_coef(l));
+        }
     }
 
     R accd[N];
@@ -384,11 +445,15 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         }
         if (baff && e.mixed) upwind_points<K, R>(a, l, l, j, e.blA, e.dbl, cC, accd, true);
     }
+    if constexpr (STAGED) {
+        put_block(accd, valid ? (int32_t)s0 : -1);
+    } else {
 #pragma unroll
-    for (int i = 0; i < N; ++i) vals[(s0 * N + i) * N + j] = accd[i];
+        for (int i = 0; i < N; ++i) vals[(s0 * N + i) * N + j] = accd[i];
+    }
     if (a.rhs) {
         if constexpr (!HOIST) rv = load_vector();
-        ((R*)a.rhs)[el * N + j] = rv;
+        if (valid) ((R*)a.rhs)[el * N + j] = rv;
     }
 }
 
@@ -402,7 +467,10 @@ __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const Asm
     constexpr int RPW = 16 / (int)sizeof(R);
     constexpr int PER = (NT / RPW + TEN_BLOCK - 1) / TEN_BLOCK;  // 16-byte tensor words per thread
     constexpr int NTP = PER * TEN_BLOCK * RPW;                   // tensor region padded to whole passes
-    __shared__ __align__(16) R st[NTP + NQ * (N + 3)];  // staged tensors, then the load vector's point tables
+    constexpr int SWP = (NQ * (N + 3) + RPW - 1) / RPW * RPW;    // point tables padded to whole words
+    using SS = StagedStores<K, R>;
+    // staged tensors, the load vector's point tables, then (STAGED) each wave's block buffer
+    __shared__ __align__(16) R st[NTP + SWP + WPB * SS::BUF];
     R* sw = st + NTP;
     const bool baff = a.bx.c[1] != 0.0 || a.bx.c[2] != 0.0 || a.by.c[1] != 0.0 || a.by.c[2] != 0.0;
     // Staging: every load of a thread (the tensors in 16-byte words, then the
@@ -463,9 +531,19 @@ __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const Asm
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int e_in = lane / N;
     const int j = lane - e_in * N;
-    const int64_t el = ((int64_t)blockIdx.x * WPB + wave) * EPW + e_in;
-    if (e_in >= EPW || el >= a.T) return;
-    tensor_element<K, R>(a, st, sw, el, j);
+    const int64_t e0 = ((int64_t)blockIdx.x * WPB + wave) * EPW;
+    const int64_t el = e0 + e_in;
+    if constexpr (SS::on) {
+        // every lane of a wave with a real element takes part in the block writes;
+        // the others compute a copy of the wave's first element and write nothing
+        if (e0 >= a.T) return;
+        const bool valid = e_in < EPW && el < a.T;
+        tensor_element<K, R>(a, st, sw, valid ? el : e0, j, st + NTP + SWP + wave * SS::BUF, valid,
+                             e_in < EPW ? e_in : 0);
+    } else {
+        if (e_in >= EPW || el >= a.T) return;
+        tensor_element<K, R>(a, st, sw, el, j);
+    }
 }
 
 // eps and alpha constant (the affine form with zero slopes), b affine

@@ -64,35 +64,87 @@ struct GemmArgs {
     int act;
 };
 
+// How an operand tile is read from global memory: its 8-element runs along k
+// are contiguous (KRUN), or along the tile's row/column index (XRUN: m for A,
+// n for B), each run a 16-byte load; otherwise element by element (SCALAR).
+enum { SCALAR = 0, KRUN = 1, XRUN = 2 };
+constexpr int GT = 32, GLD = GT + 8;  // tile edge; LDS row stride in BF16 (80 bytes: rows start on 16-byte words)
+
+// One operand tile T[x][k] (x = m or n, 32 x 32, k contiguous in LDS) of
+// X(x, k) = P[x * sx + k * sk], zero outside x < X, k < K.  64 lanes, two
+// 16-byte runs each.
+template <int MODE>
+__device__ __forceinline__ void stage_tile(uint16_t (*T)[GLD], const uint16_t* __restrict__ P, int64_t sx, int64_t sk,
+                                           int x0, int X, int k0, int K, int lane)
+{
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int c = lane + 64 * r;
+        if (MODE == KRUN) {  // run c: row x0 + c / 4, k = k0 + 8 (c % 4) .. + 7
+            const int x = x0 + (c >> 2), kk = k0 + 8 * (c & 3);
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (x < X && kk + 8 <= K) {
+                v = *reinterpret_cast<const uint4*>(P + (int64_t)x * sx + kk);
+            } else if (x < X) {
+                uint16_t e[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) e[q] = kk + q < K ? P[(int64_t)x * sx + kk + q] : 0;
+                memcpy(&v, e, 16);
+            }
+            *reinterpret_cast<uint4*>(&T[c >> 2][8 * (c & 3)]) = v;
+        } else if (MODE == XRUN) {  // run c: k = k0 + c / 4, x = x0 + 8 (c % 4) .. + 7, transposed into T
+            const int kk = k0 + (c >> 2), x = x0 + 8 * (c & 3);
+            uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (kk < K && x + 8 <= X) {
+                const uint4 v = *reinterpret_cast<const uint4*>(P + (int64_t)kk * sk + x);
+                memcpy(e, &v, 16);
+            } else if (kk < K) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) e[q] = x + q < X ? P[(int64_t)kk * sk + x + q] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) T[8 * (c & 3) + q][c >> 2] = e[q];
+        } else {  // element by element: x = c / 4, k = 8 (c % 4) .. + 7
+            const int x = x0 + (c >> 2), kk = k0 + 8 * (c & 3);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                T[c >> 2][8 * (c & 3) + q] = (x < X && kk + q < K) ? P[(int64_t)x * sx + (int64_t)(kk + q) * sk] : 0;
+        }
+    }
+}
+
+// One wavefront per 32 x 32 output tile (2 x 2 MFMA blocks of 16 x 16); per
+// k-step of 32 both operand tiles go through LDS and each lane reads its
+// operand (row or column lane % 16, k = 8 (lane / 16) .. + 7) as one 16-byte word.
+template <int AM, int BM>
 __global__ __launch_bounds__(64) void gemm_bf16_kernel(const GemmArgs g)
 {
+    __shared__ __align__(16) uint16_t As[GT][GLD];
+    __shared__ __align__(16) uint16_t Bs[GT][GLD];
     const int lane = threadIdx.x;
-    const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
-    const int r16 = lane & 15, kq = (lane >> 4) * 8;  // operand lane layout: row/col = lane%16, k = 8*(lane/16)..+7
+    const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
     f32x4_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
+    for (int k0 = 0; k0 < g.K; k0 += GT) {
+        stage_tile<AM>(As, g.A, g.sam, g.sak, m0, g.M, k0, g.K, lane);
+        stage_tile<BM>(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, g.K, lane);
+        __syncthreads();
         bf16x8_t av[2], bv[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const int m = m0 + 16 * t + r16, n = n0 + 16 * t + r16;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int k = k0 + kq + q;
-                const uint16_t a = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0;
-                const uint16_t b = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0;
-                av[t][q] = __builtin_bit_cast(__bf16, a);
-                bv[t][q] = __builtin_bit_cast(__bf16, b);
-            }
+            av[t] = *reinterpret_cast<const bf16x8_t*>(&As[16 * t + r16][kq]);
+            bv[t] = *reinterpret_cast<const bf16x8_t*>(&Bs[16 * t + r16][kq]);
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+        __syncthreads();  // the next k-step overwrites the tiles
     }
     // result lane layout: column = lane%16, rows 4*(lane/16)..+3
 #pragma unroll
@@ -319,11 +371,33 @@ extern "C" void dg_mlp_destroy(dg_mlp* m)
     delete m;
 }
 
+// operand read mode: 16-byte runs need a 16-byte aligned base and a run
+// stride that keeps every run on a 16-byte word
+static int run_mode(const uint16_t* P, int64_t sx, int64_t sk)
+{
+    if (reinterpret_cast<uintptr_t>(P) % 16 != 0) return SCALAR;
+    if (sk == 1 && sx % 8 == 0) return KRUN;
+    if (sx == 1 && sk % 8 == 0) return XRUN;
+    return SCALAR;
+}
+
+template <int AM>
+static void launch_gemm_b(int bm, dim3 grid, hipStream_t s, const GemmArgs& g)
+{
+    if (bm == KRUN) hipLaunchKernelGGL((gemm_bf16_kernel<AM, KRUN>), grid, dim3(64), 0, s, g);
+    else if (bm == XRUN) hipLaunchKernelGGL((gemm_bf16_kernel<AM, XRUN>), grid, dim3(64), 0, s, g);
+    else hipLaunchKernelGGL((gemm_bf16_kernel<AM, SCALAR>), grid, dim3(64), 0, s, g);
+}
+
 static void gemm(hipStream_t s, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
                  int64_t sbn, int M, int N, int K, const float* bias, float* Z, uint16_t* H, int ldc, int act)
 {
     GemmArgs g{A, B, sam, sak, sbk, sbn, M, N, K, bias, Z, H, ldc, act};
-    hipLaunchKernelGGL(gemm_bf16_kernel, dim3((M + 31) / 32, (N + 31) / 32), dim3(64), 0, s, g);
+    const dim3 grid((M + GT - 1) / GT, (N + GT - 1) / GT);
+    const int am = run_mode(A, sam, sak), bm = run_mode(B, sbn, sbk);
+    if (am == KRUN) launch_gemm_b<KRUN>(bm, grid, s, g);
+    else if (am == XRUN) launch_gemm_b<XRUN>(bm, grid, s, g);
+    else launch_gemm_b<SCALAR>(bm, grid, s, g);
 }
 
 extern "C" int32_t dg_mlp_forward(dg_mlp* m, const float* dev_x, int32_t B, float* dev_y, void* stream)
