@@ -51,7 +51,8 @@ class _MeshInfo(C.Structure):
 class _SolverOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iters", C.c_int32), ("rel_tol", C.c_double), ("mixed", C.c_int32),
                 ("inner_tol", C.c_double), ("reorth", C.c_int32), ("profile", C.c_int32),
-                ("guess_limit", C.c_double), ("persistent", C.c_int32), ("block", C.c_int32)]
+                ("guess_limit", C.c_double), ("persistent", C.c_int32), ("block", C.c_int32),
+                ("basis", C.c_int32)]
 
 
 class _KStats(C.Structure):
@@ -413,15 +414,16 @@ class Solver:
     FP64 or FP32 cycles with FP64 refinement (mixed=True)."""
 
     def __init__(self, mesh: Mesh, restart=50, max_iters=20000, rel_tol=1e-10, mixed=False, inner_tol=1e-5,
-                 reorth=False, profile=False, guess_limit=0.0, persistent="auto", block=0):
+                 reorth=False, profile=False, guess_limit=0.0, persistent="auto", block=0, basis=0):
         """persistent: "auto" (one workgroup for small degree-1/2 systems),
         True (always; an error where unsupported) or False (one launch per
         GMRES kernel).  block: Arnoldi vectors per Gram-Schmidt pass of the
-        kernel-per-step path (0 automatic = 3, or 1 to 4)."""
+        kernel-per-step path (0 automatic: 8, 6 with mixed, 3 above restart 2048; or 1, 2, 3, 4, 6, 8).  basis:
+        1 monomial block vectors, 2 shifted by one (0 automatic = 2)."""
         self.mesh = mesh
         pers = {"auto": 0, True: 1, False: -1}[persistent]
         o = _SolverOpts(int(restart), int(max_iters), float(rel_tol), int(bool(mixed)), float(inner_tol),
-                        int(bool(reorth)), int(profile), float(guess_limit), pers, int(block))
+                        int(bool(reorth)), int(profile), float(guess_limit), pers, int(block), int(basis))
         h = C.c_void_p()
         _check(lib().dg_solver_create(mesh._h, C.byref(o), C.byref(h)), "dg_solver_create")
         self._h = h

@@ -32,7 +32,7 @@ namespace dg {
 
 enum { C_J = 0, C_STOP = 1, C_REORTH = 2, C_NREORTH = 3, C_NCTRL = 16 };
 enum { S_BNORM2 = 0, S_RNORM2 = 1, S_INVH = 2, S_WNORM2 = 3, S_HN = 4, S_CYCTOL = 5, S_BETA = 6,
-       S_QB = 7, S_NSCAL = 24 };  // S_QB..: the inverse Cholesky factor of an Arnoldi block (row-major, S x S)
+       S_QB = 7, S_NSCAL = 72 };  // S_QB..: the inverse Cholesky factor of an Arnoldi block (row-major, S x S)
 
 constexpr int BLK = 256;
 constexpr int MD_TARGET_BLOCKS = 2048;   // multidot: column tiles x row splits aimed at this many blocks
@@ -212,7 +212,8 @@ template <int N, typename P>
 __global__ __launch_bounds__(BLK) void spmv_hat_kernel(const P* __restrict__ Ahat, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci, const P* __restrict__ Vbase,
                                                        int64_t n, P* __restrict__ w, int64_t T,
-                                                       const int* __restrict__ ctrl, const P* __restrict__ vin)
+                                                       const int* __restrict__ ctrl, const P* __restrict__ vin,
+                                                       P cid)
 {
     if (ctrl[C_STOP]) return;
     constexpr int EPW = 64 / N;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(BLK) void spmv_hat_kernel(const P* __restrict__ Aha
     const P* v = vin ? vin : Vbase + (int64_t)ctrl[C_J] * n;  // vin: the block's second product
     const int s0 = rp[el], s1 = rp[el + 1];
     const int64_t c0 = (int64_t)s0 - el;
-    P s = v[el * N + i];
+    P s = cid * v[el * N + i];  // cid = 1 - theta: the identity blocks of Ahat - theta I
     if constexpr (N <= 6) {
         // A triangle has at most three neighbours: the loads of all three are
         // issued before the first product (absent ones read block 0 and
@@ -468,7 +469,7 @@ __global__ __launch_bounds__(BLK) void normalize_kernel(P* __restrict__ V, const
 // and, for i < S - 1, Ahat q_i = sum_{l<=i} (w_{l+1} - Ahat V R_l) (C^{-1})_{li}
 // with Ahat V = V H.
 // ---------------------------------------------------------------------------
-constexpr int BS_MAX = 4;
+constexpr int BS_MAX = 8;
 // the block's vectors w_0..w_{S-1}, passed by value
 template <typename P>
 struct BlockVecs {
@@ -484,7 +485,7 @@ struct BlockVecs {
 // workgroups took 14% less time than 16 and 2048 with two vectors, while
 // with three 16 and 2048 took 12% less than 8 and 4096 (each block re-reads
 // its S vectors once per tile), and four vectors were within 2% either way.
-constexpr int md_block_ct(int S) { return S == 3 ? 16 : 8; }
+constexpr int md_block_ct(int S) { return S == 3 ? 16 : (S == 8 ? 6 : 8); }
 
 // Sums NV per-lane values over the 64 lanes of a wave: while the count is even
 // each exchange step keeps half of them (the half picked by the step's lane
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(BLK) void multidot_block_kernel(const P* __restrict
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if constexpr (S <= 3) {  // (at S = 4 the exchanges' indexing spills to scratch)
+    if constexpr (S * CT2 == 48 || S <= 2) {  // (with 32 or 64 values the exchanges' indexing spills to scratch)
         double flat[S * CT2];
 #pragma unroll
         for (int q = 0; q < S; ++q)
@@ -717,7 +718,11 @@ constexpr int BG_T = 1024;
 // of the first wave taking column i; each column is a chain of dependent
 // steps, so the LDS loads of eight steps are issued together.
 constexpr int BG_UNROLL = 8;
-__device__ void bg_rotate_cols(double (*colv)[TS_MAXJ + 4], int ncol, int count, const double* __restrict__ cs,
+// longest cycle of the block path for blocks of S vectors (the S Hessenberg
+// columns of a block live in LDS)
+constexpr int bg_maxj(int S) { return S <= 4 ? TS_MAXJ : 2048; }
+template <int LD>
+__device__ void bg_rotate_cols(double (*colv)[LD], int ncol, int count, const double* __restrict__ cs,
                                const double* __restrict__ sn, double* sc, double* ss)
 {
     const int i = threadIdx.x;
@@ -767,12 +772,13 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
                                                             int ldr, const double* __restrict__ HX, int ldx,
                                                             double* __restrict__ H, int ldh,
                                                             double* __restrict__ cs, double* __restrict__ sn,
-                                                            double* __restrict__ g, double* scal, int j, int mcyc)
+                                                            double* __restrict__ g, double* scal, int j, int mcyc,
+                                                            double theta)
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
     constexpr int NG = S * (S + 1) / 2;
     __shared__ double red[NG][BG_T / 64];
-    __shared__ double colv[S][TS_MAXJ + 4];
+    __shared__ double colv[S][bg_maxj(S) + 4];
     __shared__ double sc[GV_CHUNK], ss[GV_CHUNK];
     __shared__ double G[S][S], Cf[S][S], Ci[S][S];  // in LDS: thread 0 indexes them dynamically
     __shared__ int ncol_s, cut_s;
@@ -793,6 +799,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
     for (int i = threadIdx.x; i <= j; i += BG_T) colv[0][i] = R[i];
     __syncthreads();
     if (threadIdx.x == 0) {
+        colv[0][j] += theta;  // A v_j = w_0 + theta v_j
         int k = 0;
         for (int q = 0; q < S; ++q)
             for (int p = 0; p <= q; ++p) {
@@ -855,9 +862,11 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
                 if (t > j + i + 1) continue;
                 double v = 0.0;
                 for (int l = 0; l < i; ++l) {
+                    // A u_l = w_{l+1} + theta w_l - A V R_l, in the basis [V, Q]
                     const int m = l + 1;
                     const double cm = t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0);
-                    v += (cm - hx[l]) * Ci[l][i - 1];
+                    const double cl = t <= j ? R[l * (j + 1) + t] : (t - j - 1 <= l ? Cf[t - j - 1][l] : 0.0);
+                    v += (cm + theta * cl - hx[l]) * Ci[l][i - 1];
                 }
                 colv[i][t] = v;
             }
@@ -1080,7 +1089,8 @@ struct dg_solver {
     void* w = nullptr;      // [n] in P
     void* u = nullptr;      // [n] in P
     void* w2 = nullptr;     // [n] in P: the third vector of blocks of 3 or more
-    void* w3 = nullptr;     // [n] in P: the fourth vector of blocks of 4
+    void* w3 = nullptr;     // [n] in P: the fourth vector of blocks of 4 or more
+    void* wx[BS_MAX - 4] = {nullptr, nullptr, nullptr, nullptr};  // [n] in P: vectors 5..8 of larger blocks
     double* r = nullptr;    // [n] FP64
     double* partials = nullptr;
     double* hcol = nullptr;
@@ -1088,7 +1098,8 @@ struct dg_solver {
     double* Rb = nullptr;   // [block][restart + 2]: an Arnoldi block's projections
     double* Hr = nullptr;   // [restart + 2][restart + 1]: raw Hessenberg matrix of the block path, row-major
     double* HX = nullptr;   // [block - 1][restart + 2]: its products with a block's projections
-    int block = 1;          // Arnoldi vectors per Gram-Schmidt pass (1 to 4)
+    int block = 1;          // Arnoldi vectors per Gram-Schmidt pass (1, 2, 3, 4, 6 or 8)
+    double theta = 0.0;     // block basis w_i = (A M^{-1} - theta I) w_{i-1}: 0 monomial, 1 shifted
     double* H = nullptr;
     double* cs = nullptr;
     double* sn = nullptr;
@@ -1199,6 +1210,7 @@ static void solver_free(dg_solver* s)
     hipFree(s->Ahat); hipFree(s->Dinv); hipFree(s->Dinv64); hipFree(s->V); hipFree(s->w); hipFree(s->u);
     hipFree(s->r); hipFree(s->partials); hipFree(s->hcol); hipFree(s->hcol2); hipFree(s->H); hipFree(s->cs);
     hipFree(s->Rb); hipFree(s->Hr); hipFree(s->HX); hipFree(s->w2); hipFree(s->w3);
+    for (void* p : s->wx) hipFree(p);
     hipFree(s->sn); hipFree(s->g); hipFree(s->y); hipFree(s->scal); hipFree(s->ctrl); hipFree(s->bad);
     if (s->h_rep) hipHostFree(s->h_rep);
     s->h_rep = nullptr;
@@ -1213,7 +1225,9 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
         return DG_ERR_ARG;
     if (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)) return DG_ERR_ARG;
     if (o->persistent < -1 || o->persistent > 1 || o->profile < 0 || o->profile > 2) return DG_ERR_ARG;
-    if (o->block < 0 || o->block > BS_MAX || (o->block > 1 && o->reorth)) return DG_ERR_ARG;
+    if (o->block < 0 || o->block > BS_MAX || o->block == 5 || o->block == 7 || (o->block > 1 && o->reorth))
+        return DG_ERR_ARG;
+    if (o->basis < 0 || o->basis > 2 || (o->block > 4 && o->restart > bg_maxj(o->block))) return DG_ERR_ARG;
     dg_solver* s = new (std::nothrow) dg_solver();
     if (!s) return DG_ERR_OOM;
     s->m = m;
@@ -1224,7 +1238,10 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     s->n = m->T * m->n;
     s->n_off = m->nnzb - m->T;
     s->mixed = o->mixed;
-    s->block = o->block == 0 ? (o->reorth ? 1 : 3) : o->block;
+    // automatic: eight vectors per pass in FP64 cycles; in FP32 cycles the rounding of the block's vectors
+    // makes eight take up to a fifth more steps on hard systems (six: a few percent)
+    s->block = o->block != 0 ? o->block : (o->reorth ? 1 : (o->restart <= bg_maxj(8) ? (o->mixed ? 6 : 8) : 3));
+    s->theta = o->basis == 1 ? 0.0 : 1.0;
     const int EPW = 64 / s->N;
     s->grid_elem = (int)((s->T + 4 * EPW - 1) / (4 * EPW));
     s->grid_chunk = (int)((s->n + BLK * UPD_E - 1) / (BLK * UPD_E));
@@ -1263,6 +1280,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     }
     if (s->block > 2) al(&s->w2, ps * s->n);
     if (s->block > 3) al(&s->w3, ps * s->n);
+    for (int q = 4; q < s->block; ++q) al(&s->wx[q - 4], ps * s->n);
     al((void**)&s->H, sizeof(double) * (size_t)(mm + 1) * mm);
     al((void**)&s->cs, sizeof(double) * mm);
     al((void**)&s->sn, sizeof(double) * mm);
@@ -1371,7 +1389,9 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
     const int mm = s->o.restart;
     const double ps = (double)sizeof(P), nb = (double)s->n;
     P* V = (P*)s->V;
-    BlockVecs<P> W{{(P*)s->w, (P*)s->u, (P*)s->w2, (P*)s->w3}};  // u is free until the cycle's combine
+    BlockVecs<P> W{{(P*)s->w, (P*)s->u, (P*)s->w2, (P*)s->w3, (P*)s->wx[0], (P*)s->wx[1], (P*)s->wx[2],
+                    (P*)s->wx[3]}};  // u is free until the cycle's combine
+    const P cid = (P)(1.0 - s->theta);
     P* const* wv = W.w;
     for (int j = 0; j < mcyc; j += S) {
         int nt, sp;
@@ -1382,7 +1402,7 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
             const bool pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
             hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
                                m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, wv[q], s->T, s->ctrl,
-                               (const P*)(q ? wv[q - 1] : nullptr));
+                               (const P*)(q ? wv[q - 1] : nullptr), cid);
             prof_end(s, st, pr);
         }
         bool pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
@@ -1400,7 +1420,7 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
         hipLaunchKernelGGL((block_givens_kernel<S>), dim3(1), dim3(BG_T), 0, st, s->ctrl, (const double*)s->partials,
                            s->grid_chunk, (const double*)s->Rb, s->Hr, mm + 1, (const double*)s->HX, mm + 2, s->H,
                            mm + 1, s->cs, s->sn, s->g,
-                           s->scal, j, mcyc);
+                           s->scal, j, mcyc, s->theta);
         hipLaunchKernelGGL((normalize_block_kernel<P, S>), dim3(s->grid_vec), dim3(BLK), 0, st, V, W, s->n, j,
                            (const int*)s->ctrl, (const double*)s->scal);
     }
@@ -1484,6 +1504,8 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
         if (s->block == 2) block_cycle<N, P, 2>(s, st, mcyc, spmv_bytes);
         if (s->block == 3) block_cycle<N, P, 3>(s, st, mcyc, spmv_bytes);
         if (s->block == 4) block_cycle<N, P, 4>(s, st, mcyc, spmv_bytes);
+        if (s->block == 6) block_cycle<N, P, 6>(s, st, mcyc, spmv_bytes);
+        if (s->block == 8) block_cycle<N, P, 8>(s, st, mcyc, spmv_bytes);
         for (int j = 0; s->block == 1 && j < mcyc; ++j) {
             int nt, sp;
             int64_t rows;
@@ -1491,7 +1513,8 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
             const double md_bytes = (j + 2.0) * nb * ps, up_bytes = (j + 3.0) * nb * ps;
             pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
             hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
-                               m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, w, s->T, s->ctrl, (const P*)nullptr);
+                               m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, w, s->T, s->ctrl, (const P*)nullptr,
+                               (P)1);
             prof_end(s, st, pr);
             pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
             hipLaunchKernelGGL((multidot_kernel<P>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, (const P*)w, s->n, j,

@@ -178,16 +178,18 @@ def _fitting_restart(api, mesh, mixed):
 @pytest.mark.parametrize("case", SOLVE_CASES, ids=[c.name for c in SOLVE_CASES])
 def test_persistent_and_per_kernel_paths_agree(api, case, mixed):
     """The one-workgroup LDS solve (forced) runs the same GMRES as the
-    launch-per-kernel path: Arnoldi step counts equal up to the steps that the
-    different summation orders can move a stopping test by, and solutions that
-    agree to the tolerance."""
+    launch-per-kernel path with one Arnoldi vector per Gram-Schmidt pass:
+    Arnoldi step counts equal up to the steps that the different summation
+    orders can move a stopping test by, and solutions that agree to the
+    tolerance."""
     mesh, _, vals, rhs = _gpu_system(api, case)
     restart = _fitting_restart(api, mesh, mixed)
     if restart is None:
         pytest.skip("%d unknowns do not fit one workgroup's LDS" % mesh.n_dofs)
     out = {}
     for persistent in (True, False):
-        s = api.Solver(mesh, restart=restart, max_iters=20000, rel_tol=case.tol, mixed=mixed, persistent=persistent)
+        s = api.Solver(mesh, restart=restart, max_iters=20000, rel_tol=case.tol, mixed=mixed, persistent=persistent,
+                       block=0 if persistent else 1)
         s.setup(vals)
         x = torch.zeros_like(rhs)
         rep = s.solve(rhs, x)
@@ -382,20 +384,22 @@ def test_two_vector_blocks_match_one_vector_steps(api, case, mixed):
 
 @pytest.mark.parametrize("case", SOLVE_CASES, ids=[c.name for c in SOLVE_CASES])
 @pytest.mark.parametrize("mixed", [False, True])
-@pytest.mark.parametrize("block", [3, 4])
-def test_wider_blocks_match_one_vector_steps(api, case, mixed, block):
-    """Three or four Arnoldi vectors per Gram-Schmidt pass (w, A w, A^2 w, ...,
-    Cholesky QR of the S x S block): the tolerance judged by the oracle is
-    reached, and the step count stays close to one-vector steps (the Krylov
-    spaces are the same; the block's Gram matrix is worse conditioned, so
-    rounding differs more)."""
+@pytest.mark.parametrize("block,basis", [(3, 1), (4, 1), (3, 2), (4, 2), (6, 2), (8, 2)])
+def test_wider_blocks_match_one_vector_steps(api, case, mixed, block, basis):
+    """Blocks of S Arnoldi vectors per Gram-Schmidt pass, Cholesky QR of the
+    S x S block, monomial (w, A w, A^2 w, ...) up to four vectors or shifted
+    by one (w, (A - I) w, (A - I)^2 w, ...) up to eight: the tolerance judged
+    by the oracle is reached, and the step count stays close to one-vector
+    steps (the Krylov spaces are the same; only rounding differs).  In FP32
+    cycles eight vectors are allowed a quarter more steps: the rounding of the
+    block's vectors shows on the hard P3 case (1925 against 1581)."""
     mesh = api.Mesh.from_arrays(case.mesh, case.k)
     vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
     M, B = DC.oracle_system(case)
     its = {}
     for b in (1, block):
         s = api.Solver(mesh, restart=51, max_iters=20000, rel_tol=case.tol, mixed=mixed, inner_tol=1e-5,
-                       persistent=False, block=b)
+                       persistent=False, block=b, basis=basis)
         s.setup(vals)
         x = torch.zeros_like(rhs)
         rep = s.solve(rhs, x)
@@ -404,7 +408,7 @@ def test_wider_blocks_match_one_vector_steps(api, case, mixed, block):
                                                                              rep.cycles, rel))
         assert rep.status == 0 and rel <= case.tol * 1.01
         its[b] = rep.iters
-    assert abs(its[block] - its[1]) <= max(8, 0.15 * its[1])
+    assert abs(its[block] - its[1]) <= max(8, (0.25 if mixed and block == 8 else 0.15) * its[1])
 
 
 @pytest.mark.parametrize("restart", [2, 3, 7])
@@ -416,7 +420,7 @@ def test_two_vector_blocks_with_short_and_odd_restarts(api, restart):
     vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
     M, B = DC.oracle_system(case)
     res = {}
-    for block in (1, 2, 3, 4):
+    for block in (1, 2, 3, 4, 6, 8):
         s = api.Solver(mesh, restart=restart, max_iters=200000, rel_tol=1e-9, persistent=False, block=block)
         s.setup(vals)
         x = torch.zeros_like(rhs)
@@ -425,7 +429,7 @@ def test_two_vector_blocks_with_short_and_odd_restarts(api, restart):
         _say("  restart %d block %d: %s" % (restart, block, res[block]))
         assert rep.status == 0 and res[block][2] <= 1e-9
     assert abs(res[2][1] - res[1][1]) <= max(8, 0.1 * res[1][1])
-    for block in (3, 4):
+    for block in (3, 4, 6, 8):
         assert abs(res[block][1] - res[1][1]) <= max(8, 0.15 * res[1][1])
 
 
@@ -436,6 +440,10 @@ def test_two_vector_blocks_reject_reorth(api):
     assert e.value.status == -1
     with pytest.raises(api.DGError):
         api.Solver(mesh, restart=20, reorth=True, block=3)
+    for kw in ({"block": 5}, {"block": 9}, {"basis": 3}, {"block": 8, "restart": 2049}):
+        with pytest.raises(api.DGError):
+            api.Solver(mesh, **{"restart": 20, **kw})
+    api.Solver(mesh, restart=2048, block=8)
     for bad in (-1, 5):
         with pytest.raises(api.DGError):
             api.Solver(mesh, restart=20, block=bad)
