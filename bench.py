@@ -32,11 +32,13 @@ Other workloads (not the default line):
   --workload c3: assembly only, 512 x 512 squares jittered by +-0.2 h (seed 0, 524288 triangles), P3 IIPG
      sigma = 36 (72 on Dirichlet), rotating b = (-(y - 1/2), x - 1/2), eps = 1e-4, alpha = 1/2, f = 1,
      Dirichlet on x = 0 and y = 0, g^N = 0 elsewhere; FP64 and FP32 assembly, FP32 error vs FP64.
+  --workload mlp: the warm-start perceptron alone (inference on 512 instances, one training step on 256),
+     achieved TFLOP/s of its BF16 MFMA products against the 2.5 PFLOP/s peak.
   --workload c5: 512 held-out instances (seed 2) of the 64 x 64 P1 SIPG family (parameters as c4),
      zero guess vs the learned initial guess (perceptron + prolongation, model trained on 20000
      method solves of seed 1), FP64 and mixed cycles; step = the whole batch incl. the network.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c1|c2|c3|c4|c5|nl]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload c1|c2|c3|c4|c5|nl|mlp]
        python bench.py --profile-run     (one FP64 step + a copy probe, for rocprofv3)
 """
 from __future__ import annotations
@@ -133,7 +135,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, choices=(0, 1, 2, 3, 4, 6, 8),
                     help="Arnoldi vectors per Gram-Schmidt pass (0: the solver's choice, 3 without reorth)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=("c1", "c2", "c3", "c4", "c5", "nl"))
+    ap.add_argument("--workload", default="c2", choices=("c1", "c2", "c3", "c4", "c5", "nl", "mlp"))
     ap.add_argument("--count", type=int, default=None, help="c4 / c5: number of instances (4096 / 512)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one FP64 step and a 512 MiB device copy (counter scaling), no JSON baseline")
@@ -162,6 +164,8 @@ def main():
         return bench_c1(args, api, W, torch)
     if args.workload == "nl":
         return bench_nl(args, api, W, torch)
+    if args.workload == "mlp":
+        return bench_mlp(args, api, W, torch)
     log("building workload %dx%d P%d" % (N_GRID, N_GRID, DEGREE))
     m, mesh, P, prob = build_workload(api, W, torch)
     vals64, rhs64 = mesh.alloc_system(api.F64)
@@ -679,6 +683,68 @@ def cpu_baseline_c3(api, W, n=128):
     t = time.perf_counter() - t0
     return {"value": M.T / t / 1e6, "unit": "Melem/s (FP64 assembly)", "cores": 1, "kind": "oracle", **host_info(),
             "sample": "same problem on a %dx%d jittered mesh (%d triangles), %.2f s" % (n, n, M.T, t)}
+
+
+def bench_mlp(args, api, W, torch):
+    """The warm-start perceptron (23 -> 256 -> 256 -> 256 -> 1024, BF16 products
+    with FP32 accumulation) on its own: inference on the 512 held-out instances
+    and one training step (forward, loss, backward, Adam) on a batch of 256,
+    each timed with HIP events on the launch stream over `steps` x 50 repetitions.
+    Flops count the products only: 2 B sum_l w_l w_(l+1) forward, twice that
+    backward (activation and weight gradients), the first layer's input
+    gradient excluded (it is not formed)."""
+    import numpy as np
+    from paper_1502_02941_amd import learned as L
+    widths = W.mlp_widths()
+    model = L.load(os.path.join(ROOT, "paper_1502_02941_amd", "data", "c5_mlp.npz"))
+    feats = torch.from_numpy(L.features(L.instances(512, seed=2))).cuda()
+    stream = torch.cuda.current_stream()
+    fwd_flops = lambda B: 2.0 * B * sum(widths[l] * widths[l + 1] for l in range(len(widths) - 1))
+    bwd_flops = lambda B: 2.0 * fwd_flops(B) - 2.0 * B * widths[0] * widths[1]
+    reps = max(args.steps, 1) * 50
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        ev[1].synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps * 1e-3
+
+    ws = L.WarmStart(model, 512)
+    t_inf = timed(lambda: ws.coarse(feats))
+    net = api.MLP(widths, 256, W.mlp_init(widths, 0))
+    rng = np.random.default_rng(0)
+    X = torch.from_numpy(rng.standard_normal((256, widths[0])).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((256, widths[-1])).astype(np.float32)).cuda()
+
+    def train_step():
+        net.forward(X)
+        _, dy = net.loss_mse(T)
+        net.backward(dy)
+        net.adam_step(1e-4)
+
+    t_train = timed(train_step)
+    peak = 2500.0  # TFLOP/s, dense BF16 MFMA
+    inf_tf = fwd_flops(512) / t_inf / 1e12
+    train_tf = (fwd_flops(256) + bwd_flops(256)) / t_train / 1e12
+    log("inference (512): %.1f us, %.2f TFLOP/s; training step (256): %.1f us, %.2f TFLOP/s" % (
+        t_inf * 1e6, inf_tf, t_train * 1e6, train_tf))
+    line = {
+        "metric": "DG assembly Melem/s; solves/s at rel-res 1e-10, learned+mixed vs plain FP64",
+        "value": 512 / t_inf, "unit": "network inferences/s (batch of 512)", "n_gpus": 1, "steps": reps,
+        "warmup": 5, "ms_per_step": t_inf * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 products, f32 accumulation", "data": "synthetic (held-out instance parameters, seed 2)",
+        "config": {"workload": "warm-start perceptron 23-256-256-256-1024: inference on 512 instances; training "
+                               "step on 256", "train_step_us": t_train * 1e6, "train_tflops": train_tf},
+        "roofline": {"bound": "mfma", "kernel": "gemm_bf16_kernel (all layers, one inference)", "achieved": inf_tf,
+                     "peak": peak, "unit": "TFLOP/s", "frac": inf_tf / peak, "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def bench_c5(args, api, W, torch):

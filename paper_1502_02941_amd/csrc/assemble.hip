@@ -184,6 +184,18 @@ __device__ __forceinline__ double scalar_value(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Staged tensor layout: each n x n tensor as n columns (trial function j) of
+// TenCol<K,R>::np values (test function i), the column padded to whole 16-byte
+// words so that a lane reads its column with ds_read_b128 (P3 in FP32: 10
+// floats padded to 12, three 16-byte reads instead of five 8-byte ones).
+template <int K, typename R>
+struct TenCol {
+    static constexpr int n = (K + 1) * (K + 2) / 2;
+    static constexpr int w = 16 / (int)sizeof(R);         // R per 16-byte word
+    static constexpr int np = (n + w - 1) / w * w;         // padded column
+    static constexpr int ts = n * np;                     // one tensor
+};
+
 // Blocks written through LDS: with STAGED, a wave puts each block of its
 // elements (column j from each lane) into its own LDS buffer and writes them
 // out as whole 16-byte words, consecutive lanes on consecutive words, instead
@@ -204,6 +216,7 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     constexpr TabLayout L(K);
     using SS = StagedStores<K, R>;
     constexpr bool STAGED = SS::on;
+    constexpr int NP = TenCol<K, R>::np, TS = TenCol<K, R>::ts;  // staged column and tensor strides
     const R t_first = ((const R*)a.tab)[L.et], t_last = ((const R*)a.tab)[L.et + L.nqe - 1];
     // all global loads of the element first, so that they are in flight together;
     // the neighbours enter only through the element's own table of their
@@ -260,7 +273,7 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
     const double inv = 1.0 / det;
     // G = J^{-T} = [[G11, G12], [G21, G22]]
     const double G11 = dj22 * inv, G12 = -dj21 * inv, G21 = -dj12 * inv, G22 = dj11 * inv;
-    const R* col = st + j * N;
+    const R* col = st + j * NP;
     R* __restrict__ vals = (R*)a.vals;
     // edge vectors from vertex l to vertex l+1
     const double evx[3] = {dj11, dj12 - dj11, -dj12}, evy[3] = {dj21, dj22 - dj21, -dj22};
@@ -341,18 +354,18 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         c[2] = (R)(-hk * mL[2 * l + 1]);
         c[3] = (R)(-0.5 * deps * a.kappa * e.mKx);
         c[4] = (R)(-0.5 * deps * a.kappa * e.mKy);
-        const R* Tl = col + (TenStage::EO + 5 * (3 * l + lp)) * NN;
+        const R* Tl = col + (TenStage::EO + 5 * (3 * l + lp)) * TS;
 #pragma unroll
         for (int i = 0; i < N; ++i) acco[i] = c[0] * Tl[i];
 #pragma unroll
         for (int t = 1; t < 5; ++t) {
-            const R* T = Tl + t * NN;
+            const R* T = Tl + t * TS;
 #pragma unroll
             for (int i = 0; i < N; ++i) acco[i] += c[t] * T[i];
         }
         if (baff) {
             const R c1t = (R)(-e.s1);
-            const R* T1 = col + (TenStage::F1 + 3 * l + lp) * NN;
+            const R* T1 = col + (TenStage::F1 + 3 * l + lp) * TS;
 #pragma unroll
             for (int i = 0; i < N; ++i) acco[i] += c1t * T1[i];
             if (e.mixed) upwind_points<K, R>(a, l, lp, j, e.blA, e.dbl, -cC, acco);
@@ -408,7 +421,7 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         c[5] = (R)(cR * a.alpha.c[0] * det);
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
-            const R* T = col + (TenStage::VOL + t) * NN;
+            const R* T = col + (TenStage::VOL + t) * TS;
 #pragma unroll
             for (int i = 0; i < N; ++i) accd[i] += c[t] * T[i];
         }
@@ -422,7 +435,7 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
             cb[3] = (R)(cC * (dj11 * byb - dj21 * bxb));
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const R* T = col + (TenStage::VB + t) * NN;
+                const R* T = col + (TenStage::VB + t) * TS;
 #pragma unroll
                 for (int i = 0; i < N; ++i) accd[i] += cb[t] * T[i];
             }
@@ -434,12 +447,12 @@ __device__ __forceinline__ void tensor_element(const AsmArgs& a, const R* st, co
         const EdgeCoef e = edge_coef(l);
         const double dc = deps * (nb[l] >= 0 ? 0.5 : 1.0);
         const R c0 = (R)e.s, cx = (R)(dc * e.mKx), cy = (R)(dc * e.mKy);
-        const R* T = col + (TenStage::ED + 3 * l) * NN;
+        const R* T = col + (TenStage::ED + 3 * l) * TS;
 #pragma unroll
-        for (int i = 0; i < N; ++i) accd[i] += c0 * T[i] + cx * T[NN + i] + cy * T[2 * NN + i];
+        for (int i = 0; i < N; ++i) accd[i] += c0 * T[i] + cx * T[TS + i] + cy * T[2 * TS + i];
         if (baff) {
             const R c1t = (R)e.s1;
-            const R* T1 = col + (TenStage::E1 + l) * NN;
+            const R* T1 = col + (TenStage::E1 + l) * TS;
 #pragma unroll
             for (int i = 0; i < N; ++i) accd[i] += c1t * T1[i];
         }
@@ -463,7 +476,7 @@ __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const Asm
 {
     constexpr TabLayout L(K);
     constexpr int N = L.n, NN = N * N, NQ = L.nq, EPW = 64 / N, WPB = TEN_BLOCK / 64;
-    constexpr int NT = TenStage::COUNT * NN;
+    constexpr int NT = TenStage::COUNT * TenCol<K, R>::ts;
     constexpr int RPW = 16 / (int)sizeof(R);
     constexpr int PER = (NT / RPW + TEN_BLOCK - 1) / TEN_BLOCK;  // 16-byte tensor words per thread
     constexpr int NTP = PER * TEN_BLOCK * RPW;                   // tensor region padded to whole passes
@@ -480,10 +493,11 @@ __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const Asm
     // guarded writes.  Both staged tensor sets are whole 16-byte words and each
     // method's set starts on one (the host packs them contiguously from a
     // hipMalloc base).
-    static_assert(NT % RPW == 0 && (TenStage::CONST_B * NN) % RPW == 0, "staged tensors are whole 16-byte words");
+    static_assert(NT % RPW == 0 && (TenStage::CONST_B * TenCol<K, R>::ts) % RPW == 0,
+                  "staged tensors are whole 16-byte words");
     constexpr int PPT = (NQ * N + TEN_BLOCK - 1) / TEN_BLOCK;
     static_assert(NQ <= TEN_BLOCK, "one point per thread");
-    const int nw = (baff ? TenStage::COUNT : TenStage::CONST_B) * NN / RPW;
+    const int nw = (baff ? TenStage::COUNT : TenStage::CONST_B) * TenCol<K, R>::ts / RPW;
     const R* __restrict__ tab = (const R*)a.tab;
     uint4 buf[PER];
     R pt[3], pphi[PPT];
@@ -572,7 +586,7 @@ static int launch_k(const dg_mesh* m, const AsmArgs& a, hipStream_t s)
             // the staged set of this method (kappa = -1, 0, 1)
             const int ki = a.kappa < 0 ? 0 : (a.kappa > 0 ? 2 : 1);
             hipLaunchKernelGGL((assemble_tensor_kernel<K, R>), dim3((unsigned)grid), dim3(TEN_BLOCK), 0, s, a,
-                               ten + (size_t)ki * TenStage::COUNT * N * N);
+                               ten + (size_t)ki * TenStage::COUNT * TenCol<K, R>::ts);
             if (a.rhs) launch_load_boundary<K, R>(m, a, s);
             done = true;
         }

@@ -125,7 +125,8 @@ struct dg_mesh {
     double* d_tab64 = nullptr;
     float* d_tab32 = nullptr;
     double* d_gt = nullptr;     // [T][6] neighbour gradient maps on the edges (see AsmArgs::mL)
-    double* d_ten64 = nullptr;  // [3][TenStage::COUNT] n x n staged tensors per kappa (k <= 3)
+    double* d_ten64 = nullptr;  // [3][TenStage::COUNT] staged tensors per kappa (k <= 3): n columns (trial j) of
+                                //   test values i, each column zero-padded to whole 16-byte words
     float* d_ten32 = nullptr;
     double* d_p1map = nullptr;  // [3][3]: P1 coefficients from vertex values (k >= 1)
     double* d_mref = nullptr;   // [n][n] reference mass matrix (monomial basis only)

@@ -537,8 +537,22 @@ extern "C" int32_t dg_mesh_create_basis(const double* xy, int64_t n_nodes, const
             const std::vector<double> s = stage_tensors(degree, ref, (double)kap);
             ten.insert(ten.end(), s.begin(), s.end());
         }
-        const std::vector<float> ten32(ten.begin(), ten.end());
-        st = upload(&m->d_ten64, ten);
+        // each tensor as n columns (trial j) of values (test i), every column padded
+        // with zeros to whole 16-byte words of the precision (the kernel's layout)
+        const int n = (degree + 1) * (degree + 2) / 2;
+        auto padded = [&](int per_word) {
+            const int np = (n + per_word - 1) / per_word * per_word;
+            const size_t nt = ten.size() / ((size_t)n * n);
+            std::vector<double> out(nt * n * np, 0.0);
+            for (size_t t = 0; t < nt; ++t)
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < n; ++i) out[(t * n + j) * np + i] = ten[(t * n + j) * n + i];
+            return out;
+        };
+        const std::vector<double> ten64 = padded(2);
+        const std::vector<double> t32 = padded(4);
+        const std::vector<float> ten32(t32.begin(), t32.end());
+        st = upload(&m->d_ten64, ten64);
         if (st == DG_OK) st = upload(&m->d_ten32, ten32);
     }
     if (st == DG_OK) {

@@ -876,44 +876,62 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
             for (int t = threadIdx.x; t <= j + i + 1; t += BG_T) Hr[(int64_t)t * ldr + j + i] = colv[i][t];
     }
     // the rotations of earlier blocks on all columns at once, then the columns
-    // in turn: this block's earlier rotations, new rotation, estimate, stop test
+    // in turn (thread 0, this block's rotations and residual estimates held in
+    // LDS): this block's earlier rotations, new rotation, estimate, stop
+    // test; then the columns taken, their rotations and estimates written out
+    // (no global round trip between the columns)
     bg_rotate_cols(colv, ncol, j, cs, sn, sc, ss);
-    __shared__ int stop_s;
-    for (int i = 0; i < ncol; ++i) {
-        const int k = j + i;
-        if (threadIdx.x == 0) {
+    __shared__ int taken_s, stop_s;
+    __shared__ double bc[S], bs[S], gk[S + 1];  // this block's rotations and estimates (thread 0)
+    if (threadIdx.x == 0) {
+        const double tol = scal[S_CYCTOL];
+        gk[0] = g[j];
+        int taken = ncol, stop = 0;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (i >= ncol) break;
             double* cv = colv[i];
             double a = cv[j];
-            for (int t = j; t < k; ++t) {
-                const double b = cv[t + 1];
-                cv[t] = cs[t] * a + sn[t] * b;
-                a = -sn[t] * a + cs[t] * b;
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                if (t >= i) break;
+                const double b = cv[j + t + 1];
+                cv[j + t] = bc[t] * a + bs[t] * b;
+                a = -bs[t] * a + bc[t] * b;
             }
+            const int k = j + i;
             const double b = cv[k + 1];
             const double d = sqrt(a * a + b * b);
-            cs[k] = d == 0.0 ? 1.0 : a / d;
-            sn[k] = d == 0.0 ? 0.0 : b / d;
-            colv[i][k] = d;
-            g[k + 1] = -sn[k] * g[k];
-            g[k] = cs[k] * g[k];
-            const bool last = i == ncol - 1;
-            stop_s = (fabs(g[k + 1]) <= scal[S_CYCTOL] || k + 1 >= mcyc || (last && cut_s)) ? 1 : 0;
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t <= k; t += BG_T) H[t + (int64_t)k * ldh] = colv[i][t];
-        if (stop_s) {
-            if (threadIdx.x == 0) {
-                ctrl[C_J] = k + 1;
-                ctrl[C_REORTH] = 0;
-                ctrl[C_STOP] = 1;
+            bc[i] = d == 0.0 ? 1.0 : a / d;
+            bs[i] = d == 0.0 ? 0.0 : b / d;
+            cv[k] = d;
+            gk[i + 1] = -bs[i] * gk[i];
+            gk[i] = bc[i] * gk[i];
+            if (fabs(gk[i + 1]) <= tol || k + 1 >= mcyc || (i == ncol - 1 && cut_s)) {
+                taken = i + 1;
+                stop = 1;
+                break;
             }
-            return;
         }
-        __syncthreads();  // every thread has read stop_s before thread 0 sets it again
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (i < taken) {
+                cs[j + i] = bc[i];
+                sn[j + i] = bs[i];
+                g[j + i] = gk[i];
+            }
+        g[j + taken] = gk[taken];
+        taken_s = taken;
+        stop_s = stop;
     }
+    __syncthreads();
+    const int taken = taken_s;
+    for (int i = 0; i < taken; ++i)
+        for (int t = threadIdx.x; t <= j + i; t += BG_T) H[t + (int64_t)(j + i) * ldh] = colv[i][t];
     if (threadIdx.x == 0) {
-        ctrl[C_J] = j + ncol;
+        ctrl[C_J] = j + taken;
         ctrl[C_REORTH] = 0;
+        if (stop_s) ctrl[C_STOP] = 1;
     }
 }
 

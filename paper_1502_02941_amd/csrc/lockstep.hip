@@ -1027,44 +1027,57 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
             for (int t = threadIdx.x; t <= j + ii + 1; t += 64) Hr[t + (int64_t)(j + ii) * ldr] = dyn[ii * ldc + t];
     }
     // earlier blocks' rotations on all columns at once, then the columns in turn
+    // (thread 0, this block's rotations and estimates in LDS: no global round
+    // trip between the columns), then the columns taken written out
     ls_rotate_cols(dyn, ldc, ncol, j, cs, sn, sc, ss);
-    for (int ii = 0; ii < ncol; ++ii) {
-        const int k = j + ii;
-        double* cv = dyn + ii * ldc;
-        if (threadIdx.x == 0) {
+    __shared__ double bc[S], bs[S], gk[S + 1];
+    __shared__ int taken_s;
+    if (threadIdx.x == 0) {
+        gk[0] = g[j];
+        int taken = ncol, stop = 0;
+        for (int ii = 0; ii < ncol; ++ii) {
+            const int k = j + ii;
+            double* cv = dyn + ii * ldc;
             double a = cv[j];
-            for (int t = j; t < k; ++t) {
-                const double bv = cv[t + 1];
-                cv[t] = cs[t] * a + sn[t] * bv;
-                a = -sn[t] * a + cs[t] * bv;
+            for (int t = 0; t < ii; ++t) {
+                const double bv = cv[j + t + 1];
+                cv[j + t] = bc[t] * a + bs[t] * bv;
+                a = -bs[t] * a + bc[t] * bv;
             }
             const double bv = cv[k + 1];
             const double d = sqrt(a * a + bv * bv);
-            cs[k] = d == 0.0 ? 1.0 : a / d;
-            sn[k] = d == 0.0 ? 0.0 : bv / d;
+            bc[ii] = d == 0.0 ? 1.0 : a / d;
+            bs[ii] = d == 0.0 ? 0.0 : bv / d;
             cv[k] = d;
-            g[k + 1] = -sn[k] * g[k];
-            g[k] = cs[k] * g[k];
-            stop_s = (fabs(g[k + 1]) <= St.cyctol || k + 1 >= mcyc || (ii == ncol - 1 && cut_s)) ? 1 : 0;
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t <= k; t += 64) H[t + (int64_t)k * ldh] = cv[t];
-        if (stop_s) {
-            if (threadIdx.x == 0) {
-                St.jb = j;
-                St.bstep = step;
-                St.J = k + 1;
-                St.stop = 1;
-                atomicSub(A.counters + 1, 1);
+            gk[ii + 1] = -bs[ii] * gk[ii];
+            gk[ii] = bc[ii] * gk[ii];
+            if (fabs(gk[ii + 1]) <= St.cyctol || k + 1 >= mcyc || (ii == ncol - 1 && cut_s)) {
+                taken = ii + 1;
+                stop = 1;
+                break;
             }
-            return;
         }
-        __syncthreads();  // every thread has read stop_s before thread 0 sets it again
+        for (int ii = 0; ii < taken; ++ii) {
+            cs[j + ii] = bc[ii];
+            sn[j + ii] = bs[ii];
+            g[j + ii] = gk[ii];
+        }
+        g[j + taken] = gk[taken];
+        taken_s = taken;
+        stop_s = stop;
     }
+    __syncthreads();
+    const int taken = taken_s;
+    for (int ii = 0; ii < taken; ++ii)
+        for (int t = threadIdx.x; t <= j + ii; t += 64) H[t + (int64_t)(j + ii) * ldh] = dyn[ii * ldc + t];
     if (threadIdx.x == 0) {
         St.jb = j;
         St.bstep = step;
-        St.J = j + ncol;
+        St.J = j + taken;
+        if (stop_s) {
+            St.stop = 1;
+            atomicSub(A.counters + 1, 1);
+        }
     }
 }
 
