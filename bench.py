@@ -449,10 +449,15 @@ def bench_c4(args, api, W, torch):
         "forms": forms,
         "roofline": {"bound": "hbm", "kernel": "batch_assemble_kernel + solve kernels of the tuned split (whole batch)",
                      "achieved": F["achieved_GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": F["achieved_GB_s"] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": F["achieved_GB_s"] / HBM_PEAK_GBS,
+                     # HBM bytes of one whole 4096-instance batch (the unit `achieved` is per)
+                     "traffic": measured_traffic("c4_" + best_form, best_form) if len(insts) == 4096 else None,
+                     "algorithmic_bytes_per_batch": F["algorithmic_GB_per_batch"] * 1e9},
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c4(insts),
     }
     print(json.dumps(line), flush=True)
+    if args.profile_run:
+        copy_probe(torch)
 
 
 def bench_c1(args, api, W, torch):
