@@ -624,10 +624,16 @@ def bench_c3(args, api, W, torch):
     m, prob = build_c3(api, W)
     mesh = api.Mesh.from_arrays(m, 3)
     log("c3: %d triangles, %d dofs, nnzb %d" % (mesh.T, mesh.n_dofs, mesh.nnzb))
+    # the default vector-ALU tensor kernel, and the matrix-core (MFMA) path for comparison
+    forms = (("fp64", api.F64, api.PART_ALL), ("fp32", api.F32, api.PART_ALL),
+             ("fp64_matrix_core", api.F64, api.PART_ALL | api.ASM_MATRIX_CORE),
+             ("fp32_matrix_core", api.F32, api.PART_ALL | api.ASM_MATRIX_CORE))
     if args.profile_run:
-        vals, rhs = mesh.alloc_system(api.F64)
-        for _ in range(3):
-            api.assemble(mesh, prob, prec=api.F64, vals=vals, rhs=rhs)
+        for name, prec, parts in forms:
+            vals, rhs = mesh.alloc_system(prec)
+            for _ in range(3):
+                api.assemble(mesh, prob, prec=prec, parts=parts, vals=vals, rhs=rhs)
+            del vals, rhs
         torch.cuda.synchronize()
         copy_probe(torch)
         return
@@ -635,21 +641,26 @@ def bench_c3(args, api, W, torch):
     res = {}
     systems = {}
     reps = max(args.steps, 1) * 10
-    for name, prec in (("fp64", api.F64), ("fp32", api.F32)):
+    for name, prec, parts in forms:
         vals, rhs = mesh.alloc_system(prec)
         for _ in range(max(args.warmup, 1)):
-            api.assemble(mesh, prob, prec=prec, vals=vals, rhs=rhs)
+            api.assemble(mesh, prob, prec=prec, parts=parts, vals=vals, rhs=rhs)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record(stream)
         for _ in range(reps):
-            api.assemble(mesh, prob, prec=prec, vals=vals, rhs=rhs)
+            api.assemble(mesh, prob, prec=prec, parts=parts, vals=vals, rhs=rhs)
         ev[1].record(stream)
         ev[1].synchronize()
         t = ev[0].elapsed_time(ev[1]) / reps * 1e-3
         nbytes = assembly_bytes(mesh, 8 if prec == api.F64 else 4, f_points=False)
         res[name] = {"us": t * 1e6, "melem_s": mesh.T / t / 1e6, "GB_s": nbytes / t / 1e9,
                      "algorithmic_bytes": nbytes}
-        systems[name] = (vals, rhs)
+        if parts == api.PART_ALL:
+            systems[name] = (vals, rhs)
+        else:
+            v0, r0 = systems[name.replace("_matrix_core", "")]
+            res[name]["rel_diff_vs_default"] = float((vals.double() - v0.double()).norm() / v0.double().norm())
+            del vals, rhs
         log("%s: %.1f us, %.0f Melem/s, %.0f GB/s" % (name, t * 1e6, mesh.T / t / 1e6, nbytes / t / 1e9))
     v64, r64 = systems["fp64"]
     v32, r32 = systems["fp32"]

@@ -74,6 +74,16 @@ typedef enum { DG_BASIS_DUBINER = 0, DG_BASIS_MONOMIAL = 1 } dg_basis;
 
 /* Parts of a_h = D_h + C_h + R_h (section 2.3 eq. (dgscheme)) selected by dg_assemble. */
 enum { DG_PART_D = 1, DG_PART_C = 2, DG_PART_R = 4, DG_PART_ALL = 7 };
+/* Added to `parts`: with degree 2 or 3 and constant eps and alpha, assemble the
+ * blocks of 16 elements at a time as matrix-core (MFMA) products of their
+ * coefficient rows with the reference tensors (two launches: coefficients, then
+ * products) instead of with the default vector-ALU tensor kernel (one lane per
+ * element and trial function).  Both compute the same terms; the results differ
+ * by rounding only.  The matrix-core path keeps a [47][n_elems] FP64-sized
+ * coefficient array in the mesh, allocated by its first call (DG_ERR_OOM if
+ * that fails): dg_assemble calls on one mesh that overlap in time must not both
+ * use it.  Ignored for other degrees and for variable eps or alpha. */
+enum { DG_ASM_MATRIX_CORE = 256 };
 
 /* A coefficient or data field of eq. (1):
  *   DG_CONST     c[0]

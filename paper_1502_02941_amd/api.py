@@ -21,6 +21,7 @@ NIPG, SIPG, IIPG = 1, 2, 3
 F64, F32 = 0, 1
 DUBINER, MONOMIAL = 0, 1  # element bases (dg_basis)
 PART_D, PART_C, PART_R, PART_ALL = 1, 2, 4, 7
+ASM_MATRIX_CORE = 256  # parts flag: matrix-core (MFMA) tensor products instead of the vector-ALU kernel (k = 2, 3)
 CONST, AFFINE, GAUSS_SUM, QPOINTS = 0, 1, 2, 3
 MAX_DEGREE = 4
 

@@ -560,6 +560,444 @@ __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const Asm
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core assembly (k = 2, 3).  Every block the tensor kernel sums is a
+// combination of reference tensors with per-element coefficients, so for a
+// tile of 16 elements each block type is the product C B of their 16 x K
+// coefficient rows C with K tensors B laid out as rows of n^2 entries (MfmaSet).
+// Two launches:
+//   mf_coef_kernel        one lane per element: the element's coefficients (as
+//                         rows of a coefficient array, element-minor, so that
+//                         the stores coalesce) and the volume term of its load
+//                         vector;
+//   assemble_mfma_kernel  v_mfma_*_16x16x4 products, four tensors per step:
+//                         lane (q, r) = (lane / 16, lane % 16) supplies the
+//                         coefficient of tensor 4 s + q for the tile's element r
+//                         and the value of that tensor at entry 16 c + r of
+//                         column tile c, and receives entry 16 c + r of four of
+//                         the tile's elements.
+// A tensor value read from LDS then serves 16 elements instead of one, and the
+// product kernel does little besides reading coefficients, multiplying and
+// storing.  A wave takes 32 consecutive elements as two tiles, the even and
+// the odd ones: on a structured mesh the two triangle types alternate, and
+// each type has one neighbour edge lp per local edge, so a tile needs one
+// neighbour tensor set per edge (other meshes take one product per lp present
+// in the tile).  The coefficients of the next tile are loaded before the
+// stores of the current one are issued, and every tile issues the same number
+// of stores (buffer stores whose out-of-range lanes the hardware drops), so
+// that a wave waits for its loads without waiting for its earlier stores (both
+// share one completion counter).  Edges on which b . n changes sign add their
+// upwind term point by point, as products with point tensors read from global
+// memory (such edges are rare; those reads do wait for the stores before them).
+// ---------------------------------------------------------------------------
+constexpr int MF_BLOCK = 512;
+
+// Both take A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k, and
+// leave D[i][j] in lane j + 16 g, register v: the FP64 product with rows
+// i = g + 4 v, the FP32 one with rows i = 4 g + v (measured on gfx950).
+template <typename R>
+struct MfmaOp;
+template <>
+struct MfmaOp<double> {
+    typedef double V __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V mac(double a, double b, V c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
+    static __device__ __forceinline__ void store(double x, __amdgpu_buffer_rsrc_t rs, uint32_t off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(MfU2, x), rs, (int)off, 0, 0);
+    }
+    typedef unsigned int MfU2 __attribute__((ext_vector_type(2)));
+};
+template <>
+struct MfmaOp<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V mac(float a, float b, V c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+    static __device__ __forceinline__ void store(float x, __amdgpu_buffer_rsrc_t rs, uint32_t off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), rs, (int)off, 0, 0);
+    }
+};
+
+// A byte range for buffer stores: offsets at or beyond MF_DROP are outside it
+// and the hardware discards those lanes' stores.
+constexpr uint32_t MF_DROP = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mf_range(void* base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)(MF_DROP - 16u), 0x00020000);
+}
+
+// c[4 s + q] for the lane's q without indexing registers by a lane value
+template <typename R>
+__device__ __forceinline__ R pick4(int q, double c0, double c1, double c2, double c3)
+{
+    return (R)(q == 0 ? c0 : (q == 1 ? c1 : (q == 2 ? c2 : c3)));
+}
+
+// LDS tables of the product kernel besides the tensor sets (precision R):
+// the edge parameters and weights [8] each (zero beyond the rule).
+template <int K>
+struct MfTables {
+    static constexpr int ET = 0, EW = 8, SIZE = 16;
+};
+
+// Rows of the coefficient array (precision R, row-major [ROWS][T]).
+struct MfCoef {
+    static constexpr int VOL = 0;    // 10: SXX SXY SYY CX CY MASS VB0..VB3 (MfmaSet diagonal rows 0..9)
+    static constexpr int EDGE = 10;  // 3 x 4: E, kappa TX - DX, kappa TY - DY, E1 of edge l (0 on Neumann edges)
+    static constexpr int OFF = 22;   // 3 x 6: F, GX, GY, HX, HY, F1 of the neighbour block across edge l
+    static constexpr int UPW = 40;   // 3 x 2: |e| b . n at vertex l and its change along edge l (affine b)
+    static constexpr int MIX = 46;   // bit l: b . n changes sign along edge l (affine b)
+    static constexpr int ROWS = 47;
+};
+
+// Coefficients and the volume term of the load vector, one lane per element.
+// BAFF: b affine (else constant); FK: f constant (0), point values (1),
+// evaluated at the volume points (2).
+template <int K, typename R, bool BAFF, int FK>
+__global__ __launch_bounds__(256) void mf_coef_kernel(const AsmArgs a, const int32_t* __restrict__ ebits,
+                                                      R* __restrict__ coef)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NQ = L.nq, Q = L.nqe;
+    __shared__ R sw[NQ * (N + 3)];  // w[NQ], phi[NQ][N], xi[NQ], eta[NQ] (stage_point_tables)
+    if (a.rhs) stage_point_tables<K, R>(a, sw, 256);
+    __syncthreads();
+    const int64_t el = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (el >= a.T) return;
+    const int64_t T = a.T;
+    const R* __restrict__ tab = (const R*)a.tab;
+    const double* p = a.xy + 6 * el;
+    const double X1 = p[0], Y1 = p[1], X2 = p[2], Y2 = p[3], X3 = p[4], Y3 = p[5];
+    const double* pm = a.mL + 6 * el;
+    const int32_t bits = ebits[el];
+
+    const double cD = (a.parts & DG_PART_D) ? 1.0 : 0.0;
+    const double cC = (a.parts & DG_PART_C) ? 1.0 : 0.0;
+    const double cR = (a.parts & DG_PART_R) ? 1.0 : 0.0;
+    const double deps = cD * a.eps.c[0];
+    const double bx1 = a.bx.c[1], bx2 = a.bx.c[2], by1 = a.by.c[1], by2 = a.by.c[2];
+    const double dj11 = X2 - X1, dj12 = X3 - X1, dj21 = Y2 - Y1, dj22 = Y3 - Y1;
+    const double det = dj11 * dj22 - dj12 * dj21;
+    const double inv = 1.0 / det;
+    const double G11 = dj22 * inv, G12 = -dj21 * inv, G21 = -dj12 * inv, G22 = dj11 * inv;
+    const double t_first = (double)tab[L.et], t_last = (double)tab[L.et + Q - 1];
+    auto put = [&](int row, double v) { coef[row * T + el] = (R)v; };
+
+    // volume terms (same coefficients as tensor_element)
+    {
+        const double ed = deps * inv;
+        const double bx0 = a.bx.c[0] + bx1 * X1 + bx2 * Y1, by0 = a.by.c[0] + by1 * X1 + by2 * Y1;
+        const double bxa = bx1 * dj11 + bx2 * dj21, bxb = bx1 * dj12 + bx2 * dj22;  // d bx / d xi, d eta
+        const double bya = by1 * dj11 + by2 * dj21, byb = by1 * dj12 + by2 * dj22;
+        put(MfCoef::VOL + 0, ed * (dj22 * dj22 + dj12 * dj12));
+        put(MfCoef::VOL + 1, -ed * (dj22 * dj21 + dj12 * dj11));
+        put(MfCoef::VOL + 2, ed * (dj21 * dj21 + dj11 * dj11));
+        put(MfCoef::VOL + 3, cC * (dj22 * bx0 - dj12 * by0));
+        put(MfCoef::VOL + 4, cC * (dj11 * by0 - dj21 * bx0));
+        put(MfCoef::VOL + 5, cR * a.alpha.c[0] * det);
+        put(MfCoef::VOL + 6, cC * (dj22 * bxa - dj12 * bya));
+        put(MfCoef::VOL + 7, cC * (dj22 * bxb - dj12 * byb));
+        put(MfCoef::VOL + 8, cC * (dj11 * bya - dj21 * bxa));
+        put(MfCoef::VOL + 9, cC * (dj11 * byb - dj21 * bxb));
+    }
+    // edges: |e| n = (dy, -dx) along the edge from vertex l to vertex l+1
+    const double evx[3] = {dj11, dj12 - dj11, -dj12}, evy[3] = {dj21, dj22 - dj21, -dj22};
+    const double vx[3] = {X1, X2, X3}, vy[3] = {Y1, Y2, Y3};
+    int32_t mix = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const bool has = ((bits >> (8 + l)) & 1) != 0, neu = ((bits >> (12 + l)) & 1) != 0;
+        const double nx = evy[l], ny = -evx[l];
+        const double mKx = G11 * nx + G21 * ny, mKy = G12 * nx + G22 * ny;
+        const double sig = has ? a.sigma : a.sigma_D;
+        const double pl = a.b0 == 1.0 ? sig : sig * pow(sqrt(nx * nx + ny * ny), 1.0 - a.b0);
+        const double blA = (a.bx.c[0] + bx1 * vx[l] + bx2 * vy[l]) * nx + (a.by.c[0] + by1 * vx[l] + by2 * vy[l]) * ny;
+        const double dbl = (bx1 * evx[l] + bx2 * evy[l]) * nx + (by1 * evx[l] + by2 * evy[l]) * ny;
+        const double bl0 = blA + t_first * dbl, bl1 = blA + t_last * dbl;
+        const bool inflow = bl0 < 0.0 && bl1 < 0.0;
+        const bool mixed = (bl0 < 0.0) != (bl1 < 0.0);
+        const double es = deps * pl + cC * (inflow ? -blA : 0.0);
+        const double es1 = cC * (inflow ? -dbl : 0.0);
+        const double dc = deps * (has ? 0.5 : 1.0);
+        put(MfCoef::EDGE + 4 * l, neu ? 0.0 : es);
+        put(MfCoef::EDGE + 4 * l + 1, neu ? 0.0 : dc * mKx);
+        put(MfCoef::EDGE + 4 * l + 2, neu ? 0.0 : dc * mKy);
+        put(MfCoef::EDGE + 4 * l + 3, neu ? 0.0 : es1);
+        const double hk = 0.5 * deps, hkk = 0.5 * deps * a.kappa;
+        put(MfCoef::OFF + 6 * l, has ? -es : 0.0);
+        put(MfCoef::OFF + 6 * l + 1, has ? -hk * pm[2 * l] : 0.0);
+        put(MfCoef::OFF + 6 * l + 2, has ? -hk * pm[2 * l + 1] : 0.0);
+        put(MfCoef::OFF + 6 * l + 3, has ? -hkk * mKx : 0.0);
+        put(MfCoef::OFF + 6 * l + 4, has ? -hkk * mKy : 0.0);
+        put(MfCoef::OFF + 6 * l + 5, has ? -es1 : 0.0);
+        if constexpr (BAFF) {
+            coef[(MfCoef::UPW + 2 * l) * T + el] = (R)blA;
+            coef[(MfCoef::UPW + 2 * l + 1) * T + el] = (R)dbl;
+            if (mixed) mix |= 1 << l;
+        }
+    }
+    if constexpr (BAFF) coef[MfCoef::MIX * T + el] = (R)mix;
+
+    // volume term of the load vector: det sum_g w_g f(x_g) phi_j(x_g)
+    if (a.rhs) {
+        double rj[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) rj[j] = 0.0;
+        const double* fe = a.f.vals + el * NQ;
+#pragma unroll 1
+        for (int g = 0; g < NQ; ++g) {
+            double fg;
+            if constexpr (FK == 1) {
+                fg = fe[g];
+            } else if constexpr (FK == 0) {
+                fg = a.f.c[0];
+            } else {
+                const double xi = (double)sw[NQ * (N + 1) + g], eta = (double)sw[NQ * (N + 2) + g];
+                fg = field_at<double>(a.f, X1 + dj11 * xi + dj12 * eta, Y1 + dj21 * xi + dj22 * eta, 0);
+            }
+            const double wf = (double)sw[g] * fg;
+#pragma unroll
+            for (int j = 0; j < N; ++j) rj[j] += wf * (double)sw[NQ + g * N + j];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) ((R*)a.rhs)[el * N + j] = (R)(rj[j] * det);
+    }
+}
+
+// The coefficients a lane reads for its row's element (one tile ahead): the
+// one of each step that it supplies, the block row's first slot and the bits.
+struct MfRowA {
+    double vol[3];            // steps of the volume tensors (the third: affine b)
+    double edge[3];           // diagonal step of edge l
+    double off0[3], off1[3];  // the two steps of edge l's neighbour block
+    int32_t bits, s0, mix;
+};
+
+template <typename R, bool BAFF>
+__device__ __forceinline__ void mf_load_row(const R* __restrict__ coef, const int32_t* __restrict__ ebits,
+                                            const int32_t* __restrict__ row_ptr, const int64_t T, const int64_t el,
+                                            const int q, MfRowA& d)
+{
+    auto at = [&](int row) { return (double)coef[row * T + el]; };
+    const int q2 = q < 2 ? q : 0;  // rows 4 s + q past the end of a set read row 0 and supply zero
+    d.vol[0] = at(MfCoef::VOL + q);
+    d.vol[1] = at(MfCoef::VOL + 4 + q);
+    d.vol[2] = BAFF ? at(MfCoef::VOL + 8 + q2) : 0.0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        d.edge[l] = at(MfCoef::EDGE + 4 * l + q);
+        d.off0[l] = at(MfCoef::OFF + 6 * l + q);
+        d.off1[l] = at(MfCoef::OFF + 6 * l + 4 + q2);
+    }
+    d.bits = ebits[el];
+    d.s0 = row_ptr[el];
+    d.mix = BAFF ? (int32_t)at(MfCoef::MIX) : 0;
+    if (q >= 2) {
+        d.vol[2] = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) d.off1[l] = 0.0;
+    }
+}
+
+// One tile of 16 elements: rows r are the elements e_first + 2 r (those at or
+// beyond T are copies of element T - 1 and store nothing); el is row r's
+// element (clamped).
+template <int K, typename R, bool BAFF>
+__device__ __forceinline__ void mf_tile(const AsmArgs& a, const R* st, const R* tb, const R* __restrict__ tp,
+                                        const R* __restrict__ coef, const MfRowA& d, const int64_t el,
+                                        const int64_t e_first, const int q, const int r)
+{
+    constexpr TabLayout L(K);
+    constexpr int N = L.n, NN = N * N, Q = L.nqe;
+    constexpr int NNP = MfmaSet::nnp(K), CT = NNP / 16;
+    static_assert(Q <= MfmaSet::PTS && MfmaSet::PTS == 8, "two steps of point tensors per edge");
+    using Op = MfmaOp<R>;
+    using V = typename Op::V;
+    const int32_t bits = d.bits;
+    const double cC = (a.parts & DG_PART_C) ? 1.0 : 0.0;
+
+    V acc[CT];
+    auto clear = [&]() {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] = V{0, 0, 0, 0};
+    };
+    // one step of four tensors; B points at this lane's tensor row 4 s + q
+    auto step = [&](R av, const R* B) {
+        R b[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b[c] = B[16 * c + r];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] = Op::mac(av, b[c], acc[c]);
+    };
+    // the block of each row at its slot (slot < 0: none); a fixed number of stores
+    const int32_t sbase = __builtin_amdgcn_readfirstlane(d.s0);
+    const __amdgpu_buffer_rsrc_t rv = mf_range((R*)a.vals + (int64_t)sbase * NN);
+    auto store = [&](int32_t slot) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t sl = __shfl(slot, Op::row(q, i), 64);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const bool ok = sl >= 0 && 16 * c + r < NN;
+                Op::store(acc[c][i], rv, ok ? (uint32_t)(((sl - sbase) * NN + 16 * c + r) * (int)sizeof(R)) : MF_DROP);
+            }
+        }
+    };
+    // point-by-point upwind term of edge l (rows whose edge l is mixed): weight
+    // of point g = 4 s + q, scaled by cC on the diagonal and -cC across the edge
+    auto point_coef = [&](int l, int s, double scale) -> R {
+        const int g = 4 * s + q;
+        const int64_t T = a.T;
+        const double blA = (double)coef[(MfCoef::UPW + 2 * l) * T + el];
+        const double dbl = (double)coef[(MfCoef::UPW + 2 * l + 1) * T + el];
+        const double bl = blA + (double)tb[MfTables<K>::ET + g] * dbl;
+        return (g < Q && bl < 0.0) ? (R)(scale * (double)tb[MfTables<K>::EW + g] * -bl) : R(0);
+    };
+    const bool valid = e_first + 2 * r < a.T;
+
+    // diagonal block: volume tensors (two steps, a third for affine b), then one step per edge
+    clear();
+    step((R)d.vol[0], st + q * NNP);
+    step((R)d.vol[1], st + (4 + q) * NNP);
+    if constexpr (BAFF) step((R)d.vol[2], st + (8 + q) * NNP);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        step((R)d.edge[l], st + (12 + 4 * l + q) * NNP);
+        if constexpr (BAFF) {
+            const bool mx = ((d.mix >> l) & 1) && !((bits >> (12 + l)) & 1);
+            if (__any(mx)) {
+                step(mx ? point_coef(l, 0, cC) : R(0), tp + (l * MfmaSet::PTS + q) * NNP);
+                step(mx ? point_coef(l, 1, cC) : R(0), tp + (l * MfmaSet::PTS + 4 + q) * NNP);
+            }
+        }
+    }
+    store(valid ? d.s0 : -1);
+
+    // neighbour blocks, in the order of the block row (edges with a neighbour)
+    int32_t slot = d.s0 + 1;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const bool hl = ((bits >> (8 + l)) & 1) != 0;
+        const int lp = hl ? (bits >> (2 * l)) & 3 : -1;
+        const int32_t my_slot = valid && hl ? slot : -1;
+        if (hl) ++slot;
+        clear();
+#pragma unroll 1
+        for (int lq = 0; lq < 3; ++lq) {
+            const bool mine = lp == lq;
+            if (!__any(mine)) continue;
+            const R* B = st + (MfmaSet::DIAG + MfmaSet::OFF * (3 * l + lq) + q) * NNP;
+            step(mine ? (R)d.off0[l] : R(0), B);
+            step(mine ? (R)d.off1[l] : R(0), B + 4 * NNP);
+            if constexpr (BAFF) {
+                const bool mx = mine && ((d.mix >> l) & 1);
+                if (__any(mx)) {
+                    const R* P = tp + ((3 + 3 * l + lq) * MfmaSet::PTS + q) * NNP;
+                    step(mx ? point_coef(l, 0, -cC) : R(0), P);
+                    step(mx ? point_coef(l, 1, -cC) : R(0), P + 4 * NNP);
+                }
+            }
+        }
+        store(my_slot);
+    }
+}
+
+template <int K, typename R, bool BAFF>
+__global__ __launch_bounds__(MF_BLOCK) void assemble_mfma_kernel(const AsmArgs a, const int32_t* __restrict__ ebits,
+                                                                 const R* __restrict__ tm, const R* __restrict__ tp,
+                                                                 const R* __restrict__ coef)
+{
+    constexpr TabLayout L(K);
+    constexpr int Q = L.nqe, WPB = MF_BLOCK / 64;
+    using TB = MfTables<K>;
+    constexpr int NT = MfmaSet::COUNT * MfmaSet::nnp(K);
+    constexpr int RPW = 16 / (int)sizeof(R);
+    static_assert(NT % RPW == 0, "tensor sets are whole 16-byte words");
+    __shared__ __align__(16) R st[NT + TB::SIZE];
+    R* tb = st + NT;
+    {
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(tm);
+        uint4* dst = reinterpret_cast<uint4*>(st);
+        for (int t = threadIdx.x; t < NT / RPW; t += MF_BLOCK) dst[t] = src[t];
+        const R* __restrict__ tab = (const R*)a.tab;
+        for (int t = threadIdx.x; t < 8; t += MF_BLOCK) {
+            tb[TB::ET + t] = t < Q ? tab[L.et + t] : R(0);
+            tb[TB::EW + t] = t < Q ? tab[L.ew + t] : R(0);
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    const int64_t nwt = (a.T + 31) / 32;  // wave tiles of 32 elements, two tiles each
+    const int64_t stride = (int64_t)gridDim.x * WPB;
+    const int64_t w0 = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+    if (w0 >= nwt) return;
+    auto elem = [&](int64_t wt, int par) {
+        const int64_t e = wt * 32 + 2 * r + par;
+        return e < a.T ? e : a.T - 1;
+    };
+    MfRowA cur;
+    int64_t ecur = elem(w0, 0);
+    mf_load_row<R, BAFF>(coef, ebits, a.row_ptr, a.T, ecur, q, cur);
+    for (int64_t pass = 0;; ++pass) {
+        const int par = (int)(pass & 1);
+        const int64_t wt = w0 + (pass >> 1) * stride;
+        const int64_t wn = par ? wt + stride : wt;  // the next tile: the odd half, or the next wave tile
+        const bool more = wn < nwt;
+        const int64_t enext = more ? elem(wn, par ^ 1) : a.T - 1;
+        MfRowA nxt;
+        mf_load_row<R, BAFF>(coef, ebits, a.row_ptr, a.T, enext, q, nxt);
+        mf_tile<K, R, BAFF>(a, st, tb, tp, coef, cur, ecur, wt * 32 + par, q, r);
+        if (!more) break;
+        cur = nxt;
+        ecur = enext;
+    }
+}
+
+template <int K, typename R, bool BAFF, int FK>
+static void launch_mfma_v(const dg_mesh* m, const AsmArgs& a, const R* tm, const R* tp, hipStream_t s)
+{
+    static int per_cu = 0, cus = 0;
+    if (per_cu == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, assemble_mfma_kernel<K, R, BAFF>, MF_BLOCK, 0);
+        if (per_cu < 1) per_cu = 1;
+        if (cus < 1) cus = 1;
+    }
+    R* coef = (R*)m->d_mfcoef;
+    hipLaunchKernelGGL((mf_coef_kernel<K, R, BAFF, FK>), dim3((unsigned)((m->T + 255) / 256)), dim3(256), 0, s, a,
+                       m->d_ebits, coef);
+    const int64_t nwt = (m->T + 31) / 32;
+    const int64_t want = (nwt + MF_BLOCK / 64 - 1) / (MF_BLOCK / 64);
+    const int64_t grid = std::min<int64_t>(want, (int64_t)per_cu * cus);
+    hipLaunchKernelGGL((assemble_mfma_kernel<K, R, BAFF>), dim3((unsigned)grid), dim3(MF_BLOCK), 0, s, a,
+                       m->d_ebits, tm, tp, (const R*)coef);
+}
+
+template <int K, typename R>
+static void launch_mfma(const dg_mesh* m, const AsmArgs& a, const R* tm, const R* tp, hipStream_t s)
+{
+    const bool baff = a.bx.c[1] != 0.0 || a.bx.c[2] != 0.0 || a.by.c[1] != 0.0 || a.by.c[2] != 0.0;
+    const int fk = a.f.kind == DG_CONST ? 0 : (a.f.kind == DG_QPOINTS ? 1 : 2);
+    if (baff) {
+        if (fk == 0) launch_mfma_v<K, R, true, 0>(m, a, tm, tp, s);
+        else if (fk == 1) launch_mfma_v<K, R, true, 1>(m, a, tm, tp, s);
+        else launch_mfma_v<K, R, true, 2>(m, a, tm, tp, s);
+    } else {
+        if (fk == 0) launch_mfma_v<K, R, false, 0>(m, a, tm, tp, s);
+        else if (fk == 1) launch_mfma_v<K, R, false, 1>(m, a, tm, tp, s);
+        else launch_mfma_v<K, R, false, 2>(m, a, tm, tp, s);
+    }
+}
+
 // eps and alpha constant (the affine form with zero slopes), b affine
 static bool constant_coefficients(const AsmArgs& a)
 {
@@ -580,11 +1018,28 @@ static int launch_k(const dg_mesh* m, const AsmArgs& a, hipStream_t s)
     if constexpr (K <= 3) {
         const R* ten = std::is_same<R, double>::value ? (const R*)(const void*)m->d_ten64
                                                       : (const R*)(const void*)m->d_ten32;
-        if (a.vals && ten && constant_coefficients(a)) {
+        // the staged sets of this method (kappa = -1, 0, 1)
+        const int ki = a.kappa < 0 ? 0 : (a.kappa > 0 ? 2 : 1);
+        if constexpr (K >= 2) {
+            const R* tm = std::is_same<R, double>::value ? (const R*)(const void*)m->d_tm64
+                                                         : (const R*)(const void*)m->d_tm32;
+            const R* tp = std::is_same<R, double>::value ? (const R*)(const void*)m->d_tp64
+                                                         : (const R*)(const void*)m->d_tp32;
+            if (a.vals && tm && tp && constant_coefficients(a) && (a.parts & DG_ASM_MATRIX_CORE)) {
+                if (!m->d_mfcoef &&
+                    hipMalloc(&m->d_mfcoef, (size_t)MfCoef::ROWS * std::max<int64_t>(m->T, 1) * sizeof(double)) !=
+                        hipSuccess) {
+                    m->d_mfcoef = nullptr;
+                    return DG_ERR_OOM;
+                }
+                launch_mfma<K, R>(m, a, tm + (size_t)ki * MfmaSet::COUNT * MfmaSet::nnp(K), tp, s);
+                if (a.rhs) launch_load_boundary<K, R>(m, a, s);
+                done = true;
+            }
+        }
+        if (!done && a.vals && ten && constant_coefficients(a)) {
             const int64_t per = (TEN_BLOCK / 64) * EPW;
             const int64_t grid = (m->T + per - 1) / per;
-            // the staged set of this method (kappa = -1, 0, 1)
-            const int ki = a.kappa < 0 ? 0 : (a.kappa > 0 ? 2 : 1);
             hipLaunchKernelGGL((assemble_tensor_kernel<K, R>), dim3((unsigned)grid), dim3(TEN_BLOCK), 0, s, a,
                                ten + (size_t)ki * TenStage::COUNT * TenCol<K, R>::ts);
             if (a.rhs) launch_load_boundary<K, R>(m, a, s);
@@ -714,7 +1169,7 @@ extern "C" int32_t dg_assemble(const dg_mesh* m, const dg_problem* P, int32_t pr
 {
     if (!m || !P || !dev_vals) return DG_ERR_ARG;
     if (prec != DG_F64 && prec != DG_F32) return DG_ERR_ARG;
-    if (parts & ~(uint32_t)DG_PART_ALL) return DG_ERR_ARG;
+    if (parts & ~(uint32_t)(DG_PART_ALL | DG_ASM_MATRIX_CORE)) return DG_ERR_ARG;
     if (P->degree != m->k) return DG_ERR_ARG;
     double kappa;
     switch (P->method) {

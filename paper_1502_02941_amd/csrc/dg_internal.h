@@ -74,6 +74,24 @@ struct TenStage {
 };
 std::vector<double> stage_tensors(int k, const std::vector<double>& ten, double kappa);
 
+// Tensor sets of the matrix-core assembly (k = 2, 3): each tensor is one row
+// of nnp = 16 ceil(n^2 / 16) values in block order (entry (test i, trial j)
+// at i n + j, zero beyond n^2), so that the blocks of 16 elements are the
+// product of their 16 x K coefficient rows with K such rows.
+//   diagonal set, per kappa:  VOL 0..5 (SXX SXY SYY CX CY MASS), VB 0..3, two zero
+//                             rows, then per edge l: E, kappa TX - DX, kappa TY - DY, E1
+//   neighbour set (l, lp):    F, GX, GY, HX, HY, F1, two zero rows
+//   upwind points (any kappa): per edge l and point g (rows padded to PTS):
+//                             w-free products phi_i(l, t_g) phi_j(l, t_g), then per
+//                             (l, lp) and g: phi_i(l, t_g) psi_j(lp, 1 - t_g)
+struct MfmaSet {
+    static constexpr int DIAG = 24, OFF = 8;
+    static constexpr int COUNT = DIAG + 9 * OFF;  // rows per kappa
+    static constexpr int PTS = 8;                 // point rows per edge (k + 2 <= PTS)
+    static constexpr int PCOUNT = 3 * PTS + 9 * PTS;
+    __host__ __device__ static constexpr int nnp(int k) { return ((k + 1) * (k + 2) / 2 * ((k + 1) * (k + 2) / 2) + 15) / 16 * 16; }
+};
+
 // Field as seen by the kernels (same meaning as dg_field).
 struct FieldDev {
     int32_t kind;
@@ -116,6 +134,7 @@ struct dg_mesh {
     double* d_xy = nullptr;
     int32_t* d_nbr = nullptr;
     int32_t* d_nbr_edge = nullptr;
+    int32_t* d_ebits = nullptr;   // [T]: neighbour edges (bits 2l, 2l+1), neighbour on l (8 + l), Neumann l (12 + l)
     int32_t* d_row_ptr = nullptr;
     int32_t* d_col_idx = nullptr;
     int32_t* d_bnd_type = nullptr;
@@ -128,6 +147,13 @@ struct dg_mesh {
     double* d_ten64 = nullptr;  // [3][TenStage::COUNT] staged tensors per kappa (k <= 3): n columns (trial j) of
                                 //   test values i, each column zero-padded to whole 16-byte words
     float* d_ten32 = nullptr;
+    double* d_tm64 = nullptr;   // [3][MfmaSet::COUNT][nnp] matrix-core tensor sets per kappa (k = 2, 3)
+    float* d_tm32 = nullptr;
+    double* d_tp64 = nullptr;   // [MfmaSet::PCOUNT][nnp] upwind point products (k = 2, 3)
+    float* d_tp32 = nullptr;
+    mutable void* d_mfcoef = nullptr;  // [47][T] (FP64 room): per-element coefficients of the matrix-core
+                                       //   assembly (k = 2, 3), allocated by its first use; dg_assemble calls
+                                       //   on one mesh that overlap in time race on it
     double* d_p1map = nullptr;  // [3][3]: P1 coefficients from vertex values (k >= 1)
     double* d_mref = nullptr;   // [n][n] reference mass matrix (monomial basis only)
     double* d_etab = nullptr;   // error rule (q = k + 4): w[nqr], xi[nqr], eta[nqr], phi[nqr][n]

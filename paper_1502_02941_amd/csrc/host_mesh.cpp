@@ -303,10 +303,11 @@ std::vector<double> build_error_table(int k, int basis, int* nqr)
 
 static void free_device(dg_mesh* m)
 {
-    hipFree(m->d_xy); hipFree(m->d_nbr); hipFree(m->d_nbr_edge); hipFree(m->d_row_ptr);
+    hipFree(m->d_xy); hipFree(m->d_nbr); hipFree(m->d_nbr_edge); hipFree(m->d_ebits); hipFree(m->d_row_ptr);
     hipFree(m->d_col_idx); hipFree(m->d_bnd_type); hipFree(m->d_bnd_el); hipFree(m->d_bnd_loc);
     hipFree(m->d_bnd_elems);
     hipFree(m->d_tab64); hipFree(m->d_tab32); hipFree(m->d_p1map); hipFree(m->d_ten64); hipFree(m->d_ten32);
+    hipFree(m->d_tm64); hipFree(m->d_tm32); hipFree(m->d_tp64); hipFree(m->d_tp32); hipFree(m->d_mfcoef);
     hipFree(m->d_mref);
     hipFree(m->d_gt); hipFree(m->d_etab); hipFree(m->d_epart);
     hipFree(m->d_nodes); hipFree(m->d_elems); hipFree(m->d_eid); hipFree(m->d_owner);
@@ -490,6 +491,21 @@ extern "C" int32_t dg_mesh_create_basis(const double* xy, int64_t n_nodes, const
     if (st == DG_OK) st = upload(&m->d_xy, m->xy6);
     if (st == DG_OK) st = upload(&m->d_nbr, m->nbr);
     if (st == DG_OK) st = upload(&m->d_nbr_edge, m->nbr_edge);
+    if (st == DG_OK) {
+        // per element: neighbour edges (bits 2l, 2l+1), neighbour present (bit 8 + l),
+        // Neumann boundary edge (bit 12 + l)
+        std::vector<int32_t> eb((size_t)m->T);
+        for (int64_t K = 0; K < m->T; ++K) {
+            int32_t b = m->nbr_edge[K] & 63;
+            for (int l = 0; l < 3; ++l) {
+                const int32_t nb = m->nbr[3 * K + l];
+                if (nb >= 0) b |= 1 << (8 + l);
+                else if (m->bnd_type[-nb - 1] == 1) b |= 1 << (12 + l);
+            }
+            eb[K] = b;
+        }
+        st = upload(&m->d_ebits, eb);
+    }
     if (st == DG_OK) st = upload(&m->d_row_ptr, m->row_ptr);
     if (st == DG_OK) st = upload(&m->d_col_idx, m->col_idx);
     if (st == DG_OK) st = upload(&m->d_bnd_type, m->bnd_type);
@@ -554,6 +570,56 @@ extern "C" int32_t dg_mesh_create_basis(const double* xy, int64_t n_nodes, const
         const std::vector<float> ten32(t32.begin(), t32.end());
         st = upload(&m->d_ten64, ten64);
         if (st == DG_OK) st = upload(&m->d_ten32, ten32);
+        if (st == DG_OK && degree >= 2) {
+            // matrix-core sets: the staged tensors (trial-major) re-laid as rows in block order
+            const int nn = n * n, nnp = MfmaSet::nnp(degree);
+            std::vector<double> tm((size_t)3 * MfmaSet::COUNT * nnp, 0.0);
+            auto put = [&](int ki, int row, int src) {  // src: TenStage index, or -1 for a zero row
+                if (src < 0) return;
+                const double* S = &ten[((size_t)ki * TenStage::COUNT + src) * nn];
+                double* D = &tm[((size_t)ki * MfmaSet::COUNT + row) * nnp];
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) D[i * n + j] = S[j * n + i];
+            };
+            for (int ki = 0; ki < 3; ++ki) {
+                for (int t = 0; t < 4; ++t) put(ki, t, TenStage::VOL + t);  // SXX SXY SYY CX
+                put(ki, 4, TenStage::VOL + 4);                                // CY
+                put(ki, 5, TenStage::VOL + 5);                                // MASS
+                for (int t = 0; t < 4; ++t) put(ki, 6 + t, TenStage::VB + t);
+                for (int l = 0; l < 3; ++l) {
+                    for (int t = 0; t < 3; ++t) put(ki, 12 + 4 * l + t, TenStage::ED + 3 * l + t);
+                    put(ki, 12 + 4 * l + 3, TenStage::E1 + l);
+                }
+                for (int c = 0; c < 9; ++c) {
+                    const int base = MfmaSet::DIAG + MfmaSet::OFF * c;
+                    for (int t = 0; t < 5; ++t) put(ki, base + t, TenStage::EO + 5 * c + t);
+                    put(ki, base + 5, TenStage::F1 + c);
+                }
+            }
+            // upwind point products from the edge tables (the same values the
+            // point-by-point upwind sum multiplies)
+            const TabLayout L(degree);
+            const int Q = L.nqe;
+            std::vector<double> tp((size_t)MfmaSet::PCOUNT * nnp, 0.0);
+            auto ephi = [&](int l, int g, int i) { return m->tab64[L.ephi + (l * Q + g) * n + i]; };
+            for (int l = 0; l < 3; ++l)
+                for (int g = 0; g < Q; ++g) {
+                    double* D = &tp[((size_t)l * MfmaSet::PTS + g) * nnp];
+                    for (int i = 0; i < n; ++i)
+                        for (int j = 0; j < n; ++j) D[i * n + j] = ephi(l, g, i) * ephi(l, g, j);
+                }
+            for (int l = 0; l < 3; ++l)
+                for (int lp = 0; lp < 3; ++lp)
+                    for (int g = 0; g < Q; ++g) {
+                        double* D = &tp[((size_t)(3 + 3 * l + lp) * MfmaSet::PTS + g) * nnp];
+                        for (int i = 0; i < n; ++i)
+                            for (int j = 0; j < n; ++j) D[i * n + j] = ephi(l, g, i) * ephi(lp, Q - 1 - g, j);
+                    }
+            st = upload(&m->d_tm64, tm);
+            if (st == DG_OK) st = upload(&m->d_tm32, std::vector<float>(tm.begin(), tm.end()));
+            if (st == DG_OK) st = upload(&m->d_tp64, tp);
+            if (st == DG_OK) st = upload(&m->d_tp32, std::vector<float>(tp.begin(), tp.end()));
+        }
     }
     if (st == DG_OK) {
         // P[m][v]: coefficient of basis function m in the linear function with

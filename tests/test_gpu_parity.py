@@ -59,6 +59,67 @@ def test_fp64_assembly_matches_oracle(api, case):
     assert np.abs(bg - B.rhs).max() <= 1e-12 * max(np.abs(B.rhs).max(), 1e-300)
 
 
+TENSOR_K = [c for c in SMALL if c.k in (2, 3)]
+
+
+@pytest.mark.parametrize("case", TENSOR_K, ids=[c.name for c in TENSOR_K])
+def test_matrix_core_tensor_kernel_matches_oracle(api, case):
+    """k = 2, 3: the matrix-core (MFMA) assembly, selected by a parts flag,
+    against the oracle (the default vector-ALU kernel is covered above)."""
+    _say("matrix-core assembly parity %s" % case.name)
+    mesh, _, vals, rhs = _gpu_system(api, case, parts=7 | api.ASM_MATRIX_CORE)
+    M, B = DC.oracle_system(case)
+    Ag = api.bsr_to_scipy(mesh, vals).tocsr()
+    assert DC.rel_fro(Ag, B.to_scipy()) <= 1e-12
+    d, mx = DC.max_abs_diff(Ag, B.to_scipy())
+    assert d <= 1e-12 * mx
+    assert DC.rel_fro(rhs.cpu().numpy(), B.rhs) <= 1e-12
+
+
+def _shuffled_mesh(n, seed):
+    """A jittered structured mesh with its elements in random order and each
+    element's vertices rotated by a random amount (orientation kept), so that
+    the 16-element tiles of the matrix-core kernel meet every neighbour-edge
+    combination and every local edge numbering."""
+    m = W.structured_mesh(n, dirichlet=("bottom", "left"), neumann=("top", "right"), jitter=0.2, seed=seed)
+    rng = np.random.default_rng(seed)
+    el = np.asarray(m.elems)[rng.permutation(m.T)]
+    rot = rng.integers(0, 3, size=len(el))
+    el = np.stack([np.roll(e, -s) for e, s in zip(el, rot)]).astype(np.int32)
+    return W.MeshArrays(nodes=m.nodes, elems=el, dirichlet=m.dirichlet, neumann=m.neumann)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("method", [1, 2, 3])
+@pytest.mark.parametrize("k", [2, 3])
+def test_shuffled_mesh_assembly_matches_oracle(api, k, method, prec):
+    """Elements in random order with rotated local numbering (a tile of 16
+    elements holds every neighbour-edge pairing), rotating b (edges on which
+    b . n changes sign take the point-by-point upwind term), mixed boundaries:
+    both tensor kernels against the oracle."""
+    m = _shuffled_mesh(9, 40 + k + method)
+    sigma = 3.0 * k * (k + 1) if method != 1 else 1.0
+    kappa = {1: 1.0, 2: -1.0, 3: 0.0}[method]
+    mesh = api.Mesh.from_arrays(m, k)
+    F = api.Field
+    gs = [(0.3, 0.6, 0.1, 1.0), (0.7, 0.2, 0.05, -0.5)]
+    P = api.Problem(method, k, sigma, eps=0.03, bx=F.affine(0.5, 0.0, -1.0), by=F.affine(-0.5, 1.0, 0.0),
+                    alpha=0.7, f=F.gauss_sum(gs), gD=0.25, gN=-0.5)
+    M = O.Mesh(m.nodes, m.elems, m.dirichlet, m.neumann)
+    B = O.assemble(M, k, sigma=sigma, kappa=kappa, eps=0.03, bx=O.Field.affine(0.5, 0.0, -1.0),
+                   by=O.Field.affine(-0.5, 1.0, 0.0), alpha=0.7, f=O.Field.gauss_sum(gs), gD=0.25, gN=-0.5)
+    Ao = B.to_scipy()
+    for parts in (7, 7 | api.ASM_MATRIX_CORE):
+        _say("shuffled mesh k=%d method=%d prec=%d parts=%d" % (k, method, prec, parts))
+        vals, rhs = api.assemble(mesh, P, prec=prec, parts=parts)
+        Ag = api.bsr_to_scipy(mesh, vals).tocsr()
+        tol = 1e-12 if prec == 0 else 2e-6
+        assert DC.rel_fro(Ag, Ao) <= tol
+        d, mx = DC.max_abs_diff(Ag, Ao)
+        assert d <= (1e-12 if prec == 0 else 1e-5) * mx
+        assert DC.rel_fro(rhs.double().cpu().numpy(), B.rhs) <= tol
+
+
 SUPER = DC.superpenalty_cases()
 
 
@@ -112,10 +173,11 @@ def test_parts_match_oracle(api, parts):
     assert DC.rel_fro(Ag, Bp.to_scipy()) <= 1e-12
 
 
-def test_fp32_assembly_error_vs_oracle(api):
-    for case in (SMALL[0], SMALL[8], SMALL[-3]):
+@pytest.mark.parametrize("parts", [7, 7 | 256], ids=["default", "matrix_core"])
+def test_fp32_assembly_error_vs_oracle(api, parts):
+    for case in (SMALL[0], SMALL[5], SMALL[8], SMALL[-3]):
         _say("fp32 assembly %s" % case.name)
-        mesh, _, vals, rhs = _gpu_system(api, case, prec=1)
+        mesh, _, vals, rhs = _gpu_system(api, case, prec=1, parts=parts)
         assert vals.dtype == torch.float32
         M, B = DC.oracle_system(case)
         e = DC.rel_fro(api.bsr_to_scipy(mesh, vals).tocsr(), B.to_scipy())
@@ -124,12 +186,13 @@ def test_fp32_assembly_error_vs_oracle(api):
         assert e <= 2e-6 and eb <= 2e-6
 
 
+@pytest.mark.parametrize("parts", [7, 7 | 256], ids=["default", "matrix_core"])
 @pytest.mark.parametrize("name", ["jit13_p3_m1_mixedbc_rot", "jit11_p3_m2_mixedbc_const"])
-def test_assembly_bitwise_deterministic(api, name):
-    """Point path (affine b) and reference-tensor path (constant coefficients)."""
+def test_assembly_bitwise_deterministic(api, name, parts):
+    """Reference-tensor paths (constant eps and alpha; affine and constant b)."""
     case = [c for c in SMALL if c.name == name][0]
-    mesh, prob, v1, r1 = _gpu_system(api, case)
-    v2, r2 = api.assemble(mesh, prob)
+    mesh, prob, v1, r1 = _gpu_system(api, case, parts=parts)
+    v2, r2 = api.assemble(mesh, prob, parts=parts)
     torch.cuda.synchronize()
     assert torch.equal(v1, v2) and torch.equal(r1, r2)
 
