@@ -90,6 +90,8 @@ def launched_kernel(cls, prec, block):
     functions per element) for Arnoldi blocks of `block` vectors."""
     if cls == "spmv_hat":
         return "spmv_hat_kernel<6, %s>" % prec
+    if block == 8 and cls == "multidot":
+        return "multidot_mfma_kernel<%s>" % prec
     if block > 1 and cls in ("multidot", "update"):
         return "%s_block_kernel<%s, %d>" % (cls, prec, block)
     return "%s_kernel<%s>" % (cls, prec)

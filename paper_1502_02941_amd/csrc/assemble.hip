@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "asm_device.h"
+#include "mfma.h"
 
 namespace dg {
 
@@ -591,39 +592,6 @@ __global__ __launch_bounds__(TEN_BLOCK, 4) void assemble_tensor_kernel(const Asm
 // memory (such edges are rare; those reads do wait for the stores before them).
 // ---------------------------------------------------------------------------
 constexpr int MF_BLOCK = 512;
-
-// Both take A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k, and
-// leave D[i][j] in lane j + 16 g, register v: the FP64 product with rows
-// i = g + 4 v, the FP32 one with rows i = 4 g + v (measured on gfx950).
-template <typename R>
-struct MfmaOp;
-template <>
-struct MfmaOp<double> {
-    typedef double V __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ V mac(double a, double b, V c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
-    static __device__ __forceinline__ void store(double x, __amdgpu_buffer_rsrc_t rs, uint32_t off)
-    {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(MfU2, x), rs, (int)off, 0, 0);
-    }
-    typedef unsigned int MfU2 __attribute__((ext_vector_type(2)));
-};
-template <>
-struct MfmaOp<float> {
-    typedef float V __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ V mac(float a, float b, V c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
-    static __device__ __forceinline__ void store(float x, __amdgpu_buffer_rsrc_t rs, uint32_t off)
-    {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), rs, (int)off, 0, 0);
-    }
-};
 
 // A byte range for buffer stores: offsets at or beyond MF_DROP are outside it
 // and the hardware discards those lanes' stores.
