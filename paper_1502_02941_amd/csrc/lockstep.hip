@@ -19,6 +19,7 @@
 
 #include "dg_internal.h"
 #include "lockstep.h"
+#include "mfma.h"
 
 namespace dg {
 
@@ -753,6 +754,108 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot_block_kernel(const LsArgs A
     }
 }
 
+// The same partials for blocks of eight vectors on the matrix cores, as the
+// single-system solver forms them: for each tile of LS_MF_CT = 32 basis
+// columns the chunk's four waves each take a quarter of its rows in 32-row
+// pieces, staged in LDS with coalesced loads (the next piece's loads in flight
+// during the products), and accumulate V_tile^T W in FP64 16 x 16 x 4 products
+// (FP32 data converted; the eight vectors fill half of the 16 product
+// columns); the four waves' sums are added in LDS at the end of each tile.
+constexpr int LS_MF_CT = 32, LS_MF_CH = 32;
+template <typename P>
+__global__ __launch_bounds__(LS_BT) void ls_multidot_mfma_kernel(const LsArgs A)
+{
+    if (ls_all_ended(A)) return;
+    constexpr int S = 8, CT = LS_MF_CT, CH = LS_MF_CH, WPB = LS_BT / 64, NA = CT / 16;
+    constexpr int STR = sizeof(P) == 8 ? CH + 1 : CH + 2;  // padded row stride of the staged pieces
+    constexpr int NSUB = LS_CH / WPB / CH;                  // pieces per wave and tile
+    static_assert(NSUB * CH * WPB == LS_CH && CH == 32, "a lane loads row lane % 32 of two columns");
+    using Op = MfmaOp<double>;
+    using VR = typename Op::V;
+    __shared__ P sv[WPB][CT * STR];
+    __shared__ P sw[WPB][S * STR];
+    __shared__ double red[WPB][CT * S];
+    const int64_t b = blockIdx.x;
+    const int i = ls_find(A.rblk, A.count, b);
+    const LsState& St = A.state[i];
+    if (!ls_running(St)) return;
+    const LsInst& I = A.inst[i];
+    const int64_t ch = b - A.rblk[i];
+    const int J = St.J, ncols = J + 1;
+    const int ntiles = (ncols + CT - 1) / CT;
+    const P* V = (const P*)A.V + I.v_off;
+    const P* wv[S];
+#pragma unroll
+    for (int v = 0; v < S; ++v) wv[v] = ls_block_vec<P>(A, v) + I.x_off;
+    const int64_t r1 = min((ch + 1) * (int64_t)LS_CH, I.n);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, li = lane & 15;
+    const int lr = lane & 31, lc = lane >> 5;  // loads: row lr of columns 2 c + lc
+    const int64_t wr0 = ch * LS_CH + (int64_t)wave * (NSUB * CH);
+    P* mv = sv[wave];
+    P* mw = sw[wave];
+    double* part = A.part + I.part_off;
+    P x[CT / 2], y[S / 2];
+    auto load = [&](int s) {
+        const int t0 = (s / NSUB) * CT;
+        const int64_t r = wr0 + (int64_t)(s % NSUB) * CH + lr;
+        const bool in = r < r1;
+#pragma unroll
+        for (int c = 0; c < CT / 2; ++c) {  // columns past J read column J and are discarded
+            const int cc = t0 + 2 * c + lc;
+            x[c] = in ? __builtin_nontemporal_load(V + (int64_t)(cc < ncols ? cc : J) * I.n + r) : P(0);
+        }
+#pragma unroll
+        for (int v = 0; v < S / 2; ++v) y[v] = in ? wv[2 * v + lc][r] : P(0);
+    };
+    VR acc[NA];
+#pragma unroll
+    for (int h = 0; h < NA; ++h) acc[h] = VR{0, 0, 0, 0};
+    const int total = ntiles * NSUB;
+    load(0);
+    for (int s = 0; s < total; ++s) {
+#pragma unroll
+        for (int c = 0; c < CT / 2; ++c) mv[(2 * c + lc) * STR + lr] = x[c];
+#pragma unroll
+        for (int v = 0; v < S / 2; ++v) mw[(2 * v + lc) * STR + lr] = y[v];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (s + 1 < total) load(s + 1);
+#pragma unroll
+        for (int t = 0; t < CH / 4; ++t) {
+            const double bv = (double)mw[(li & 7) * STR + 4 * t + q];
+#pragma unroll
+            for (int h = 0; h < NA; ++h) {
+                const double av = (double)mv[(16 * h + li) * STR + 4 * t + q];
+                acc[h] = Op::mac(av, li < S ? bv : 0.0, acc[h]);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (s % NSUB == NSUB - 1) {  // end of a tile: the four waves' sums
+            const int t0 = (s / NSUB) * CT;
+            if (li < S) {
+#pragma unroll
+                for (int h = 0; h < NA; ++h)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) red[wave][(16 * h + Op::row(q, v)) * S + li] = acc[h][v];
+            }
+#pragma unroll
+            for (int h = 0; h < NA; ++h) acc[h] = VR{0, 0, 0, 0};
+            __syncthreads();
+            for (int k = threadIdx.x; k < CT * S; k += LS_BT) {
+                const int c = k / S, v = k - c * S;
+                if (t0 + c < ncols)
+                    part[((int64_t)v * ncols + t0 + c) * I.nchunks + ch] =
+                        (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // w_r -= sum_{c<=J} R_r[c] V_c (R_r = hcol + r (J+1)) and the Gram partials of
 // the results, pair k = (p, q), p <= q in the order (0,0), (0,1), (1,1), (0,2),
 // (1,2), (2,2), at red[red_off + k nchunks + chunk]
@@ -1233,7 +1336,10 @@ static void ls_cycle_blocks(const LsArgs& A, const LsDims& d, hipStream_t st)
     const size_t dyn = sizeof(double) * S * (size_t)ldc;
     for (int j = 0, step = 1; j < d.max_m; j += S, ++step) {
         for (int q = 0; q < S; ++q) hipLaunchKernelGGL((ls_spmv_kernel<P>), d.ge, d.be, 0, st, A, q, 1.0 - A.theta);
-        hipLaunchKernelGGL((ls_multidot_block_kernel<P, S>), d.gr, d.be, 0, st, A);
+        if constexpr (S == 8)
+            hipLaunchKernelGGL((ls_multidot_mfma_kernel<P>), d.gr, d.be, 0, st, A);
+        else
+            hipLaunchKernelGGL((ls_multidot_block_kernel<P, S>), d.gr, d.be, 0, st, A);
         hipLaunchKernelGGL(ls_reduce_kernel, d.gi, d.be, 0, st, A, S);
         hipLaunchKernelGGL((ls_update_block_kernel<P, S>), d.gr, d.be, 0, st, A);
         hipLaunchKernelGGL((ls_block_givens_kernel<S>), d.gi, dim3(64), dyn, st, A, step, ldc);
