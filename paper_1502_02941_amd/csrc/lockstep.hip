@@ -28,6 +28,7 @@ constexpr int LS_CH = 1024;      // rows per row chunk (one workgroup each); mea
 constexpr int LS_CT = 16;        // Gram-Schmidt columns reduced together (8: same, 32: slower)
 constexpr int LS_GV = 512;       // Givens staging chunk
 constexpr int LS_BATCH = 8;      // loads issued together in the serial loops of the block kernels
+constexpr int LS_GT = 256;       // threads of the block Givens kernel (its Hessenberg products take one row each)
 
 __device__ __forceinline__ double ls_wave_sum(double v)
 {
@@ -975,7 +976,7 @@ __device__ void ls_rotate_cols(double* base, int ld, int ncol, int count, const 
     for (int i0 = 0; i0 < count; i0 += LS_GV) {
         const int cnt = min(count - i0, LS_GV);
         __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += 64) {
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
             sc[t] = cs[i0 + t];
             ss[t] = sn[i0 + t];
         }
@@ -1010,14 +1011,14 @@ __device__ void ls_rotate_cols(double* base, int ld, int ncol, int count, const 
     __syncthreads();
 }
 
-// one block of 64 threads per instance: Gram sums, Cholesky (pivot i is
+// one block of LS_GT threads per instance: Gram sums, Cholesky (pivot i is
 // resolvable when c_ii > 1e-8 sqrt(G_ii), pivot 0 when c_00 > 1e-300), the
 // block's raw Hessenberg columns (Hr, leading dimension m + 2) and, rotated,
 // into H; residual estimates and stop tests.  A block with p < S resolvable
 // pivots takes columns J..J+p and ends the cycle; C^{-1} goes to the state for
 // the normalisation.  Dynamic LDS: S columns of max_m + 4.
 template <int S>
-__global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int step, int ldc)
+__global__ __launch_bounds__(LS_GT) void ls_block_givens_kernel(const LsArgs A, int step, int ldc)
 {
     constexpr int NG = S * (S + 1) / 2;
     extern __shared__ double dyn[];
@@ -1039,12 +1040,14 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
     double acc[NG];
 #pragma unroll
     for (int k = 0; k < NG; ++k) acc[k] = 0.0;
-    for (int c = threadIdx.x; c < I.nchunks; c += 64)
+    if (threadIdx.x < 64) {  // the Gram partials: wave 0 (thread 0 factors them)
+        for (int c = threadIdx.x; c < I.nchunks; c += 64)
 #pragma unroll
-        for (int k = 0; k < NG; ++k) acc[k] += red[(int64_t)k * I.nchunks + c];
+            for (int k = 0; k < NG; ++k) acc[k] += red[(int64_t)k * I.nchunks + c];
 #pragma unroll
-    for (int k = 0; k < NG; ++k) acc[k] = ls_wave_sum(acc[k]);
-    for (int t = threadIdx.x; t <= j; t += 64) dyn[t] = R[t] + (t == j ? A.theta : 0.0);  // Ahat v_J = w_0 + theta v_J
+        for (int k = 0; k < NG; ++k) acc[k] = ls_wave_sum(acc[k]);
+    }
+    for (int t = threadIdx.x; t <= j; t += LS_GT) dyn[t] = R[t] + (t == j ? A.theta : 0.0);  // Ahat v_J = w_0 + theta v_J
     if (threadIdx.x == 0) {
         int k = 0;
         for (int q = 0; q < S; ++q)
@@ -1087,11 +1090,11 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
     }
     __syncthreads();
     const int ncol = ncol_s;
-    for (int t = threadIdx.x; t <= j + 1; t += 64) Hr[t + (int64_t)j * ldr] = dyn[t];
+    for (int t = threadIdx.x; t <= j + 1; t += LS_GT) Hr[t + (int64_t)j * ldr] = dyn[t];
     __syncthreads();
     // columns J+1 .. J+ncol-1 from the raw column J and the earlier raw columns
     if (ncol > 1) {
-        for (int t = threadIdx.x; t <= j + ncol; t += 64) {
+        for (int t = threadIdx.x; t <= j + ncol; t += LS_GT) {
             double hx[S - 1];
 #pragma unroll
             for (int l = 0; l < S - 1; ++l) hx[l] = 0.0;
@@ -1127,7 +1130,7 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
         }
         __syncthreads();
         for (int ii = 1; ii < ncol; ++ii)
-            for (int t = threadIdx.x; t <= j + ii + 1; t += 64) Hr[t + (int64_t)(j + ii) * ldr] = dyn[ii * ldc + t];
+            for (int t = threadIdx.x; t <= j + ii + 1; t += LS_GT) Hr[t + (int64_t)(j + ii) * ldr] = dyn[ii * ldc + t];
     }
     // earlier blocks' rotations on all columns at once, then the columns in turn
     // (thread 0, this block's rotations and estimates in LDS: no global round
@@ -1172,7 +1175,7 @@ __global__ __launch_bounds__(64) void ls_block_givens_kernel(const LsArgs A, int
     __syncthreads();
     const int taken = taken_s;
     for (int ii = 0; ii < taken; ++ii)
-        for (int t = threadIdx.x; t <= j + ii; t += 64) H[t + (int64_t)(j + ii) * ldh] = dyn[ii * ldc + t];
+        for (int t = threadIdx.x; t <= j + ii; t += LS_GT) H[t + (int64_t)(j + ii) * ldh] = dyn[ii * ldc + t];
     if (threadIdx.x == 0) {
         St.jb = j;
         St.bstep = step;
@@ -1342,7 +1345,7 @@ static void ls_cycle_blocks(const LsArgs& A, const LsDims& d, hipStream_t st)
             hipLaunchKernelGGL((ls_multidot_block_kernel<P, S>), d.gr, d.be, 0, st, A);
         hipLaunchKernelGGL(ls_reduce_kernel, d.gi, d.be, 0, st, A, S);
         hipLaunchKernelGGL((ls_update_block_kernel<P, S>), d.gr, d.be, 0, st, A);
-        hipLaunchKernelGGL((ls_block_givens_kernel<S>), d.gi, dim3(64), dyn, st, A, step, ldc);
+        hipLaunchKernelGGL((ls_block_givens_kernel<S>), d.gi, dim3(LS_GT), dyn, st, A, step, ldc);
         hipLaunchKernelGGL((ls_normalize_block_kernel<P, S>), d.gr, d.be, 0, st, A, step);
     }
 }
