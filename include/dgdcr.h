@@ -235,20 +235,22 @@ typedef struct {
                              systems of at most 4096 unknowns; 1: always (DG_ERR_ARG if unsupported);
                              -1: never */
     int32_t block;        /* Arnoldi vectors per Gram-Schmidt pass of the kernel-per-step path, S: 1 = one
-                             (w = A M^{-1} v_j, then h = V^T w and w -= V h); S = 2, 3, 4, 6 or 8 = a block
-                             of S vectors (w_0 from v_j, each next one from the one before, see basis)
+                             (w = A M^{-1} v_j, then h = V^T w and w -= V h); S = 2, 3, 4, 6, 8 or 16 = a
+                             block of S vectors (w_0 from v_j, each next one from the one before, see basis)
                              projected on the basis in one pass, orthonormalised by Cholesky QR, its S
                              Hessenberg columns recovered from the block: the basis is read once per S
-                             steps.  0 = automatic (8, or 6 with mixed, when restart <= 2048; else 3; 1 with reorth).
-                             A block whose Gram matrix has an unresolvable pivot (Cholesky pivot <= 1e-8 of
-                             the vector's norm) ends the cycle at the last column it determines.  S > 4
-                             needs restart <= 2048.  DG_ERR_ARG for other values, or for S > 1 with reorth. */
+                             steps.  0 = automatic (16 with FP64 cycles when restart <= 640; else 8, or 6 with
+                             mixed, when restart <= 2048; else 3; 1 with reorth).  A block whose Gram matrix has
+                             an unresolvable pivot (Cholesky pivot <= 1e-8 of the vector's norm) ends the cycle
+                             at the last column it determines.  S > 4 needs restart <= 2048, S = 16 restart
+                             <= 640 and FP64 cycles (mixed = 0).  DG_ERR_ARG for other values, or for S > 1 with
+                             reorth. */
     int32_t basis;        /* how a block's vectors are formed: 1 = monomial, w_i = A M^{-1} w_{i-1} (its Gram
                              matrix grows ill-conditioned with S: on the 256 x 256 P2 boundary-layer system
                              four vectors already take more steps); 2 = shifted by one,
                              w_i = (A M^{-1} - I) w_{i-1}, the products with the off-diagonal blocks of
                              A M^{-1} alone, which stay well conditioned (the same steps as one vector per
-                             pass up to eight); 0 = automatic (2).  The Krylov space is the same either way. */
+                             pass up to sixteen on the boundary-layer system); 0 = automatic (2).  The Krylov space is the same either way. */
 } dg_solver_opts;
 
 typedef struct {

@@ -33,7 +33,7 @@ namespace dg {
 
 enum { C_J = 0, C_STOP = 1, C_REORTH = 2, C_NREORTH = 3, C_NCTRL = 16 };
 enum { S_BNORM2 = 0, S_RNORM2 = 1, S_INVH = 2, S_WNORM2 = 3, S_HN = 4, S_CYCTOL = 5, S_BETA = 6,
-       S_QB = 7, S_NSCAL = 72 };  // S_QB..: the inverse Cholesky factor of an Arnoldi block (row-major, S x S)
+       S_QB = 7, S_NSCAL = 7 + 16 * 16 + 1 };  // S_QB..: the inverse Cholesky factor of an Arnoldi block (row-major, S x S)
 
 constexpr int BLK = 256;
 constexpr int MD_TARGET_BLOCKS = 2048;   // multidot: column tiles x row splits aimed at this many blocks
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(BLK) void normalize_kernel(P* __restrict__ V, const
 // and, for i < S - 1, Ahat q_i = sum_{l<=i} (w_{l+1} - Ahat V R_l) (C^{-1})_{li}
 // with Ahat V = V H.
 // ---------------------------------------------------------------------------
-constexpr int BS_MAX = 8;
+constexpr int BS_MAX = 16;
 // the block's vectors w_0..w_{S-1}, passed by value
 template <typename P>
 struct BlockVecs {
@@ -611,19 +611,22 @@ template <typename P>
 struct MfStage {
     static constexpr int STR = sizeof(P) == 8 ? MF_CH + 1 : MF_CH + 2;  // padded row stride (elements)
 };
-template <typename P>
+// S = 8 or 16; with GRAM the columns are the block's vectors themselves (j + 1
+// = S of them: the Gram matrix of a block of sixteen after its update).
+template <typename P, int S = 8, bool GRAM = false>
 __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict__ V, BlockVecs<P> W, int64_t n, int j,
                                                             int64_t rows_per_split, const int* ctrl,
                                                             double* __restrict__ partials)
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
-    constexpr int S = 8, STR = MfStage<P>::STR, WPB = BLK / 64, NA = MF_CT / 16;
+    static_assert(S == 8 || S == 16, "eight or sixteen vectors");
+    constexpr int STR = MfStage<P>::STR, WPB = BLK / 64, NA = MF_CT / 16;
     using Op = MfmaOp<double>;  // FP32 data too: the dots are summed in FP64, as by the vector-ALU kernel
     using VR = typename Op::V;
     __shared__ __align__(16) P sv[WPB][MF_CT * STR];  // after the row loop: the waves' partial sums
     __shared__ P sw[WPB][S * STR];
     static_assert(sizeof(sv) >= sizeof(double) * WPB * MF_CT * S, "room for the partial sums");
-    const int ncols = j + 1;
+    const int ncols = GRAM ? S : j + 1;
     const int c0 = blockIdx.x * MF_CT;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
     const int64_t r1 = r0 + rows_per_split < n ? r0 + rows_per_split : n;
@@ -648,10 +651,22 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
 #pragma unroll
         for (int c = 0; c < MF_CT / LPC; ++c) {  // columns past j read column j and are discarded
             const int cc = c0 + LPC * c + lc;
-            x[c] = in ? __builtin_nontemporal_load(V + (int64_t)(cc < ncols ? cc : j) * n + r) : P(0);
+            if constexpr (GRAM) {  // columns 2 c and 2 c + 1 are vectors of the block (none past S)
+                static_assert(!GRAM || LPC == 2, "two columns per lane");
+                if (LPC * c < S) {
+                    const P* col = lc ? wv[(LPC * c + 1) % S] : wv[(LPC * c) % S];
+                    x[c] = in ? col[r] : P(0);
+                } else {
+                    x[c] = P(0);
+                }
+            } else
+                x[c] = in ? __builtin_nontemporal_load(V + (int64_t)(cc < ncols ? cc : j) * n + r) : P(0);
         }
 #pragma unroll
-        for (int v = 0; v < S / LPC; ++v) y[v] = in ? wv[LPC * v + lc][r] : P(0);
+        for (int v = 0; v < S / LPC; ++v) {
+            const P* yp = lc ? wv[(LPC * v + 1) % S] : wv[(LPC * v) % S];
+            y[v] = in ? yp[r] : P(0);
+        }
     };
     int64_t cb = r0 + (int64_t)wave * MF_CH;
     if (cb < r1) load(cb);
@@ -666,7 +681,7 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
         if (cb + (int64_t)WPB * MF_CH < r1) load(cb + (int64_t)WPB * MF_CH);
 #pragma unroll
         for (int t = 0; t < MF_CH / 4; ++t) {
-            const double b = (double)mw[(i & 7) * STR + 4 * t + q];
+            const double b = (double)mw[(i & (S - 1)) * STR + 4 * t + q];
 #pragma unroll
             for (int h = 0; h < NA; ++h) {
                 const double a = (double)mv[(16 * h + i) * STR + 4 * t + q];
@@ -677,7 +692,7 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // lane (i, q) holds the dots of column 16 h + row(q, v) with vector i (i < 8)
+    // lane (i, q) holds the dots of column 16 h + row(q, v) with vector i (i < S)
     __syncthreads();
     double(*red)[MF_CT * S] = reinterpret_cast<double(*)[MF_CT * S]>(&sv[0][0]);
     if (i < S) {
@@ -813,6 +828,73 @@ __global__ __launch_bounds__(BLK) void update_block_kernel(const P* __restrict__
     }
 }
 
+// w_r -= sum_{c<=j} R_r[c] V_c for the sixteen vectors of a block, UP16_E
+// rows per thread, without Gram partials (136 pair sums per row would not fit
+// in registers: blocks of sixteen form their Gram matrix afterwards with the
+// matrix-core dot kernel on the updated vectors).  The coefficients R_r[c] are
+// wave-uniform (scalar loads); the workgroups after the first nchunk take the
+// Hessenberg products, as in update_block_kernel.
+constexpr int UP16_E = 2;
+template <typename P>
+__global__ __launch_bounds__(BLK) void update16_kernel(const P* __restrict__ V, BlockVecs<P> W, int64_t n, int j,
+                                                       const int* ctrl, const double* __restrict__ R, int nchunk,
+                                                       const double* __restrict__ Hrow, int ldr,
+                                                       double* __restrict__ HX, int ldx)
+{
+    if (ctrl[C_STOP] || ctrl[C_J] != j) return;
+    constexpr int S = 16, E = UP16_E;
+    if ((int)blockIdx.x >= nchunk) {
+        const int lane = threadIdx.x & 63;
+        const int t = ((int)blockIdx.x - nchunk) * (BLK / 64) + (threadIdx.x >> 6);
+        if (t > j) return;
+        const double* hr = Hrow + (int64_t)t * ldr;
+        double acc[S - 1];
+#pragma unroll
+        for (int l = 0; l < S - 1; ++l) acc[l] = 0.0;
+        for (int c = (t > 0 ? t - 1 : 0) + lane; c < j; c += 64) {
+            const double h = hr[c];
+#pragma unroll
+            for (int l = 0; l < S - 1; ++l) acc[l] += h * R[l * (j + 1) + c];
+        }
+#pragma unroll
+        for (int l = 0; l < S - 1; ++l) {
+            const double v = wave_sum(acc[l]);
+            if (lane == 0) HX[l * ldx + t] = v;
+        }
+        return;
+    }
+    const int64_t base = (int64_t)blockIdx.x * (BLK * E) + threadIdx.x;
+    double u[S][E];
+    bool in[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t t = base + (int64_t)e * BLK;
+        in[e] = t < n;
+#pragma unroll
+        for (int q = 0; q < S; ++q) u[q][e] = in[e] ? (double)W.w[q][t] : 0.0;
+    }
+    for (int c = 0; c <= j; ++c) {
+        const P* vc = V + (int64_t)c * n;
+        double a[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) a[e] = in[e] ? (double)__builtin_nontemporal_load(vc + base + (int64_t)e * BLK) : 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const double h = R[q * (j + 1) + c];
+#pragma unroll
+            for (int e = 0; e < E; ++e) u[q][e] -= h * a[e];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (in[e]) {
+            const int64_t t = base + (int64_t)e * BLK;
+#pragma unroll
+            for (int q = 0; q < S; ++q) W.w[q][t] = (P)u[q][e];
+        }
+    }
+}
+
 // One workgroup: Gram reduction, Cholesky (pivot i is resolvable when c_ii >
 // 1e-8 sqrt(G_ii), pivot 0 when c_00 > 1e-300), the block's Hessenberg
 // columns (raw copies in the row-major Hr, leading dimension ldr; rotated in H, leading
@@ -828,7 +910,7 @@ constexpr int BG_T = 1024;
 constexpr int BG_UNROLL = 8;
 // longest cycle of the block path for blocks of S vectors (the S Hessenberg
 // columns of a block live in LDS)
-constexpr int bg_maxj(int S) { return S <= 4 ? TS_MAXJ : 2048; }
+constexpr int bg_maxj(int S) { return S <= 4 ? TS_MAXJ : (S <= 8 ? 2048 : 640); }
 template <int LD>
 __device__ void bg_rotate_cols(double (*colv)[LD], int ncol, int count, const double* __restrict__ cs,
                                const double* __restrict__ sn, double* sc, double* ss)
@@ -885,13 +967,13 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
     constexpr int NG = S * (S + 1) / 2;
-    __shared__ double red[NG][BG_T / 64];
+    __shared__ double red[S <= 8 ? NG : 1][BG_T / 64];  // S = 16: gp holds the reduced Gram matrix
     __shared__ double colv[S][bg_maxj(S) + 4];
     __shared__ double sc[GV_CHUNK], ss[GV_CHUNK];
     __shared__ double G[S][S], Cf[S][S], Ci[S][S];  // in LDS: thread 0 indexes them dynamically
     __shared__ int ncol_s, cut_s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    {
+    if constexpr (S <= 8) {
         double acc[NG];
 #pragma unroll
         for (int k = 0; k < NG; ++k) acc[k] = 0.0;
@@ -912,7 +994,11 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
         for (int q = 0; q < S; ++q)
             for (int p = 0; p <= q; ++p) {
                 double v = 0.0;
-                for (int w = 0; w < BG_T / 64; ++w) v += red[k][w];
+                if constexpr (S <= 8) {
+                    for (int w = 0; w < BG_T / 64; ++w) v += red[k][w];
+                } else {
+                    v = gp[p * S + q];
+                }
                 G[p][q] = G[q][p] = v;
                 ++k;
             }
@@ -1055,22 +1141,23 @@ __global__ __launch_bounds__(BLK) void normalize_block_kernel(P* __restrict__ V,
     const P* wv[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) wv[q] = W.w[q];
-    double ci[S][S];
-#pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-        for (int q = 0; q < S; ++q) ci[p][q] = scal[S_QB + p * S + q];
+    // C^{-1} in LDS (at S = 16 its 256 entries would not fit in registers)
+    __shared__ double ci[S][S];
+    for (int k = threadIdx.x; k < S * S; k += BLK) ci[k / S][k % S] = scal[S_QB + k];
+    __syncthreads();
     P* out = V + (int64_t)(j + 1) * n;
     for (int64_t r = (int64_t)blockIdx.x * BLK + threadIdx.x; r < n; r += (int64_t)gridDim.x * BLK) {
         double u[S];
 #pragma unroll
         for (int q = 0; q < S; ++q) u[q] = (double)wv[q][r];
-#pragma unroll
+        constexpr int NU = S <= 8 ? S : 1;  // sixteen outputs: a loop, with C^{-1} read from LDS
+#pragma unroll NU
         for (int i = 0; i < S; ++i) {
             if (i < nq) {
                 double v = 0.0;
 #pragma unroll
-                for (int l = 0; l <= i; ++l) v += u[l] * ci[l][i];
+                for (int l = 0; l < S; ++l)
+                    if (l <= i) v += u[l] * ci[l][i];
                 out[(int64_t)i * n + r] = (P)v;
             }
         }
@@ -1216,7 +1303,9 @@ struct dg_solver {
     void* u = nullptr;      // [n] in P
     void* w2 = nullptr;     // [n] in P: the third vector of blocks of 3 or more
     void* w3 = nullptr;     // [n] in P: the fourth vector of blocks of 4 or more
-    void* wx[BS_MAX - 4] = {nullptr, nullptr, nullptr, nullptr};  // [n] in P: vectors 5..8 of larger blocks
+    void* wx[BS_MAX - 4] = {};  // [n] in P: vectors 5..16 of larger blocks
+    double* G16 = nullptr;      // [16][16] Gram matrix of a block of sixteen (blocks of 16 only)
+    int64_t npartials = 0;      // doubles in partials
     double* r = nullptr;    // [n] FP64
     double* partials = nullptr;
     double* hcol = nullptr;
@@ -1351,6 +1440,7 @@ static void solver_free(dg_solver* s)
     hipFree(s->r); hipFree(s->partials); hipFree(s->hcol); hipFree(s->hcol2); hipFree(s->H); hipFree(s->cs);
     hipFree(s->Rb); hipFree(s->Hr); hipFree(s->HX); hipFree(s->w2); hipFree(s->w3);
     for (void* p : s->wx) hipFree(p);
+    hipFree(s->G16);
     hipFree(s->sn); hipFree(s->g); hipFree(s->y); hipFree(s->scal); hipFree(s->ctrl); hipFree(s->bad);
     if (s->h_rep) hipHostFree(s->h_rep);
     s->h_rep = nullptr;
@@ -1365,8 +1455,11 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
         return DG_ERR_ARG;
     if (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)) return DG_ERR_ARG;
     if (o->persistent < -1 || o->persistent > 1 || o->profile < 0 || o->profile > 2) return DG_ERR_ARG;
-    if (o->block < 0 || o->block > BS_MAX || o->block == 5 || o->block == 7 || (o->block > 1 && o->reorth))
-        return DG_ERR_ARG;
+    const bool block_ok = o->block == 0 || (o->block >= 1 && o->block <= 4) || o->block == 6 || o->block == 8 ||
+                          o->block == 16;
+    // sixteen vectors in FP64 cycles only (in FP32 the block's sixteenth power loses too much: on a P3 IIPG test
+    // 3582 steps against 1581 for one vector per pass)
+    if (!block_ok || (o->block > 1 && o->reorth) || (o->block == 16 && o->mixed)) return DG_ERR_ARG;
     if (o->basis < 0 || o->basis > 2 || (o->block > 4 && o->restart > bg_maxj(o->block))) return DG_ERR_ARG;
     dg_solver* s = new (std::nothrow) dg_solver();
     if (!s) return DG_ERR_OOM;
@@ -1380,7 +1473,11 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     s->mixed = o->mixed;
     // automatic: eight vectors per pass in FP64 cycles; in FP32 cycles the rounding of the block's vectors
     // makes eight take up to a fifth more steps on hard systems (six: a few percent)
-    s->block = o->block != 0 ? o->block : (o->reorth ? 1 : (o->restart <= bg_maxj(8) ? (o->mixed ? 6 : 8) : 3));
+    s->block = o->block != 0 ? o->block
+                             : (o->reorth ? 1
+                                          : (!o->mixed && o->restart <= bg_maxj(16)
+                                                 ? 16
+                                                 : (o->restart <= bg_maxj(8) ? (o->mixed ? 6 : 8) : 3)));
     s->theta = o->basis == 1 ? 0.0 : 1.0;
     const int EPW = 64 / s->N;
     s->grid_elem = (int)((s->T + 4 * EPW - 1) / (4 * EPW));
@@ -1399,10 +1496,16 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
             s->md_shape2(j, S, &nt, &sp, &rows);
             maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * S);
         }
-        s->md_shape_mf(j, &nt, &sp, &rows);
-        maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * 8);
+        s->md_shape_mf(j, &nt, &sp, &rows);  // eight or sixteen vectors
+        maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * BS_MAX);
     }
     maxgrid = std::max<int64_t>(maxgrid, BS_MAX * (BS_MAX + 1) / 2 * (int64_t)s->grid_chunk);
+    {  // the Gram matrix of a block of sixteen: 16 x 16 columns in the shape of column count 16
+        int nt, sp;
+        int64_t rows;
+        s->md_shape_mf(BS_MAX - 1, &nt, &sp, &rows);
+        maxgrid = std::max<int64_t>(maxgrid, (int64_t)BS_MAX * BS_MAX * sp);
+    }
     bool ok = true;
     auto al = [&](void** p, size_t bytes) { if (ok && hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) { *p = nullptr; ok = false; } };
     al(&s->Ahat, ps * NN * std::max<int64_t>(s->n_off, 1));
@@ -1413,6 +1516,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     al(&s->u, ps * s->n);
     al((void**)&s->r, sizeof(double) * s->n);
     al((void**)&s->partials, sizeof(double) * (size_t)maxgrid);
+    s->npartials = maxgrid;
     al((void**)&s->hcol, sizeof(double) * (mm + 2));
     al((void**)&s->hcol2, sizeof(double) * (mm + 2));
     if (s->block > 1) {
@@ -1423,6 +1527,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     if (s->block > 2) al(&s->w2, ps * s->n);
     if (s->block > 3) al(&s->w3, ps * s->n);
     for (int q = 4; q < s->block; ++q) al(&s->wx[q - 4], ps * s->n);
+    if (s->block == 16) al((void**)&s->G16, sizeof(double) * 16 * 16);
     al((void**)&s->H, sizeof(double) * (size_t)(mm + 1) * mm);
     al((void**)&s->cs, sizeof(double) * mm);
     al((void**)&s->sn, sizeof(double) * mm);
@@ -1531,17 +1636,26 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
     const int mm = s->o.restart;
     const double ps = (double)sizeof(P), nb = (double)s->n;
     P* V = (P*)s->V;
-    BlockVecs<P> W{{(P*)s->w, (P*)s->u, (P*)s->w2, (P*)s->w3, (P*)s->wx[0], (P*)s->wx[1], (P*)s->wx[2],
-                    (P*)s->wx[3]}};  // u is free until the cycle's combine
+    BlockVecs<P> W{};  // u is free until the cycle's combine
+    {
+        void* const vecs[BS_MAX] = {s->w, s->u, s->w2, s->w3, s->wx[0], s->wx[1], s->wx[2], s->wx[3],
+                                    s->wx[4], s->wx[5], s->wx[6], s->wx[7], s->wx[8], s->wx[9], s->wx[10], s->wx[11]};
+        for (int q = 0; q < BS_MAX; ++q) W.w[q] = (P*)vecs[q];
+    }
     const P cid = (P)(1.0 - s->theta);
     P* const* wv = W.w;
     for (int j = 0; j < mcyc; j += S) {
         int nt, sp;
         int64_t rows;
-        constexpr bool MF = S == 8;  // blocks of eight: the dots on the matrix cores
+        constexpr bool MF = S == 8 || S == 16;  // blocks of eight or sixteen: the dots on the matrix cores
         if (MF) s->md_shape_mf(j, &nt, &sp, &rows);
         else s->md_shape2(j, S, &nt, &sp, &rows);
         const double md_bytes = (j + 1.0 + S) * nb * ps, up_bytes = (j + 1.0 + 2 * S) * nb * ps;
+        if ((int64_t)S * (j + 1) * sp > s->npartials) {  // the partials of this shape do not fit (a sizing bug)
+            fprintf(stderr, "dgdcr: block dot partials %lld exceed %lld\n", (long long)S * (j + 1) * sp,
+                    (long long)s->npartials);
+            abort();
+        }
         for (int q = 0; q < S; ++q) {
             const bool pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
             hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
@@ -1550,8 +1664,8 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
             prof_end(s, st, pr);
         }
         bool pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
-        if (MF)
-            hipLaunchKernelGGL((multidot_mfma_kernel<P>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, W, s->n, j,
+        if constexpr (S == 8 || S == 16)
+            hipLaunchKernelGGL((multidot_mfma_kernel<P, S>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, W, s->n, j,
                                rows, (const int*)s->ctrl, s->partials);
         else
             hipLaunchKernelGGL((multidot_block_kernel<P, S>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, W, s->n, j,
@@ -1561,14 +1675,34 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
                            (const double*)s->partials, S * (j + 1), sp, j, (const int*)s->ctrl, s->Rb, 0);
         pr = prof_begin(s, st, PK_UPDATE, up_bytes, j, 0);
         const int hrows = (j + 1 + BLK / 64 - 1) / (BLK / 64);  // workgroups of the Hessenberg products
-        hipLaunchKernelGGL((update_block_kernel<P, S>), dim3(s->grid_chunk + hrows), dim3(BLK), 0, st, (const P*)V, W,
-                           s->n, j, (const int*)s->ctrl, s->partials, (const double*)s->Rb, s->grid_chunk,
-                           (const double*)s->Hr, mm + 1, s->HX, mm + 2);
-        prof_end(s, st, pr);
-        hipLaunchKernelGGL((block_givens_kernel<S>), dim3(1), dim3(BG_T), 0, st, s->ctrl, (const double*)s->partials,
-                           s->grid_chunk, (const double*)s->Rb, s->Hr, mm + 1, (const double*)s->HX, mm + 2, s->H,
-                           mm + 1, s->cs, s->sn, s->g,
-                           s->scal, j, mcyc, s->theta);
+        const double* gram = s->partials;  // Gram partials (pairs x grid_chunk), or at S = 16 the reduced matrix
+        if constexpr (S == 16) {
+            const int g16 = (int)((s->n + BLK * UP16_E - 1) / (BLK * UP16_E));
+            hipLaunchKernelGGL((update16_kernel<P>), dim3(g16 + hrows), dim3(BLK), 0, st, (const P*)V, W, s->n, j,
+                               (const int*)s->ctrl, (const double*)s->Rb, g16, (const double*)s->Hr, mm + 1, s->HX,
+                               mm + 2);
+            prof_end(s, st, pr);
+            int gt, gs;
+            int64_t grows;
+            s->md_shape_mf(S - 1, &gt, &gs, &grows);
+            if ((int64_t)S * S * gs > s->npartials) {
+                fprintf(stderr, "dgdcr: block Gram partials exceed %lld\n", (long long)s->npartials);
+                abort();
+            }
+            hipLaunchKernelGGL((multidot_mfma_kernel<P, S, true>), dim3(gt, gs), dim3(BLK), 0, st, (const P*)V, W,
+                               s->n, j, grows, (const int*)s->ctrl, s->partials);
+            hipLaunchKernelGGL(reduce_cols_kernel, dim3((S * S + 3) / 4), dim3(BLK), 0, st, (const double*)s->partials,
+                               S * S, gs, j, (const int*)s->ctrl, s->G16, 0);
+            gram = s->G16;
+        } else {
+            hipLaunchKernelGGL((update_block_kernel<P, S>), dim3(s->grid_chunk + hrows), dim3(BLK), 0, st, (const P*)V,
+                               W, s->n, j, (const int*)s->ctrl, s->partials, (const double*)s->Rb, s->grid_chunk,
+                               (const double*)s->Hr, mm + 1, s->HX, mm + 2);
+            prof_end(s, st, pr);
+        }
+        hipLaunchKernelGGL((block_givens_kernel<S>), dim3(1), dim3(BG_T), 0, st, s->ctrl, gram, s->grid_chunk,
+                           (const double*)s->Rb, s->Hr, mm + 1, (const double*)s->HX, mm + 2, s->H, mm + 1, s->cs,
+                           s->sn, s->g, s->scal, j, mcyc, s->theta);
         hipLaunchKernelGGL((normalize_block_kernel<P, S>), dim3(s->grid_vec), dim3(BLK), 0, st, V, W, s->n, j,
                            (const int*)s->ctrl, (const double*)s->scal);
     }
@@ -1654,6 +1788,7 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
         if (s->block == 4) block_cycle<N, P, 4>(s, st, mcyc, spmv_bytes);
         if (s->block == 6) block_cycle<N, P, 6>(s, st, mcyc, spmv_bytes);
         if (s->block == 8) block_cycle<N, P, 8>(s, st, mcyc, spmv_bytes);
+        if (s->block == 16) block_cycle<N, P, 16>(s, st, mcyc, spmv_bytes);
         for (int j = 0; s->block == 1 && j < mcyc; ++j) {
             int nt, sp;
             int64_t rows;
