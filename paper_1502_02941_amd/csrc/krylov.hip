@@ -987,6 +987,79 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
         }
     }
     for (int i = threadIdx.x; i <= j; i += BG_T) colv[0][i] = R[i];
+    if constexpr (S > 8) {
+        // sixteen vectors: the Cholesky factor and its inverse on the lanes of wave 0 (thread 0 alone spent most
+        // of this kernel's time on them): lane q holds column q of the Gram matrix, the pivots and the rows of
+        // the factor are shared by shuffles, and lane q then solves C x = e_q for column q of C^{-1}
+        __shared__ int pok_s;
+        for (int k = threadIdx.x; k < S * S; k += BG_T) Cf[k / S][k % S] = Ci[k / S][k % S] = 0.0;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int q = threadIdx.x;
+            double a[S];
+#pragma unroll
+            for (int i = 0; i < S; ++i) a[i] = q < S ? gp[i * S + q] : 0.0;  // G[i][q]
+            const double g0 = q < S ? gp[q * S + q] : 0.0;
+            int pok = 0;
+            bool alive = true;
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const double d = __shfl(a[k], k, 64);  // the updated pivot G[k][k]
+                const double gkk = __shfl(g0, k, 64);
+                const double ckk = d > 0.0 ? sqrt(d) : 0.0;
+                const bool ok = isfinite(ckk) && (k == 0 ? ckk > 1e-300 : ckk > 1e-8 * sqrt(gkk));
+                if (alive) {  // the same on every lane
+                    if (q == k) Cf[k][k] = isfinite(ckk) ? ckk : 0.0;
+                    if (!ok) {
+                        alive = false;
+                    } else {
+                        const double rkq = q > k && q < S ? a[k] / ckk : 0.0;  // C[k][q]
+                        if (q > k && q < S) Cf[k][q] = rkq;
+#pragma unroll
+                        for (int i = k + 1; i < S; ++i) {
+                            const double rki = __shfl(rkq, i, 64);  // C[k][i]
+                            if (i <= q) a[i] -= rki * rkq;
+                        }
+                        ++pok;
+                    }
+                }
+            }
+            if (q == 0) pok_s = pok;
+        }
+        __syncthreads();
+        if (threadIdx.x < pok_s) {  // C x = e_q on the resolvable leading triangle
+            const int q = threadIdx.x;
+            double x[S];
+#pragma unroll
+            for (int i = S - 1; i >= 0; --i) {
+                if (i > q) {
+                    x[i] = 0.0;
+                } else if (i == q) {
+                    x[i] = 1.0 / Cf[i][i];
+                } else {
+                    double v = 0.0;
+#pragma unroll
+                    for (int m = i + 1; m < S; ++m)
+                        if (m <= q) v += Cf[i][m] * x[m];
+                    x[i] = -v / Cf[i][i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+                if (i <= q) Ci[i][q] = x[i];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            colv[0][j] += theta;  // A v_j = w_0 + theta v_j
+            const int pok = pok_s;
+            int ncol = S < mcyc - j ? S : mcyc - j;
+            if (pok < S && ncol > pok + 1) ncol = pok + 1;
+            ncol_s = ncol;
+            cut_s = pok < S ? 1 : 0;
+            colv[0][j + 1] = Cf[0][0];
+        }
+        for (int k = threadIdx.x; k < S * S; k += BG_T) scal[S_QB + k] = Ci[k / S][k % S];
+    } else {
     __syncthreads();
     if (threadIdx.x == 0) {
         colv[0][j] += theta;  // A v_j = w_0 + theta v_j
@@ -1037,6 +1110,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
         for (int p = 0; p < S; ++p)
             for (int q = 0; q < S; ++q) scal[S_QB + p * S + q] = Ci[p][q];
     }
+    }
     __syncthreads();
     const int ncol = ncol_s;
     for (int i = threadIdx.x; i <= j + 1; i += BG_T) Hr[(int64_t)i * ldr + j] = colv[0][i];
@@ -1044,24 +1118,26 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
     // columns j+1 .. j+ncol-1, from the raw column j and the earlier raw columns
     if (ncol > 1) {
         for (int t = threadIdx.x; t <= j + ncol; t += BG_T) {
-            double hx[S - 1];
+            // row t of [R; C] (the block's coefficients on V below row j + 1, the Cholesky factor above), read
+            // once: the products below use its entries up to column ncol - 1
+            double rc[S];
 #pragma unroll
-            for (int l = 0; l < S - 1; ++l) hx[l] = 0.0;
-            if (t <= j + 1) {  // (Hr R_l)[t]: columns below j from HX, column j here
-                const double h = colv[0][t];
+            for (int m = 0; m < S; ++m)
+                rc[m] = m >= ncol ? 0.0 : (t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0));
+            double e[S - 1];  // (A u_l)[t] = w_{l+1} + theta w_l - A V R_l in the basis [V, Q]
+            const double h = t <= j + 1 ? colv[0][t] : 0.0;  // (Hr R_l)[t]: columns below j from HX, column j here
 #pragma unroll
-                for (int l = 0; l < S - 1; ++l) hx[l] = (t <= j ? HX[l * ldx + t] : 0.0) + h * R[l * (j + 1) + j];
+            for (int l = 0; l < S - 1; ++l) {
+                const double hx = t <= j + 1 ? (t <= j ? HX[l * ldx + t] : 0.0) + h * R[l * (j + 1) + j] : 0.0;
+                e[l] = rc[l + 1] + theta * rc[l] - hx;
             }
+#pragma unroll 1
             for (int i = 1; i < ncol; ++i) {
                 if (t > j + i + 1) continue;
                 double v = 0.0;
-                for (int l = 0; l < i; ++l) {
-                    // A u_l = w_{l+1} + theta w_l - A V R_l, in the basis [V, Q]
-                    const int m = l + 1;
-                    const double cm = t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0);
-                    const double cl = t <= j ? R[l * (j + 1) + t] : (t - j - 1 <= l ? Cf[t - j - 1][l] : 0.0);
-                    v += (cm + theta * cl - hx[l]) * Ci[l][i - 1];
-                }
+#pragma unroll
+                for (int l = 0; l < S - 1; ++l)
+                    if (l < i) v += e[l] * Ci[l][i - 1];
                 colv[i][t] = v;
             }
         }

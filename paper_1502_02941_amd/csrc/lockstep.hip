@@ -1115,16 +1115,21 @@ __global__ __launch_bounds__(LS_GT) void ls_block_givens_kernel(const LsArgs A, 
                     for (int l = 0; l < S - 1; ++l) hx[l] += h * R[l * (j + 1) + c];
                 }
             }
+            // row t of [R; C] (coefficients on V below row j + 1, the Cholesky factor above), read once
+            double rc[S];
+#pragma unroll
+            for (int m = 0; m < S; ++m)
+                rc[m] = m >= ncol ? 0.0 : (t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0));
+            double e[S - 1];  // Ahat u_l = w_{l+1} + theta w_l - Ahat V R_l, in the basis [V, Q]
+#pragma unroll
+            for (int l = 0; l < S - 1; ++l) e[l] = rc[l + 1] + A.theta * rc[l] - hx[l];
+#pragma unroll 1
             for (int ii = 1; ii < ncol; ++ii) {
                 if (t > j + ii + 1) continue;
                 double v = 0.0;
-                for (int l = 0; l < ii; ++l) {
-                    const int m = l + 1;
-                    // Ahat u_l = w_{l+1} + theta w_l - Ahat V R_l, in the basis [V, Q]
-                    const double cm = t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0);
-                    const double cl = t <= j ? R[l * (j + 1) + t] : (t - j - 1 <= l ? Cf[t - j - 1][l] : 0.0);
-                    v += (cm + A.theta * cl - hx[l]) * Ci[l][ii - 1];
-                }
+#pragma unroll
+                for (int l = 0; l < S - 1; ++l)
+                    if (l < ii) v += e[l] * Ci[l][ii - 1];
                 dyn[ii * ldc + t] = v;
             }
         }
