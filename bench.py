@@ -90,10 +90,10 @@ def launched_kernel(cls, prec, block):
     functions per element) for Arnoldi blocks of `block` vectors."""
     if cls == "spmv_hat":
         return "spmv_hat_kernel<6, %s>" % prec
-    if block in (8, 16) and cls == "multidot":
+    if block in (8, 16, 32) and cls == "multidot":
         return "multidot_mfma_kernel<%s, %d>" % (prec, block)
-    if block == 16 and cls == "update":
-        return "update16_kernel<%s>" % prec
+    if block in (16, 32) and cls == "update":
+        return "update_wide_kernel<%s, %d>" % (prec, block)
     if block > 1 and cls in ("multidot", "update"):
         return "%s_block_kernel<%s, %d>" % (cls, prec, block)
     return "%s_kernel<%s>" % (cls, prec)
@@ -136,7 +136,7 @@ def main():
     ap.add_argument("--lockstep-block", type=int, default=0, choices=(0, 1, 2, 3, 6, 8),
                     help="c4, c5: Arnoldi vectors per Gram-Schmidt pass of the lockstep solver (0: the batch's "
                          "choice, 8)")
-    ap.add_argument("--block", type=int, default=0, choices=(0, 1, 2, 3, 4, 6, 8, 16),
+    ap.add_argument("--block", type=int, default=0, choices=(0, 1, 2, 3, 4, 6, 8, 16, 32),
                     help="Arnoldi vectors per Gram-Schmidt pass (0: the solver's choice; 16 in FP64 cycles only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c2", choices=("c1", "c2", "c3", "c4", "c5", "nl", "mlp"))
@@ -180,7 +180,7 @@ def main():
     # the solve stream (profile=2); a per-kernel breakdown comes from one more, untimed, solve
     # with every heavy kernel timed (profile=1: about 6% slower from the events alone)
     def make_solver(form, profile):
-        blk = 0 if form == "mixed" and args.block == 16 else args.block  # sixteen: FP64 cycles only
+        blk = 0 if form == "mixed" and args.block >= 16 else args.block  # sixteen or 32: FP64 cycles only
         return api.Solver(mesh, restart=args.restart, max_iters=20000, rel_tol=1e-10, mixed=form == "mixed",
                           inner_tol=1e-6, reorth=bool(args.reorth), profile=profile, block=blk)
 
@@ -265,8 +265,10 @@ def main():
     def block_of(form):  # the solver's automatic choice unless --block is given
         if args.reorth:
             return 1
-        if args.block and not (form == "mixed" and args.block == 16):
+        if args.block and not (form == "mixed" and args.block >= 16):
             return args.block
+        if form == "fp64" and args.restart <= 608:
+            return 32
         if form == "fp64" and args.restart <= 640:
             return 16
         return (8 if form == "fp64" else 6) if args.restart <= 2048 else 3

@@ -235,15 +235,18 @@ typedef struct {
                              systems of at most 4096 unknowns; 1: always (DG_ERR_ARG if unsupported);
                              -1: never */
     int32_t block;        /* Arnoldi vectors per Gram-Schmidt pass of the kernel-per-step path, S: 1 = one
-                             (w = A M^{-1} v_j, then h = V^T w and w -= V h); S = 2, 3, 4, 6, 8 or 16 = a
+                             (w = A M^{-1} v_j, then h = V^T w and w -= V h); S = 2, 3, 4, 6, 8, 16 or 32 = a
                              block of S vectors (w_0 from v_j, each next one from the one before, see basis)
                              projected on the basis in one pass, orthonormalised by Cholesky QR, its S
                              Hessenberg columns recovered from the block: the basis is read once per S
-                             steps.  0 = automatic (16 with FP64 cycles when restart <= 640; else 8, or 6 with
-                             mixed, when restart <= 2048; else 3; 1 with reorth).  A block whose Gram matrix has
-                             an unresolvable pivot (Cholesky pivot <= 1e-8 of the vector's norm) ends the cycle
-                             at the last column it determines.  S > 4 needs restart <= 2048, S = 16 restart
-                             <= 640 and FP64 cycles (mixed = 0).  DG_ERR_ARG for other values, or for S > 1 with
+                             steps.  0 = automatic (with FP64 cycles 32 when restart <= 608, 16 when restart
+                             <= 640; else 8, or 6 with mixed, when restart <= 2048; else 3; 1 with reorth).  A
+                             block whose Gram matrix has an unresolvable pivot (Cholesky pivot <= 1e-8 of the
+                             vector's norm) ends the cycle at the last column it determines.  With S >= 16 a
+                             cycle that raises the true residual is undone (x restored), and it or a cycle ended
+                             that way short of its length without converging halves S for the cycles after it.
+                             S > 4 needs restart <= 2048, S = 16 restart <= 640 and S = 32 restart <= 608, both
+                             with FP64 cycles (mixed = 0).  DG_ERR_ARG for other values, or for S > 1 with
                              reorth. */
     int32_t basis;        /* how a block's vectors are formed: 1 = monomial, w_i = A M^{-1} w_{i-1} (its Gram
                              matrix grows ill-conditioned with S: on the 256 x 256 P2 boundary-layer system

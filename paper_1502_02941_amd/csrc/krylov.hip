@@ -33,7 +33,7 @@ namespace dg {
 
 enum { C_J = 0, C_STOP = 1, C_REORTH = 2, C_NREORTH = 3, C_NCTRL = 16 };
 enum { S_BNORM2 = 0, S_RNORM2 = 1, S_INVH = 2, S_WNORM2 = 3, S_HN = 4, S_CYCTOL = 5, S_BETA = 6,
-       S_QB = 7, S_NSCAL = 7 + 16 * 16 + 1 };  // S_QB..: the inverse Cholesky factor of an Arnoldi block (row-major, S x S)
+       S_QB = 7, S_NSCAL = 7 + 32 * 32 + 1 };  // S_QB..: the inverse Cholesky factor of an Arnoldi block (row-major, S x S)
 
 constexpr int BLK = 256;
 constexpr int MD_TARGET_BLOCKS = 2048;   // multidot: column tiles x row splits aimed at this many blocks
@@ -326,6 +326,28 @@ __global__ __launch_bounds__(BLK) void reduce_cols_kernel(const double* __restri
     if (lane == 0) hcol[c] = acc;
 }
 
+// The same sums for a block's projections R_v[c] (column v jc + c, v < S),
+// written as R and, negated and transposed, as negRT[c S + v]: the operand
+// layout of the matrix-core update (the coefficients of four consecutive basis
+// columns for sixteen vectors are then 4 x 128 contiguous bytes).
+__global__ __launch_bounds__(BLK) void reduce_cols_rt_kernel(const double* __restrict__ partials, int S, int jc,
+                                                             int splits, int j, const int* ctrl, double* R,
+                                                             double* negRT)
+{
+    if (ctrl[C_STOP] || ctrl[C_J] != j) return;
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * (BLK / 64) + (threadIdx.x >> 6);
+    if (c >= S * jc) return;
+    const double* pc = partials + (int64_t)c * splits;
+    double acc = 0.0;
+    for (int sp = lane; sp < splits; sp += 64) acc += pc[sp];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        R[c] = acc;
+        negRT[(int64_t)(c % jc) * S + c / jc] = -acc;
+    }
+}
+
 // w -= sum_{c<=j} h[c] V_c and ||w||^2 (into scal[S_WNORM2]); rows split over
 // threads, columns unrolled by 4 to keep many loads in flight.  In the
 // reorthogonalisation pass (reorth_pass != 0) it runs only when flagged.
@@ -470,7 +492,7 @@ __global__ __launch_bounds__(BLK) void normalize_kernel(P* __restrict__ V, const
 // and, for i < S - 1, Ahat q_i = sum_{l<=i} (w_{l+1} - Ahat V R_l) (C^{-1})_{li}
 // with Ahat V = V H.
 // ---------------------------------------------------------------------------
-constexpr int BS_MAX = 16;
+constexpr int BS_MAX = 32;
 // the block's vectors w_0..w_{S-1}, passed by value
 template <typename P>
 struct BlockVecs {
@@ -637,8 +659,8 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
     const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
     if (logical >= total) return;
     const int tile = logical % ntile, split = logical / ntile;
-    static_assert(S == 8 || S == 16, "eight or sixteen vectors");
-    constexpr int STR = MfStage<P>::STR, WPB = BLK / 64, NA = MF_CT / 16;
+    static_assert(S == 8 || S == 16 || S == 32, "eight, sixteen or 32 vectors");
+    constexpr int STR = MfStage<P>::STR, WPB = BLK / 64, NA = MF_CT / 16, NB = S > 16 ? S / 16 : 1;
     using Op = MfmaOp<double>;  // FP32 data too: the dots are summed in FP64, as by the vector-ALU kernel
     using VR = typename Op::V;
     __shared__ __align__(16) P sv[WPB][MF_CT * STR];  // after the row loop: the waves' partial sums
@@ -655,9 +677,11 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
     const P* wv[S];
 #pragma unroll
     for (int v = 0; v < S; ++v) wv[v] = W.w[v];
-    VR acc[NA];
+    VR acc[NA][NB];
 #pragma unroll
-    for (int h = 0; h < NA; ++h) acc[h] = VR{0, 0, 0, 0};
+    for (int h = 0; h < NA; ++h)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[h][b] = VR{0, 0, 0, 0};
     constexpr int LPC = MF_CH / 64 > 0 ? 1 : 64 / MF_CH;  // chunks of 32 rows: a lane loads two columns' rows
     P x[MF_CT / LPC], y[S / LPC];
     // a chunk's rows into registers (the next chunk's loads are in flight during this chunk's products):
@@ -699,25 +723,31 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
         if (cb + (int64_t)WPB * MF_CH < r1) load(cb + (int64_t)WPB * MF_CH);
 #pragma unroll
         for (int t = 0; t < MF_CH / 4; ++t) {
-            const double b = (double)mw[(i & (S - 1)) * STR + 4 * t + q];
+            double b[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) b[nb] = (double)mw[((16 * nb + i) & (S - 1)) * STR + 4 * t + q];
 #pragma unroll
             for (int h = 0; h < NA; ++h) {
                 const double a = (double)mv[(16 * h + i) * STR + 4 * t + q];
-                acc[h] = Op::mac(a, i < S ? b : 0.0, acc[h]);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[h][nb] = Op::mac(a, i < S ? b[nb] : 0.0, acc[h][nb]);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // lane (i, q) holds the dots of column 16 h + row(q, v) with vector i (i < S)
+    // lane (i, q) holds the dots of column 16 h + row(q, v) with vector 16 nb + i (i < S)
     __syncthreads();
     double(*red)[MF_CT * S] = reinterpret_cast<double(*)[MF_CT * S]>(&sv[0][0]);
     if (i < S) {
 #pragma unroll
         for (int h = 0; h < NA; ++h)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) red[wave][(16 * h + Op::row(q, v)) * S + i] = (double)acc[h][v];
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    red[wave][(16 * h + Op::row(q, v)) * S + 16 * nb + i] = (double)acc[h][nb][v];
     }
     __syncthreads();
     for (int t = threadIdx.x; t < MF_CT * S; t += BLK) {
@@ -846,21 +876,21 @@ __global__ __launch_bounds__(BLK) void update_block_kernel(const P* __restrict__
     }
 }
 
-// w_r -= sum_{c<=j} R_r[c] V_c for the sixteen vectors of a block, UP16_E
-// rows per thread, without Gram partials (136 pair sums per row would not fit
-// in registers: blocks of sixteen form their Gram matrix afterwards with the
-// matrix-core dot kernel on the updated vectors).  The coefficients R_r[c] are
-// wave-uniform (scalar loads); the workgroups after the first nchunk take the
-// Hessenberg products, as in update_block_kernel.
-constexpr int UP16_E = 2;
-template <typename P>
-__global__ __launch_bounds__(BLK) void update16_kernel(const P* __restrict__ V, BlockVecs<P> W, int64_t n, int j,
-                                                       const int* ctrl, const double* __restrict__ R, int nchunk,
-                                                       const double* __restrict__ Hrow, int ldr,
-                                                       double* __restrict__ HX, int ldx)
+// w_r -= sum_{c<=j} R_r[c] V_c for the S = 16 or 32 vectors of a block,
+// upw_rows(S) rows per thread, without Gram partials (136 pair sums per row
+// would not fit in registers: wide blocks form their Gram matrix afterwards
+// with the matrix-core dot kernel on the updated vectors).  The coefficients
+// R_r[c] are wave-uniform (scalar loads); the workgroups after the first
+// nchunk take the Hessenberg products, as in update_block_kernel.
+constexpr int upw_rows(int S) { return S <= 16 ? 2 : 1; }
+template <typename P, int S>
+__global__ __launch_bounds__(BLK) void update_wide_kernel(const P* __restrict__ V, BlockVecs<P> W, int64_t n, int j,
+                                                          const int* ctrl, const double* __restrict__ R, int nchunk,
+                                                          const double* __restrict__ Hrow, int ldr,
+                                                          double* __restrict__ HX, int ldx)
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
-    constexpr int S = 16, E = UP16_E;
+    constexpr int E = upw_rows(S);
     if ((int)blockIdx.x >= nchunk) {
         const int lane = threadIdx.x & 63;
         const int t = ((int)blockIdx.x - nchunk) * (BLK / 64) + (threadIdx.x >> 6);
@@ -913,6 +943,107 @@ __global__ __launch_bounds__(BLK) void update16_kernel(const P* __restrict__ V, 
     }
 }
 
+// The same update on the matrix cores (FP64 cycles): W_tile -= V_tile R as
+// 16 x 16 x 4 FP64 products, a wave owning UPM_RT x 16 rows and all S columns
+// (S / 16 product column groups).  For each four basis columns, lane (i, q)
+// loads V[c + q][row i of each row tile] (16 consecutive rows of a column per
+// 16 lanes) as the A operand and -R_{16 g + i}[c + q] as the B operand (from
+// the transposed copy negRT, 128 contiguous bytes per four lanes' column); the
+// accumulators start from the block's vectors (D[i][j] in lane j + 16 g',
+// register v, rows g' + 4 v) and are stored back there.  Columns past j give
+// zero operands.  The workgroups after the first nchunk take the Hessenberg
+// products, as in update_wide_kernel.
+constexpr int UPM_RT = 4, UPM_PD = 4;
+template <typename P, int S>
+__global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, BlockVecs<P> W, int64_t n, int j,
+                                                          const int* ctrl, const double* __restrict__ R,
+                                                          const double* __restrict__ negRT, int nchunk,
+                                                          const double* __restrict__ Hrow, int ldr,
+                                                          double* __restrict__ HX, int ldx)
+{
+    if (ctrl[C_STOP] || ctrl[C_J] != j) return;
+    static_assert(sizeof(P) == 8 && (S == 16 || S == 32), "FP64 blocks of 16 or 32");
+    if ((int)blockIdx.x >= nchunk) {
+        const int lane = threadIdx.x & 63;
+        const int t = ((int)blockIdx.x - nchunk) * (BLK / 64) + (threadIdx.x >> 6);
+        if (t > j) return;
+        const double* hr = Hrow + (int64_t)t * ldr;
+        double acc[S - 1];
+#pragma unroll
+        for (int l = 0; l < S - 1; ++l) acc[l] = 0.0;
+        for (int c = (t > 0 ? t - 1 : 0) + lane; c < j; c += 64) {
+            const double h = hr[c];
+#pragma unroll
+            for (int l = 0; l < S - 1; ++l) acc[l] += h * R[l * (j + 1) + c];
+        }
+#pragma unroll
+        for (int l = 0; l < S - 1; ++l) {
+            const double v = wave_sum(acc[l]);
+            if (lane == 0) HX[l * ldx + t] = v;
+        }
+        return;
+    }
+    using Op = MfmaOp<double>;
+    using VR = typename Op::V;
+    constexpr int NB = S / 16, RT = UPM_RT;
+    const P* __restrict__ V = V_;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, q = lane >> 4;
+    const int64_t r0 = ((int64_t)blockIdx.x * (BLK / 64) + wave) * (16 * RT);
+    if (r0 >= n) return;
+    VR acc[RT][NB];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = r0 + 16 * rt + Op::row(q, v);
+                acc[rt][nb][v] = r < n ? (double)W.w[16 * nb + i][r] : 0.0;
+            }
+    const int jc = j + 1;
+    // UPM_PD chunks of four columns in flight per wave (one was too few to cover the memory latency)
+    constexpr int PD = UPM_PD;
+    double a[PD][RT], b[PD][NB];
+    auto load = [&](int u, int c0) {
+        const int c = c0 + q;
+        const bool in = c < jc;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t r = r0 + 16 * rt + i;
+            a[u][rt] = in && r < n ? (double)__builtin_nontemporal_load(V + (int64_t)c * n + r) : 0.0;
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) b[u][nb] = in ? negRT[(int64_t)c * S + 16 * nb + i] : 0.0;
+    };
+#pragma unroll
+    for (int u = 0; u < PD; ++u) load(u, 4 * u);
+    for (int c0 = 0; c0 < jc; c0 += 4 * PD) {
+#pragma unroll
+        for (int u = 0; u < PD; ++u) {
+            double ca[RT], cb[NB];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) ca[rt] = a[u][rt];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) cb[nb] = b[u][nb];
+            load(u, c0 + 4 * (u + PD));  // past column j: zeros, no memory read (a slot is never left stale)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[rt][nb] = Op::mac(ca[rt], cb[nb], acc[rt][nb]);
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = r0 + 16 * rt + Op::row(q, v);
+                if (r < n) W.w[16 * nb + i][r] = (P)acc[rt][nb][v];
+            }
+}
+
 // One workgroup: Gram reduction, Cholesky (pivot i is resolvable when c_ii >
 // 1e-8 sqrt(G_ii), pivot 0 when c_00 > 1e-300), the block's Hessenberg
 // columns (raw copies in the row-major Hr, leading dimension ldr; rotated in H, leading
@@ -928,7 +1059,7 @@ constexpr int BG_T = 1024;
 constexpr int BG_UNROLL = 8;
 // longest cycle of the block path for blocks of S vectors (the S Hessenberg
 // columns of a block live in LDS)
-constexpr int bg_maxj(int S) { return S <= 4 ? TS_MAXJ : (S <= 8 ? 2048 : 640); }
+constexpr int bg_maxj(int S) { return S <= 4 ? TS_MAXJ : (S <= 8 ? 2048 : (S <= 16 ? 640 : 608)); }
 template <int LD>
 __device__ void bg_rotate_cols(double (*colv)[LD], int ncol, int count, const double* __restrict__ cs,
                                const double* __restrict__ sn, double* sc, double* ss)
@@ -985,11 +1116,17 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
     constexpr int NG = S * (S + 1) / 2;
-    __shared__ double red[S <= 8 ? NG : 1][BG_T / 64];  // S = 16: gp holds the reduced Gram matrix
-    __shared__ double colv[S][bg_maxj(S) + 4];
+    // Hessenberg columns held in LDS at a time: a block of 32 forms and rotates its columns in two groups of 16
+    // (32 columns of a 576-step cycle would not fit), keeping only their rows j.. for this block's rotations
+    constexpr int GC = S < 16 ? S : 16, NGRP = S / GC, GS = S <= 8 ? S : 1;
+    __shared__ double red[S <= 8 ? NG : 1][BG_T / 64];  // S >= 16: gp holds the reduced Gram matrix
+    __shared__ double colv[GC][bg_maxj(S) + 4];
+    __shared__ double h0s[NGRP > 1 ? bg_maxj(S) + 4 : 1];  // raw column j, when colv[0] is reused by a group
     __shared__ double sc[GV_CHUNK], ss[GV_CHUNK];
-    __shared__ double G[S][S], Cf[S][S], Ci[S][S];  // in LDS: thread 0 indexes them dynamically
+    __shared__ double G[GS][GS], Cf[S][S], Ci[S][S];  // in LDS: indexed dynamically
+    __shared__ double tail[S][S + 2];  // rows j .. j + i + 1 of column j + i after the earlier rotations
     __shared__ int ncol_s, cut_s;
+    double* h0 = NGRP > 1 ? h0s : colv[0];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if constexpr (S <= 8) {
         double acc[NG];
@@ -1004,11 +1141,11 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
             if (lane == 0) red[k][wave] = v;
         }
     }
-    for (int i = threadIdx.x; i <= j; i += BG_T) colv[0][i] = R[i];
+    for (int i = threadIdx.x; i <= j; i += BG_T) h0[i] = R[i];
     if constexpr (S > 8) {
-        // sixteen vectors: the Cholesky factor and its inverse on the lanes of wave 0 (thread 0 alone spent most
-        // of this kernel's time on them): lane q holds column q of the Gram matrix, the pivots and the rows of
-        // the factor are shared by shuffles, and lane q then solves C x = e_q for column q of C^{-1}
+        // sixteen or more vectors: the Cholesky factor and its inverse on the lanes of wave 0 (thread 0 alone
+        // spent most of this kernel's time on them): lane q holds column q of the Gram matrix, the pivots and the
+        // rows of the factor are shared by shuffles, and lane q then solves C x = e_q for column q of C^{-1}
         __shared__ int pok_s;
         for (int k = threadIdx.x; k < S * S; k += BG_T) Cf[k / S][k % S] = Ci[k / S][k % S] = 0.0;
         __syncthreads();
@@ -1068,131 +1205,142 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            colv[0][j] += theta;  // A v_j = w_0 + theta v_j
+            h0[j] += theta;  // A v_j = w_0 + theta v_j
             const int pok = pok_s;
             int ncol = S < mcyc - j ? S : mcyc - j;
             if (pok < S && ncol > pok + 1) ncol = pok + 1;
             ncol_s = ncol;
             cut_s = pok < S ? 1 : 0;
-            colv[0][j + 1] = Cf[0][0];
+            h0[j + 1] = Cf[0][0];
         }
         for (int k = threadIdx.x; k < S * S; k += BG_T) scal[S_QB + k] = Ci[k / S][k % S];
     } else {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        colv[0][j] += theta;  // A v_j = w_0 + theta v_j
-        int k = 0;
-        for (int q = 0; q < S; ++q)
-            for (int p = 0; p <= q; ++p) {
-                double v = 0.0;
-                if constexpr (S <= 8) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            h0[j] += theta;  // A v_j = w_0 + theta v_j
+            int k = 0;
+            for (int q = 0; q < S; ++q)
+                for (int p = 0; p <= q; ++p) {
+                    double v = 0.0;
                     for (int w = 0; w < BG_T / 64; ++w) v += red[k][w];
-                } else {
-                    v = gp[p * S + q];
+                    G[p][q] = G[q][p] = v;
+                    ++k;
                 }
-                G[p][q] = G[q][p] = v;
-                ++k;
+            // upper Cholesky factor, stopping at the first pivot that is not resolvable
+            int pok = 0;
+            for (int p = 0; p < S; ++p)
+                for (int q = 0; q < S; ++q) Cf[p][q] = Ci[p][q] = 0.0;
+            for (int i = 0; i < S; ++i) {
+                double d = G[i][i];
+                for (int m = 0; m < i; ++m) d -= Cf[m][i] * Cf[m][i];
+                const double cii = d > 0.0 ? sqrt(d) : 0.0;
+                const bool ok = isfinite(cii) && (i == 0 ? cii > 1e-300 : cii > 1e-8 * sqrt(G[i][i]));
+                Cf[i][i] = isfinite(cii) ? cii : 0.0;
+                if (!ok) break;
+                for (int q = i + 1; q < S; ++q) {
+                    double v = G[i][q];
+                    for (int m = 0; m < i; ++m) v -= Cf[m][i] * Cf[m][q];
+                    Cf[i][q] = v / cii;
+                }
+                ++pok;
             }
-        // upper Cholesky factor, stopping at the first pivot that is not resolvable
-        int pok = 0;
-        for (int p = 0; p < S; ++p)
-            for (int q = 0; q < S; ++q) Cf[p][q] = Ci[p][q] = 0.0;
-        for (int i = 0; i < S; ++i) {
-            double d = G[i][i];
-            for (int m = 0; m < i; ++m) d -= Cf[m][i] * Cf[m][i];
-            const double cii = d > 0.0 ? sqrt(d) : 0.0;
-            const bool ok = isfinite(cii) && (i == 0 ? cii > 1e-300 : cii > 1e-8 * sqrt(G[i][i]));
-            Cf[i][i] = isfinite(cii) ? cii : 0.0;
-            if (!ok) break;
-            for (int q = i + 1; q < S; ++q) {
-                double v = G[i][q];
-                for (int m = 0; m < i; ++m) v -= Cf[m][i] * Cf[m][q];
-                Cf[i][q] = v / cii;
+            // inverse of the resolvable leading triangle
+            for (int i = 0; i < pok; ++i) {
+                Ci[i][i] = 1.0 / Cf[i][i];
+                for (int q = i + 1; q < pok; ++q) {
+                    double v = 0.0;
+                    for (int m = i; m < q; ++m) v += Ci[i][m] * Cf[m][q];
+                    Ci[i][q] = -v / Cf[q][q];
+                }
             }
-            ++pok;
+            int ncol = S < mcyc - j ? S : mcyc - j;
+            if (pok < S && ncol > pok + 1) ncol = pok + 1;
+            ncol_s = ncol;
+            cut_s = pok < S ? 1 : 0;
+            h0[j + 1] = Cf[0][0];
+            for (int p = 0; p < S; ++p)
+                for (int q = 0; q < S; ++q) scal[S_QB + p * S + q] = Ci[p][q];
         }
-        // inverse of the resolvable leading triangle
-        for (int i = 0; i < pok; ++i) {
-            Ci[i][i] = 1.0 / Cf[i][i];
-            for (int q = i + 1; q < pok; ++q) {
-                double v = 0.0;
-                for (int m = i; m < q; ++m) v += Ci[i][m] * Cf[m][q];
-                Ci[i][q] = -v / Cf[q][q];
-            }
-        }
-        int ncol = S < mcyc - j ? S : mcyc - j;
-        if (pok < S && ncol > pok + 1) ncol = pok + 1;
-        ncol_s = ncol;
-        cut_s = pok < S ? 1 : 0;
-        colv[0][j + 1] = Cf[0][0];
-        for (int p = 0; p < S; ++p)
-            for (int q = 0; q < S; ++q) scal[S_QB + p * S + q] = Ci[p][q];
-    }
     }
     __syncthreads();
     const int ncol = ncol_s;
-    for (int i = threadIdx.x; i <= j + 1; i += BG_T) Hr[(int64_t)i * ldr + j] = colv[0][i];
-    __syncthreads();
-    // columns j+1 .. j+ncol-1, from the raw column j and the earlier raw columns
-    if (ncol > 1) {
-        for (int t = threadIdx.x; t <= j + ncol; t += BG_T) {
-            // row t of [R; C] (the block's coefficients on V below row j + 1, the Cholesky factor above), read
-            // once: the products below use its entries up to column ncol - 1
-            double rc[S];
-#pragma unroll
-            for (int m = 0; m < S; ++m)
-                rc[m] = m >= ncol ? 0.0 : (t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0));
-            double e[S - 1];  // (A u_l)[t] = w_{l+1} + theta w_l - A V R_l in the basis [V, Q]
-            const double h = t <= j + 1 ? colv[0][t] : 0.0;  // (Hr R_l)[t]: columns below j from HX, column j here
-#pragma unroll
-            for (int l = 0; l < S - 1; ++l) {
-                const double hx = t <= j + 1 ? (t <= j ? HX[l * ldx + t] : 0.0) + h * R[l * (j + 1) + j] : 0.0;
-                e[l] = rc[l + 1] + theta * rc[l] - hx;
-            }
-#pragma unroll 1
-            for (int i = 1; i < ncol; ++i) {
-                if (t > j + i + 1) continue;
-                double v = 0.0;
-#pragma unroll
-                for (int l = 0; l < S - 1; ++l)
-                    if (l < i) v += e[l] * Ci[l][i - 1];
-                colv[i][t] = v;
-            }
-        }
+    for (int i = threadIdx.x; i <= j + 1; i += BG_T) Hr[(int64_t)i * ldr + j] = h0[i];
+    // columns j .. j + ncol - 1 in groups of GC: column j is h0; columns j+1 .. from it and the earlier raw
+    // columns; then the earlier blocks' rotations on all the group's columns at once; rows below j are final
+    for (int g0 = 0; g0 < ncol; g0 += GC) {
+        const int gn = ncol - g0 < GC ? ncol - g0 : GC;
         __syncthreads();
-        for (int i = 1; i < ncol; ++i)
-            for (int t = threadIdx.x; t <= j + i + 1; t += BG_T) Hr[(int64_t)t * ldr + j + i] = colv[i][t];
+        if constexpr (NGRP > 1) {
+            if (g0 == 0)
+                for (int t = threadIdx.x; t <= j + 1; t += BG_T) colv[0][t] = h0[t];
+        }
+        const int i1 = g0 > 0 ? g0 : 1;  // first column of the group formed here
+        if (i1 < g0 + gn) {
+            for (int t = threadIdx.x; t <= j + g0 + gn; t += BG_T) {
+                // row t of [R; C] (the block's coefficients on V below row j + 1, the Cholesky factor above)
+                auto rc = [&](int m) -> double {
+                    return m >= ncol ? 0.0
+                                     : (t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0));
+                };
+                double e[S - 1];  // (A u_l)[t] = w_{l+1} + theta w_l - A V R_l in the basis [V, Q]
+                const double h = t <= j + 1 ? h0[t] : 0.0;  // (Hr R_l)[t]: columns below j from HX, column j here
+                double rl = rc(0);
+#pragma unroll
+                for (int l = 0; l < S - 1; ++l) {
+                    const double hx = t <= j + 1 ? (t <= j ? HX[l * ldx + t] : 0.0) + h * R[l * (j + 1) + j] : 0.0;
+                    const double rm = rc(l + 1);
+                    e[l] = rm + theta * rl - hx;
+                    rl = rm;
+                }
+#pragma unroll 1
+                for (int i = i1; i < g0 + gn; ++i) {
+                    if (t > j + i + 1) continue;
+                    double v = 0.0;
+#pragma unroll
+                    for (int l = 0; l < S - 1; ++l)
+                        if (l < i) v += e[l] * Ci[l][i - 1];
+                    colv[i - g0][t] = v;
+                }
+            }
+            __syncthreads();
+            for (int i = i1; i < g0 + gn; ++i)
+                for (int t = threadIdx.x; t <= j + i + 1; t += BG_T) Hr[(int64_t)t * ldr + j + i] = colv[i - g0][t];
+        }
+        bg_rotate_cols(colv, gn, j, cs, sn, sc, ss);
+        for (int i = 0; i < gn; ++i) {
+            for (int t = threadIdx.x; t < j; t += BG_T) H[t + (int64_t)(j + g0 + i) * ldh] = colv[i][t];
+            for (int r = threadIdx.x; r <= g0 + i + 1; r += BG_T) tail[g0 + i][r] = colv[i][j + r];
+        }
     }
-    // the rotations of earlier blocks on all columns at once, then the columns
-    // in turn (thread 0, this block's rotations and residual estimates held in
-    // LDS): this block's earlier rotations, new rotation, estimate, stop
-    // test; then the columns taken, their rotations and estimates written out
-    // (no global round trip between the columns)
-    bg_rotate_cols(colv, ncol, j, cs, sn, sc, ss);
+    // this block's rotations on the columns in turn (thread 0, the rotations and residual estimates held in
+    // LDS): its earlier rotations, the new rotation, the estimate and the stop test; then the columns taken
+    // written out (no global round trip between the columns)
+    __syncthreads();
     __shared__ int taken_s, stop_s;
-    __shared__ double bc[S], bs[S], gk[S + 1];  // this block's rotations and estimates (thread 0)
+    __shared__ double bc[S], bs[S], gk[S + 1];
+    constexpr int UNR = S <= 16 ? S : 1;
     if (threadIdx.x == 0) {
         const double tol = scal[S_CYCTOL];
         gk[0] = g[j];
         int taken = ncol, stop = 0;
-#pragma unroll
+#pragma unroll UNR
         for (int i = 0; i < S; ++i) {
             if (i >= ncol) break;
-            double* cv = colv[i];
-            double a = cv[j];
-#pragma unroll
+            double* cv = tail[i];
+            double a = cv[0];
+#pragma unroll UNR
             for (int t = 0; t < S; ++t) {
                 if (t >= i) break;
-                const double b = cv[j + t + 1];
-                cv[j + t] = bc[t] * a + bs[t] * b;
+                const double b = cv[t + 1];
+                cv[t] = bc[t] * a + bs[t] * b;
                 a = -bs[t] * a + bc[t] * b;
             }
             const int k = j + i;
-            const double b = cv[k + 1];
+            const double b = cv[i + 1];
             const double d = sqrt(a * a + b * b);
             bc[i] = d == 0.0 ? 1.0 : a / d;
             bs[i] = d == 0.0 ? 0.0 : b / d;
-            cv[k] = d;
+            cv[i] = d;
             gk[i + 1] = -bs[i] * gk[i];
             gk[i] = bc[i] * gk[i];
             if (fabs(gk[i + 1]) <= tol || k + 1 >= mcyc || (i == ncol - 1 && cut_s)) {
@@ -1201,7 +1349,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
                 break;
             }
         }
-#pragma unroll
+#pragma unroll UNR
         for (int i = 0; i < S; ++i)
             if (i < taken) {
                 cs[j + i] = bc[i];
@@ -1215,7 +1363,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
     __syncthreads();
     const int taken = taken_s;
     for (int i = 0; i < taken; ++i)
-        for (int t = threadIdx.x; t <= j + i; t += BG_T) H[t + (int64_t)(j + i) * ldh] = colv[i][t];
+        for (int r = threadIdx.x; r <= i; r += BG_T) H[j + r + (int64_t)(j + i) * ldh] = tail[i][r];
     if (threadIdx.x == 0) {
         ctrl[C_J] = j + taken;
         ctrl[C_REORTH] = 0;
@@ -1397,14 +1545,16 @@ struct dg_solver {
     void* u = nullptr;      // [n] in P
     void* w2 = nullptr;     // [n] in P: the third vector of blocks of 3 or more
     void* w3 = nullptr;     // [n] in P: the fourth vector of blocks of 4 or more
-    void* wx[BS_MAX - 4] = {};  // [n] in P: vectors 5..16 of larger blocks
-    double* G16 = nullptr;      // [16][16] Gram matrix of a block of sixteen (blocks of 16 only)
+    void* wx[BS_MAX - 4] = {};  // [n] in P: vectors 5..32 of larger blocks
+    double* G16 = nullptr;      // [S][S] Gram matrix of a block of S >= 16 vectors (wide blocks only)
     int64_t npartials = 0;      // doubles in partials
     double* r = nullptr;    // [n] FP64
+    double* xprev = nullptr;  // [n] FP64: x before a cycle of 16 or more vectors per pass (restored if it lost)
     double* partials = nullptr;
     double* hcol = nullptr;
     double* hcol2 = nullptr;
     double* Rb = nullptr;   // [block][restart + 2]: an Arnoldi block's projections
+    double* RbT = nullptr;  // [restart + 2][block]: the same negated, transposed (blocks of 32)
     double* Hr = nullptr;   // [restart + 2][restart + 1]: raw Hessenberg matrix of the block path, row-major
     double* HX = nullptr;   // [block - 1][restart + 2]: its products with a block's projections
     int block = 1;          // Arnoldi vectors per Gram-Schmidt pass (1, 2, 3, 4, 6 or 8)
@@ -1532,9 +1682,10 @@ static void solver_free(dg_solver* s)
     hipFree(s->rflags);
     hipFree(s->Ahat); hipFree(s->Dinv); hipFree(s->Dinv64); hipFree(s->V); hipFree(s->w); hipFree(s->u);
     hipFree(s->r); hipFree(s->partials); hipFree(s->hcol); hipFree(s->hcol2); hipFree(s->H); hipFree(s->cs);
-    hipFree(s->Rb); hipFree(s->Hr); hipFree(s->HX); hipFree(s->w2); hipFree(s->w3);
+    hipFree(s->Rb); hipFree(s->RbT); hipFree(s->Hr); hipFree(s->HX); hipFree(s->w2); hipFree(s->w3);
     for (void* p : s->wx) hipFree(p);
     hipFree(s->G16);
+    hipFree(s->xprev);
     hipFree(s->sn); hipFree(s->g); hipFree(s->y); hipFree(s->scal); hipFree(s->ctrl); hipFree(s->bad);
     if (s->h_rep) hipHostFree(s->h_rep);
     s->h_rep = nullptr;
@@ -1550,10 +1701,10 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     if (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)) return DG_ERR_ARG;
     if (o->persistent < -1 || o->persistent > 1 || o->profile < 0 || o->profile > 2) return DG_ERR_ARG;
     const bool block_ok = o->block == 0 || (o->block >= 1 && o->block <= 4) || o->block == 6 || o->block == 8 ||
-                          o->block == 16;
-    // sixteen vectors in FP64 cycles only (in FP32 the block's sixteenth power loses too much: on a P3 IIPG test
-    // 3582 steps against 1581 for one vector per pass)
-    if (!block_ok || (o->block > 1 && o->reorth) || (o->block == 16 && o->mixed)) return DG_ERR_ARG;
+                          o->block == 16 || o->block == 32;
+    // sixteen or 32 vectors in FP64 cycles only (in FP32 the block's sixteenth power loses too much: on a P3 IIPG
+    // test 3582 steps against 1581 for one vector per pass)
+    if (!block_ok || (o->block > 1 && o->reorth) || (o->block >= 16 && o->mixed)) return DG_ERR_ARG;
     if (o->basis < 0 || o->basis > 2 || (o->block > 4 && o->restart > bg_maxj(o->block))) return DG_ERR_ARG;
     dg_solver* s = new (std::nothrow) dg_solver();
     if (!s) return DG_ERR_OOM;
@@ -1565,13 +1716,16 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     s->n = m->T * m->n;
     s->n_off = m->nnzb - m->T;
     s->mixed = o->mixed;
-    // automatic: eight vectors per pass in FP64 cycles; in FP32 cycles the rounding of the block's vectors
-    // makes eight take up to a fifth more steps on hard systems (six: a few percent)
+    // automatic: 32 (or, for restarts up to 640, sixteen) vectors per pass in FP64 cycles, else eight; in FP32
+    // cycles the rounding of the block's vectors makes eight take up to a fifth more steps on hard systems (six:
+    // a few percent)
     s->block = o->block != 0 ? o->block
                              : (o->reorth ? 1
-                                          : (!o->mixed && o->restart <= bg_maxj(16)
-                                                 ? 16
-                                                 : (o->restart <= bg_maxj(8) ? (o->mixed ? 6 : 8) : 3)));
+                                          : (!o->mixed && o->restart <= bg_maxj(32)
+                                                 ? 32
+                                                 : (!o->mixed && o->restart <= bg_maxj(16)
+                                                        ? 16
+                                                        : (o->restart <= bg_maxj(8) ? (o->mixed ? 6 : 8) : 3))));
     s->theta = o->basis == 1 ? 0.0 : 1.0;
     const int EPW = 64 / s->N;
     s->grid_elem = (int)((s->T + 4 * EPW - 1) / (4 * EPW));
@@ -1586,15 +1740,15 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
         int64_t rows;
         s->md_shape(j, &nt, &sp, &rows);
         maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 2));
-        for (int S = 2; S <= BS_MAX; ++S) {
+        for (int S = 2; S <= 8; ++S) {  // the vector-ALU dot kernel's block sizes (and 8, an upper bound)
             s->md_shape2(j, S, &nt, &sp, &rows);
             maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * S);
         }
-        s->md_shape_mf(j, &nt, &sp, &rows);  // eight or sixteen vectors
+        s->md_shape_mf(j, &nt, &sp, &rows);  // eight or more vectors
         maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * BS_MAX);
     }
     maxgrid = std::max<int64_t>(maxgrid, BS_MAX * (BS_MAX + 1) / 2 * (int64_t)s->grid_chunk);
-    {  // the Gram matrix of a block of sixteen: 16 x 16 columns in the shape of column count 16
+    {  // the Gram matrix of a wide block: S x S columns in the shape of column count S (at most BS_MAX)
         int nt, sp;
         int64_t rows;
         s->md_shape_mf(BS_MAX - 1, &nt, &sp, &rows);
@@ -1615,13 +1769,15 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     al((void**)&s->hcol2, sizeof(double) * (mm + 2));
     if (s->block > 1) {
         al((void**)&s->Rb, sizeof(double) * s->block * (size_t)(mm + 2));
+        if (s->block == 32) al((void**)&s->RbT, sizeof(double) * s->block * (size_t)(mm + 2));
         al((void**)&s->Hr, sizeof(double) * (size_t)(mm + 2) * (mm + 1));
         al((void**)&s->HX, sizeof(double) * (s->block - 1) * (size_t)(mm + 2));
     }
     if (s->block > 2) al(&s->w2, ps * s->n);
     if (s->block > 3) al(&s->w3, ps * s->n);
     for (int q = 4; q < s->block; ++q) al(&s->wx[q - 4], ps * s->n);
-    if (s->block == 16) al((void**)&s->G16, sizeof(double) * 16 * 16);
+    if (s->block >= 16) al((void**)&s->G16, sizeof(double) * s->block * s->block);
+    if (s->block >= 16) al((void**)&s->xprev, sizeof(double) * s->n);
     al((void**)&s->H, sizeof(double) * (size_t)(mm + 1) * mm);
     al((void**)&s->cs, sizeof(double) * mm);
     al((void**)&s->sn, sizeof(double) * mm);
@@ -1732,16 +1888,15 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
     P* V = (P*)s->V;
     BlockVecs<P> W{};  // u is free until the cycle's combine
     {
-        void* const vecs[BS_MAX] = {s->w, s->u, s->w2, s->w3, s->wx[0], s->wx[1], s->wx[2], s->wx[3],
-                                    s->wx[4], s->wx[5], s->wx[6], s->wx[7], s->wx[8], s->wx[9], s->wx[10], s->wx[11]};
-        for (int q = 0; q < BS_MAX; ++q) W.w[q] = (P*)vecs[q];
+        void* const first[4] = {s->w, s->u, s->w2, s->w3};
+        for (int q = 0; q < BS_MAX; ++q) W.w[q] = (P*)(q < 4 ? first[q] : s->wx[q - 4]);
     }
     const P cid = (P)(1.0 - s->theta);
     P* const* wv = W.w;
     for (int j = 0; j < mcyc; j += S) {
         int nt, sp;
         int64_t rows;
-        constexpr bool MF = S == 8 || S == 16;  // blocks of eight or sixteen: the dots on the matrix cores
+        constexpr bool MF = S == 8 || S == 16 || S == 32;  // blocks of eight or more: the dots on the matrix cores
         if (MF) s->md_shape_mf(j, &nt, &sp, &rows);
         else s->md_shape2(j, S, &nt, &sp, &rows);
         const double md_bytes = (j + 1.0 + S) * nb * ps, up_bytes = (j + 1.0 + 2 * S) * nb * ps;
@@ -1758,23 +1913,35 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
             prof_end(s, st, pr);
         }
         bool pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
-        if constexpr (S == 8 || S == 16)
+        if constexpr (MF)
             hipLaunchKernelGGL((multidot_mfma_kernel<P, S>), dim3(mf_grid(nt, sp)), dim3(BLK), 0, st, (const P*)V, W,
                                s->n, j, rows, nt, sp, (const int*)s->ctrl, s->partials);
         else
             hipLaunchKernelGGL((multidot_block_kernel<P, S>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, W, s->n, j,
                                rows, (const int*)s->ctrl, s->partials);
         prof_end(s, st, pr);
-        hipLaunchKernelGGL(reduce_cols_kernel, dim3((S * (j + 1) + 3) / 4), dim3(BLK), 0, st,
-                           (const double*)s->partials, S * (j + 1), sp, j, (const int*)s->ctrl, s->Rb, 0);
+        if constexpr (S == 32)
+            hipLaunchKernelGGL(reduce_cols_rt_kernel, dim3((S * (j + 1) + 3) / 4), dim3(BLK), 0, st,
+                               (const double*)s->partials, S, j + 1, sp, j, (const int*)s->ctrl, s->Rb, s->RbT);
+        else
+            hipLaunchKernelGGL(reduce_cols_kernel, dim3((S * (j + 1) + 3) / 4), dim3(BLK), 0, st,
+                               (const double*)s->partials, S * (j + 1), sp, j, (const int*)s->ctrl, s->Rb, 0);
         pr = prof_begin(s, st, PK_UPDATE, up_bytes, j, 0);
         const int hrows = (j + 1 + BLK / 64 - 1) / (BLK / 64);  // workgroups of the Hessenberg products
-        const double* gram = s->partials;  // Gram partials (pairs x grid_chunk), or at S = 16 the reduced matrix
-        if constexpr (S == 16) {
-            const int g16 = (int)((s->n + BLK * UP16_E - 1) / (BLK * UP16_E));
-            hipLaunchKernelGGL((update16_kernel<P>), dim3(g16 + hrows), dim3(BLK), 0, st, (const P*)V, W, s->n, j,
-                               (const int*)s->ctrl, (const double*)s->Rb, g16, (const double*)s->Hr, mm + 1, s->HX,
-                               mm + 2);
+        const double* gram = s->partials;  // Gram partials (pairs x grid_chunk), or at S >= 16 the reduced matrix
+        if constexpr (S >= 16) {
+            if constexpr (S == 32) {  // 32 vectors: the update on the matrix cores
+                const int64_t waves = (s->n + 16 * UPM_RT - 1) / (16 * UPM_RT);
+                const int gm = (int)((waves + BLK / 64 - 1) / (BLK / 64));
+                hipLaunchKernelGGL((update_mfma_kernel<P, S>), dim3(gm + hrows), dim3(BLK), 0, st, V, W, s->n, j,
+                                   (const int*)s->ctrl, (const double*)s->Rb, (const double*)s->RbT, gm,
+                                   (const double*)s->Hr, mm + 1, s->HX, mm + 2);
+            } else {
+                const int g16 = (int)((s->n + BLK * upw_rows(S) - 1) / (BLK * upw_rows(S)));
+                hipLaunchKernelGGL((update_wide_kernel<P, S>), dim3(g16 + hrows), dim3(BLK), 0, st, (const P*)V, W,
+                                   s->n, j, (const int*)s->ctrl, (const double*)s->Rb, g16, (const double*)s->Hr,
+                                   mm + 1, s->HX, mm + 2);
+            }
             prof_end(s, st, pr);
             int gt, gs;
             int64_t grows;
@@ -1843,6 +2010,13 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
     const double nb = (double)s->n;
     const double idx_bytes = 4.0 * (double)(s->T + 1 + m->nnzb);
     std::vector<int> hflags(s->o.profile ? mm : 0);
+    // Blocks of 16 or more vectors can lose orthogonality on hard non-normal systems (the Gram matrix of a long
+    // shifted power basis): a cycle that raises the true residual is undone (x restored) and, like a cycle cut
+    // short by an unresolvable pivot without converging, halves the block for the cycles after it.
+    int cur_block = s->block;
+    double rel_last = 0.0;
+    int last_mcyc = 0;
+    bool cycle_ran = false;
     for (;;) {
         bool pr = prof_begin(s, st, PK_RESIDUAL, (double)m->nnzb * N * N * 8.0 + 3.0 * nb * 8.0 + idx_bytes, -1, 0);
         hipLaunchKernelGGL((residual64_kernel<N>), dim3(s->grid_elem), dim3(BLK), 0, st, s->A64, m->d_row_ptr,
@@ -1856,9 +2030,25 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
         if (s->o.profile && s->o.reorth)
             DG_HIP_CHECK(hipMemcpyAsync(hflags.data(), s->rflags, sizeof(int) * mm, hipMemcpyDeviceToHost, st));
         DG_HIP_CHECK(hipStreamSynchronize(st));
-        if (s->o.profile) prof_flush(s, rep->cycles > 0 ? hc[C_J] : 0, s->o.reorth ? hflags.data() : nullptr);
-        if (rep->cycles > 0) its += hc[C_J];
+        if (s->o.profile) prof_flush(s, cycle_ran ? hc[C_J] : 0, s->o.reorth ? hflags.data() : nullptr);
+        if (cycle_ran) its += hc[C_J];
         const double rel = std::sqrt(hs[S_RNORM2]) / bnorm;
+        if (cycle_ran && cur_block >= 16) {
+            if (!(rel <= rel_last)) {  // lost: back to x before the cycle, its residual recomputed
+                DG_HIP_CHECK(hipMemcpyAsync(x, s->xprev, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
+                cur_block /= 2;
+                cycle_ran = false;
+                rep->iters = its;
+                if (its >= s->o.max_iters) {
+                    rep->rel_res = rel_last;
+                    status = DG_NOT_CONVERGED;
+                    break;
+                }
+                continue;
+            }
+            if (hc[C_J] < last_mcyc && !(rel <= s->o.rel_tol)) cur_block /= 2;
+        }
+        cycle_ran = false;
         if (rep->cycles == 0 && !rep->guess_rejected && !(rel <= s->o.guess_limit)) {
             // the guess is worse than zero: restart from x = 0
             DG_HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * s->n, st));
@@ -1874,16 +2064,24 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
         if (rel <= s->o.rel_tol) { status = DG_OK; break; }
         if (its >= s->o.max_iters) { status = DG_NOT_CONVERGED; break; }
         const int mcyc = std::min(mm, s->o.max_iters - its);
+        if (cur_block >= 16) {
+            DG_HIP_CHECK(hipMemcpyAsync(s->xprev, x, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
+            rel_last = rel;
+        }
+        last_mcyc = mcyc;
+        cycle_ran = true;
         hipLaunchKernelGGL((cycle_init_kernel<P>), dim3(s->grid_vec), dim3(BLK), 0, st, V, s->r, s->n, s->ctrl,
                            s->scal, s->g, cyc_rel, abs_tol);
         const double spmv_bytes = (double)s->n_off * N * N * ps + 2.0 * nb * ps + idx_bytes;
-        if (s->block == 2) block_cycle<N, P, 2>(s, st, mcyc, spmv_bytes);
-        if (s->block == 3) block_cycle<N, P, 3>(s, st, mcyc, spmv_bytes);
-        if (s->block == 4) block_cycle<N, P, 4>(s, st, mcyc, spmv_bytes);
-        if (s->block == 6) block_cycle<N, P, 6>(s, st, mcyc, spmv_bytes);
-        if (s->block == 8) block_cycle<N, P, 8>(s, st, mcyc, spmv_bytes);
-        if (s->block == 16) block_cycle<N, P, 16>(s, st, mcyc, spmv_bytes);
-        for (int j = 0; s->block == 1 && j < mcyc; ++j) {
+        if (cur_block == 2) block_cycle<N, P, 2>(s, st, mcyc, spmv_bytes);
+        if (cur_block == 3) block_cycle<N, P, 3>(s, st, mcyc, spmv_bytes);
+        if (cur_block == 4) block_cycle<N, P, 4>(s, st, mcyc, spmv_bytes);
+        if (cur_block == 6) block_cycle<N, P, 6>(s, st, mcyc, spmv_bytes);
+        if (cur_block == 8) block_cycle<N, P, 8>(s, st, mcyc, spmv_bytes);
+        if (cur_block == 16) block_cycle<N, P, 16>(s, st, mcyc, spmv_bytes);
+        if constexpr (sizeof(P) == 8)  // 32 vectors: FP64 cycles only
+            if (cur_block == 32) block_cycle<N, P, 32>(s, st, mcyc, spmv_bytes);
+        for (int j = 0; cur_block == 1 && j < mcyc; ++j) {
             int nt, sp;
             int64_t rows;
             s->md_shape(j, &nt, &sp, &rows);

@@ -447,22 +447,28 @@ def test_two_vector_blocks_match_one_vector_steps(api, case, mixed):
 
 @pytest.mark.parametrize("case", SOLVE_CASES, ids=[c.name for c in SOLVE_CASES])
 @pytest.mark.parametrize("mixed", [False, True])
-@pytest.mark.parametrize("block,basis", [(3, 1), (4, 1), (3, 2), (4, 2), (6, 2), (8, 2), (16, 2)])
+@pytest.mark.parametrize("block,basis", [(3, 1), (4, 1), (3, 2), (4, 2), (6, 2), (8, 2), (16, 2), (32, 2)])
 def test_wider_blocks_match_one_vector_steps(api, case, mixed, block, basis):
     """Blocks of S Arnoldi vectors per Gram-Schmidt pass, Cholesky QR of the
     S x S block, monomial (w, A w, A^2 w, ...) up to four vectors or shifted
-    by one (w, (A - I) w, (A - I)^2 w, ...) up to sixteen: the tolerance
+    by one (w, (A - I) w, (A - I)^2 w, ...) up to 32: the tolerance
     judged by the oracle is reached, and the step count stays close to
     one-vector steps (the Krylov spaces are the same; only rounding differs).
     In FP32 cycles eight vectors are allowed a quarter more steps: the rounding
     of the block's vectors shows on the hard P3 case (1925 against 1581).
-    Sixteen vectors (whose Gram matrix comes from a separate pass over the
-    updated vectors) are for FP64 cycles only and rejected with FP32 ones
-    (3582 against 1581 there)."""
+    Sixteen or 32 vectors (whose Gram matrix comes from a separate pass over
+    the updated vectors; 32 form their Hessenberg columns in two groups) are
+    for FP64 cycles only and rejected with FP32 ones (3582 against 1581 there
+    with sixteen).  A restart of 51 leaves a ragged last block.  With 32 the
+    first cycle on the smallest diffusion system (8 x 8 P1 SIPG) ends at an
+    unresolvable pivot and the cycles after it run with sixteen (72 against
+    56 steps), and on the hard P3 IIPG system a 32-vector cycle that raised
+    the residual is undone before sixteen take over (1747 against 1570): a
+    third more steps are allowed there."""
     mesh = api.Mesh.from_arrays(case.mesh, case.k)
-    if mixed and block == 16:  # sixteen vectors only in FP64 cycles
+    if mixed and block >= 16:  # sixteen or 32 vectors only in FP64 cycles
         with pytest.raises(api.DGError):
-            api.Solver(mesh, restart=51, mixed=True, inner_tol=1e-5, persistent=False, block=16, basis=basis)
+            api.Solver(mesh, restart=51, mixed=True, inner_tol=1e-5, persistent=False, block=block, basis=basis)
         return
     vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
     M, B = DC.oracle_system(case)
@@ -478,7 +484,12 @@ def test_wider_blocks_match_one_vector_steps(api, case, mixed, block, basis):
                                                                              rep.cycles, rel))
         assert rep.status == 0 and rel <= case.tol * 1.01
         its[b] = rep.iters
-    assert abs(its[block] - its[1]) <= max(8, (0.25 if mixed and block >= 8 else 0.15) * its[1])
+    rel_slack = 0.25 if mixed and block >= 8 else (0.3 if block == 32 else 0.15)
+    assert abs(its[block] - its[1]) <= max(8, rel_slack * its[1])
+    if case.name.startswith("c2like") and block >= 16:
+        # transport systems keep the one-vector step count with wide blocks: a wide block that lost (and fell
+        # back to narrower ones) would show here
+        assert abs(its[block] - its[1]) <= 2
 
 
 @pytest.mark.parametrize("restart", [2, 3, 7])
@@ -490,7 +501,7 @@ def test_two_vector_blocks_with_short_and_odd_restarts(api, restart):
     vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
     M, B = DC.oracle_system(case)
     res = {}
-    for block in (1, 2, 3, 4, 6, 8, 16):
+    for block in (1, 2, 3, 4, 6, 8, 16, 32):
         s = api.Solver(mesh, restart=restart, max_iters=200000, rel_tol=1e-9, persistent=False, block=block)
         s.setup(vals)
         x = torch.zeros_like(rhs)
@@ -499,7 +510,7 @@ def test_two_vector_blocks_with_short_and_odd_restarts(api, restart):
         _say("  restart %d block %d: %s" % (restart, block, res[block]))
         assert rep.status == 0 and res[block][2] <= 1e-9
     assert abs(res[2][1] - res[1][1]) <= max(8, 0.1 * res[1][1])
-    for block in (3, 4, 6, 8, 16):
+    for block in (3, 4, 6, 8, 16, 32):
         assert abs(res[block][1] - res[1][1]) <= max(8, 0.15 * res[1][1])
 
 
@@ -511,11 +522,14 @@ def test_two_vector_blocks_reject_reorth(api):
     with pytest.raises(api.DGError):
         api.Solver(mesh, restart=20, reorth=True, block=3)
     for kw in ({"block": 5}, {"block": 9}, {"block": 12}, {"block": 17}, {"basis": 3}, {"block": 8, "restart": 2049},
-               {"block": 16, "restart": 641}, {"block": 16, "reorth": True}):
+               {"block": 16, "restart": 641}, {"block": 16, "reorth": True}, {"block": 31}, {"block": 33},
+               {"block": 64}, {"block": 32, "restart": 609}, {"block": 32, "reorth": True},
+               {"block": 32, "mixed": True, "inner_tol": 1e-5}):
         with pytest.raises(api.DGError):
             api.Solver(mesh, **{"restart": 20, **kw})
     api.Solver(mesh, restart=2048, block=8)
     api.Solver(mesh, restart=640, block=16)
+    api.Solver(mesh, restart=608, block=32)
     for bad in (-1, 5):
         with pytest.raises(api.DGError):
             api.Solver(mesh, restart=20, block=bad)
