@@ -225,7 +225,9 @@ typedef struct {
     int32_t reorth;       /* 1: second classical Gram-Schmidt pass when the first loses > 1/sqrt(2) of the norm */
     int32_t profile;      /* 1: time the heavy kernels with HIP events on the solve stream (dg_solver_profile);
                              2: only the Gram-Schmidt dot kernel (two events per launch instead of ten per
-                             block, for timing the solve with its dominant kernel); DG_ERR_ARG above 2 */
+                             block, for timing the solve with its dominant kernel); 3: as 2, and on the block
+                             path each block's run of S SpMV launches under one pair of events (counted as S
+                             launches, the gaps between them included); DG_ERR_ARG above 3 */
     double guess_limit;   /* the initial guess is replaced by zero when ||F - A x0|| > guess_limit ||F||
                              or is not finite; <= 0 selects 1 + 1e-8 (no worse than the zero guess;
                              the margin absorbs the rounding of the two norms); +inf keeps any finite guess */

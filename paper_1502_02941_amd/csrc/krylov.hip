@@ -208,7 +208,13 @@ __global__ __launch_bounds__(BLK) void form_ahat_kernel(const double* __restrict
 // ---------------------------------------------------------------------------
 // Arnoldi kernels (precision P for vectors, FP64 for reductions)
 // ---------------------------------------------------------------------------
-// w = v + sum_L Ahat_KL v_L ; lane per (element, row i)
+// w = v + sum_L Ahat_KL v_L ; lane per (element, row i).  The grid is a
+// multiple of 8 workgroups and workgroup b takes element group
+// (b mod 8) (grid / 8) + b / 8: the hardware deals consecutive workgroups to
+// the eight XCDs in turn, so each XCD sweeps one contiguous eighth of the
+// elements and finds the neighbour blocks of v that the rows next to its own
+// fetched in its own L2 (element-ordered meshes keep neighbours close).
+inline int spmv_grid(int grid_elem) { return (grid_elem + 7) / 8 * 8; }
 template <int N, typename P>
 __global__ __launch_bounds__(BLK) void spmv_hat_kernel(const P* __restrict__ Ahat, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci, const P* __restrict__ Vbase,
@@ -220,7 +226,8 @@ __global__ __launch_bounds__(BLK) void spmv_hat_kernel(const P* __restrict__ Aha
     constexpr int EPW = 64 / N;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int e = lane / N, i = lane - e * N;
-    const int64_t el = ((int64_t)blockIdx.x * 4 + wave) * EPW + e;
+    const int64_t grp = (int64_t)(blockIdx.x & 7) * (gridDim.x / 8) + (blockIdx.x >> 3);
+    const int64_t el = (grp * 4 + wave) * EPW + e;
     if (e >= EPW || el >= T) return;
     const P* v = vin ? vin : Vbase + (int64_t)ctrl[C_J] * n;  // vin: the block's second product
     const int s0 = rp[el], s1 = rp[el + 1];
@@ -629,6 +636,9 @@ __global__ __launch_bounds__(BLK) void multidot_block_kernel(const P* __restrict
 // product (so that no step waits for the previous one) no faster.
 constexpr int MF_CT = 32, MF_CH = 32;  // basis columns per tile, rows per staged chunk
 constexpr int mf_target_blocks() { return 2048; }
+// basis columns per tile of the dot kernel for blocks of S vectors (the Gram pass of a block keeps MF_CT)
+constexpr int MF_CT_WIDE = 32;
+constexpr int mf_ct(int S) { return S > 16 ? MF_CT_WIDE : MF_CT; }
 inline int mf_grid(int ntile, int nsplit) { return (ntile * nsplit + 7) / 8 * 8; }
 template <typename P>
 struct MfStage {
@@ -660,14 +670,15 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
     if (logical >= total) return;
     const int tile = logical % ntile, split = logical / ntile;
     static_assert(S == 8 || S == 16 || S == 32, "eight, sixteen or 32 vectors");
-    constexpr int STR = MfStage<P>::STR, WPB = BLK / 64, NA = MF_CT / 16, NB = S > 16 ? S / 16 : 1;
+    constexpr int CT = GRAM ? MF_CT : mf_ct(S);  // columns of this tile
+    constexpr int STR = MfStage<P>::STR, WPB = BLK / 64, NA = CT / 16, NB = S > 16 ? S / 16 : 1;
     using Op = MfmaOp<double>;  // FP32 data too: the dots are summed in FP64, as by the vector-ALU kernel
     using VR = typename Op::V;
-    __shared__ __align__(16) P sv[WPB][MF_CT * STR];  // after the row loop: the waves' partial sums
+    __shared__ __align__(16) P sv[WPB][CT * STR];  // after the row loop: the waves' partial sums
     __shared__ P sw[WPB][S * STR];
-    static_assert(sizeof(sv) >= sizeof(double) * WPB * MF_CT * S, "room for the partial sums");
+    static_assert(sizeof(sv) >= sizeof(double) * WPB * CT * S, "room for the partial sums");
     const int ncols = GRAM ? S : j + 1;
-    const int c0 = tile * MF_CT;
+    const int c0 = tile * CT;
     const int64_t r0 = (int64_t)split * rows_per_split;
     const int64_t r1 = r0 + rows_per_split < n ? r0 + rows_per_split : n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -683,7 +694,7 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[h][b] = VR{0, 0, 0, 0};
     constexpr int LPC = MF_CH / 64 > 0 ? 1 : 64 / MF_CH;  // chunks of 32 rows: a lane loads two columns' rows
-    P x[MF_CT / LPC], y[S / LPC];
+    P x[CT / LPC], y[S / LPC];
     // a chunk's rows into registers (the next chunk's loads are in flight during this chunk's products):
     // lane l loads row l % MF_CH of columns (l / MF_CH) + LPC c
     const int lr = lane % MF_CH, lc = lane / MF_CH;
@@ -691,7 +702,7 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
         const int64_t r = cb + lr;
         const bool in = r < r1;
 #pragma unroll
-        for (int c = 0; c < MF_CT / LPC; ++c) {  // columns past j read column j and are discarded
+        for (int c = 0; c < CT / LPC; ++c) {  // columns past j read column j and are discarded
             const int cc = c0 + LPC * c + lc;
             if constexpr (GRAM) {  // columns 2 c and 2 c + 1 are vectors of the block (none past S)
                 static_assert(!GRAM || LPC == 2, "two columns per lane");
@@ -714,7 +725,7 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
     if (cb < r1) load(cb);
     for (; cb < r1; cb += (int64_t)WPB * MF_CH) {
 #pragma unroll
-        for (int c = 0; c < MF_CT / LPC; ++c) mv[(LPC * c + lc) * STR + lr] = x[c];
+        for (int c = 0; c < CT / LPC; ++c) mv[(LPC * c + lc) * STR + lr] = x[c];
 #pragma unroll
         for (int v = 0; v < S / LPC; ++v) mw[(LPC * v + lc) * STR + lr] = y[v];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -739,7 +750,7 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
     }
     // lane (i, q) holds the dots of column 16 h + row(q, v) with vector 16 nb + i (i < S)
     __syncthreads();
-    double(*red)[MF_CT * S] = reinterpret_cast<double(*)[MF_CT * S]>(&sv[0][0]);
+    double(*red)[CT * S] = reinterpret_cast<double(*)[CT * S]>(&sv[0][0]);
     if (i < S) {
 #pragma unroll
         for (int h = 0; h < NA; ++h)
@@ -750,7 +761,7 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
                     red[wave][(16 * h + Op::row(q, v)) * S + 16 * nb + i] = (double)acc[h][nb][v];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < MF_CT * S; t += BLK) {
+    for (int t = threadIdx.x; t < CT * S; t += BLK) {
         const int c = t / S, v = t - c * S;
         double sum = 0.0;
 #pragma unroll
@@ -1053,6 +1064,9 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
 // lies in the span to working accuracy); (C^{-1}) goes to scal for the
 // normalisation.
 constexpr int BG_T = 1024;
+// threads of the block Givens kernel for blocks of S vectors: 32 take 512 (the Hessenberg products of a row then
+// have 256 registers per lane instead of 128)
+constexpr int bg_threads(int S) { return S > 16 ? 512 : BG_T; }
 // Rotations 0..count-1 (cs, sn) applied to columns 0..ncol-1 of colv, lane i
 // of the first wave taking column i; each column is a chain of dependent
 // steps, so the LDS loads of eight steps are issued together.
@@ -1070,7 +1084,7 @@ __device__ void bg_rotate_cols(double (*colv)[LD], int ncol, int count, const do
     for (int i0 = 0; i0 < count; i0 += GV_CHUNK) {
         const int cnt = count - i0 < GV_CHUNK ? count - i0 : GV_CHUNK;
         __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += BG_T) {
+        for (int t = threadIdx.x; t < cnt; t += (int)blockDim.x) {
             sc[t] = cs[i0 + t];
             ss[t] = sn[i0 + t];
         }
@@ -1106,7 +1120,7 @@ __device__ void bg_rotate_cols(double (*colv)[LD], int ncol, int count, const do
 }
 
 template <int S>
-__global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const double* __restrict__ gp, int nparts,
+__global__ __launch_bounds__(bg_threads(S)) void block_givens_kernel(int* ctrl, const double* __restrict__ gp, int nparts,
                                                             const double* __restrict__ R, double* __restrict__ Hr,
                                                             int ldr, const double* __restrict__ HX, int ldx,
                                                             double* __restrict__ H, int ldh,
@@ -1115,11 +1129,12 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
                                                             double theta)
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
+    constexpr int NT = bg_threads(S);
     constexpr int NG = S * (S + 1) / 2;
     // Hessenberg columns held in LDS at a time: a block of 32 forms and rotates its columns in two groups of 16
     // (32 columns of a 576-step cycle would not fit), keeping only their rows j.. for this block's rotations
     constexpr int GC = S < 16 ? S : 16, NGRP = S / GC, GS = S <= 8 ? S : 1;
-    __shared__ double red[S <= 8 ? NG : 1][BG_T / 64];  // S >= 16: gp holds the reduced Gram matrix
+    __shared__ double red[S <= 8 ? NG : 1][NT / 64];  // S >= 16: gp holds the reduced Gram matrix
     __shared__ double colv[GC][bg_maxj(S) + 4];
     __shared__ double h0s[NGRP > 1 ? bg_maxj(S) + 4 : 1];  // raw column j, when colv[0] is reused by a group
     __shared__ double sc[GV_CHUNK], ss[GV_CHUNK];
@@ -1132,7 +1147,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
         double acc[NG];
 #pragma unroll
         for (int k = 0; k < NG; ++k) acc[k] = 0.0;
-        for (int t = threadIdx.x; t < nparts; t += BG_T)
+        for (int t = threadIdx.x; t < nparts; t += NT)
 #pragma unroll
             for (int k = 0; k < NG; ++k) acc[k] += gp[k * nparts + t];
 #pragma unroll
@@ -1141,13 +1156,13 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
             if (lane == 0) red[k][wave] = v;
         }
     }
-    for (int i = threadIdx.x; i <= j; i += BG_T) h0[i] = R[i];
+    for (int i = threadIdx.x; i <= j; i += NT) h0[i] = R[i];
     if constexpr (S > 8) {
         // sixteen or more vectors: the Cholesky factor and its inverse on the lanes of wave 0 (thread 0 alone
         // spent most of this kernel's time on them): lane q holds column q of the Gram matrix, the pivots and the
         // rows of the factor are shared by shuffles, and lane q then solves C x = e_q for column q of C^{-1}
         __shared__ int pok_s;
-        for (int k = threadIdx.x; k < S * S; k += BG_T) Cf[k / S][k % S] = Ci[k / S][k % S] = 0.0;
+        for (int k = threadIdx.x; k < S * S; k += NT) Cf[k / S][k % S] = Ci[k / S][k % S] = 0.0;
         __syncthreads();
         if (threadIdx.x < 64) {
             const int q = threadIdx.x;
@@ -1184,24 +1199,33 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
         __syncthreads();
         if (threadIdx.x < pok_s) {  // C x = e_q on the resolvable leading triangle
             const int q = threadIdx.x;
-            double x[S];
+            if constexpr (S <= 16) {
+                double x[S];
 #pragma unroll
-            for (int i = S - 1; i >= 0; --i) {
-                if (i > q) {
-                    x[i] = 0.0;
-                } else if (i == q) {
-                    x[i] = 1.0 / Cf[i][i];
-                } else {
+                for (int i = S - 1; i >= 0; --i) {
+                    if (i > q) {
+                        x[i] = 0.0;
+                    } else if (i == q) {
+                        x[i] = 1.0 / Cf[i][i];
+                    } else {
+                        double v = 0.0;
+#pragma unroll
+                        for (int m = i + 1; m < S; ++m)
+                            if (m <= q) v += Cf[i][m] * x[m];
+                        x[i] = -v / Cf[i][i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < S; ++i)
+                    if (i <= q) Ci[i][q] = x[i];
+            } else {  // 32: the column built in place in LDS (32 values per lane would spill)
+                Ci[q][q] = 1.0 / Cf[q][q];
+                for (int i = q - 1; i >= 0; --i) {
                     double v = 0.0;
-#pragma unroll
-                    for (int m = i + 1; m < S; ++m)
-                        if (m <= q) v += Cf[i][m] * x[m];
-                    x[i] = -v / Cf[i][i];
+                    for (int m = i + 1; m <= q; ++m) v += Cf[i][m] * Ci[m][q];
+                    Ci[i][q] = -v / Cf[i][i];
                 }
             }
-#pragma unroll
-            for (int i = 0; i < S; ++i)
-                if (i <= q) Ci[i][q] = x[i];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1213,7 +1237,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
             cut_s = pok < S ? 1 : 0;
             h0[j + 1] = Cf[0][0];
         }
-        for (int k = threadIdx.x; k < S * S; k += BG_T) scal[S_QB + k] = Ci[k / S][k % S];
+        for (int k = threadIdx.x; k < S * S; k += NT) scal[S_QB + k] = Ci[k / S][k % S];
     } else {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1222,7 +1246,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
             for (int q = 0; q < S; ++q)
                 for (int p = 0; p <= q; ++p) {
                     double v = 0.0;
-                    for (int w = 0; w < BG_T / 64; ++w) v += red[k][w];
+                    for (int w = 0; w < NT / 64; ++w) v += red[k][w];
                     G[p][q] = G[q][p] = v;
                     ++k;
                 }
@@ -1264,7 +1288,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
     }
     __syncthreads();
     const int ncol = ncol_s;
-    for (int i = threadIdx.x; i <= j + 1; i += BG_T) Hr[(int64_t)i * ldr + j] = h0[i];
+    for (int i = threadIdx.x; i <= j + 1; i += NT) Hr[(int64_t)i * ldr + j] = h0[i];
     // columns j .. j + ncol - 1 in groups of GC: column j is h0; columns j+1 .. from it and the earlier raw
     // columns; then the earlier blocks' rotations on all the group's columns at once; rows below j are final
     for (int g0 = 0; g0 < ncol; g0 += GC) {
@@ -1272,11 +1296,11 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
         __syncthreads();
         if constexpr (NGRP > 1) {
             if (g0 == 0)
-                for (int t = threadIdx.x; t <= j + 1; t += BG_T) colv[0][t] = h0[t];
+                for (int t = threadIdx.x; t <= j + 1; t += NT) colv[0][t] = h0[t];
         }
         const int i1 = g0 > 0 ? g0 : 1;  // first column of the group formed here
         if (i1 < g0 + gn) {
-            for (int t = threadIdx.x; t <= j + g0 + gn; t += BG_T) {
+            for (int t = threadIdx.x; t <= j + g0 + gn; t += NT) {
                 // row t of [R; C] (the block's coefficients on V below row j + 1, the Cholesky factor above)
                 auto rc = [&](int m) -> double {
                     return m >= ncol ? 0.0
@@ -1304,12 +1328,12 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
             }
             __syncthreads();
             for (int i = i1; i < g0 + gn; ++i)
-                for (int t = threadIdx.x; t <= j + i + 1; t += BG_T) Hr[(int64_t)t * ldr + j + i] = colv[i - g0][t];
+                for (int t = threadIdx.x; t <= j + i + 1; t += NT) Hr[(int64_t)t * ldr + j + i] = colv[i - g0][t];
         }
         bg_rotate_cols(colv, gn, j, cs, sn, sc, ss);
         for (int i = 0; i < gn; ++i) {
-            for (int t = threadIdx.x; t < j; t += BG_T) H[t + (int64_t)(j + g0 + i) * ldh] = colv[i][t];
-            for (int r = threadIdx.x; r <= g0 + i + 1; r += BG_T) tail[g0 + i][r] = colv[i][j + r];
+            for (int t = threadIdx.x; t < j; t += NT) H[t + (int64_t)(j + g0 + i) * ldh] = colv[i][t];
+            for (int r = threadIdx.x; r <= g0 + i + 1; r += NT) tail[g0 + i][r] = colv[i][j + r];
         }
     }
     // this block's rotations on the columns in turn (thread 0, the rotations and residual estimates held in
@@ -1363,7 +1387,7 @@ __global__ __launch_bounds__(BG_T) void block_givens_kernel(int* ctrl, const dou
     __syncthreads();
     const int taken = taken_s;
     for (int i = 0; i < taken; ++i)
-        for (int r = threadIdx.x; r <= i; r += BG_T) H[j + r + (int64_t)(j + i) * ldh] = tail[i][r];
+        for (int r = threadIdx.x; r <= i; r += NT) H[j + r + (int64_t)(j + i) * ldh] = tail[i][r];
     if (threadIdx.x == 0) {
         ctrl[C_J] = j + taken;
         ctrl[C_REORTH] = 0;
@@ -1573,7 +1597,7 @@ struct dg_solver {
     dg_solve_report* h_rep = nullptr;  // pinned host report written by that kernel
     int ready = 0;
     // built-in profiler (opts.profile): HIP events around the heavy kernels
-    struct Rec { int cls; double bytes; int j; int pass; hipEvent_t e0, e1; };
+    struct Rec { int cls; double bytes; int j; int pass; hipEvent_t e0, e1; int nl; };  // nl: launches timed
     std::vector<hipEvent_t> evpool;
     size_t evused = 0;
     std::vector<Rec> pending;
@@ -1583,7 +1607,7 @@ struct dg_solver {
     void md_shape(int j, int* tiles, int* splits, int64_t* rows) const;
     // the same for the Arnoldi block of S vectors starting at column j
     void md_shape2(int j, int S, int* tiles, int* splits, int64_t* rows) const;
-    void md_shape_mf(int j, int* tiles, int* splits, int64_t* rows) const;
+    void md_shape_mf(int j, int* tiles, int* splits, int64_t* rows, int ct = dg::MF_CT) const;
 };
 
 void dg_solver::md_shape(int j, int* tiles, int* splits, int64_t* rows) const
@@ -1614,9 +1638,9 @@ void dg_solver::md_shape2(int j, int S, int* tiles, int* splits, int64_t* rows) 
     *rows = r;
 }
 
-void dg_solver::md_shape_mf(int j, int* tiles, int* splits, int64_t* rows) const
+void dg_solver::md_shape_mf(int j, int* tiles, int* splits, int64_t* rows, int ct) const
 {
-    const int nt = (j + 1 + dg::MF_CT - 1) / dg::MF_CT;
+    const int nt = (j + 1 + ct - 1) / ct;
     const int64_t max_splits = std::max<int64_t>(1, n / dg::MD_MIN_ROWS);
     int64_t sp = (dg::mf_target_blocks() + nt - 1) / nt;
     sp = std::max<int64_t>(1, std::min<int64_t>(sp, max_splits));
@@ -1641,10 +1665,11 @@ static hipEvent_t prof_event(dg_solver* s)
 }
 
 // brackets one launch: returns true if recording (call prof_end after the launch)
-static bool prof_begin(dg_solver* s, hipStream_t st, int cls, double bytes, int j, int pass)
+static bool prof_begin(dg_solver* s, hipStream_t st, int cls, double bytes, int j, int pass, int nl = 1)
 {
-    if (!s->o.profile || (s->o.profile == 2 && cls != PK_MULTIDOT)) return false;
-    dg_solver::Rec r{cls, bytes, j, pass, prof_event(s), prof_event(s)};
+    if (!s->o.profile || (s->o.profile >= 2 && cls != PK_MULTIDOT && !(s->o.profile == 3 && cls == PK_SPMV)))
+        return false;
+    dg_solver::Rec r{cls, bytes, j, pass, prof_event(s), prof_event(s), nl};
     if (!r.e0 || !r.e1) return false;
     hipEventRecord(r.e0, st);
     s->pending.push_back(r);
@@ -1667,7 +1692,7 @@ static void prof_flush(dg_solver* s, int J, const int* rflags)
         if (r.j == -2) bytes = ((double)J + 1.0) * (double)s->n * (s->mixed ? 4.0 : 8.0);  // combine: J columns + u
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) continue;
-        s->pl[r.cls]++;
+        s->pl[r.cls] += r.nl;
         s->pms[r.cls] += ms;
         s->pbytes[r.cls] += bytes;
     }
@@ -1699,7 +1724,7 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
     if (o->restart < 1 || o->restart > 4096 || o->max_iters < 0 || !(o->rel_tol > 0) || (o->mixed != 0 && o->mixed != 1))
         return DG_ERR_ARG;
     if (o->mixed && !(o->inner_tol > 0 && o->inner_tol < 1)) return DG_ERR_ARG;
-    if (o->persistent < -1 || o->persistent > 1 || o->profile < 0 || o->profile > 2) return DG_ERR_ARG;
+    if (o->persistent < -1 || o->persistent > 1 || o->profile < 0 || o->profile > 3) return DG_ERR_ARG;
     const bool block_ok = o->block == 0 || (o->block >= 1 && o->block <= 4) || o->block == 6 || o->block == 8 ||
                           o->block == 16 || o->block == 32;
     // sixteen or 32 vectors in FP64 cycles only (in FP32 the block's sixteenth power loses too much: on a P3 IIPG
@@ -1744,8 +1769,10 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
             s->md_shape2(j, S, &nt, &sp, &rows);
             maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * S);
         }
-        s->md_shape_mf(j, &nt, &sp, &rows);  // eight or more vectors
-        maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * BS_MAX);
+        for (const int ct : {dg::MF_CT, dg::MF_CT_WIDE}) {  // eight or more vectors
+            s->md_shape_mf(j, &nt, &sp, &rows, ct);
+            maxgrid = std::max<int64_t>(maxgrid, (int64_t)sp * (j + 1) * BS_MAX);
+        }
     }
     maxgrid = std::max<int64_t>(maxgrid, BS_MAX * (BS_MAX + 1) / 2 * (int64_t)s->grid_chunk);
     {  // the Gram matrix of a wide block: S x S columns in the shape of column count S (at most BS_MAX)
@@ -1897,7 +1924,7 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
         int nt, sp;
         int64_t rows;
         constexpr bool MF = S == 8 || S == 16 || S == 32;  // blocks of eight or more: the dots on the matrix cores
-        if (MF) s->md_shape_mf(j, &nt, &sp, &rows);
+        if (MF) s->md_shape_mf(j, &nt, &sp, &rows, mf_ct(S));
         else s->md_shape2(j, S, &nt, &sp, &rows);
         const double md_bytes = (j + 1.0 + S) * nb * ps, up_bytes = (j + 1.0 + 2 * S) * nb * ps;
         if ((int64_t)S * (j + 1) * sp > s->npartials) {  // the partials of this shape do not fit (a sizing bug)
@@ -1905,13 +1932,17 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
                     (long long)s->npartials);
             abort();
         }
+        // profile 3: one event pair around the block's S SpMV launches (S launches, gaps included)
+        const bool spmv_group = s->o.profile == 3;
+        const bool prg = spmv_group && prof_begin(s, st, PK_SPMV, spmv_bytes * S, j, 0, S);
         for (int q = 0; q < S; ++q) {
-            const bool pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
-            hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
-                               m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, wv[q], s->T, s->ctrl,
-                               (const P*)(q ? wv[q - 1] : nullptr), cid);
+            const bool pr = !spmv_group && prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
+            hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(spmv_grid(s->grid_elem)), dim3(BLK), 0, st,
+                               (const P*)s->Ahat, m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, wv[q], s->T,
+                               s->ctrl, (const P*)(q ? wv[q - 1] : nullptr), cid);
             prof_end(s, st, pr);
         }
+        prof_end(s, st, prg);
         bool pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
         if constexpr (MF)
             hipLaunchKernelGGL((multidot_mfma_kernel<P, S>), dim3(mf_grid(nt, sp)), dim3(BLK), 0, st, (const P*)V, W,
@@ -1961,9 +1992,9 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
                                (const double*)s->Hr, mm + 1, s->HX, mm + 2);
             prof_end(s, st, pr);
         }
-        hipLaunchKernelGGL((block_givens_kernel<S>), dim3(1), dim3(BG_T), 0, st, s->ctrl, gram, s->grid_chunk,
-                           (const double*)s->Rb, s->Hr, mm + 1, (const double*)s->HX, mm + 2, s->H, mm + 1, s->cs,
-                           s->sn, s->g, s->scal, j, mcyc, s->theta);
+        hipLaunchKernelGGL((block_givens_kernel<S>), dim3(1), dim3(bg_threads(S)), 0, st, s->ctrl, gram,
+                           s->grid_chunk, (const double*)s->Rb, s->Hr, mm + 1, (const double*)s->HX, mm + 2, s->H,
+                           mm + 1, s->cs, s->sn, s->g, s->scal, j, mcyc, s->theta);
         hipLaunchKernelGGL((normalize_block_kernel<P, S>), dim3(s->grid_vec), dim3(BLK), 0, st, V, W, s->n, j,
                            (const int*)s->ctrl, (const double*)s->scal);
     }
@@ -2087,9 +2118,9 @@ static int solve_np(dg_solver* s, const double* b, double* x, dg_solve_report* r
             s->md_shape(j, &nt, &sp, &rows);
             const double md_bytes = (j + 2.0) * nb * ps, up_bytes = (j + 3.0) * nb * ps;
             pr = prof_begin(s, st, PK_SPMV, spmv_bytes, j, 0);
-            hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(s->grid_elem), dim3(BLK), 0, st, (const P*)s->Ahat,
-                               m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, w, s->T, s->ctrl, (const P*)nullptr,
-                               (P)1);
+            hipLaunchKernelGGL((spmv_hat_kernel<N, P>), dim3(spmv_grid(s->grid_elem)), dim3(BLK), 0, st,
+                               (const P*)s->Ahat, m->d_row_ptr, m->d_col_idx, (const P*)V, s->n, w, s->T, s->ctrl,
+                               (const P*)nullptr, (P)1);
             prof_end(s, st, pr);
             pr = prof_begin(s, st, PK_MULTIDOT, md_bytes, j, 0);
             hipLaunchKernelGGL((multidot_kernel<P>), dim3(nt, sp), dim3(BLK), 0, st, (const P*)V, (const P*)w, s->n, j,

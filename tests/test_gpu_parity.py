@@ -538,13 +538,14 @@ def test_two_vector_blocks_reject_reorth(api):
 
 def test_profile_levels(api):
     """opts.profile: 1 times every heavy kernel class, 2 the Gram-Schmidt dot
-    kernel alone (the solve is the same: equal iterations and residual);
-    other values are rejected."""
+    kernel alone, 3 that kernel and each block's run of SpMV launches under one
+    pair of events (the solve is the same: equal iterations and residual, and
+    equal launch counts); other values are rejected."""
     case = SOLVE_CASES[0]
     mesh = api.Mesh.from_arrays(case.mesh, case.k)
     vals, rhs = api.assemble(mesh, DC.gpu_problem(case, mesh, api))
     out = {}
-    for level in (1, 2):
+    for level in (1, 2, 3):
         s = api.Solver(mesh, restart=40, rel_tol=1e-10, persistent=False, profile=level)
         s.setup(vals)
         x = torch.zeros_like(rhs)
@@ -552,10 +553,13 @@ def test_profile_levels(api):
         kern = {k: v for k, v in s.profile(reset=True).items() if v[0] > 0}
         out[level] = (rep.iters, rep.rel_res, kern)
         _say("  profile %d: %d its, classes %s" % (level, rep.iters, sorted(kern)))
-    assert out[1][0] == out[2][0] and out[1][1] == out[2][1]
+    assert out[1][0] == out[2][0] == out[3][0] and out[1][1] == out[2][1] == out[3][1]
     assert {"spmv_hat", "multidot", "update"} <= set(out[1][2])
     assert set(out[2][2]) == {"multidot"}
-    assert out[2][2]["multidot"][0] == out[1][2]["multidot"][0]
-    for bad in (-1, 3):
+    assert set(out[3][2]) == {"multidot", "spmv_hat"}
+    assert out[2][2]["multidot"][0] == out[1][2]["multidot"][0] == out[3][2]["multidot"][0]
+    assert out[3][2]["spmv_hat"][0] == out[1][2]["spmv_hat"][0]
+    assert abs(out[3][2]["spmv_hat"][2] - out[1][2]["spmv_hat"][2]) <= 1e-9 * out[1][2]["spmv_hat"][2]
+    for bad in (-1, 4):
         with pytest.raises(api.DGError):
             api.Solver(mesh, restart=40, profile=bad)
