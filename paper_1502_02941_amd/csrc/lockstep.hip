@@ -399,6 +399,9 @@ __device__ __forceinline__ P* ls_block_vec(const LsArgs& A, int r)
 }
 
 template <typename P>
+// Workgroups stay in the hardware's round-robin order over the XCDs: dealing each XCD a contiguous eighth of the
+// batch's element blocks (as the single-system SpMV does) was slower here (256-instance sample: 37.2 -> 47.5 us
+// per FP64 launch), the instances that had finished their cycle leaving whole XCDs idle.
 __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src, double cid)
 {
     if (ls_all_ended(A)) return;
