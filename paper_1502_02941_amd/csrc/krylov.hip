@@ -1064,9 +1064,9 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
 // lies in the span to working accuracy); (C^{-1}) goes to scal for the
 // normalisation.
 constexpr int BG_T = 1024;
-// threads of the block Givens kernel for blocks of S vectors: 32 take 512 (the Hessenberg products of a row then
+// threads of the block Givens kernel for blocks of S vectors: 16 and 32 take 512 (the Hessenberg products then
 // have 256 registers per lane instead of 128)
-constexpr int bg_threads(int S) { return S > 16 ? 512 : BG_T; }
+constexpr int bg_threads(int S) { return S >= 16 ? 512 : BG_T; }
 // Rotations 0..count-1 (cs, sn) applied to columns 0..ncol-1 of colv, lane i
 // of the first wave taking column i; each column is a chain of dependent
 // steps, so the LDS loads of eight steps are issued together.
@@ -1199,33 +1199,24 @@ __global__ __launch_bounds__(bg_threads(S)) void block_givens_kernel(int* ctrl, 
         __syncthreads();
         if (threadIdx.x < pok_s) {  // C x = e_q on the resolvable leading triangle
             const int q = threadIdx.x;
-            if constexpr (S <= 16) {
-                double x[S];
+            double x[S];  // in registers (the S = 32 kernel has 256 per lane)
 #pragma unroll
-                for (int i = S - 1; i >= 0; --i) {
-                    if (i > q) {
-                        x[i] = 0.0;
-                    } else if (i == q) {
-                        x[i] = 1.0 / Cf[i][i];
-                    } else {
-                        double v = 0.0;
-#pragma unroll
-                        for (int m = i + 1; m < S; ++m)
-                            if (m <= q) v += Cf[i][m] * x[m];
-                        x[i] = -v / Cf[i][i];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < S; ++i)
-                    if (i <= q) Ci[i][q] = x[i];
-            } else {  // 32: the column built in place in LDS (32 values per lane would spill)
-                Ci[q][q] = 1.0 / Cf[q][q];
-                for (int i = q - 1; i >= 0; --i) {
+            for (int i = S - 1; i >= 0; --i) {
+                if (i > q) {
+                    x[i] = 0.0;
+                } else if (i == q) {
+                    x[i] = 1.0 / Cf[i][i];
+                } else {
                     double v = 0.0;
-                    for (int m = i + 1; m <= q; ++m) v += Cf[i][m] * Ci[m][q];
-                    Ci[i][q] = -v / Cf[i][i];
+#pragma unroll
+                    for (int m = i + 1; m < S; ++m)
+                        if (m <= q) v += Cf[i][m] * x[m];
+                    x[i] = -v / Cf[i][i];
                 }
             }
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+                if (i <= q) Ci[i][q] = x[i];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1300,30 +1291,54 @@ __global__ __launch_bounds__(bg_threads(S)) void block_givens_kernel(int* ctrl, 
         }
         const int i1 = g0 > 0 ? g0 : 1;  // first column of the group formed here
         if (i1 < g0 + gn) {
-            for (int t = threadIdx.x; t <= j + g0 + gn; t += NT) {
+            // column i at row t is sum_{l<i} e_t[l] (C^{-1})_{l,i-1}, e_t[l] = (A u_l)[t] = w_{l+1} + theta w_l -
+            // A V R_l in the basis [V, Q]: the rows times the upper triangle of C^{-1} as FP64 16 x 16 x 4
+            // matrix-core products, a wave taking 16 rows at a time; lane (c, k) forms e of row c of the tile for
+            // l = k (mod 4) only, and holds C^{-1}[4 s + k][16 ct + c] as its B operands throughout
+            using Op = MfmaOp<double>;
+            constexpr int NS = (S - 1 + 3) / 4, NCT = (S - 1 + 15) / 16;
+            const int lane = threadIdx.x & 63, c = lane & 15, k = lane >> 4;
+            double bop[NCT][NS];
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const int l = 4 * q + k, col = 16 * ct + c;
+                    bop[ct][q] = l < S - 1 && col < S - 1 ? Ci[l][col] : 0.0;
+                }
+            const int nrows = j + g0 + gn + 1;  // rows 0 .. j + g0 + gn
+            for (int tile = threadIdx.x >> 6; tile * 16 < nrows; tile += NT / 64) {
+                const int t = tile * 16 + c;  // row c of the tile (A operand)
                 // row t of [R; C] (the block's coefficients on V below row j + 1, the Cholesky factor above)
                 auto rc = [&](int m) -> double {
                     return m >= ncol ? 0.0
                                      : (t <= j ? R[m * (j + 1) + t] : (t - j - 1 <= m ? Cf[t - j - 1][m] : 0.0));
                 };
-                double e[S - 1];  // (A u_l)[t] = w_{l+1} + theta w_l - A V R_l in the basis [V, Q]
                 const double h = t <= j + 1 ? h0[t] : 0.0;  // (Hr R_l)[t]: columns below j from HX, column j here
-                double rl = rc(0);
+                double aop[NS];
 #pragma unroll
-                for (int l = 0; l < S - 1; ++l) {
-                    const double hx = t <= j + 1 ? (t <= j ? HX[l * ldx + t] : 0.0) + h * R[l * (j + 1) + j] : 0.0;
-                    const double rm = rc(l + 1);
-                    e[l] = rm + theta * rl - hx;
-                    rl = rm;
+                for (int q = 0; q < NS; ++q) {
+                    const int l = 4 * q + k;
+                    if (l < S - 1) {
+                        const double hx =
+                            t <= j + 1 ? (t <= j ? HX[l * ldx + t] : 0.0) + h * R[l * (j + 1) + j] : 0.0;
+                        aop[q] = rc(l + 1) + theta * rc(l) - hx;
+                    } else {
+                        aop[q] = 0.0;
+                    }
                 }
-#pragma unroll 1
-                for (int i = i1; i < g0 + gn; ++i) {
-                    if (t > j + i + 1) continue;
-                    double v = 0.0;
 #pragma unroll
-                    for (int l = 0; l < S - 1; ++l)
-                        if (l < i) v += e[l] * Ci[l][i - 1];
-                    colv[i - g0][t] = v;
+                for (int ct = 0; ct < NCT; ++ct) {
+                    typename Op::V acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) acc = Op::mac(aop[q], bop[ct][q], acc);
+                    // D[r][c] in lane c + 16 g, register v, r = Op::row(g, v): column i = 16 ct + c + 1
+                    const int i = 16 * ct + c + 1;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = tile * 16 + Op::row(k, v);
+                        if (i >= i1 && i < g0 + gn && row <= j + i + 1) colv[i - g0][row] = acc[v];
+                    }
                 }
             }
             __syncthreads();
@@ -1336,62 +1351,54 @@ __global__ __launch_bounds__(bg_threads(S)) void block_givens_kernel(int* ctrl, 
             for (int r = threadIdx.x; r <= g0 + i + 1; r += NT) tail[g0 + i][r] = colv[i][j + r];
         }
     }
-    // this block's rotations on the columns in turn (thread 0, the rotations and residual estimates held in
-    // LDS): its earlier rotations, the new rotation, the estimate and the stop test; then the columns taken
-    // written out (no global round trip between the columns)
+    // this block's own rotations, pipelined over the lanes of wave 0: lane i holds rows j .. j + i + 1 of column
+    // j + i; at step t lane t's column has had rotations 0 .. t - 1 applied, so its rows t and t + 1 give
+    // rotation t, which every later column then takes at once (a column of thread-0 loops through LDS was the
+    // slowest part of this kernel); the estimate and the stop test follow each rotation, then the columns
+    // taken are written out
     __syncthreads();
-    __shared__ int taken_s, stop_s;
-    __shared__ double bc[S], bs[S], gk[S + 1];
-    constexpr int UNR = S <= 16 ? S : 1;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x;
+        double tr[S + 2];
+#pragma unroll
+        for (int r = 0; r < S + 2; ++r) tr[r] = i < ncol && r <= i + 1 ? tail[i < S ? i : 0][r] : 0.0;
         const double tol = scal[S_CYCTOL];
-        gk[0] = g[j];
+        double gcur = g[j];
         int taken = ncol, stop = 0;
-#pragma unroll UNR
-        for (int i = 0; i < S; ++i) {
-            if (i >= ncol) break;
-            double* cv = tail[i];
-            double a = cv[0];
-#pragma unroll UNR
-            for (int t = 0; t < S; ++t) {
-                if (t >= i) break;
-                const double b = cv[t + 1];
-                cv[t] = bc[t] * a + bs[t] * b;
-                a = -bs[t] * a + bc[t] * b;
-            }
-            const int k = j + i;
-            const double b = cv[i + 1];
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            if (t >= ncol || stop) break;  // the same on every lane
+            const double a = __shfl(tr[t], t, 64), b = __shfl(tr[t + 1], t, 64);
             const double d = sqrt(a * a + b * b);
-            bc[i] = d == 0.0 ? 1.0 : a / d;
-            bs[i] = d == 0.0 ? 0.0 : b / d;
-            cv[i] = d;
-            gk[i + 1] = -bs[i] * gk[i];
-            gk[i] = bc[i] * gk[i];
-            if (fabs(gk[i + 1]) <= tol || k + 1 >= mcyc || (i == ncol - 1 && cut_s)) {
-                taken = i + 1;
+            const double c = d == 0.0 ? 1.0 : a / d, sr = d == 0.0 ? 0.0 : b / d;
+            if (i == t) tr[t] = d;
+            if (i > t) {
+                const double x0 = tr[t], x1 = tr[t + 1];
+                tr[t] = c * x0 + sr * x1;
+                tr[t + 1] = -sr * x0 + c * x1;
+            }
+            const double gnext = -sr * gcur;
+            if (i == 0) {
+                cs[j + t] = c;
+                sn[j + t] = sr;
+                g[j + t] = c * gcur;
+            }
+            gcur = gnext;
+            if (fabs(gnext) <= tol || j + t + 1 >= mcyc || (t == ncol - 1 && cut_s)) {
+                taken = t + 1;
                 stop = 1;
-                break;
             }
         }
-#pragma unroll UNR
-        for (int i = 0; i < S; ++i)
-            if (i < taken) {
-                cs[j + i] = bc[i];
-                sn[j + i] = bs[i];
-                g[j + i] = gk[i];
-            }
-        g[j + taken] = gk[taken];
-        taken_s = taken;
-        stop_s = stop;
-    }
-    __syncthreads();
-    const int taken = taken_s;
-    for (int i = 0; i < taken; ++i)
-        for (int r = threadIdx.x; r <= i; r += NT) H[j + r + (int64_t)(j + i) * ldh] = tail[i][r];
-    if (threadIdx.x == 0) {
-        ctrl[C_J] = j + taken;
-        ctrl[C_REORTH] = 0;
-        if (stop_s) ctrl[C_STOP] = 1;
+        if (i < taken)
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+                if (r <= i) H[j + r + (int64_t)(j + i) * ldh] = tr[r];
+        if (i == 0) {
+            g[j + taken] = gcur;
+            ctrl[C_J] = j + taken;
+            ctrl[C_REORTH] = 0;
+            if (stop) ctrl[C_STOP] = 1;
+        }
     }
 }
 
