@@ -1169,15 +1169,15 @@ __global__ __launch_bounds__(bg_threads(S)) void block_givens_kernel(int* ctrl, 
             double a[S];
 #pragma unroll
             for (int i = 0; i < S; ++i) a[i] = q < S ? gp[i * S + q] : 0.0;  // G[i][q]
-            const double g0 = q < S ? gp[q * S + q] : 0.0;
+            const double sg = q < S ? sqrt(gp[q * S + q]) : 0.0;           // sqrt(G[q][q]) for the pivot test
             int pok = 0;
             bool alive = true;
 #pragma unroll
             for (int k = 0; k < S; ++k) {
                 const double d = __shfl(a[k], k, 64);  // the updated pivot G[k][k]
-                const double gkk = __shfl(g0, k, 64);
+                const double sgk = __shfl(sg, k, 64);
                 const double ckk = d > 0.0 ? sqrt(d) : 0.0;
-                const bool ok = isfinite(ckk) && (k == 0 ? ckk > 1e-300 : ckk > 1e-8 * sqrt(gkk));
+                const bool ok = isfinite(ckk) && (k == 0 ? ckk > 1e-300 : ckk > 1e-8 * sgk);
                 if (alive) {  // the same on every lane
                     if (q == k) Cf[k][k] = isfinite(ckk) ? ckk : 0.0;
                     if (!ok) {
@@ -1185,9 +1185,14 @@ __global__ __launch_bounds__(bg_threads(S)) void block_givens_kernel(int* ctrl, 
                     } else {
                         const double rkq = q > k && q < S ? a[k] / ckk : 0.0;  // C[k][q]
                         if (q > k && q < S) Cf[k][q] = rkq;
+                        // row k of C back from LDS, one broadcast read per entry (the wave's LDS accesses run
+                        // in order; the fences keep the compiler from moving the reads above the writes)
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
                         for (int i = k + 1; i < S; ++i) {
-                            const double rki = __shfl(rkq, i, 64);  // C[k][i]
+                            const double rki = Cf[k][i];  // C[k][i]
                             if (i <= q) a[i] -= rki * rkq;
                         }
                         ++pok;
@@ -1199,20 +1204,19 @@ __global__ __launch_bounds__(bg_threads(S)) void block_givens_kernel(int* ctrl, 
         __syncthreads();
         if (threadIdx.x < pok_s) {  // C x = e_q on the resolvable leading triangle
             const int q = threadIdx.x;
-            double x[S];  // in registers (the S = 32 kernel has 256 per lane)
+            // back substitution by columns: once x_m is known its products join the sums of the rows above,
+            // so each step waits for one division and one multiply-add (in registers: the wide-block kernels
+            // have 256 per lane)
+            double x[S], v[S];
 #pragma unroll
-            for (int i = S - 1; i >= 0; --i) {
-                if (i > q) {
-                    x[i] = 0.0;
-                } else if (i == q) {
-                    x[i] = 1.0 / Cf[i][i];
-                } else {
-                    double v = 0.0;
+            for (int i = 0; i < S; ++i) v[i] = 0.0;
 #pragma unroll
-                    for (int m = i + 1; m < S; ++m)
-                        if (m <= q) v += Cf[i][m] * x[m];
-                    x[i] = -v / Cf[i][i];
-                }
+            for (int m = S - 1; m >= 0; --m) {
+                x[m] = m > q ? 0.0 : (m == q ? 1.0 / Cf[m][m] : -v[m] / Cf[m][m]);
+                if (m <= q)
+#pragma unroll
+                    for (int i = 0; i < S; ++i)
+                        if (i < m) v[i] += Cf[i][m] * x[m];
             }
 #pragma unroll
             for (int i = 0; i < S; ++i)
