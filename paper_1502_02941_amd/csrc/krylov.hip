@@ -979,18 +979,22 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
         const int t = ((int)blockIdx.x - nchunk) * (BLK / 64) + (threadIdx.x >> 6);
         if (t > j) return;
         const double* hr = Hrow + (int64_t)t * ldr;
-        double acc[S - 1];
+        // 16 products at a time (all S - 1 at once set this kernel's register count for its main path too)
+        for (int l0 = 0; l0 < S - 1; l0 += 16) {
+            double acc[16];
 #pragma unroll
-        for (int l = 0; l < S - 1; ++l) acc[l] = 0.0;
-        for (int c = (t > 0 ? t - 1 : 0) + lane; c < j; c += 64) {
-            const double h = hr[c];
+            for (int l = 0; l < 16; ++l) acc[l] = 0.0;
+            for (int c = (t > 0 ? t - 1 : 0) + lane; c < j; c += 64) {
+                const double h = hr[c];
 #pragma unroll
-            for (int l = 0; l < S - 1; ++l) acc[l] += h * R[l * (j + 1) + c];
-        }
+                for (int l = 0; l < 16; ++l)
+                    if (l0 + l < S - 1) acc[l] += h * R[(l0 + l) * (j + 1) + c];
+            }
 #pragma unroll
-        for (int l = 0; l < S - 1; ++l) {
-            const double v = wave_sum(acc[l]);
-            if (lane == 0) HX[l * ldx + t] = v;
+            for (int l = 0; l < 16; ++l) {
+                const double v = wave_sum(acc[l]);
+                if (lane == 0 && l0 + l < S - 1) HX[(l0 + l) * ldx + t] = v;
+            }
         }
         return;
     }
@@ -1002,6 +1006,17 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
     const int i = lane & 15, q = lane >> 4;
     const int64_t r0 = ((int64_t)blockIdx.x * (BLK / 64) + wave) * (16 * RT);
     if (r0 >= n) return;
+    // this lane's block vectors (16 nb + i), picked once: indexing the pointer array by the lane's column
+    // kept all S pointers live in registers
+    P* wl[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        P* pw = W.w[16 * nb];
+#pragma unroll
+        for (int u = 1; u < 16; ++u)
+            if (i == u) pw = W.w[16 * nb + u];
+        wl[nb] = pw;
+    }
     VR acc[RT][NB];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -1010,7 +1025,7 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t r = r0 + 16 * rt + Op::row(q, v);
-                acc[rt][nb][v] = r < n ? (double)W.w[16 * nb + i][r] : 0.0;
+                acc[rt][nb][v] = r < n ? (double)wl[nb][r] : 0.0;
             }
     const int jc = j + 1;
     // UPM_PD chunks of four columns in flight per wave (one was too few to cover the memory latency)
@@ -1051,7 +1066,7 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t r = r0 + 16 * rt + Op::row(q, v);
-                if (r < n) W.w[16 * nb + i][r] = (P)acc[rt][nb][v];
+                if (r < n) wl[nb][r] = (P)acc[rt][nb][v];
             }
 }
 
