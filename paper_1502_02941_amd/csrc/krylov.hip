@@ -636,14 +636,12 @@ __global__ __launch_bounds__(BLK) void multidot_block_kernel(const P* __restrict
 // product (so that no step waits for the previous one) no faster.
 constexpr int MF_CT = 32, MF_CH = 32;  // basis columns per tile, rows per staged chunk
 constexpr int mf_target_blocks() { return 2048; }
-// basis columns per tile of the dot kernel for blocks of S vectors (the Gram pass of a block keeps MF_CT)
-constexpr int MF_CT_WIDE = 32;
+// basis columns per tile and rows per staged chunk of the dot kernel for blocks of 32 vectors (the Gram pass
+// of a block keeps MF_CT and MF_CH); on 786432 unknowns over a 538-step cycle, 16 columns took 540 us per launch
+// against 478 and chunks of 16 rows (half the LDS, three waves per SIMD instead of two) 819 us
+constexpr int MF_CT_WIDE = 32, MF_CH_WIDE = 32;
 constexpr int mf_ct(int S) { return S > 16 ? MF_CT_WIDE : MF_CT; }
 inline int mf_grid(int ntile, int nsplit) { return (ntile * nsplit + 7) / 8 * 8; }
-template <typename P>
-struct MfStage {
-    static constexpr int STR = sizeof(P) == 8 ? MF_CH + 1 : MF_CH + 2;  // padded row stride (elements)
-};
 // S = 8 or 16; with GRAM the columns are the block's vectors themselves (j + 1
 // = S of them: the Gram matrix of a block of sixteen after its update).
 //
@@ -670,21 +668,23 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
     if (logical >= total) return;
     const int tile = logical % ntile, split = logical / ntile;
     static_assert(S == 8 || S == 16 || S == 32, "eight, sixteen or 32 vectors");
-    constexpr int CT = GRAM ? MF_CT : mf_ct(S);  // columns of this tile
-    constexpr int STR = MfStage<P>::STR, WPB = BLK / 64, NA = CT / 16, NB = S > 16 ? S / 16 : 1;
+    constexpr int CT = GRAM ? MF_CT : mf_ct(S);       // columns of this tile
+    constexpr int CH = GRAM || S <= 16 ? MF_CH : MF_CH_WIDE;  // rows per staged chunk
+    constexpr int STR = sizeof(P) == 8 ? CH + 1 : CH + 2;  // padded row stride (elements)
+    constexpr int WPB = BLK / 64, NA = CT / 16, NB = S > 16 ? S / 16 : 1;
     using Op = MfmaOp<double>;  // FP32 data too: the dots are summed in FP64, as by the vector-ALU kernel
     using VR = typename Op::V;
-    __shared__ __align__(16) P sv[WPB][CT * STR];  // after the row loop: the waves' partial sums
-    __shared__ P sw[WPB][S * STR];
-    static_assert(sizeof(sv) >= sizeof(double) * WPB * CT * S, "room for the partial sums");
+    // each wave's staged columns, then its staged block vectors; after the row loop the waves' partial sums
+    __shared__ __align__(16) P stage[WPB][(CT + S) * STR];
+    static_assert(sizeof(stage) >= sizeof(double) * WPB * CT * S, "room for the partial sums");
     const int ncols = GRAM ? S : j + 1;
     const int c0 = tile * CT;
     const int64_t r0 = (int64_t)split * rows_per_split;
     const int64_t r1 = r0 + rows_per_split < n ? r0 + rows_per_split : n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, i = lane & 15;
-    P* mv = sv[wave];
-    P* mw = sw[wave];
+    P* mv = stage[wave];
+    P* mw = stage[wave] + CT * STR;
     const P* wv[S];
 #pragma unroll
     for (int v = 0; v < S; ++v) wv[v] = W.w[v];
@@ -693,21 +693,27 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
     for (int h = 0; h < NA; ++h)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[h][b] = VR{0, 0, 0, 0};
-    constexpr int LPC = MF_CH / 64 > 0 ? 1 : 64 / MF_CH;  // chunks of 32 rows: a lane loads two columns' rows
+    constexpr int LPC = 64 / CH;  // columns whose rows one load instruction covers (2 for 32-row chunks)
     P x[CT / LPC], y[S / LPC];
     // a chunk's rows into registers (the next chunk's loads are in flight during this chunk's products):
-    // lane l loads row l % MF_CH of columns (l / MF_CH) + LPC c
-    const int lr = lane % MF_CH, lc = lane / MF_CH;
+    // lane l loads row l % CH of columns (l / CH) + LPC c
+    const int lr = lane % CH, lc = lane / CH;
+    auto pick = [&](int base) -> const P* {  // wv[base + lc], selected among constant indices
+        const P* p = wv[base % S];
+#pragma unroll
+        for (int u = 1; u < LPC; ++u)
+            if (lc == u) p = wv[(base + u) % S];
+        return p;
+    };
     auto load = [&](int64_t cb) {
         const int64_t r = cb + lr;
         const bool in = r < r1;
 #pragma unroll
         for (int c = 0; c < CT / LPC; ++c) {  // columns past j read column j and are discarded
             const int cc = c0 + LPC * c + lc;
-            if constexpr (GRAM) {  // columns 2 c and 2 c + 1 are vectors of the block (none past S)
-                static_assert(!GRAM || LPC == 2, "two columns per lane");
+            if constexpr (GRAM) {  // columns LPC c .. LPC c + LPC - 1 are vectors of the block (none past S)
                 if (LPC * c < S) {
-                    const P* col = lc ? wv[(LPC * c + 1) % S] : wv[(LPC * c) % S];
+                    const P* col = pick(LPC * c);
                     x[c] = in ? col[r] : P(0);
                 } else {
                     x[c] = P(0);
@@ -717,13 +723,13 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
         }
 #pragma unroll
         for (int v = 0; v < S / LPC; ++v) {
-            const P* yp = lc ? wv[(LPC * v + 1) % S] : wv[(LPC * v) % S];
+            const P* yp = pick(LPC * v);
             y[v] = in ? yp[r] : P(0);
         }
     };
-    int64_t cb = r0 + (int64_t)wave * MF_CH;
+    int64_t cb = r0 + (int64_t)wave * CH;
     if (cb < r1) load(cb);
-    for (; cb < r1; cb += (int64_t)WPB * MF_CH) {
+    for (; cb < r1; cb += (int64_t)WPB * CH) {
 #pragma unroll
         for (int c = 0; c < CT / LPC; ++c) mv[(LPC * c + lc) * STR + lr] = x[c];
 #pragma unroll
@@ -731,9 +737,9 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (cb + (int64_t)WPB * MF_CH < r1) load(cb + (int64_t)WPB * MF_CH);
+        if (cb + (int64_t)WPB * CH < r1) load(cb + (int64_t)WPB * CH);
 #pragma unroll
-        for (int t = 0; t < MF_CH / 4; ++t) {
+        for (int t = 0; t < CH / 4; ++t) {
             double b[NB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) b[nb] = (double)mw[((16 * nb + i) & (S - 1)) * STR + 4 * t + q];
@@ -750,7 +756,7 @@ __global__ __launch_bounds__(BLK) void multidot_mfma_kernel(const P* __restrict_
     }
     // lane (i, q) holds the dots of column 16 h + row(q, v) with vector 16 nb + i (i < S)
     __syncthreads();
-    double(*red)[CT * S] = reinterpret_cast<double(*)[CT * S]>(&sv[0][0]);
+    double(*red)[CT * S] = reinterpret_cast<double(*)[CT * S]>(&stage[0][0]);
     if (i < S) {
 #pragma unroll
         for (int h = 0; h < NA; ++h)
