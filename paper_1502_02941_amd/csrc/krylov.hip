@@ -1517,7 +1517,15 @@ __global__ __launch_bounds__(1024) void trisolve_kernel(const int* ctrl, const d
         __syncthreads();
         for (int k = threadIdx.x; k < c0; k += blockDim.x) {
             double s = rhs[k];
-            for (int c = 0; c < pb; ++c) s -= H[k + (int64_t)(c0 + c) * ldh] * ys[c];
+            int c = 0;
+            for (; c + 16 <= pb; c += 16) {  // sixteen loads in flight, summed in column order as below
+                double hv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) hv[u] = H[k + (int64_t)(c0 + c + u) * ldh];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) s -= hv[u] * ys[c + u];
+            }
+            for (; c < pb; ++c) s -= H[k + (int64_t)(c0 + c) * ldh] * ys[c];
             rhs[k] = s;
         }
         for (int c = threadIdx.x; c < pb; c += blockDim.x) y[c0 + c] = ys[c];
