@@ -28,7 +28,8 @@ constexpr int LS_CH = 1024;      // rows per row chunk (one workgroup each); mea
 constexpr int LS_CT = 16;        // Gram-Schmidt columns reduced together (8: same, 32: slower)
 constexpr int LS_GV = 512;       // Givens staging chunk
 constexpr int LS_BATCH = 8;      // loads issued together in the serial loops of the block kernels
-constexpr int LS_GT = 256;       // threads of the block Givens kernel (its Hessenberg products take one row each)
+constexpr int LS_GT = 512;       // threads of the block Givens kernel (its Hessenberg products take a row per
+constexpr int LS_SEG = 4;        // group of LS_SEG lanes)
 
 __device__ __forceinline__ double ls_wave_sum(double v)
 {
@@ -1097,26 +1098,37 @@ __global__ __launch_bounds__(LS_GT) void ls_block_givens_kernel(const LsArgs A, 
     __syncthreads();
     // columns J+1 .. J+ncol-1 from the raw column J and the earlier raw columns
     if (ncol > 1) {
-        for (int t = threadIdx.x; t <= j + ncol; t += LS_GT) {
+        // a row per group of LS_SEG adjacent lanes: lane g of the group sums every LS_SEG-th entry of the row
+        // from the g-th on (the walk along a row is a chain of dependent loads: a quarter as long), the partial
+        // sums are combined by shuffles, and the group's lanes then take the columns in turn
+        constexpr int SEG = LS_SEG;
+        const int sg = threadIdx.x % SEG;
+        for (int t = threadIdx.x / SEG; t <= j + ncol; t += LS_GT / SEG) {
             double hx[S - 1];
 #pragma unroll
             for (int l = 0; l < S - 1; ++l) hx[l] = 0.0;
-            if (t <= j + 1) {  // (Hr R_l)[t], loads issued LS_BATCH at a time, summed in order
-                int c = t > 0 ? t - 1 : 0;
-                for (; c + LS_BATCH <= j + 1; c += LS_BATCH) {
-                    double h[LS_BATCH];
+            if (t <= j + 1) {  // (Hr R_l)[t], loads issued HB at a time
+                constexpr int HB = LS_BATCH;
+                int c = (t > 0 ? t - 1 : 0) + sg;
+                for (; c + SEG * (HB - 1) <= j; c += SEG * HB) {
+                    double h[HB];
 #pragma unroll
-                    for (int u = 0; u < LS_BATCH; ++u) h[u] = Hr[t + (int64_t)(c + u) * ldr];
+                    for (int u = 0; u < HB; ++u) h[u] = Hr[t + (int64_t)(c + SEG * u) * ldr];
 #pragma unroll
-                    for (int u = 0; u < LS_BATCH; ++u)
+                    for (int u = 0; u < HB; ++u)
 #pragma unroll
-                        for (int l = 0; l < S - 1; ++l) hx[l] += h[u] * R[l * (j + 1) + c + u];
+                        for (int l = 0; l < S - 1; ++l) hx[l] += h[u] * R[l * (j + 1) + c + SEG * u];
                 }
-                for (; c <= j; ++c) {
+                for (; c <= j; c += SEG) {
                     const double h = Hr[t + (int64_t)c * ldr];
 #pragma unroll
                     for (int l = 0; l < S - 1; ++l) hx[l] += h * R[l * (j + 1) + c];
                 }
+            }
+#pragma unroll
+            for (int l = 0; l < S - 1; ++l) {  // the group's lanes share a row and leave the loop together
+#pragma unroll
+                for (int o = 1; o < SEG; o *= 2) hx[l] += __shfl_xor(hx[l], o, 64);
             }
             // row t of [R; C] (coefficients on V below row j + 1, the Cholesky factor above), read once
             double rc[S];
@@ -1127,7 +1139,7 @@ __global__ __launch_bounds__(LS_GT) void ls_block_givens_kernel(const LsArgs A, 
 #pragma unroll
             for (int l = 0; l < S - 1; ++l) e[l] = rc[l + 1] + A.theta * rc[l] - hx[l];
 #pragma unroll 1
-            for (int ii = 1; ii < ncol; ++ii) {
+            for (int ii = 1 + sg; ii < ncol; ii += SEG) {
                 if (t > j + ii + 1) continue;
                 double v = 0.0;
 #pragma unroll
