@@ -893,12 +893,15 @@ __global__ __launch_bounds__(BLK) void update_block_kernel(const P* __restrict__
     }
 }
 
-// w_r -= sum_{c<=j} R_r[c] V_c for the S = 16 or 32 vectors of a block,
-// upw_rows(S) rows per thread, without Gram partials (136 pair sums per row
-// would not fit in registers: wide blocks form their Gram matrix afterwards
-// with the matrix-core dot kernel on the updated vectors).  The coefficients
-// R_r[c] are wave-uniform (scalar loads); the workgroups after the first
-// nchunk take the Hessenberg products, as in update_block_kernel.
+// w_r -= sum_{c<=j} R_r[c] V_c for the sixteen vectors of a block (FP64 or
+// FP32 data; 32 vectors take the matrix-core update below: here, one row per
+// thread, their 32 strided coefficient loads per basis column made the launch
+// 1009 us against 466), upw_rows(S) rows per thread, without Gram partials
+// (136 pair sums per row would not fit in registers: wide blocks form their
+// Gram matrix afterwards with the matrix-core dot kernel on the updated
+// vectors).  The coefficients R_r[c] are wave-uniform (scalar loads); the
+// workgroups after the first nchunk take the Hessenberg products, as in
+// update_block_kernel.
 constexpr int upw_rows(int S) { return S <= 16 ? 2 : 1; }
 template <typename P, int S>
 __global__ __launch_bounds__(BLK) void update_wide_kernel(const P* __restrict__ V, BlockVecs<P> W, int64_t n, int j,
