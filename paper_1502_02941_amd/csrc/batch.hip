@@ -833,19 +833,20 @@ extern "C" int32_t dg_batch_create(const dg_instance* in, int32_t count, const d
                 const int N = (I.k + 1) * (I.k + 2) / 2;
                 const int64_t n = I.T * N;
                 const int64_t nch = ls_row_chunks(n), neb = ls_elem_blocks(I.k, I.T);
-                const double add = (double)i_V[id] * ps + (double)i_ahat[id] * ps + (double)i_dinv[id] * (8 + ps) +
+                const size_t nV = (size_t)(I.m + 1) * ls_vstride(n);  // the basis with aligned columns
+                const double add = (double)nV * ps + (double)i_ahat[id] * ps + (double)i_dinv[id] * (8 + ps) +
                                    (double)(I.m + 2) * nch * 8 * lsb + (double)lsg * nch * 8 +
                                    (double)(I.m + 1) * (I.m + 6) * 8 +
                                    (double)(I.m + 2) * (I.m + 1) * 8;
                 if (!li.empty() && bytes + add > budget) break;
                 LsInst L{};
-                L.T = I.T; L.n = n; L.k = I.k; L.m = I.m; L.id = id; L.id_local = (int32_t)li.size();
+                L.T = I.T; L.n = n; L.vs = ls_vstride(n); L.k = I.k; L.m = I.m; L.id = id; L.id_local = (int32_t)li.size();
                 L.nchunks = (int32_t)nch; L.neblk = (int32_t)neb;
                 L.rp_off = I.rp_off; L.ci_off = I.ci_off; L.val_off = I.val_off; L.x_off = I.x_off;
                 L.dinv_off = dinv; L.ahat_off = ahat; L.v_off = V; L.part_off = part;
                 L.red_off = red; L.red2_off = red2; L.hc_off = hc; L.h_off = hh; L.H_off = H; L.Hr_off = Hr;
                 // lsb (m + 2) columns of partials, lsb (lsb + 1) / 2 Gram sums per row chunk
-                dinv += i_dinv[id]; ahat += i_ahat[id]; V += i_V[id]; part += (size_t)lsb * (I.m + 2) * nch;
+                dinv += i_dinv[id]; ahat += i_ahat[id]; V += nV; part += (size_t)lsb * (I.m + 2) * nch;
                 red += lsg * (size_t)nch; red2 += neb; hc += (size_t)lsb * ((size_t)I.m + 2); hh += I.m + 1;
                 H += (size_t)(I.m + 1) * I.m; Hr += (size_t)(I.m + 2) * (I.m + 1);
                 eb.push_back(eb.back() + neb);

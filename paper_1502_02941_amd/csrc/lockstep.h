@@ -11,6 +11,7 @@ namespace dg {
 
 struct LsInst {
     int64_t T, n;
+    int64_t vs;                // column stride of the instance's Krylov basis: n rounded up to LS_VALIGN rows
     int32_t k, m;              // degree, restart length
     int32_t id, id_local;      // batch instance index, index within the lockstep chunk
     int32_t nchunks, neblk;    // row chunks, element blocks
@@ -21,6 +22,10 @@ struct LsInst {
 };
 
 constexpr int LS_SMAX = 8;  // most Arnoldi vectors per Gram-Schmidt pass
+// basis columns start on whole 32-row pieces (256 bytes in FP64, 128 in FP32): the dot kernel's staged pieces
+// then never straddle a cache line (with columns starting at c n they straddled nearly always)
+constexpr int64_t LS_VALIGN = 32;
+inline int64_t ls_vstride(int64_t n) { return (n + LS_VALIGN - 1) / LS_VALIGN * LS_VALIGN; }
 
 struct LsState {
     int32_t active, stop, J, mcyc, its, cycles, status, pad;

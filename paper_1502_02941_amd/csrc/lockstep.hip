@@ -415,7 +415,7 @@ __global__ __launch_bounds__(LS_BT) void ls_spmv_kernel(const LsArgs A, int src,
     const int32_t* rp = A.row_ptr + I.rp_off;
     const int32_t* ci = A.col_idx + I.ci_off;
     // src 0: (Ahat - theta I) v_J into w; src r > 0: a block's w_r = (Ahat - theta I) w_{r-1}
-    const P* v = src == 0 ? (const P*)A.V + I.v_off + (int64_t)S.J * I.n : ls_block_vec<P>(A, src - 1) + I.x_off;
+    const P* v = src == 0 ? (const P*)A.V + I.v_off + (int64_t)S.J * I.vs : ls_block_vec<P>(A, src - 1) + I.x_off;
     const P* Ah = (const P*)A.Ahat + I.ahat_off;
     const P* own = (const P*)A.DinvP + I.dinv_off + (e.el * N + e.j) * N;  // a row that always exists
     double s;
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot_kernel(const LsArgs A)
     for (int t0 = 0; t0 < ncols; t0 += LS_CT) {
         const P* col[LS_CT];
 #pragma unroll
-        for (int c = 0; c < LS_CT; ++c) col[c] = (t0 + c <= J) ? V + (int64_t)(t0 + c) * I.n : w;
+        for (int c = 0; c < LS_CT; ++c) col[c] = (t0 + c <= J) ? V + (int64_t)(t0 + c) * I.vs : w;
         double ac[LS_CT];
 #pragma unroll
         for (int c = 0; c < LS_CT; ++c) ac[c] = 0.0;
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(LS_BT) void ls_update_kernel(const LsArgs A)
     P* w = (P*)A.w + I.x_off;
     const double* h = A.hcol + I.hc_off;
     const int64_t r0 = ch * LS_CH, r1 = min(r0 + LS_CH, I.n);
-    const int64_t n = I.n;
+    const int64_t n = I.vs;  // basis column stride
     double acc = 0.0;
     // E rows per thread advance through the columns together (4 columns x E
     // rows of loads in flight)
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(LS_BT) void ls_normalize_kernel(const LsArgs A)
     const LsInst& I = A.inst[i];
     const int64_t ch = b - A.rblk[i];
     const P sc = (P)S.invh;
-    P* vn = (P*)A.V + I.v_off + (int64_t)S.J * I.n;
+    P* vn = (P*)A.V + I.v_off + (int64_t)S.J * I.vs;
     const P* w = (const P*)A.w + I.x_off;
     const int64_t r1 = min((ch + 1) * (int64_t)LS_CH, I.n);
     for (int64_t t = ch * LS_CH + threadIdx.x; t < r1; t += LS_BT) vn[t] = w[t] * sc;
@@ -719,7 +719,7 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot_block_kernel(const LsArgs A
     for (int t0 = 0; t0 < ncols; t0 += LS_CT2) {
         const P* col[LS_CT2];
 #pragma unroll
-        for (int c = 0; c < LS_CT2; ++c) col[c] = (t0 + c <= J) ? V + (int64_t)(t0 + c) * I.n : wv[0];  // past J: discarded
+        for (int c = 0; c < LS_CT2; ++c) col[c] = (t0 + c <= J) ? V + (int64_t)(t0 + c) * I.vs : wv[0];  // past J: discarded
         double a[S][LS_CT2];
 #pragma unroll
         for (int q = 0; q < S; ++q)
@@ -808,7 +808,7 @@ __global__ __launch_bounds__(LS_BT) void ls_multidot_mfma_kernel(const LsArgs A)
 #pragma unroll
         for (int c = 0; c < CT / 2; ++c) {  // columns past J read column J and are discarded
             const int cc = t0 + 2 * c + lc;
-            x[c] = in ? __builtin_nontemporal_load(V + (int64_t)(cc < ncols ? cc : J) * I.n + r) : P(0);
+            x[c] = in ? __builtin_nontemporal_load(V + (int64_t)(cc < ncols ? cc : J) * I.vs + r) : P(0);
         }
 #pragma unroll
         for (int v = 0; v < S / 2; ++v) y[v] = in ? wv[2 * v + lc][r] : P(0);
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(LS_BT) void ls_update_block_kernel(const LsArgs A)
     for (int q = 0; q < S; ++q) wv[q] = ls_block_vec<P>(A, q) + I.x_off;
     const double* R = A.hcol + I.hc_off;
     const int64_t r0 = ch * LS_CH, r1 = min(r0 + LS_CH, I.n);
-    const int64_t n = I.n;
+    const int64_t n = I.vs;  // basis column stride
     double gs[NG];
 #pragma unroll
     for (int k = 0; k < NG; ++k) gs[k] = 0.0;
@@ -1230,7 +1230,7 @@ __global__ __launch_bounds__(LS_BT) void ls_normalize_block_kernel(const LsArgs 
     const P* wv[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) wv[q] = ls_block_vec<P>(A, q) + I.x_off;
-    P* out = (P*)A.V + I.v_off + (int64_t)(St.jb + 1) * I.n;
+    P* out = (P*)A.V + I.v_off + (int64_t)(St.jb + 1) * I.vs;
     const int64_t r1 = min((ch + 1) * (int64_t)LS_CH, I.n);
     for (int64_t t = ch * LS_CH + threadIdx.x; t < r1; t += LS_BT) {
         double u[S];
@@ -1242,7 +1242,7 @@ __global__ __launch_bounds__(LS_BT) void ls_normalize_block_kernel(const LsArgs 
                 double v = 0.0;
 #pragma unroll
                 for (int l = 0; l <= ii; ++l) v += u[l] * ci[l][ii];
-                out[(int64_t)ii * I.n + t] = (P)v;
+                out[(int64_t)ii * I.vs + t] = (P)v;
             }
         }
     }
@@ -1291,7 +1291,7 @@ __global__ __launch_bounds__(LS_BT) void ls_combine_kernel(const LsArgs A)
     const int64_t r1 = min((ch + 1) * (int64_t)LS_CH, I.n);
     for (int64_t t = ch * LS_CH + threadIdx.x; t < r1; t += LS_BT) {
         double s = 0.0;
-        for (int c = 0; c < J; ++c) s += y[c] * (double)V[(int64_t)c * I.n + t];
+        for (int c = 0; c < J; ++c) s += y[c] * (double)V[(int64_t)c * I.vs + t];
         u[t] = (P)s;
     }
 }
