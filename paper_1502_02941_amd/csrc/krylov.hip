@@ -355,6 +355,40 @@ __global__ __launch_bounds__(BLK) void reduce_cols_rt_kernel(const double* __res
     }
 }
 
+// The Gram matrix of a block of 32 vectors from the matrix-core update's
+// per-workgroup partials: GP_N values per split (three 16 x 16 products G00,
+// G01, G11; value e = 256 p + 64 v + l is register v of lane l of product p),
+// split-major.  Workgroup (cg, sg) sums splits sg per .. sg per + per - 1 of
+// columns 64 cg .. 64 cg + 63, four waves in a fixed order; with G null it
+// writes the sums to out[sg][e], else it expands them into the symmetric
+// row-major 32 x 32 G (G01 also as G10).
+constexpr int GP_N = 3 * 256;
+__global__ __launch_bounds__(BLK) void reduce_gram_kernel(const double* __restrict__ parts, int nsplit, int per,
+                                                          int j, const int* ctrl, double* __restrict__ out,
+                                                          double* __restrict__ G)
+{
+    if (ctrl[C_STOP] || ctrl[C_J] != j) return;
+    __shared__ double sh[BLK / 64][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = (int)blockIdx.x * 64 + lane;
+    const int s0 = (int)blockIdx.y * per, s1 = s0 + per < nsplit ? s0 + per : nsplit;
+    double acc = 0.0;
+    for (int sp = s0 + wave; sp < s1; sp += BLK / 64) acc += parts[(int64_t)sp * GP_N + e];
+    sh[wave][lane] = acc;
+    __syncthreads();
+    if (wave) return;
+    const double v = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+    if (!G) {
+        out[(int64_t)blockIdx.y * GP_N + e] = v;
+        return;
+    }
+    const int p = e >> 8, r = (e >> 6) & 3, l = e & 63;
+    const int x = MfmaOp<double>::row(l >> 4, r), y = l & 15;  // D[x][y] of product p
+    const int a = p == 2 ? 16 : 0, b = p == 0 ? 0 : 16;
+    G[(a + x) * 32 + b + y] = v;
+    if (p == 1) G[(b + y) * 32 + a + x] = v;
+}
+
 // w -= sum_{c<=j} h[c] V_c and ||w||^2 (into scal[S_WNORM2]); rows split over
 // threads, columns unrolled by 4 to keep many loads in flight.  In the
 // reorthogonalisation pass (reorth_pass != 0) it runs only when flagged.
@@ -972,17 +1006,27 @@ __global__ __launch_bounds__(BLK) void update_wide_kernel(const P* __restrict__ 
 // accumulators start from the block's vectors (D[i][j] in lane j + 16 g',
 // register v, rows g' + 4 v) and are stored back there.  Columns past j give
 // zero operands.  The workgroups after the first nchunk take the Hessenberg
-// products, as in update_wide_kernel.
+// products, as in update_wide_kernel.  The updated tile also gives this
+// workgroup's share of the block's Gram matrix U^T U: register v of lane
+// (y, g) holds row g + 4 v of column y, which is both the A operand U^T[y][g]
+// and the B operand U[g][y] of a product over those four rows, so G00, G01 and
+// G11 are 16 x 16 x 4 products of the accumulators themselves; the four waves'
+// sums go to gpart[blockIdx.x][GP_N] (reduce_gram_kernel).
 constexpr int UPM_RT = 4, UPM_PD = 4;
+// workgroups of the row tiles (each wave 16 UPM_RT rows), and the splits one
+// workgroup of the first Gram reduction pass sums
+inline int upm_grid(int64_t n) { return (int)(((n + 16 * UPM_RT - 1) / (16 * UPM_RT) + BLK / 64 - 1) / (BLK / 64)); }
+constexpr int GP_PER = 64;
 template <typename P, int S>
 __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, BlockVecs<P> W, int64_t n, int j,
                                                           const int* ctrl, const double* __restrict__ R,
                                                           const double* __restrict__ negRT, int nchunk,
                                                           const double* __restrict__ Hrow, int ldr,
-                                                          double* __restrict__ HX, int ldx)
+                                                          double* __restrict__ HX, int ldx,
+                                                          double* __restrict__ gpart)
 {
     if (ctrl[C_STOP] || ctrl[C_J] != j) return;
-    static_assert(sizeof(P) == 8 && (S == 16 || S == 32), "FP64 blocks of 16 or 32");
+    static_assert(sizeof(P) == 8 && S == 32 && BLK == 256, "FP64 blocks of 32, four waves (the Gram partials)");
     if ((int)blockIdx.x >= nchunk) {
         const int lane = threadIdx.x & 63;
         const int t = ((int)blockIdx.x - nchunk) * (BLK / 64) + (threadIdx.x >> 6);
@@ -1014,7 +1058,7 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, q = lane >> 4;
     const int64_t r0 = ((int64_t)blockIdx.x * (BLK / 64) + wave) * (16 * RT);
-    if (r0 >= n) return;
+    const bool live = r0 < n;  // a wave past the last row still takes part in the Gram sum (with zeros)
     // this lane's block vectors (16 nb + i), picked once: indexing the pointer array by the lane's column
     // kept all S pointers live in registers
     P* wl[NB];
@@ -1036,7 +1080,7 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
                 const int64_t r = r0 + 16 * rt + Op::row(q, v);
                 acc[rt][nb][v] = r < n ? (double)wl[nb][r] : 0.0;
             }
-    const int jc = j + 1;
+    const int jc = live ? j + 1 : 0;
     // UPM_PD chunks of four columns in flight per wave (one was too few to cover the memory latency)
     constexpr int PD = UPM_PD;
     double a[PD][RT], b[PD][NB];
@@ -1077,6 +1121,31 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
                 const int64_t r = r0 + 16 * rt + Op::row(q, v);
                 if (r < n) wl[nb][r] = (P)acc[rt][nb][v];
             }
+    VR g[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) g[p][v] = 0.0;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            g[0] = Op::mac(acc[rt][0][v], acc[rt][0][v], g[0]);
+            g[1] = Op::mac(acc[rt][0][v], acc[rt][1][v], g[1]);
+            g[2] = Op::mac(acc[rt][1][v], acc[rt][1][v], g[2]);
+        }
+    __shared__ double gs[BLK / 64][GP_N];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gs[wave][256 * p + 64 * v + lane] = g[p][v];
+    __syncthreads();
+    double* gp = gpart + (int64_t)blockIdx.x * GP_N;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const int e = 256 * p + (int)threadIdx.x;
+        gp[e] = (gs[0][e] + gs[1][e]) + (gs[2][e] + gs[3][e]);
+    }
 }
 
 // One workgroup: Gram reduction, Cholesky (pivot i is resolvable when c_ii >
@@ -1818,6 +1887,10 @@ extern "C" int32_t dg_solver_create(const dg_mesh* m, const dg_solver_opts* o, d
         }
     }
     maxgrid = std::max<int64_t>(maxgrid, BS_MAX * (BS_MAX + 1) / 2 * (int64_t)s->grid_chunk);
+    {  // the matrix-core update's Gram partials and the first reduction pass's sums
+        const int64_t gm = dg::upm_grid(s->n);
+        maxgrid = std::max<int64_t>(maxgrid, (gm + (gm + dg::GP_PER - 1) / dg::GP_PER) * dg::GP_N);
+    }
     {  // the Gram matrix of a wide block: S x S columns in the shape of column count S (at most BS_MAX)
         int nt, sp;
         int64_t rows;
@@ -2003,19 +2076,23 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
         pr = prof_begin(s, st, PK_UPDATE, up_bytes, j, 0);
         const int hrows = (j + 1 + BLK / 64 - 1) / (BLK / 64);  // workgroups of the Hessenberg products
         const double* gram = s->partials;  // Gram partials (pairs x grid_chunk), or at S >= 16 the reduced matrix
-        if constexpr (S >= 16) {
-            if constexpr (S == 32) {  // 32 vectors: the update on the matrix cores
-                const int64_t waves = (s->n + 16 * UPM_RT - 1) / (16 * UPM_RT);
-                const int gm = (int)((waves + BLK / 64 - 1) / (BLK / 64));
-                hipLaunchKernelGGL((update_mfma_kernel<P, S>), dim3(gm + hrows), dim3(BLK), 0, st, V, W, s->n, j,
-                                   (const int*)s->ctrl, (const double*)s->Rb, (const double*)s->RbT, gm,
-                                   (const double*)s->Hr, mm + 1, s->HX, mm + 2);
-            } else {
-                const int g16 = (int)((s->n + BLK * upw_rows(S) - 1) / (BLK * upw_rows(S)));
-                hipLaunchKernelGGL((update_wide_kernel<P, S>), dim3(g16 + hrows), dim3(BLK), 0, st, (const P*)V, W,
-                                   s->n, j, (const int*)s->ctrl, (const double*)s->Rb, g16, (const double*)s->Hr,
-                                   mm + 1, s->HX, mm + 2);
-            }
+        if constexpr (S == 32) {  // 32 vectors: the update on the matrix cores, the Gram matrix from its tiles
+            const int gm = upm_grid(s->n), sg = (gm + GP_PER - 1) / GP_PER;
+            hipLaunchKernelGGL((update_mfma_kernel<P, S>), dim3(gm + hrows), dim3(BLK), 0, st, V, W, s->n, j,
+                               (const int*)s->ctrl, (const double*)s->Rb, (const double*)s->RbT, gm,
+                               (const double*)s->Hr, mm + 1, s->HX, mm + 2, s->partials);
+            prof_end(s, st, pr);
+            double* stage = s->partials + (int64_t)gm * GP_N;
+            hipLaunchKernelGGL(reduce_gram_kernel, dim3(GP_N / 64, sg), dim3(BLK), 0, st, (const double*)s->partials,
+                               gm, GP_PER, j, (const int*)s->ctrl, stage, nullptr);
+            hipLaunchKernelGGL(reduce_gram_kernel, dim3(GP_N / 64, 1), dim3(BLK), 0, st, (const double*)stage, sg, sg,
+                               j, (const int*)s->ctrl, nullptr, s->G16);
+            gram = s->G16;
+        } else if constexpr (S == 16) {
+            const int g16 = (int)((s->n + BLK * upw_rows(S) - 1) / (BLK * upw_rows(S)));
+            hipLaunchKernelGGL((update_wide_kernel<P, S>), dim3(g16 + hrows), dim3(BLK), 0, st, (const P*)V, W, s->n,
+                               j, (const int*)s->ctrl, (const double*)s->Rb, g16, (const double*)s->Hr, mm + 1, s->HX,
+                               mm + 2);
             prof_end(s, st, pr);
             int gt, gs;
             int64_t grows;
