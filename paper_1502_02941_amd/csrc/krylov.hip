@@ -1534,6 +1534,71 @@ __global__ __launch_bounds__(BLK) void normalize_block_kernel(P* __restrict__ V,
     }
 }
 
+// The same for blocks of 32 (FP64) on the matrix cores, as the transposed
+// product Q_tile^T = (C^{-1})^T U_tile^T: a wave owns NRM_RT x 16 rows; lane
+// (i, k) takes (C^{-1})_{c+k, 16 nb + i} (zero below the diagonal) as the A
+// operand and u_{c+k} at row i of the tile (16 consecutive rows per 16 lanes,
+// zero for vectors past the ones taken, so no stale value reaches a sum) as the
+// B operand.  Column 16 nb + g + 4 v, row i of the result is register v of lane
+// i + 16 g, so a store writes 16 consecutive rows of four columns.  (Read from
+// LDS as wave-uniform operands, C^{-1} cost 528 LDS reads per row.)
+constexpr int NRM_RT = 4;
+static_assert(NRM_RT == UPM_RT, "launched on the grid of the matrix-core update (upm_grid)");
+template <typename P, int S>
+__global__ __launch_bounds__(BLK) void normalize_mfma_kernel(P* __restrict__ V, BlockVecs<P> W, int64_t n, int j,
+                                                             const int* ctrl, const double* __restrict__ scal)
+{
+    static_assert(sizeof(P) == 8 && S == 32, "FP64 blocks of 32");
+    const int t = ctrl[C_J] - j;
+    const int nq = ctrl[C_STOP] ? t - 1 : t;
+    if (t < 1 || t > S || nq < 1) return;
+    using Op = MfmaOp<double>;
+    using VR = typename Op::V;
+    constexpr int RT = NRM_RT, NC = S / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, k = lane >> 4;
+    const int64_t r0 = ((int64_t)blockIdx.x * (BLK / 64) + wave) * (16 * RT);
+    if (r0 >= n) return;  // no barrier below
+    double b[RT][NC];
+#pragma unroll
+    for (int c4 = 0; c4 < NC; ++c4) {
+        const int c = 4 * c4 + k;
+        const P* src = W.w[4 * c4];
+#pragma unroll
+        for (int u = 1; u < 4; ++u)
+            if (k == u) src = W.w[4 * c4 + u];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t r = r0 + 16 * rt + i;
+            b[rt][c4] = c < nq && r < n ? (double)src[r] : 0.0;
+        }
+    }
+    double a[2][NC];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int c4 = 0; c4 < NC; ++c4) {
+            const int c = 4 * c4 + k, col = 16 * nb + i;
+            a[nb][c4] = c <= col ? scal[S_QB + c * S + col] : 0.0;
+        }
+    P* out = V + (int64_t)(j + 1) * n;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t r = r0 + 16 * rt + i;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            VR acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c4 = 0; c4 < (nb ? NC : NC / 2); ++c4) acc = Op::mac(a[nb][c4], b[rt][c4], acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = 16 * nb + Op::row(k, v);
+                if (col < nq && r < n) out[(int64_t)col * n + r] = (P)acc[v];
+            }
+        }
+    }
+}
+
 // start of a cycle: V_0 = r / beta, g = (beta, 0, ...), counters reset
 template <typename P>
 __global__ __launch_bounds__(BLK) void cycle_init_kernel(P* __restrict__ V, const double* __restrict__ r, int64_t n,
@@ -2115,8 +2180,12 @@ static void block_cycle(dg_solver* s, hipStream_t st, int mcyc, double spmv_byte
         hipLaunchKernelGGL((block_givens_kernel<S>), dim3(1), dim3(bg_threads(S)), 0, st, s->ctrl, gram,
                            s->grid_chunk, (const double*)s->Rb, s->Hr, mm + 1, (const double*)s->HX, mm + 2, s->H,
                            mm + 1, s->cs, s->sn, s->g, s->scal, j, mcyc, s->theta);
-        hipLaunchKernelGGL((normalize_block_kernel<P, S>), dim3(s->grid_vec), dim3(BLK), 0, st, V, W, s->n, j,
-                           (const int*)s->ctrl, (const double*)s->scal);
+        if constexpr (S == 32)
+            hipLaunchKernelGGL((normalize_mfma_kernel<P, S>), dim3(upm_grid(s->n)), dim3(BLK), 0, st, V, W, s->n, j,
+                               (const int*)s->ctrl, (const double*)s->scal);
+        else
+            hipLaunchKernelGGL((normalize_block_kernel<P, S>), dim3(s->grid_vec), dim3(BLK), 0, st, V, W, s->n, j,
+                               (const int*)s->ctrl, (const double*)s->scal);
     }
 }
 
