@@ -456,10 +456,12 @@ def test_wider_blocks_match_one_vector_steps(api, case, mixed, block, basis):
     one-vector steps (the Krylov spaces are the same; only rounding differs).
     In FP32 cycles eight vectors are allowed a quarter more steps: the rounding
     of the block's vectors shows on the hard P3 case (1925 against 1581).
-    Sixteen or 32 vectors (whose Gram matrix comes from a separate pass over
-    the updated vectors; 32 form their Hessenberg columns in two groups) are
-    for FP64 cycles only and rejected with FP32 ones (3582 against 1581 there
-    with sixteen).  A restart of 51 leaves a ragged last block.  With 32 the
+    Sixteen or 32 vectors are for FP64 cycles only and rejected with FP32 ones
+    (3582 against 1581 there with sixteen).  Sixteen take their Gram matrix
+    from a separate pass over the updated vectors; 32 from the matrix-core
+    update's own tiles (the 8 x 8, 20 x 20 and P3 13 x 13 meshes leave waves
+    past the last row, which add zeros to it), normalise on the matrix cores
+    and form their Hessenberg columns in two groups.  A restart of 51 leaves a ragged last block.  With 32 the
     first cycle on the smallest diffusion system (8 x 8 P1 SIPG) ends at an
     unresolvable pivot and the cycles after it run with sixteen (72 against
     56 steps), and on the hard P3 IIPG system a 32-vector cycle that raised
