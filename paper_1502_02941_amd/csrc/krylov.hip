@@ -1012,7 +1012,7 @@ __global__ __launch_bounds__(BLK) void update_wide_kernel(const P* __restrict__ 
 // and the B operand U[g][y] of a product over those four rows, so G00, G01 and
 // G11 are 16 x 16 x 4 products of the accumulators themselves; the four waves'
 // sums go to gpart[blockIdx.x][GP_N] (reduce_gram_kernel).
-constexpr int UPM_RT = 4, UPM_PD = 4;
+constexpr int UPM_RT = 4, UPM_PD = 6;
 // workgroups of the row tiles (each wave 16 UPM_RT rows), and the splits one
 // workgroup of the first Gram reduction pass sums
 inline int upm_grid(int64_t n) { return (int)(((n + 16 * UPM_RT - 1) / (16 * UPM_RT) + BLK / 64 - 1) / (BLK / 64)); }
@@ -1081,7 +1081,8 @@ __global__ __launch_bounds__(BLK) void update_mfma_kernel(P* __restrict__ V_, Bl
                 acc[rt][nb][v] = r < n ? (double)wl[nb][r] : 0.0;
             }
     const int jc = live ? j + 1 : 0;
-    // UPM_PD chunks of four columns in flight per wave (one was too few to cover the memory latency)
+    // UPM_PD chunks of four columns in flight per wave (one was too few to cover the memory latency; 4: 452, 6:
+    // 447, 8: 530 us per launch on the 256 x 256 P2 system, the last at one wave per SIMD)
     constexpr int PD = UPM_PD;
     double a[PD][RT], b[PD][NB];
     auto load = [&](int u, int c0) {
